@@ -1,0 +1,197 @@
+"""Pins of the oracle's multigrid: schedule, Galerkin property, smoother facts,
+convergence to the direct solution, and measured vs LFA contraction."""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from oracle import dg_time, lfa, multigrid, spacetime
+
+
+# Schedules of the five workloads derived from the rule of Sec. 4 (full iff
+# mu_L >= mu*, semi otherwise; space to one node; time to one slab).
+CONFIG_SCHEDULES = [
+    # (d, n, N, T, pt, schedule)
+    (1, 31, 16, 1.0, 1, "ffff"),
+    (2, 127, 256, 1.0, 1, "ffffffss"),
+    (3, 63, 1024, 1.0, 1, "ffffsfssss"),
+    (2, 255, 512, 1.0, 2, "fffffffss"),
+    (2, 255, 1024, 1.0, 1, "fffffffsss"),
+]
+
+
+@pytest.mark.parametrize("d,n,N,T,pt,sched", CONFIG_SCHEDULES)
+def test_config_schedules(d, n, N, T, pt, sched):
+    levels, kinds = multigrid.coarsening_schedule(n, N, T, pt)
+    assert kinds == sched
+    assert levels[-1][1] == 1
+
+
+def test_figure_restriction_cases():
+    # Fig. chap4figureRestriction: 8 time levels, 4 space levels (n = 15, N = 128),
+    # mu_7 = 10 mu* and mu_7 = mu*.  The figure image is missing; the rule
+    # of Sec. 4 gives these sequences (semi doubles mu, full halves it).
+    for pt in (0, 1):
+        ms = dg_time.mu_star(pt)
+        n, N = 15, 128
+        h = 1.0 / (n + 1)
+        for c, expect in ((10.0, "fffssss"), (1.0, "fsfsfss")):
+            T = c * ms * h ** 2 * N
+            _, kinds = multigrid.coarsening_schedule(n, N, T, pt, mu_star=ms)
+            assert kinds == expect, (pt, c, kinds)
+
+
+def test_schedule_rules_semi_full():
+    _, k = multigrid.coarsening_schedule(15, 16, 1.0, 1, rule=multigrid.SEMI)
+    assert k == "ssss"
+    _, k = multigrid.coarsening_schedule(15, 64, 1e-6, 1, rule=multigrid.FULL)
+    assert k == "fffsss"
+    # a mu far below mu* never coarsens space with the paper's rule until it grows
+    _, k = multigrid.coarsening_schedule(7, 8, 1e-4, 1)
+    assert k == "sss"
+
+
+@pytest.mark.parametrize("d,pt,kind", [(1, 0, "f"), (1, 1, "s"), (1, 2, "f"), (2, 1, "f"),
+                                       (2, 1, "s"), (3, 1, "f"), (3, 0, "s")])
+def test_galerkin_identity(d, pt, kind):
+    # Rediscretised coarse operator equals P^T L P (Q1 nested, DG jumps vanish
+    # inside a coarse slab).
+    n, N = 7, 4
+    fine = spacetime.SpaceTimeLevel(d, n, N, pt, 0.1)
+    nc = (n - 1) // 2 if kind == "f" else n
+    coarse = spacetime.SpaceTimeLevel(d, nc, N // 2, pt, 0.2)
+    P = multigrid.transfer(fine, coarse, kind)
+    G = (P.T @ fine.L @ P - coarse.L).toarray()
+    assert np.abs(G).max() < 1e-13 * max(1.0, abs(coarse.L).max())
+
+
+@pytest.mark.parametrize("d,pt", [(1, 1), (2, 2)])
+def test_omega1_block_jacobi_exact_after_N_sweeps(d, pt):
+    # Undamped block Jacobi on a block lower-bidiagonal L is nilpotent: N sweeps are exact.
+    N = 8
+    H = multigrid.Hierarchy(d, 3, N, pt, omega=1.0)
+    lev = H.fine
+    rng = np.random.default_rng(2)
+    F = rng.normal(size=(lev.dof, 1))
+    u = np.zeros_like(F)
+    k = len(H.levels) - 1
+    for _ in range(N):
+        u = H.smooth(k, u, F)
+    ref = spla.spsolve(lev.L.tocsc(), F[:, 0])
+    assert np.allclose(u[:, 0], ref, rtol=1e-12, atol=1e-13)
+
+
+def test_single_slab_damped_step_halves_error():
+    # One slab: D = L, so one step with omega = 1/2 halves the error exactly.
+    H = multigrid.Hierarchy(2, 7, 1, 1, omega=0.5)
+    lev = H.fine
+    rng = np.random.default_rng(4)
+    F = rng.normal(size=(lev.dof, 1))
+    ue = spla.spsolve(lev.L.tocsc(), F[:, 0])[:, None]
+    u = rng.normal(size=(lev.dof, 1))
+    u1 = H.smooth(0, u, F)
+    assert np.allclose(u1 - ue, 0.5 * (u - ue), rtol=1e-12, atol=1e-13)
+
+
+@pytest.mark.parametrize("d,n,N,pt", [(1, 15, 16, 0), (1, 31, 16, 1), (2, 7, 16, 1),
+                                       (2, 15, 8, 2), (3, 7, 8, 1)])
+def test_vcycle_converges_to_direct_solution(d, n, N, pt):
+    H = multigrid.Hierarchy(d, n, N, pt)
+    rng = np.random.default_rng(d * 100 + n)
+    F = rng.uniform(-1, 1, (H.fine.dof, 2))
+    u, hist, _ = H.solve(F, rtol=1e-10, maxit=40)
+    assert np.all(hist[-1] <= 1e-10)
+    ref = np.stack([spla.spsolve(H.fine.L.tocsc(), F[:, i]) for i in range(2)], axis=1)
+    assert np.linalg.norm(u - ref) / np.linalg.norm(ref) < 1e-8
+    # Tables of Sec. 4 report 4-9 cycles to 1e-8 for the paper's discretisations.
+    assert len(hist) - 1 <= 14
+
+
+def test_adjoint_vcycle_converges_to_backward_substitution():
+    H = multigrid.Hierarchy(2, 15, 16, 1, transpose=True)
+    rng = np.random.default_rng(9)
+    g = rng.normal(size=(H.fine.dof, 1))
+    lam, hist, _ = H.solve(g, rtol=1e-11, maxit=40)
+    ref = spacetime.forward_substitution(H.fine, g, transpose=True)
+    assert np.linalg.norm(lam - ref) / np.linalg.norm(ref) < 1e-9
+
+
+def test_vcycle_with_zero_rhs_stays_zero():
+    H = multigrid.Hierarchy(1, 7, 4, 1)
+    u, hist, _ = H.solve(np.zeros((H.fine.dof, 1)))
+    assert np.all(u == 0.0) and hist[-1][0] == 0.0
+
+
+# ---------------------------------------------------------------- LFA pins
+
+
+@pytest.mark.parametrize("pt", [0, 1, 2, 3])
+@pytest.mark.parametrize("mu", [1e-3, 0.3, 10.0, 1e3])
+def test_semi_smoothing_factor_bound(pt, mu):
+    # Lemmas chap4_lemma21 / chap4_lemma21b: sup over high time frequencies <= 1/sqrt 2 at omega = 1/2,
+    # attained at theta_x = 0, theta_t = pi/2.
+    s = lfa.smoothing_factor(pt, mu, "s", ngrid=33)
+    assert s <= 1 / np.sqrt(2) + 1e-12
+    assert s >= 1 / np.sqrt(2) - 1e-12
+
+
+@pytest.mark.parametrize("pt", [0, 1, 2])
+@pytest.mark.parametrize("mu", [0.01, 0.29, 1.0, 100.0])
+def test_full_smoothing_factor(pt, mu):
+    # Lemma chap4_lemma22: sup over theta_t of S-hat = 1/2 (1 + |alpha|), alpha = R(-mu beta(theta_x));
+    # over theta_x in [pi/2, pi] (beta in [3, 12]) the factor is 1/2 (1 + max |alpha|).
+    # Lemma chap4_lemma23's 1/2 (1 + R(-3 mu)) needs R decreasing on [-12 mu, -3 mu]; that holds
+    # for p_t = 0 at every mu, and for p_t >= 1 only for some mu (e.g. not p_t = 2, mu = 1).
+    ng = 65
+    s = lfa.smoothing_factor(pt, mu, "f", ngrid=ng)
+    tx = np.linspace(np.pi / 2, np.pi, ng)
+    alpha = np.abs(dg_time.stability_function(pt, -mu * lfa.beta(tx)))
+    assert abs(s - 0.5 * (1 + alpha.max())) < 1e-12
+    if pt == 0:
+        assert abs(s - 0.5 * (1 + dg_time.stability_function(pt, -3 * mu))) < 1e-12
+
+
+@pytest.mark.parametrize("kind", ["s", "f"])
+def test_lfa_galerkin_in_symbol_space(kind):
+    sym = lfa.Symbols(1, 64 / 1024 ** 2, 1 / 1024)
+    for tx in (0.0, 0.3, -1.2, np.pi / 2):
+        for tt in (0.0, 0.7, -1.5):
+            assert sym.galerkin_defect(tx, tt, kind) < 1e-12 * 1e3
+
+
+def test_lfa_two_grid_claims():
+    # Sec. 3.2 (text about the missing plots): semi-coarsening <= 1/2 for all mu;
+    # p_t = 1 "much smaller" than p_t = 0 (read: smaller worst case over mu, and
+    # smaller for mu <= 1; at mu >> 1 both approach 1/4); full coarsening
+    # <= 1/2 iff mu >= mu*.
+    g = dict(nx_grid=128, nt_grid=32)
+    s0 = {mu: lfa.two_grid_factor(0, mu, "s", **g) for mu in (1e-4, 1.0, 1e2, 1e4)}
+    s1 = {mu: lfa.two_grid_factor(1, mu, "s", **g) for mu in (1e-4, 1.0, 1e2, 1e4)}
+    assert max(s0.values()) <= 0.5 + 1e-9 and max(s1.values()) <= 0.5 + 1e-9
+    assert max(s1.values()) < max(s0.values()) - 0.1
+    assert s1[1e-4] < s0[1e-4] - 0.2 and s1[1.0] < s0[1.0] - 0.1
+    for pt in (0, 1):
+        ms = dg_time.mu_star(pt)
+        assert abs(lfa.two_grid_factor(pt, ms, "f", **g) - 0.5) < 1e-9
+        assert lfa.two_grid_factor(pt, 2 * ms, "f", **g) <= 0.5 + 1e-9
+        assert lfa.two_grid_factor(pt, 10 * ms, "f", **g) <= 0.5 + 1e-9
+        assert lfa.two_grid_factor(pt, 0.5 * ms, "f", **g) > 0.6
+        assert lfa.two_grid_factor(pt, 0.01, "f", **g) > 0.9
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("mu,kind", [(64.0, "s"), (64.0, "f"), (4.0, "f")])
+def test_measured_two_grid_matches_lfa(mu, kind):
+    # Protocol of Sec. 3.2: f = 0, random u0 in [0,1], two-grid cycle with
+    # exact coarse solve, factor max_k ||r^{k+1}|| / ||r^k||.  p_t = 1, nu = 1.
+    n, N, pt = 255, 64, 1
+    h = 1.0 / (n + 1)
+    T = mu * h ** 2 * N
+    rule = multigrid.FULL if kind == "f" else multigrid.SEMI
+    H = multigrid.Hierarchy(1, n, N, pt, T=T, nu1=1, nu2=1, rule=rule)
+    rng = np.random.default_rng(0)
+    u0 = rng.uniform(0, 1, (H.fine.dof, 1))
+    F = np.zeros_like(u0)
+    meas = multigrid.measured_contraction(H, u0, F, iters=60)
+    theory = lfa.two_grid_factor(pt, mu, kind, 1, 1, nx_grid=256, nt_grid=64)
+    assert abs(meas - theory) <= 0.05 * theory, (meas, theory)
+    assert meas <= 0.5
