@@ -1,0 +1,214 @@
+"""Benchmark: space-time multigrid V-cycles on one MI355X.
+
+Workload (default): 2-D heat equation on the unit square, Q1 with 127 x 127
+interior nodes, N = 256 DG(p_t=1) slabs on (0,1) (mu = tau/h^2 = 64),
+f = sum of 8 seeded Gaussian bumps, u0 = sin(pi x) sin(pi y); FP64.
+A step is one V-cycle of the whole hot path (residual, damped block-Jacobi
+smoothing by fast diagonalisation, restriction, prolongation, coarsest solve)
+plus the fine residual norm used by the stopping test.  Inputs are resident
+in HBM before the timed region starts.
+
+Prints one JSON line.  Besides DoF*V-cycles/s it reports the time to a 1e-10
+relative residual for the FP64 solve and for the mixed-precision solve (FP32
+inner V-cycle inside FP64 iterative refinement), the roofline position of the
+dominant kernel (per-launch durations from HIP events recorded by the library
+around each launch during a profiled pass of the same steps), and the CPU
+oracle timed on a bounded sample of the same workload family.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
+FP64_MFMA_PEAK_TFS = 78.6    # MI355X dense FP64 matrix
+FP32_MFMA_PEAK_TFS = 157.3   # MI355X dense FP32 matrix
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", type=int, default=2, help="workload index (1..5)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-graph", action="store_true", help="launch kernels eagerly instead of replaying a hipGraph")
+    ap.add_argument("--only-timed", action="store_true", help="timed V-cycles only (for profiler runs)")
+    return ap.parse_args()
+
+
+def cpu_baseline(budget_s=20.0):
+    """Oracle V-cycles on a reduced member of the same family (same mu, p_t)."""
+    import numpy as np
+
+    from oracle import multigrid, spacetime
+    from paper_1411_0519_amd import workloads
+
+    d, n, N, pt = 2, 63, 64, 1      # mu = (1/64) * 64^2 = 64, like the 127^2 x 256 workload
+    t0 = time.perf_counter()
+    H = multigrid.Hierarchy(d, n, N, pt)
+    f, u0 = workloads.make(d, n, N, batch=1, seed=2, f="bumps", u0="sine1")
+    F = spacetime.rhs(H.fine, f, u0)
+    setup = time.perf_counter() - t0
+    k = len(H.levels) - 1
+    u = np.zeros_like(F)
+    H.vcycle(k, u, F)                 # factorisations happen on first use
+    cycles = 0
+    t0 = time.perf_counter()
+    while True:
+        u = H.vcycle(k, u, F)
+        _ = np.linalg.norm(H.residual(k, u, F))
+        cycles += 1
+        el = time.perf_counter() - t0
+        if el > budget_s or cycles >= 50:
+            break
+    rate = H.fine.dof * cycles / el
+    return {"value": rate, "unit": "DoF*V-cycles/s", "cores": 1, "kind": "oracle",
+            "sample": f"2-D n={n} N={N} p_t={pt} (mu=64, {H.fine.dof} DoF), {cycles} V-cycles + residual "
+                      f"norm each, {el:.1f} s; setup {setup:.1f} s excluded; scipy CSR SpMV and SuperLU "
+                      f"solves run on one thread",
+            "host_cpus_available": len(os.sched_getaffinity(0))}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_1411_0519_amd import stmg, workloads
+
+    dev = "cuda:0"
+    w = workloads.WORKLOADS[args.workload]
+    d, n, N, pt, b = w["dim"], w["n"], w["N"], w["pt"], w["batch"]
+    _, f, u0 = workloads.workload(args.workload)
+    stream = torch.cuda.Stream(device=dev)
+    result = {}
+    with torch.cuda.stream(stream):
+        S = stmg.Solver(d, n, N, pt=pt, batch=b, device=dev)
+        fg = torch.from_numpy(f.ravel()).to(dev)
+        ug0 = torch.from_numpy(u0.ravel()).to(dev)
+        F = S.rhs(fg, ug0)
+        dof = S.level_dof(0)
+        u = torch.zeros(dof, dtype=torch.float64, device=dev)
+        if not args.no_graph:
+            S.set_graph(True)
+        # warmup (also records the graph)
+        S.solve(F, u=u, rtol=0.0, maxit=max(args.warmup, 1), raise_on_noconv=False)
+        torch.cuda.synchronize()
+        u.zero_()
+        t0 = time.perf_counter()
+        _, its, _ = S.solve(F, u=u, rtol=0.0, maxit=args.steps, raise_on_noconv=False)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        assert its == args.steps
+        ms = 1e3 * el / args.steps
+        value = dof * args.steps / el
+        if args.only_timed:
+            print(json.dumps({"metric": "space-time DoF*V-cycles/s", "value": value, "ms_per_step": ms}))
+            return
+
+        # time to a 1e-10 relative residual, FP64 (setup excluded)
+        u.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        u64, its64, hist64 = S.solve(F, u=u, rtol=1e-10, maxit=100)
+        torch.cuda.synchronize()
+        t64 = time.perf_counter() - t0
+
+        # profiled pass (eager, HIP events around every launch)
+        S.set_graph(False)
+        u2 = torch.zeros_like(u)
+        S.solve(F, u=u2, rtol=0.0, maxit=2, raise_on_noconv=False)
+        S.profile_start()
+        S.solve(F, u=u2, rtol=0.0, maxit=args.steps, raise_on_noconv=False)
+        torch.cuda.synchronize()
+        kinds = ["residual", "dst_x", "dst_y", "tsolve", "restrict", "prolong", "other"]
+        if d == 3:
+            kinds.insert(3, "dst_z")
+        prof = {}
+        for k in kinds:
+            tot, cnt = S.profile_read(k, level=-1)
+            tot0, cnt0 = S.profile_read(k, level=0)
+            prof[k] = {"ms_total": tot, "launches": cnt, "fine_ms_total": tot0, "fine_launches": cnt0}
+        S.profile_stop()
+        if not args.no_graph:
+            S.set_graph(True)
+
+        # mixed precision: FP32 inner V-cycle, FP64 refinement
+        M = stmg.Solver(d, n, N, pt=pt, batch=b, device=dev, precision="mixed")
+        if not args.no_graph:
+            M.set_graph(True)
+        um = torch.zeros_like(u)
+        M.solve(F, u=um, rtol=0.0, maxit=2, raise_on_noconv=False)   # warm + record graph
+        um.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        um, itsm, histm = M.solve(F, u=um, rtol=1e-10, maxit=100)
+        torch.cuda.synchronize()
+        tm = time.perf_counter() - t0
+        err_mixed = (torch.linalg.vector_norm(um - u64) / torch.linalg.vector_norm(u64)).item()
+
+    # roofline of the dominant kernel on the fine level
+    L0 = S.levels[0]
+    nvals = b * L0["N"] * S.nt * L0["n"] ** d
+    cand = {k: v for k, v in prof.items() if k.startswith("dst") and v["fine_launches"] > 0}
+    dom = max(cand, key=lambda k: cand[k]["fine_ms_total"])
+    avg_ms = cand[dom]["fine_ms_total"] / cand[dom]["fine_launches"]
+    flops = 2.0 * L0["n"] * nvals                      # one length-n dot product per output value
+    achieved = flops / (avg_ms * 1e-3) / 1e12
+    npad = 16
+    while npad < L0["n"]:
+        npad *= 2
+    roof = {"kernel": f"k_dst<double, {npad // 16}, {'true' if dom == 'dst_x' else 'false'}> ({dom}, fine level)",
+            "bound": "mfma", "achieved": achieved, "peak": FP64_MFMA_PEAK_TFS, "unit": "TFLOP/s",
+            "frac": achieved / FP64_MFMA_PEAK_TFS, "traffic": None,
+            "avg_launch_ms": avg_ms, "flops_per_launch": flops}
+    r0 = prof["residual"]
+    res_avg = r0["fine_ms_total"] / max(r0["fine_launches"], 1)
+    res_bytes = 3 * 8 * nvals                           # read u, F; write r
+    res_gbs = res_bytes / (res_avg * 1e-3) / 1e9
+    total_prof = sum(v["ms_total"] for v in prof.values())
+    out = {
+        "metric": "space-time DoF*V-cycles/s (+ time-to-1e-10, mixed vs FP64)",
+        "value": value,
+        "unit": "DoF*V-cycles/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{w['name']}: {d}-D Q1 {n}^{d} interior, N={N} slabs, DG p_t={pt}, "
+                               f"batch {b}, FP64, omega=1/2, nu1=nu2=2, schedule {S.schedule}",
+                   "dof": dof, "levels": S.nlev, "graph": not args.no_graph},
+        "time_to_1e-10": {"fp64_s": t64, "fp64_cycles": its64, "mixed_s": tm, "mixed_cycles": itsm,
+                          "speedup_mixed_vs_fp64": t64 / tm,
+                          "mixed_rel_error_vs_fp64": err_mixed,
+                          "fp64_final_relres": hist64[-1][0], "mixed_final_relres": histm[-1][0]},
+        "roofline": roof,
+        "residual_kernel": {"bound": "hbm", "achieved": res_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                            "frac": res_gbs / HBM_PEAK_GBS, "avg_launch_ms": res_avg,
+                            "bytes_per_launch": res_bytes},
+        "kernel_breakdown_ms_per_step": {k: v["ms_total"] / args.steps for k, v in prof.items()},
+        "profiled_ms_per_step": total_prof / args.steps,
+    }
+    if not args.no_cpu_baseline:
+        cb = cpu_baseline()
+        out["cpu_baseline"] = cb
+        out["gpu_over_cpu"] = value / cb["value"]
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

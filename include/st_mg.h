@@ -1,0 +1,183 @@
+/*
+ * st_mg.h -- C ABI of the MI355X (gfx950) space-time multigrid library.
+ *
+ * Method: Gander & Neumueller, "Analysis of a new space-time parallel
+ * multigrid algorithm for parabolic problems" (arXiv 1411.0519).
+ * Problem (Sec. 1, eq. chap4_modelproblem): du/dt - Laplace(u) = f on
+ * (0,1)^d x (0,T), u = 0 on the boundary, u(.,0) = u0.  Discretisation:
+ * Q1 finite elements on the uniform grid with n interior nodes per
+ * dimension (h = 1/(n+1)), discontinuous Galerkin of order p_t in time on N
+ * slabs (tau = T/N) with the shifted Legendre basis
+ * psi_l(t) = P_l(2 (t - t_{n-1})/tau - 1).  The all-at-once system
+ * L u = F (eq. chap4_generalLinearSystem) has diagonal blocks
+ * A = K_tau (x) M_h + M_tau (x) K_h and sub-diagonal blocks -N_tau (x) M_h.
+ *
+ * Solver (Sec. 2, Sec. 4): V-cycles (gamma = 1) with nu1/nu2 damped
+ * block-Jacobi steps u <- u + omega D^{-1}(F - L u) (eq. chap4_smoother),
+ * D = diag{A} inverted exactly (eq. chap4_smootherExact) by fast
+ * diagonalisation; restriction R = P^T with P from eq.
+ * chap4_restrictionTime (time) and eq. chap4_spaceRestrictionProlongation
+ * (space); full space-time coarsening iff mu_L = tau_L/h_L^2 >= mu*
+ * (Remark chap4_remarkCriticalDiscretizationParameter), otherwise time
+ * semi-coarsening; coarsest level = one time slab, solved exactly.
+ *
+ * Conventions for every entry point:
+ *  - return value: ST_OK (0) or a negative ST_E* code; st_mg_last_error()
+ *    gives a message.  A handle may be used by one host thread at a time.
+ *  - vectors are DEVICE pointers, contiguous, laid out
+ *    [batch][slab][time dof l][z][y][x] (x fastest), batch-major; element
+ *    type double for ST_FP64 and ST_MIXED, float for ST_FP32.  The caller
+ *    owns every vector; the library only borrows them for the call.
+ *  - `stream` is a hipStream_t (NULL = default stream).  All device work is
+ *    enqueued on it; entry points that return host values (norms, iteration
+ *    counts) synchronise that stream before returning.
+ *  - "level" indices count from the finest (0) to the coarsest (nlev-1).
+ */
+#ifndef ST_MG_H
+#define ST_MG_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct st_mg* st_mg_t;
+
+enum {
+  ST_OK = 0,
+  ST_EINVAL = -1,      /* invalid argument or parameter combination        */
+  ST_ENOMEM = -2,      /* host or device allocation failed                 */
+  ST_EHIP = -3,        /* a HIP runtime call failed                        */
+  ST_ENOCONV = -4,     /* maxit reached before rtol (u holds last iterate)  */
+  ST_ESTATE = -5,      /* call not valid in the handle's state             */
+  ST_EWORKSPACE = -6,  /* no workspace bound, or bound workspace too small */
+  ST_ENAN = -7         /* residual norm became NaN or Inf                  */
+};
+
+enum {
+  ST_COARSEN_AUTO = 0, /* Sec. 4 rule: full iff mu_L >= mu* and n_L > 1, else semi */
+  ST_COARSEN_SEMI = 1, /* time semi-coarsening only                             */
+  ST_COARSEN_FULL = 2  /* full space-time coarsening while n_L > 1, then semi   */
+};
+
+enum {
+  ST_FP64 = 0,  /* every level in double                                          */
+  ST_FP32 = 1,  /* every level in float, norms accumulated in double             */
+  ST_MIXED = 2  /* double outer iterative refinement: fine residual and update in
+                   double, inner V-cycle in float, coarsest solve in double       */
+};
+
+typedef struct {
+  int dim;          /* d in {1,2,3}                                              */
+  int n;            /* interior nodes per dimension, n = 2^m - 1, 1 <= n <= 255  */
+  double T;         /* final time > 0                                            */
+  int N;            /* number of time slabs, a power of two                      */
+  int pt;           /* DG order p_t, 0 <= p_t <= 3                               */
+  double omega;     /* damping omega_t of the block-Jacobi smoother (0,1]        */
+  int nu1, nu2;     /* pre-/post-smoothing steps, >= 0                           */
+  int coarsen;      /* ST_COARSEN_*                                              */
+  double mu_star;   /* <= 0: computed from R(-3 mu*) = sqrt(2) - 1               */
+  int precision;    /* ST_FP64 | ST_FP32 | ST_MIXED                              */
+  int batch;        /* number of right-hand sides b >= 1                         */
+} st_mg_params;
+
+/* Fill defaults: d=1, n=31, T=1, N=16, p_t=1, omega=1/2, nu1=nu2=2 (Sec. 4,
+ * Example chap4_example1), AUTO coarsening, FP64, batch 1. */
+void st_mg_default_params(st_mg_params* p);
+
+/* Validate parameters, build the level hierarchy (Sec. 4 rule) and upload the
+ * per-level constants (DST matrices, per-mode inverse blocks).  Allocates
+ * only the constant tables; no vector workspace.  *out owned by the caller
+ * until st_mg_destroy. */
+int st_mg_setup(const st_mg_params* p, st_mg_t* out);
+int st_mg_destroy(st_mg_t h);
+const char* st_mg_last_error(st_mg_t h);
+
+/* Bytes of device workspace the solver needs (coarse-level vectors, the
+ * fine residual, one transform buffer and reduction partials). */
+int st_mg_workspace_bytes(st_mg_t h, size_t* bytes);
+/* Bind caller-owned device memory (256-byte aligned, >= workspace bytes);
+ * dptr == NULL asks the library to allocate and own it (freed by destroy). */
+int st_mg_bind_workspace(st_mg_t h, void* dptr, size_t bytes);
+
+/* Hierarchy description: number of levels, schedule string of nlev-1
+ * characters 'f' (full) / 's' (semi) from fine to coarse, NUL-terminated
+ * (cap >= nlev).  Per level: n_L, N_L, tau_L, mu_L = tau_L/h_L^2. */
+int st_mg_levels(st_mg_t h, int* nlev, char* schedule, int cap);
+int st_mg_level_info(st_mg_t h, int level, int* n, int* N, double* tau, double* mu);
+/* Fine-level sizes: vector length per right-hand side (N N_t n^d) and the
+ * nodal lengths of f (N n^d) and u0 (n^d) per right-hand side. */
+int st_mg_sizes(st_mg_t h, long long* dof, long long* f_len, long long* u0_len);
+
+/* Right-hand side from nodal data (Sec. 1 load vector; u0 enters slab 1
+ * through N_tau (x) M_h, eq. (equation1) with n = 0):
+ *   F[b][n][l] = (int_slab psi_l dt) M_h f[b][n],  F[b][0][l] += psi_l(t_0^+) M_h u0[b].
+ * f: [b][N][n^d], u0: [b][n^d] (NULL = 0), both in the handle's vector type
+ * (double for ST_MIXED).  F: fine vector. */
+int st_mg_rhs(st_mg_t h, const void* f, const void* u0, void* F, void* stream);
+/* Transpose of st_mg_rhs (for gradients): grad_f[b][n] = sum_l (int psi_l) M_h lam[b][n][l],
+ * grad_u0[b] = sum_l psi_l(t_0^+) M_h lam[b][0][l].  Either output may be NULL. */
+int st_mg_rhs_adjoint(st_mg_t h, const void* lam, void* grad_f, void* grad_u0, void* stream);
+
+/* ---- level operators (finest = level 0); vectors sized for that level ----
+ * prec selects the arithmetic (ST_FP64: double vectors, ST_FP32: float);
+ * transpose != 0 applies L^T instead of L (the adjoint problem L^T lam = g). */
+/* r = F - L u  (eq. chap4_smoother's defect); norms2 (nullable, host, batch
+ * doubles) receives ||r_b||_2^2 per right-hand side. */
+int st_mg_residual(st_mg_t h, int level, int prec, int transpose, const void* u, const void* F,
+                   void* r, double* norms2, void* stream);
+/* x = D^{-1} r, D = diag{A}: exact slab solves by fast diagonalisation. */
+int st_mg_block_solve(st_mg_t h, int level, int prec, int transpose, const void* r, void* x,
+                      void* stream);
+/* One damped block-Jacobi step u <- u + omega D^{-1}(F - L u). */
+int st_mg_smooth(st_mg_t h, int level, int prec, int transpose, void* u, const void* F,
+                 void* stream);
+/* F_c = R r_f = P^T r_f from level to level+1. */
+int st_mg_restrict(st_mg_t h, int level, int prec, const void* r_fine, void* F_coarse, void* stream);
+/* u_f += P e_c from level+1 to level. */
+int st_mg_prolong_add(st_mg_t h, int level, int prec, const void* e_coarse, void* u_fine,
+                      void* stream);
+
+/* ---- cycles and solves on the finest level ----
+ * One V-cycle u <- MG(u, F) (ST_MIXED: one refinement step: FP64 residual,
+ * FP32 V-cycle for the correction, FP64 update).  relres (nullable, host,
+ * batch doubles) receives ||F - L u_new|| / ||F - L u_old|| per RHS. */
+int st_mg_vcycle(st_mg_t h, void* u, const void* F, double* relres, void* stream);
+/* Repeat V-cycles until ||F - L u_k||_2 <= rtol ||F - L u_0||_2 for every
+ * RHS or maxit cycles.  u is the initial guess on entry.  *iters = cycles
+ * done; hist (nullable, host) receives (maxit+1) x batch relative residuals
+ * (row k = after k cycles).  Returns ST_ENOCONV if maxit is reached. */
+int st_mg_solve(st_mg_t h, void* u, const void* F, double rtol, int maxit, int* iters,
+                double* hist, void* stream);
+/* Adjoint solve L^T lam = g (backward in time, transposed blocks, same
+ * hierarchy and transfers), lam in/out (initial guess), then the gradients
+ * of J(f, u0) with dJ/du = g: grad_f and grad_u0 as in st_mg_rhs_adjoint
+ * (each nullable).  Same stopping rule and outputs as st_mg_solve. */
+int st_mg_adjoint(st_mg_t h, const void* g, void* lam, void* grad_f, void* grad_u0, double rtol,
+                  int maxit, int* iters, double* hist, void* stream);
+
+/* Graph mode: 1 = record one V-cycle per (u, F, transpose) as a hipGraph on
+ * first use and replay it; 0 = launch kernels directly (default).  Graph mode
+ * needs a non-NULL stream. */
+int st_mg_set_graph(st_mg_t h, int enable);
+
+/* Per-kernel timing with HIP events recorded around every launch on the
+ * launch stream (eager mode only; ST_ESTATE in graph mode).  start clears
+ * previous records; read synchronises on the last event and returns the
+ * summed duration (ms) and launch count of one kernel kind on one level
+ * (level -1 = all levels). */
+enum {
+  ST_PROF_RESIDUAL = 0, ST_PROF_DST_X = 1, ST_PROF_DST_Y = 2, ST_PROF_DST_Z = 3,
+  ST_PROF_TSOLVE = 4, ST_PROF_RESTRICT = 5, ST_PROF_PROLONG = 6, ST_PROF_OTHER = 7,
+  ST_PROF_KINDS = 8
+};
+int st_mg_profile_start(st_mg_t h);
+int st_mg_profile_stop(st_mg_t h);
+int st_mg_profile_read(st_mg_t h, int kind, int level, double* total_ms, int* count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ST_MG_H */

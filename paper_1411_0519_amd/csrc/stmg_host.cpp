@@ -1,0 +1,1085 @@
+// Host side of the space-time multigrid library: parameter validation, the
+// level hierarchy (coarsening rule of Sec. 4), per-level constant tables for
+// the fast-diagonalisation block solve, workspace binding, the V-cycle /
+// solve / adjoint drivers, and the C ABI declared in st_mg.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "st_mg.h"
+#include "stmg_internal.h"
+
+using namespace stmg;
+
+namespace {
+
+constexpr double PI = 3.14159265358979323846;
+
+// ------------------------------------------------------------ small dense helpers
+// Legendre P_l(s) by the three-term recurrence.
+double legendre(int l, double s) {
+  if (l == 0) return 1.0;
+  double p0 = 1.0, p1 = s;
+  for (int k = 2; k <= l; ++k) {
+    const double p2 = ((2.0 * k - 1.0) * s * p1 - (k - 1.0) * p0) / k;
+    p0 = p1;
+    p1 = p2;
+  }
+  return p1;
+}
+
+// Gauss-Legendre nodes/weights on [-1,1] (Newton on P_q).
+void gauss_legendre(int q, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(q, 0.0);
+  w.assign(q, 0.0);
+  for (int i = 0; i < q; ++i) {
+    double s = std::cos(PI * (i + 0.75) / (q + 0.5));
+    for (int it = 0; it < 100; ++it) {
+      const double p = legendre(q, s), pm = legendre(q - 1, s);
+      const double dp = q * (s * p - pm) / (s * s - 1.0);
+      const double ds = p / dp;
+      s -= ds;
+      if (std::fabs(ds) < 1e-16) break;
+    }
+    const double p = legendre(q, s), pm = legendre(q - 1, s);
+    const double dp = q * (s * p - pm) / (s * s - 1.0);
+    x[i] = s;
+    w[i] = 2.0 / ((1.0 - s * s) * dp * dp);
+  }
+}
+
+// In-place inverse of a small dense matrix (Gauss-Jordan, partial pivoting).
+bool invert(int n, double* A) {
+  std::vector<double> I(n * n, 0.0);
+  for (int i = 0; i < n; ++i) I[i * n + i] = 1.0;
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::fabs(A[r * n + c]) > std::fabs(A[piv * n + c])) piv = r;
+    if (A[piv * n + c] == 0.0) return false;
+    if (piv != c)
+      for (int k = 0; k < n; ++k) {
+        std::swap(A[c * n + k], A[piv * n + k]);
+        std::swap(I[c * n + k], I[piv * n + k]);
+      }
+    const double d = A[c * n + c];
+    for (int k = 0; k < n; ++k) {
+      A[c * n + k] /= d;
+      I[c * n + k] /= d;
+    }
+    for (int r = 0; r < n; ++r)
+      if (r != c) {
+        const double f = A[r * n + c];
+        if (f == 0.0) continue;
+        for (int k = 0; k < n; ++k) {
+          A[r * n + k] -= f * A[c * n + k];
+          I[r * n + k] -= f * I[c * n + k];
+        }
+      }
+  }
+  std::memcpy(A, I.data(), sizeof(double) * n * n);
+  return true;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Level {
+  int n = 0, N = 0;
+  long long nx = 0;
+  double tau = 0, h = 0, mu = 0;
+  char kind = 0;          // transition to the next coarser level: 'f' or 's'; 0 on the coarsest
+  int np = 0;             // padded transform size (16..256)
+  double* S64 = nullptr;  // DST-I in MFMA fragment order
+  float* S32 = nullptr;
+  double* G64 = nullptr;  // per-mode inverse blocks [nx][nt][nt]
+  float* G32 = nullptr;
+  void* u = nullptr;      // workspace vectors (inner precision), coarse levels only
+  void* F = nullptr;
+  void* r = nullptr;
+  long long dof(int nt, int b) const { return (long long)b * N * nt * nx; }
+};
+
+struct GraphCache {
+  hipGraphExec_t exec = nullptr;
+  const void* u = nullptr;
+  const void* F = nullptr;
+  int transpose = -1;
+  hipStream_t stream = nullptr;
+};
+
+}  // namespace
+
+struct st_mg {
+  st_mg_params p{};
+  int nt = 0;
+  double mu_star = 0;
+  std::vector<Level> lv;
+  double Kt[NT_MAX * NT_MAX] = {};   // K_tau (independent of tau for the Legendre basis)
+  double Mh[NT_MAX * NT_MAX] = {};   // M_tau / tau
+  double ca[NT_MAX] = {};            // psi_l(t_{n-1}^+): N_tau = ca cb^T
+  double cb[NT_MAX] = {};            // psi_l(t_n^-)
+  double ints[NT_MAX] = {};          // int_slab psi_l dt / tau
+  double R1T[NT_MAX * NT_MAX] = {};  // time prolongation blocks (independent of tau)
+  double R2T[NT_MAX * NT_MAX] = {};
+  // workspace
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  bool ws_owned = false;
+  void* tmp = nullptr;   // transform buffer, inner precision, fine size
+  void* r0 = nullptr;    // fine residual, inner precision
+  void* F32 = nullptr;   // mixed: inner right-hand side (fine, float)
+  void* e32 = nullptr;   // mixed: inner correction (fine, float)
+  double *cu64 = nullptr, *cF64 = nullptr, *cr64 = nullptr, *ct64 = nullptr;  // mixed: coarsest in double
+  double* partial = nullptr;
+  long long partial_per_batch = 0;
+  double* norm_dev = nullptr;
+  int graph = 0;
+  GraphCache gc;
+  // per-launch event pairs while profiling is on
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  struct ProfRec { int kind, level; size_t e0, e1; };
+  std::vector<ProfRec> prof_recs;
+  std::string err;
+};
+
+namespace {
+
+int fail(st_mg_t h, int code, const char* fmt, ...) {
+  if (h) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    h->err = buf;
+  }
+  return code;
+}
+
+#define HIPCHK(h, call)                                                              \
+  do {                                                                               \
+    hipError_t e_ = (call);                                                          \
+    if (e_ != hipSuccess) return fail(h, ST_EHIP, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+#define CHK(call)              \
+  do {                         \
+    int rc_ = (call);          \
+    if (rc_ != ST_OK) return rc_; \
+  } while (0)
+
+bool is_pow2(long long x) { return x > 0 && (x & (x - 1)) == 0; }
+
+// ------------------------------------------------------------------ profiling
+// Event pair around one launch: begin() returns a ticket, end() closes it.
+size_t prof_event(st_mg* h) {
+  if (h->ev_used == h->ev_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return (size_t)-1;
+    h->ev_pool.push_back(e);
+  }
+  return h->ev_used++;
+}
+
+struct ProfScope {
+  st_mg* h;
+  int kind, level;
+  hipStream_t s;
+  size_t e0 = (size_t)-1;
+  ProfScope(st_mg* h_, int kind_, int level_, hipStream_t s_) : h(h_), kind(kind_), level(level_), s(s_) {
+    if (h->prof) {
+      e0 = prof_event(h);
+      if (e0 != (size_t)-1) (void)hipEventRecord(h->ev_pool[e0], s);
+    }
+  }
+  ~ProfScope() {
+    if (h->prof && e0 != (size_t)-1) {
+      const size_t e1 = prof_event(h);
+      if (e1 == (size_t)-1) return;
+      (void)hipEventRecord(h->ev_pool[e1], s);
+      h->prof_recs.push_back({kind, level, e0, e1});
+    }
+  }
+};
+
+// ---------------------------------------------------------------- time basis
+// Shifted Legendre basis on a slab: M_tau = tau diag(1/(2l+1));
+// K_tau[k][l] = 1 - 2 [l < k and k - l odd] (from -int psi_l psi_k' + psi_l(t_n) psi_k(t_n));
+// psi_l(t_n^-) = 1, psi_l(t_{n-1}^+) = (-1)^l.
+void time_basis(st_mg* h) {
+  const int nt = h->nt;
+  for (int k = 0; k < nt; ++k) {
+    for (int l = 0; l < nt; ++l) {
+      h->Kt[k * nt + l] = 1.0 - ((l < k && ((k - l) & 1)) ? 2.0 : 0.0);
+      h->Mh[k * nt + l] = (k == l) ? 1.0 / (2.0 * k + 1.0) : 0.0;
+    }
+    h->ca[k] = (k & 1) ? -1.0 : 1.0;
+    h->cb[k] = 1.0;
+    h->ints[k] = (k == 0) ? 1.0 : 0.0;
+  }
+  // R_s^T[k][l]: Legendre coefficient k (fine slab s) of the coarse basis
+  // function P_l restricted to that half: P_l((x + 2s - 1)/2), x in [-1,1].
+  std::vector<double> gx, gw;
+  gauss_legendre(nt + 2, gx, gw);
+  for (int s = 0; s < 2; ++s) {
+    double* RT = s == 0 ? h->R1T : h->R2T;
+    for (int k = 0; k < nt; ++k)
+      for (int l = 0; l < nt; ++l) {
+        double acc = 0.0;
+        for (size_t q = 0; q < gx.size(); ++q)
+          acc += gw[q] * legendre(k, gx[q]) * legendre(l, 0.5 * (gx[q] + 2.0 * s - 1.0));
+        RT[k * nt + l] = 0.5 * (2.0 * k + 1.0) * acc;
+      }
+  }
+}
+
+// Stability function R(z) = b^T (K - z M/tau)^{-1} a (trace of the rank-one
+// matrix (K + lam M)^{-1} N with lam tau = -z; Lemma chap4_theorem2).
+double stability(const st_mg* h, double z) {
+  const int nt = h->nt;
+  double A[NT_MAX * NT_MAX];
+  for (int i = 0; i < nt * nt; ++i) A[i] = h->Kt[i] - z * h->Mh[i];
+  if (!invert(nt, A)) return NAN;
+  double r = 0.0;
+  for (int i = 0; i < nt; ++i)
+    for (int j = 0; j < nt; ++j) r += h->cb[i] * A[i * nt + j] * h->ca[j];
+  return r;
+}
+
+// mu*: first root of R(-3 mu) = sqrt(2) - 1 on (0, 5]
+// (Remark chap4_remarkCriticalDiscretizationParameter).
+double critical_mu(const st_mg* h) {
+  const double target = std::sqrt(2.0) - 1.0;
+  double lo = 0.0, hi = -1.0;
+  const int steps = 5000;
+  double prev = stability(h, 0.0) - target;
+  for (int i = 1; i <= steps; ++i) {
+    const double m = 5.0 * i / steps;
+    const double v = stability(h, -3.0 * m) - target;
+    if (prev > 0.0 && v <= 0.0) {
+      lo = 5.0 * (i - 1) / steps;
+      hi = m;
+      break;
+    }
+    prev = v;
+  }
+  if (hi < 0) return NAN;
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (stability(h, -3.0 * mid) - target > 0.0) lo = mid;
+    else hi = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+int padded_size(int n) {
+  int np = 16;
+  while (np < n) np *= 2;
+  return np;
+}
+
+// Upload the level's DST matrix (fragment order) and per-mode blocks G_k.
+int build_level_tables(st_mg* h, Level& L) {
+  const int n = L.n, np = L.np, nt = h->nt, d = h->p.dim;
+  // orthonormal DST-I, S[k][i] = sqrt(2/(n+1)) sin(pi (k+1)(i+1)/(n+1)), zero padded
+  std::vector<double> S((size_t)np * np, 0.0);
+  const double sc = std::sqrt(2.0 / (n + 1));
+  for (int k = 0; k < n; ++k)
+    for (int i = 0; i < n; ++i) S[(size_t)k * np + i] = sc * std::sin(PI * (k + 1.0) * (i + 1.0) / (n + 1));
+  const int nb = np / 16, ni = np / 4;
+  std::vector<double> frag((size_t)np * np);
+  std::vector<float> frag32((size_t)np * np);
+  for (int kb = 0; kb < nb; ++kb)
+    for (int ib = 0; ib < ni; ++ib)
+      for (int lane = 0; lane < 64; ++lane) {
+        const size_t o = ((size_t)kb * ni + ib) * 64 + lane;
+        frag[o] = S[(size_t)(kb * 16 + (lane & 15)) * np + ib * 4 + (lane >> 4)];
+        frag32[o] = (float)frag[o];
+      }
+  // per-mode blocks: mu_k K + nu_k M with mu_k = prod m, nu_k = sum_a kappa_a prod_{b!=a} m_b,
+  // m = h/3 (2 + cos), kappa = 2/h (1 - cos) at angle (k+1) pi h
+  const double hh = L.h;
+  std::vector<double> m1(n), k1(n);
+  for (int k = 0; k < n; ++k) {
+    const double c = std::cos((k + 1) * PI * hh);
+    m1[k] = hh / 3.0 * (2.0 + c);
+    k1[k] = 2.0 / hh * (1.0 - c);
+  }
+  const long long nx = L.nx;
+  std::vector<double> G((size_t)nx * nt * nt);
+  std::vector<float> G32((size_t)nx * nt * nt);
+  for (long long j = 0; j < nx; ++j) {
+    int idx[3] = {(int)(j % n), d >= 2 ? (int)((j / n) % n) : 0, d == 3 ? (int)(j / ((long long)n * n)) : 0};
+    double mu = 1.0;
+    for (int a = 0; a < d; ++a) mu *= m1[idx[a]];
+    double nu = 0.0;
+    for (int a = 0; a < d; ++a) {
+      double t = k1[idx[a]];
+      for (int b = 0; b < d; ++b)
+        if (b != a) t *= m1[idx[b]];
+      nu += t;
+    }
+    double blk[NT_MAX * NT_MAX];
+    for (int i = 0; i < nt * nt; ++i) blk[i] = mu * h->Kt[i] + nu * L.tau * h->Mh[i];
+    if (!invert(nt, blk)) return fail(h, ST_EINVAL, "singular slab block at mode %lld", j);
+    for (int i = 0; i < nt * nt; ++i) {
+      G[(size_t)j * nt * nt + i] = blk[i];
+      G32[(size_t)j * nt * nt + i] = (float)blk[i];
+    }
+  }
+  HIPCHK(h, hipMalloc(&L.S64, frag.size() * sizeof(double)));
+  HIPCHK(h, hipMalloc(&L.S32, frag32.size() * sizeof(float)));
+  HIPCHK(h, hipMalloc(&L.G64, G.size() * sizeof(double)));
+  HIPCHK(h, hipMalloc(&L.G32, G32.size() * sizeof(float)));
+  HIPCHK(h, hipMemcpy(L.S64, frag.data(), frag.size() * sizeof(double), hipMemcpyHostToDevice));
+  HIPCHK(h, hipMemcpy(L.S32, frag32.data(), frag32.size() * sizeof(float), hipMemcpyHostToDevice));
+  HIPCHK(h, hipMemcpy(L.G64, G.data(), G.size() * sizeof(double), hipMemcpyHostToDevice));
+  HIPCHK(h, hipMemcpy(L.G32, G32.data(), G32.size() * sizeof(float), hipMemcpyHostToDevice));
+  return ST_OK;
+}
+
+// --------------------------------------------------------------- precisions
+template <typename T> const T* Sof(const Level& L);
+template <> const double* Sof<double>(const Level& L) { return L.S64; }
+template <> const float* Sof<float>(const Level& L) { return L.S32; }
+template <typename T> const T* Gof(const Level& L);
+template <> const double* Gof<double>(const Level& L) { return L.G64; }
+template <> const float* Gof<float>(const Level& L) { return L.G32; }
+
+template <typename T>
+ResidArgs<T> resid_args(const st_mg* h, const Level& L, bool transpose) {
+  ResidArgs<T> a{};
+  const int nt = h->nt;
+  for (int l = 0; l < nt; ++l)
+    for (int k = 0; k < nt; ++k) {
+      a.K[l * nt + k] = (T)(transpose ? h->Kt[k * nt + l] : h->Kt[l * nt + k]);
+      a.M[l * nt + k] = (T)(L.tau * h->Mh[l * nt + k]);
+    }
+  for (int l = 0; l < nt; ++l) {
+    a.ca[l] = (T)(transpose ? h->cb[l] : h->ca[l]);
+    a.cb[l] = (T)(transpose ? h->ca[l] : h->cb[l]);
+  }
+  a.wm[0] = a.wm[2] = (T)(L.h / 6.0);
+  a.wm[1] = (T)(4.0 * L.h / 6.0);
+  a.wk[0] = a.wk[2] = (T)(-1.0 / L.h);
+  a.wk[1] = (T)(2.0 / L.h);
+  a.n = L.n;
+  a.nx = L.nx;
+  a.N = L.N;
+  a.batch = h->p.batch;
+  a.dir = transpose ? +1 : -1;
+  return a;
+}
+
+template <typename T>
+TransferArgs<T> transfer_args(const st_mg* h, int lf) {
+  const Level& F = h->lv[lf];
+  const Level& C = h->lv[lf + 1];
+  TransferArgs<T> a{};
+  for (int i = 0; i < h->nt * h->nt; ++i) {
+    a.R1T[i] = (T)h->R1T[i];
+    a.R2T[i] = (T)h->R2T[i];
+  }
+  a.nf = F.n;
+  a.nc = C.n;
+  a.nxf = F.nx;
+  a.nxc = C.nx;
+  a.Nc = C.N;
+  a.batch = h->p.batch;
+  return a;
+}
+
+template <typename T>
+RhsArgs<T> rhs_args(const st_mg* h) {
+  const Level& L = h->lv[0];
+  RhsArgs<T> a{};
+  for (int l = 0; l < h->nt; ++l) {
+    a.ints[l] = (T)(L.tau * h->ints[l]);
+    a.ca[l] = (T)h->ca[l];
+  }
+  a.wm[0] = a.wm[2] = (T)(L.h / 6.0);
+  a.wm[1] = (T)(4.0 * L.h / 6.0);
+  a.n = L.n;
+  a.nx = L.nx;
+  a.N = L.N;
+  a.batch = h->p.batch;
+  return a;
+}
+
+// ------------------------------------------------------------------ operators
+template <typename Tin, typename Tout>
+int op_residual(st_mg* h, int l, bool transpose, const Tin* u, const Tin* F, Tout* r, bool norms,
+                hipStream_t s) {
+  const Level& L = h->lv[l];
+  const ResidArgs<Tin> a = resid_args<Tin>(h, L, transpose);
+  {
+    ProfScope ps(h, ST_PROF_RESIDUAL, l, s);
+    HIPCHK(h, (launch_residual<Tin, Tout>(h->p.dim, h->nt, u, F, r, a, norms ? h->partial : nullptr, s)));
+  }
+  if (norms) {
+    ProfScope ps(h, ST_PROF_OTHER, l, s);
+    const long long per = (long long)residual_blocks_per_slab(L.nx) * L.N;
+    HIPCHK(h, launch_norm_final(h->partial, per, h->p.batch, h->norm_dev, s));
+  }
+  return ST_OK;
+}
+
+// x = D^{-1} src written into dst with `mode` (store / += omega x / = omega x).
+// Passes alternate between the buffers A and B; src is only read.
+template <typename T>
+int op_block_solve(st_mg* h, int l, bool transpose, const T* src, T* dst, int mode, T omega, T* A,
+                   T* B, hipStream_t s) {
+  const Level& L = h->lv[l];
+  const int d = h->p.dim, n = L.n, nt = h->nt;
+  const long long outer = (long long)h->p.batch * L.N * nt;
+  const long long nn = n;
+  // axis a: view [outer * n^(d-1-a)][n][n^a]
+  auto pass = [&](int axis, const T* in, T* out, int md, T om) -> int {
+    long long inner = 1;
+    for (int i = 0; i < axis; ++i) inner *= nn;
+    long long rest = 1;
+    for (int i = axis + 1; i < d; ++i) rest *= nn;
+    const long long ncols = outer * rest * inner;
+    ProfScope ps(h, ST_PROF_DST_X + axis, l, s);
+    HIPCHK(h, launch_dst<T>(L.np, axis == 0, in, out, Sof<T>(L), n, inner, ncols, om, md, s));
+    return ST_OK;
+  };
+  const T* cur = src;
+  T* bufs[2] = {A, B};
+  int nb = 0;
+  for (int axis = 0; axis < d; ++axis) {
+    T* out = bufs[nb];
+    CHK(pass(axis, cur, out, MODE_STORE, T(1)));
+    cur = out;
+    nb ^= 1;
+  }
+  {
+    ProfScope ps(h, ST_PROF_TSOLVE, l, s);
+    HIPCHK(h, launch_tsolve<T>(nt, const_cast<T*>(cur), Gof<T>(L), L.nx, (long long)h->p.batch * L.N,
+                               transpose ? 1 : 0, s));
+  }
+  for (int axis = d - 1; axis >= 0; --axis) {
+    if (axis == 0) {
+      CHK(pass(axis, cur, dst, mode, omega));
+    } else {
+      T* out = bufs[nb];
+      CHK(pass(axis, cur, out, MODE_STORE, T(1)));
+      cur = out;
+      nb ^= 1;
+    }
+  }
+  return ST_OK;
+}
+
+template <typename T>
+int op_restrict(st_mg* h, int l, const T* rf, T* Fc, hipStream_t s) {
+  const TransferArgs<T> a = transfer_args<T>(h, l);
+  ProfScope ps(h, ST_PROF_RESTRICT, l, s);
+  HIPCHK(h, launch_restrict<T>(h->p.dim, h->nt, h->lv[l].kind == 'f', rf, Fc, a, s));
+  return ST_OK;
+}
+
+template <typename T>
+int op_prolong(st_mg* h, int l, const T* ec, T* uf, hipStream_t s) {
+  const TransferArgs<T> a = transfer_args<T>(h, l);
+  ProfScope ps(h, ST_PROF_PROLONG, l, s);
+  HIPCHK(h, launch_prolong<T>(h->p.dim, h->nt, h->lv[l].kind == 'f', ec, uf, a, s));
+  return ST_OK;
+}
+
+// ------------------------------------------------------------------- V-cycle
+template <typename T>
+T* level_r(st_mg* h, int l) { return (T*)(l == 0 ? h->r0 : h->lv[l].r); }
+
+template <typename T>
+int coarsest_solve(st_mg* h, bool transpose, T* u, const T* F, hipStream_t s);
+
+template <>
+int coarsest_solve<double>(st_mg* h, bool transpose, double* u, const double* F, hipStream_t s) {
+  const int l = (int)h->lv.size() - 1;
+  return op_block_solve<double>(h, l, transpose, F, u, MODE_SET_SCALED, 1.0, (double*)h->tmp,
+                                level_r<double>(h, l), s);
+}
+
+template <>
+int coarsest_solve<float>(st_mg* h, bool transpose, float* u, const float* F, hipStream_t s) {
+  const int l = (int)h->lv.size() - 1;
+  if (h->p.precision == ST_MIXED) {
+    // exact coarsest solve kept in double
+    const long long len = h->lv[l].dof(h->nt, h->p.batch);
+    HIPCHK(h, launch_cast_f32_f64(F, h->cF64, len, s));
+    CHK(op_block_solve<double>(h, l, transpose, h->cF64, h->cu64, MODE_SET_SCALED, 1.0, h->ct64,
+                               h->cr64, s));
+    HIPCHK(h, launch_cast_f64_f32(h->cu64, u, len, s));
+    return ST_OK;
+  }
+  return op_block_solve<float>(h, l, transpose, F, u, MODE_SET_SCALED, 1.0f, (float*)h->tmp,
+                               level_r<float>(h, l), s);
+}
+
+// One V-cycle on level l.  u_zero: u holds no valid data and is treated as 0
+// (coarse-level corrections).  r_ready: level_r already holds F - L u.
+template <typename T>
+int vcycle(st_mg* h, int l, bool transpose, T* u, const T* F, bool u_zero, bool r_ready,
+           hipStream_t s) {
+  const int last = (int)h->lv.size() - 1;
+  if (l == last) return coarsest_solve<T>(h, transpose, u, F, s);
+  const T om = (T)h->p.omega;
+  T* r = level_r<T>(h, l);
+  T* A = (T*)h->tmp;
+  for (int i = 0; i < h->p.nu1; ++i) {
+    if (i == 0 && u_zero) {
+      CHK(op_block_solve<T>(h, l, transpose, F, u, MODE_SET_SCALED, om, A, r, s));
+    } else {
+      if (!(i == 0 && r_ready)) CHK((op_residual<T, T>(h, l, transpose, u, F, r, false, s)));
+      CHK(op_block_solve<T>(h, l, transpose, r, u, MODE_ADD_SCALED, om, A, r, s));
+    }
+  }
+  const Level& C = h->lv[l + 1];
+  T* uc = (T*)C.u;
+  T* Fc = (T*)C.F;
+  if (h->p.nu1 == 0 && u_zero) {
+    CHK(op_restrict<T>(h, l, F, Fc, s));
+  } else {
+    if (!(h->p.nu1 == 0 && r_ready)) CHK((op_residual<T, T>(h, l, transpose, u, F, r, false, s)));
+    CHK(op_restrict<T>(h, l, r, Fc, s));
+  }
+  CHK(vcycle<T>(h, l + 1, transpose, uc, Fc, true, false, s));
+  if (h->p.nu1 == 0 && u_zero) {
+    const long long len = h->lv[l].dof(h->nt, h->p.batch);
+    // u has no defined content yet: start the correction from zero (a fill
+    // kernel rather than a memset node, so the cycle stays graph-capturable)
+    HIPCHK(h, launch_fill<T>(u, len, s));
+  }
+  CHK(op_prolong<T>(h, l, uc, u, s));
+  for (int i = 0; i < h->p.nu2; ++i) {
+    CHK((op_residual<T, T>(h, l, transpose, u, F, r, false, s)));
+    CHK(op_block_solve<T>(h, l, transpose, r, u, MODE_ADD_SCALED, om, A, r, s));
+  }
+  return ST_OK;
+}
+
+int read_norms(st_mg* h, double* out, hipStream_t s) {
+  HIPCHK(h, hipMemcpyAsync(out, h->norm_dev, sizeof(double) * h->p.batch, hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  for (int b = 0; b < h->p.batch; ++b) out[b] = std::sqrt(out[b]);
+  return ST_OK;
+}
+
+// Fine-level residual norms ||F - L u|| into h->norm_dev (squared); leaves the
+// residual in the buffer the next cycle starts from.
+template <typename T>
+int fine_residual_norm(st_mg* h, bool transpose, const void* u, const void* F, hipStream_t s) {
+  if (h->p.precision == ST_MIXED)
+    return op_residual<double, float>(h, 0, transpose, (const double*)u, (const double*)F,
+                                      (float*)h->F32, true, s);
+  return op_residual<T, T>(h, 0, transpose, (const T*)u, (const T*)F, level_r<T>(h, 0), true, s);
+}
+
+// One cycle of the outer iteration given that the fine residual is ready:
+// FP64/FP32: V-cycle reusing r; mixed: inner float V-cycle on L e = r, u += e.
+template <typename T>
+int cycle_body(st_mg* h, bool transpose, void* u, const void* F, hipStream_t s) {
+  if (h->p.precision == ST_MIXED) {
+    CHK(vcycle<float>(h, 0, transpose, (float*)h->e32, (const float*)h->F32, true, false, s));
+    const long long len = h->lv[0].dof(h->nt, h->p.batch);
+    HIPCHK(h, launch_axpy_f32_f64((double*)u, (const float*)h->e32, len, s));
+    return ST_OK;
+  }
+  return vcycle<T>(h, 0, transpose, (T*)u, (const T*)F, false, true, s);
+}
+
+int check_ready(st_mg* h) {
+  if (!h) return ST_EINVAL;
+  if (!h->ws) return fail(h, ST_EWORKSPACE, "no workspace bound (st_mg_bind_workspace)");
+  return ST_OK;
+}
+
+// cycle + residual norm, replayed from a hipGraph when graph mode is on
+template <typename T>
+int cycle_and_norm(st_mg* h, bool transpose, void* u, const void* F, hipStream_t s) {
+  if (!h->graph) {
+    CHK(cycle_body<T>(h, transpose, u, F, s));
+    return fine_residual_norm<T>(h, transpose, u, F, s);
+  }
+  if (s == nullptr) return fail(h, ST_EINVAL, "graph mode needs a non-default stream");
+  GraphCache& g = h->gc;
+  if (!(g.exec && g.u == u && g.F == F && g.transpose == (int)transpose && g.stream == s)) {
+    if (g.exec) {
+      (void)hipGraphExecDestroy(g.exec);
+      g.exec = nullptr;
+    }
+    hipGraph_t graph;
+    HIPCHK(h, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    int rc = cycle_body<T>(h, transpose, u, F, s);
+    if (rc == ST_OK) rc = fine_residual_norm<T>(h, transpose, u, F, s);
+    hipError_t e = hipStreamEndCapture(s, &graph);
+    if (rc != ST_OK) return rc;
+    if (e != hipSuccess) return fail(h, ST_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(h, ST_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    g.u = u;
+    g.F = F;
+    g.transpose = (int)transpose;
+    g.stream = s;
+  }
+  HIPCHK(h, hipGraphLaunch(g.exec, s));
+  return ST_OK;
+}
+
+template <typename T>
+int solve_impl(st_mg* h, bool transpose, void* u, const void* F, double rtol, int maxit, int* iters,
+               double* hist, hipStream_t s) {
+  const int b = h->p.batch;
+  std::vector<double> nrm(b), scale(b), rel(b);
+  CHK(fine_residual_norm<T>(h, transpose, u, F, s));
+  CHK(read_norms(h, nrm.data(), s));
+  for (int i = 0; i < b; ++i) {
+    if (!std::isfinite(nrm[i])) {
+      if (iters) *iters = 0;
+      return fail(h, ST_ENAN, "initial residual norm is not finite (rhs %d)", i);
+    }
+    scale[i] = nrm[i] > 0 ? nrm[i] : 1.0;
+    rel[i] = nrm[i] > 0 ? 1.0 : 0.0;
+    if (hist) hist[i] = rel[i];
+  }
+  int k = 0;
+  auto converged = [&]() {
+    for (int i = 0; i < b; ++i)
+      if (!(rel[i] <= rtol)) return false;
+    return true;
+  };
+  while (k < maxit && !converged()) {
+    CHK(cycle_and_norm<T>(h, transpose, u, F, s));
+    CHK(read_norms(h, nrm.data(), s));
+    ++k;
+    for (int i = 0; i < b; ++i) {
+      rel[i] = nrm[i] / scale[i];
+      if (hist) hist[(size_t)k * b + i] = rel[i];
+      if (!std::isfinite(rel[i])) {
+        if (iters) *iters = k;
+        return fail(h, ST_ENAN, "residual norm is not finite after cycle %d (rhs %d)", k, i);
+      }
+    }
+  }
+  if (iters) *iters = k;
+  if (!converged()) return fail(h, ST_ENOCONV, "not converged to %g in %d cycles", rtol, maxit);
+  return ST_OK;
+}
+
+int inner_bytes(const st_mg* h) { return h->p.precision == ST_FP64 ? 8 : 4; }
+
+// Workspace layout (every piece 256-byte aligned).  Returns total bytes and,
+// when base != NULL, assigns the pointers.
+size_t layout(st_mg* h, char* base) {
+  const int b = h->p.batch, nt = h->nt;
+  const size_t ib = (size_t)inner_bytes(h);
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> void* {
+    void* p = base ? base + off : nullptr;
+    off += align256(bytes);
+    return p;
+  };
+  const long long fine = h->lv[0].dof(nt, b);
+  h->tmp = take(fine * ib);
+  h->r0 = take(fine * ib);
+  for (size_t l = 1; l < h->lv.size(); ++l) {
+    Level& L = h->lv[l];
+    const long long len = L.dof(nt, b);
+    L.u = take(len * ib);
+    L.F = take(len * ib);
+    L.r = take(len * ib);
+  }
+  if (h->p.precision == ST_MIXED) {
+    h->F32 = take(fine * 4);
+    h->e32 = take(fine * 4);
+    const long long cl = h->lv.back().dof(nt, b);
+    h->cu64 = (double*)take(cl * 8);
+    h->cF64 = (double*)take(cl * 8);
+    h->cr64 = (double*)take(cl * 8);
+    h->ct64 = (double*)take(cl * 8);
+  }
+  const Level& L0 = h->lv[0];
+  h->partial_per_batch = std::max<long long>((long long)residual_blocks_per_slab(L0.nx) * L0.N, 1024);
+  h->partial = (double*)take(sizeof(double) * h->partial_per_batch * b);
+  h->norm_dev = (double*)take(sizeof(double) * b);
+  return off;
+}
+
+int check_level(st_mg* h, int level, int prec, bool need_next) {
+  if (!h) return ST_EINVAL;
+  CHK(check_ready(h));
+  if (level < 0 || level >= (int)h->lv.size() || (need_next && level + 1 >= (int)h->lv.size()))
+    return fail(h, ST_EINVAL, "level %d out of range (levels: %zu)", level, h->lv.size());
+  if (prec != ST_FP64 && prec != ST_FP32) return fail(h, ST_EINVAL, "prec must be ST_FP64 or ST_FP32");
+  if (prec == ST_FP64 && h->p.precision != ST_FP64)
+    return fail(h, ST_EINVAL, "FP64 level operators need a handle set up with ST_FP64");
+  if (prec == ST_FP32 && h->p.precision == ST_FP64)
+    return fail(h, ST_EINVAL, "FP32 level operators need a handle set up with ST_FP32 or ST_MIXED");
+  return ST_OK;
+}
+
+}  // namespace
+
+// ================================================================== C ABI
+extern "C" {
+
+void st_mg_default_params(st_mg_params* p) {
+  if (!p) return;
+  p->dim = 1;
+  p->n = 31;
+  p->T = 1.0;
+  p->N = 16;
+  p->pt = 1;
+  p->omega = 0.5;
+  p->nu1 = 2;
+  p->nu2 = 2;
+  p->coarsen = ST_COARSEN_AUTO;
+  p->mu_star = 0.0;
+  p->precision = ST_FP64;
+  p->batch = 1;
+}
+
+int st_mg_setup(const st_mg_params* p, st_mg_t* out) {
+  if (!p || !out) return ST_EINVAL;
+  *out = nullptr;
+  st_mg* h = new (std::nothrow) st_mg();
+  if (!h) return ST_ENOMEM;
+  h->p = *p;
+  auto bad = [&](const char* msg) {
+    h->err = msg;
+    return ST_EINVAL;
+  };
+  int rc = ST_OK;
+  if (p->dim < 1 || p->dim > 3) rc = bad("dim must be 1, 2 or 3");
+  else if (p->n < 1 || p->n > 255 || !is_pow2((long long)p->n + 1)) rc = bad("n must be 2^m - 1 with 1 <= n <= 255");
+  else if (!(p->T > 0.0) || !std::isfinite(p->T)) rc = bad("T must be positive");
+  else if (!is_pow2(p->N) || p->N > (1 << 20)) rc = bad("N must be a power of two (<= 2^20)");
+  else if (p->pt < 0 || p->pt > NT_MAX - 1) rc = bad("p_t must be in 0..3");
+  else if (!(p->omega > 0.0 && p->omega <= 1.0)) rc = bad("omega must be in (0, 1]");
+  else if (p->nu1 < 0 || p->nu2 < 0 || p->nu1 + p->nu2 > 64) rc = bad("nu1, nu2 must be >= 0");
+  else if (p->coarsen < ST_COARSEN_AUTO || p->coarsen > ST_COARSEN_FULL) rc = bad("unknown coarsening rule");
+  else if (p->precision < ST_FP64 || p->precision > ST_MIXED) rc = bad("unknown precision");
+  else if (p->batch < 1) rc = bad("batch must be >= 1");
+  if (rc != ST_OK) {
+    // keep the handle alive only to report the message: return it so the caller can read it
+    *out = h;
+    return rc;
+  }
+  h->nt = p->pt + 1;
+  time_basis(h);
+  h->mu_star = p->mu_star > 0.0 ? p->mu_star : critical_mu(h);
+  if (!std::isfinite(h->mu_star)) {
+    h->err = "could not compute mu*";
+    *out = h;
+    return ST_EINVAL;
+  }
+  // hierarchy: Sec. 4 rule; space down to one node, time down to one slab
+  int n = p->n, N = p->N;
+  double tau = p->T / p->N;
+  while (true) {
+    Level L;
+    L.n = n;
+    L.N = N;
+    L.nx = 1;
+    for (int i = 0; i < p->dim; ++i) L.nx *= n;
+    L.tau = tau;
+    L.h = 1.0 / (n + 1);
+    L.mu = tau / (L.h * L.h);
+    L.np = padded_size(n);
+    if (N == 1) {
+      h->lv.push_back(L);
+      break;
+    }
+    bool full;
+    if (p->coarsen == ST_COARSEN_FULL) full = n > 1;
+    else if (p->coarsen == ST_COARSEN_SEMI) full = false;
+    else full = n > 1 && L.mu >= h->mu_star * (1.0 - 1e-12);
+    L.kind = full ? 'f' : 's';
+    h->lv.push_back(L);
+    if (full) n = (n - 1) / 2;
+    N /= 2;
+    tau *= 2.0;
+  }
+  for (auto& L : h->lv) {
+    rc = build_level_tables(h, L);
+    if (rc != ST_OK) {
+      *out = h;
+      return rc;
+    }
+  }
+  *out = h;
+  return ST_OK;
+}
+
+int st_mg_destroy(st_mg_t h) {
+  if (!h) return ST_OK;
+  if (h->gc.exec) (void)hipGraphExecDestroy(h->gc.exec);
+  for (auto& L : h->lv) {
+    (void)hipFree(L.S64);
+    (void)hipFree(L.S32);
+    (void)hipFree(L.G64);
+    (void)hipFree(L.G32);
+  }
+  if (h->ws_owned && h->ws) (void)hipFree(h->ws);
+  for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
+  delete h;
+  return ST_OK;
+}
+
+const char* st_mg_last_error(st_mg_t h) { return h ? h->err.c_str() : "null handle"; }
+
+int st_mg_workspace_bytes(st_mg_t h, size_t* bytes) {
+  if (!h || !bytes) return ST_EINVAL;
+  if (h->lv.empty()) return fail(h, ST_ESTATE, "handle was not set up");
+  *bytes = layout(h, nullptr);
+  return ST_OK;
+}
+
+int st_mg_bind_workspace(st_mg_t h, void* dptr, size_t bytes) {
+  if (!h) return ST_EINVAL;
+  if (h->lv.empty()) return fail(h, ST_ESTATE, "handle was not set up");
+  const size_t need = layout(h, nullptr);
+  if (h->gc.exec) {
+    (void)hipGraphExecDestroy(h->gc.exec);
+    h->gc.exec = nullptr;
+  }
+  if (h->ws_owned && h->ws) {
+    (void)hipFree(h->ws);
+    h->ws = nullptr;
+    h->ws_owned = false;
+  }
+  if (dptr == nullptr) {
+    void* p = nullptr;
+    if (hipMalloc(&p, need) != hipSuccess) return fail(h, ST_ENOMEM, "hipMalloc(%zu) failed", need);
+    h->ws = p;
+    h->ws_owned = true;
+    h->ws_bytes = need;
+  } else {
+    if (bytes < need) return fail(h, ST_EWORKSPACE, "workspace of %zu bytes < %zu needed", bytes, need);
+    if (((uintptr_t)dptr & 255) != 0) return fail(h, ST_EWORKSPACE, "workspace must be 256-byte aligned");
+    h->ws = dptr;
+    h->ws_bytes = bytes;
+  }
+  layout(h, (char*)h->ws);
+  return ST_OK;
+}
+
+int st_mg_levels(st_mg_t h, int* nlev, char* schedule, int cap) {
+  if (!h || h->lv.empty()) return ST_EINVAL;
+  const int nl = (int)h->lv.size();
+  if (nlev) *nlev = nl;
+  if (schedule) {
+    if (cap < nl) return fail(h, ST_EINVAL, "schedule buffer needs %d bytes", nl);
+    for (int i = 0; i < nl - 1; ++i) schedule[i] = h->lv[i].kind;
+    schedule[nl - 1] = '\0';
+  }
+  return ST_OK;
+}
+
+int st_mg_level_info(st_mg_t h, int level, int* n, int* N, double* tau, double* mu) {
+  if (!h || level < 0 || level >= (int)h->lv.size()) return ST_EINVAL;
+  const Level& L = h->lv[level];
+  if (n) *n = L.n;
+  if (N) *N = L.N;
+  if (tau) *tau = L.tau;
+  if (mu) *mu = L.mu;
+  return ST_OK;
+}
+
+int st_mg_sizes(st_mg_t h, long long* dof, long long* f_len, long long* u0_len) {
+  if (!h || h->lv.empty()) return ST_EINVAL;
+  const Level& L = h->lv[0];
+  if (dof) *dof = (long long)L.N * h->nt * L.nx;
+  if (f_len) *f_len = (long long)L.N * L.nx;
+  if (u0_len) *u0_len = L.nx;
+  return ST_OK;
+}
+
+int st_mg_rhs(st_mg_t h, const void* f, const void* u0, void* F, void* stream) {
+  if (!h || h->lv.empty() || !f || !F) return h ? fail(h, ST_EINVAL, "null argument") : ST_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  if (h->p.precision == ST_FP32) {
+    HIPCHK(h, launch_rhs<float>(h->p.dim, h->nt, (const float*)f, (const float*)u0, (float*)F,
+                                rhs_args<float>(h), s));
+  } else {
+    HIPCHK(h, launch_rhs<double>(h->p.dim, h->nt, (const double*)f, (const double*)u0, (double*)F,
+                                 rhs_args<double>(h), s));
+  }
+  return ST_OK;
+}
+
+int st_mg_rhs_adjoint(st_mg_t h, const void* lam, void* grad_f, void* grad_u0, void* stream) {
+  if (!h || h->lv.empty() || !lam) return h ? fail(h, ST_EINVAL, "null argument") : ST_EINVAL;
+  if (!grad_f && !grad_u0) return ST_OK;
+  hipStream_t s = (hipStream_t)stream;
+  if (h->p.precision == ST_FP32) {
+    HIPCHK(h, launch_rhs_adjoint<float>(h->p.dim, h->nt, (const float*)lam, (float*)grad_f,
+                                        (float*)grad_u0, rhs_args<float>(h), s));
+  } else {
+    HIPCHK(h, launch_rhs_adjoint<double>(h->p.dim, h->nt, (const double*)lam, (double*)grad_f,
+                                         (double*)grad_u0, rhs_args<double>(h), s));
+  }
+  return ST_OK;
+}
+
+int st_mg_residual(st_mg_t h, int level, int prec, int transpose, const void* u, const void* F,
+                   void* r, double* norms2, void* stream) {
+  CHK(check_level(h, level, prec, false));
+  if (!u || !F || !r) return fail(h, ST_EINVAL, "null vector");
+  hipStream_t s = (hipStream_t)stream;
+  const bool nrm = norms2 != nullptr && level == 0;
+  if (norms2 != nullptr && level != 0) return fail(h, ST_EINVAL, "norms only on level 0");
+  if (prec == ST_FP64)
+    CHK((op_residual<double, double>(h, level, transpose != 0, (const double*)u, (const double*)F,
+                                     (double*)r, nrm, s)));
+  else
+    CHK((op_residual<float, float>(h, level, transpose != 0, (const float*)u, (const float*)F,
+                                   (float*)r, nrm, s)));
+  if (nrm) {
+    HIPCHK(h, hipMemcpyAsync(norms2, h->norm_dev, sizeof(double) * h->p.batch, hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+  }
+  return ST_OK;
+}
+
+int st_mg_block_solve(st_mg_t h, int level, int prec, int transpose, const void* r, void* x,
+                      void* stream) {
+  CHK(check_level(h, level, prec, false));
+  if (!r || !x) return fail(h, ST_EINVAL, "null vector");
+  hipStream_t s = (hipStream_t)stream;
+  if (prec == ST_FP64)
+    return op_block_solve<double>(h, level, transpose != 0, (const double*)r, (double*)x, MODE_STORE,
+                                  1.0, (double*)h->tmp, level_r<double>(h, level), s);
+  return op_block_solve<float>(h, level, transpose != 0, (const float*)r, (float*)x, MODE_STORE, 1.0f,
+                               (float*)h->tmp, level_r<float>(h, level), s);
+}
+
+int st_mg_smooth(st_mg_t h, int level, int prec, int transpose, void* u, const void* F, void* stream) {
+  CHK(check_level(h, level, prec, false));
+  if (!u || !F) return fail(h, ST_EINVAL, "null vector");
+  hipStream_t s = (hipStream_t)stream;
+  if (prec == ST_FP64) {
+    double* r = level_r<double>(h, level);
+    CHK((op_residual<double, double>(h, level, transpose != 0, (const double*)u, (const double*)F, r, false, s)));
+    return op_block_solve<double>(h, level, transpose != 0, r, (double*)u, MODE_ADD_SCALED, h->p.omega,
+                                  (double*)h->tmp, r, s);
+  }
+  float* r = level_r<float>(h, level);
+  CHK((op_residual<float, float>(h, level, transpose != 0, (const float*)u, (const float*)F, r, false, s)));
+  return op_block_solve<float>(h, level, transpose != 0, r, (float*)u, MODE_ADD_SCALED, (float)h->p.omega,
+                               (float*)h->tmp, r, s);
+}
+
+int st_mg_restrict(st_mg_t h, int level, int prec, const void* r_fine, void* F_coarse, void* stream) {
+  CHK(check_level(h, level, prec, true));
+  if (!r_fine || !F_coarse) return fail(h, ST_EINVAL, "null vector");
+  hipStream_t s = (hipStream_t)stream;
+  if (prec == ST_FP64) return op_restrict<double>(h, level, (const double*)r_fine, (double*)F_coarse, s);
+  return op_restrict<float>(h, level, (const float*)r_fine, (float*)F_coarse, s);
+}
+
+int st_mg_prolong_add(st_mg_t h, int level, int prec, const void* e_coarse, void* u_fine, void* stream) {
+  CHK(check_level(h, level, prec, true));
+  if (!e_coarse || !u_fine) return fail(h, ST_EINVAL, "null vector");
+  hipStream_t s = (hipStream_t)stream;
+  if (prec == ST_FP64) return op_prolong<double>(h, level, (const double*)e_coarse, (double*)u_fine, s);
+  return op_prolong<float>(h, level, (const float*)e_coarse, (float*)u_fine, s);
+}
+
+int st_mg_vcycle(st_mg_t h, void* u, const void* F, double* relres, void* stream) {
+  CHK(check_ready(h));
+  if (!u || !F) return fail(h, ST_EINVAL, "null vector");
+  hipStream_t s = (hipStream_t)stream;
+  const int b = h->p.batch;
+  std::vector<double> n0(b), n1(b);
+  if (h->p.precision == ST_FP32) {
+    CHK(fine_residual_norm<float>(h, false, u, F, s));
+    if (relres) CHK(read_norms(h, n0.data(), s));
+    CHK(cycle_and_norm<float>(h, false, u, F, s));
+  } else {
+    CHK(fine_residual_norm<double>(h, false, u, F, s));
+    if (relres) CHK(read_norms(h, n0.data(), s));
+    CHK(cycle_and_norm<double>(h, false, u, F, s));
+  }
+  if (relres) {
+    CHK(read_norms(h, n1.data(), s));
+    for (int i = 0; i < b; ++i) relres[i] = n0[i] > 0 ? n1[i] / n0[i] : 0.0;
+  }
+  return ST_OK;
+}
+
+int st_mg_solve(st_mg_t h, void* u, const void* F, double rtol, int maxit, int* iters, double* hist,
+                void* stream) {
+  CHK(check_ready(h));
+  if (!u || !F || maxit < 0 || !(rtol >= 0.0)) return fail(h, ST_EINVAL, "invalid argument");
+  hipStream_t s = (hipStream_t)stream;
+  if (h->p.precision == ST_FP32) return solve_impl<float>(h, false, u, F, rtol, maxit, iters, hist, s);
+  return solve_impl<double>(h, false, u, F, rtol, maxit, iters, hist, s);
+}
+
+int st_mg_adjoint(st_mg_t h, const void* g, void* lam, void* grad_f, void* grad_u0, double rtol,
+                  int maxit, int* iters, double* hist, void* stream) {
+  CHK(check_ready(h));
+  if (!g || !lam || maxit < 0 || !(rtol >= 0.0)) return fail(h, ST_EINVAL, "invalid argument");
+  hipStream_t s = (hipStream_t)stream;
+  int rc;
+  if (h->p.precision == ST_FP32) rc = solve_impl<float>(h, true, lam, g, rtol, maxit, iters, hist, s);
+  else rc = solve_impl<double>(h, true, lam, g, rtol, maxit, iters, hist, s);
+  if (rc != ST_OK && rc != ST_ENOCONV) return rc;
+  const int rc2 = st_mg_rhs_adjoint(h, lam, grad_f, grad_u0, stream);
+  return rc2 != ST_OK ? rc2 : rc;
+}
+
+int st_mg_set_graph(st_mg_t h, int enable) {
+  if (!h) return ST_EINVAL;
+  if (enable && h->prof) return fail(h, ST_ESTATE, "stop profiling before enabling graph mode");
+  h->graph = enable ? 1 : 0;
+  if (!h->graph && h->gc.exec) {
+    (void)hipGraphExecDestroy(h->gc.exec);
+    h->gc.exec = nullptr;
+  }
+  return ST_OK;
+}
+
+int st_mg_profile_start(st_mg_t h) {
+  if (!h) return ST_EINVAL;
+  if (h->graph) return fail(h, ST_ESTATE, "profiling needs eager mode (graph mode is on)");
+  h->prof = true;
+  h->ev_used = 0;
+  h->prof_recs.clear();
+  return ST_OK;
+}
+
+int st_mg_profile_stop(st_mg_t h) {
+  if (!h) return ST_EINVAL;
+  h->prof = false;
+  return ST_OK;
+}
+
+int st_mg_profile_read(st_mg_t h, int kind, int level, double* total_ms, int* count) {
+  if (!h || kind < 0 || kind >= ST_PROF_KINDS) return ST_EINVAL;
+  double tot = 0.0;
+  int cnt = 0;
+  if (!h->prof_recs.empty()) HIPCHK(h, hipEventSynchronize(h->ev_pool[h->prof_recs.back().e1]));
+  for (const auto& r : h->prof_recs) {
+    if (r.kind != kind || (level >= 0 && r.level != level)) continue;
+    float ms = 0.0f;
+    HIPCHK(h, hipEventElapsedTime(&ms, h->ev_pool[r.e0], h->ev_pool[r.e1]));
+    tot += ms;
+    ++cnt;
+  }
+  if (total_ms) *total_ms = tot;
+  if (count) *count = cnt;
+  return ST_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,92 @@
+// Internal declarations shared by the HIP kernels and the host driver.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace stmg {
+
+constexpr int NT_MAX = 4;          // DG order p_t <= 3
+constexpr int TILE_COLS = 64;      // columns per workgroup of the transform kernel
+
+// Residual r = F - L u (or F - L^T u) on one level.  Time coefficients are
+// already arranged for the direction: forward uses K_tau, N_tau = ca cb^T and
+// the previous slab (dir = -1); the adjoint uses K_tau^T, N_tau^T = cb ca^T and
+// the next slab (dir = +1).  M_tau is symmetric.
+template <typename T>
+struct ResidArgs {
+  T K[NT_MAX * NT_MAX];   // K[l*NT + k]
+  T M[NT_MAX * NT_MAX];
+  T ca[NT_MAX];           // row factor of the coupling block
+  T cb[NT_MAX];           // column factor (combination of the neighbour slab)
+  T wm[3];                // 1-D mass stencil  h/6 * (1, 4, 1)
+  T wk[3];                // 1-D stiffness stencil  1/h * (-1, 2, -1)
+  int n;                  // interior nodes per dimension
+  long long nx;           // n^d
+  int N;                  // slabs
+  int batch;
+  int dir;                // -1 forward, +1 adjoint
+};
+
+// Restriction / prolongation between a fine level (Nf = 2 Nc slabs) and a coarse level.
+template <typename T>
+struct TransferArgs {
+  T R1T[NT_MAX * NT_MAX];  // R1^T[l*NT + k]: fine slab 2m   <- coarse slab m
+  T R2T[NT_MAX * NT_MAX];  // R2^T[l*NT + k]: fine slab 2m+1 <- coarse slab m
+  int nf, nc;              // interior nodes per dimension (nc == nf for semi)
+  long long nxf, nxc;
+  int Nc;                  // coarse slabs
+  int batch;
+};
+
+// Load vector from nodal data.
+template <typename T>
+struct RhsArgs {
+  T ints[NT_MAX];   // int_slab psi_l dt
+  T ca[NT_MAX];     // psi_l(t_0^+)
+  T wm[3];
+  int n;
+  long long nx;
+  int N;
+  int batch;
+};
+
+enum { MODE_STORE = 0, MODE_ADD_SCALED = 1, MODE_SET_SCALED = 2 };
+
+// ---- launchers (defined in stmg_kernels.hip) ----
+template <typename Tin, typename Tout>
+hipError_t launch_residual(int dim, int nt, const Tin* u, const Tin* F, Tout* r,
+                           const ResidArgs<Tin>& a, double* partial, hipStream_t s);
+unsigned residual_blocks_per_slab(long long nx);
+
+template <typename T>
+hipError_t launch_dst(int np, bool xaxis, const T* in, T* out, const T* Sfrag, int n,
+                      long long inner, long long ncols, T omega, int mode, hipStream_t s);
+template <typename T>
+hipError_t launch_tsolve(int nt, T* buf, const T* G, long long nx, long long nslab, int transpose,
+                         hipStream_t s);
+template <typename T>
+hipError_t launch_restrict(int dim, int nt, bool full, const T* rf, T* Fc, const TransferArgs<T>& a,
+                           hipStream_t s);
+template <typename T>
+hipError_t launch_prolong(int dim, int nt, bool full, const T* ec, T* uf, const TransferArgs<T>& a,
+                          hipStream_t s);
+template <typename T>
+hipError_t launch_rhs(int dim, int nt, const T* f, const T* u0, T* F, const RhsArgs<T>& a,
+                      hipStream_t s);
+template <typename T>
+hipError_t launch_rhs_adjoint(int dim, int nt, const T* lam, T* gf, T* gu0, const RhsArgs<T>& a,
+                              hipStream_t s);
+template <typename T>
+hipError_t launch_sumsq(const T* v, long long len, int batch, double* partial, unsigned gx,
+                        hipStream_t s);
+hipError_t launch_norm_final(const double* partial, long long per_batch, int batch, double* out,
+                             hipStream_t s);
+template <typename T>
+hipError_t launch_fill(T* v, long long len, hipStream_t s);
+hipError_t launch_axpy_f32_f64(double* u, const float* e, long long len, hipStream_t s);
+hipError_t launch_cast_f64_f32(const double* in, float* out, long long len, hipStream_t s);
+hipError_t launch_cast_f32_f64(const float* in, double* out, long long len, hipStream_t s);
+
+}  // namespace stmg

@@ -1,0 +1,333 @@
+"""ctypes binding of libstmg.so (C ABI in include/st_mg.h).
+
+Argument marshalling only: every step of the solver runs in the HIP library.
+PyTorch supplies device memory (vectors and the workspace) and the stream.
+The library must be built (``__graft_entry__.build()``); loading fails loudly
+otherwise, and nothing here falls back to a CPU implementation.
+"""
+import ctypes
+import os
+
+import torch
+
+ST_OK, ST_EINVAL, ST_ENOMEM, ST_EHIP, ST_ENOCONV, ST_ESTATE, ST_EWORKSPACE, ST_ENAN = 0, -1, -2, -3, -4, -5, -6, -7
+COARSEN = {"auto": 0, "semi": 1, "full": 2}
+PRECISION = {"fp64": 0, "fp32": 1, "mixed": 2}
+FP64, FP32 = 0, 1
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libstmg.so")
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int), ("n", ctypes.c_int), ("T", ctypes.c_double), ("N", ctypes.c_int),
+        ("pt", ctypes.c_int), ("omega", ctypes.c_double), ("nu1", ctypes.c_int), ("nu2", ctypes.c_int),
+        ("coarsen", ctypes.c_int), ("mu_star", ctypes.c_double), ("precision", ctypes.c_int),
+        ("batch", ctypes.c_int),
+    ]
+
+
+class STMGError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"st_mg error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+_vp, _i, _d, _sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int)
+_llp = ctypes.POINTER(ctypes.c_longlong)
+
+SIGNATURES = {
+    "st_mg_default_params": (None, [ctypes.POINTER(Params)]),
+    "st_mg_setup": (_i, [ctypes.POINTER(Params), ctypes.POINTER(_vp)]),
+    "st_mg_destroy": (_i, [_vp]),
+    "st_mg_last_error": (ctypes.c_char_p, [_vp]),
+    "st_mg_workspace_bytes": (_i, [_vp, ctypes.POINTER(_sz)]),
+    "st_mg_bind_workspace": (_i, [_vp, _vp, _sz]),
+    "st_mg_levels": (_i, [_vp, _ip, ctypes.c_char_p, _i]),
+    "st_mg_level_info": (_i, [_vp, _i, _ip, _ip, _dp, _dp]),
+    "st_mg_sizes": (_i, [_vp, _llp, _llp, _llp]),
+    "st_mg_rhs": (_i, [_vp, _vp, _vp, _vp, _vp]),
+    "st_mg_rhs_adjoint": (_i, [_vp, _vp, _vp, _vp, _vp]),
+    "st_mg_residual": (_i, [_vp, _i, _i, _i, _vp, _vp, _vp, _dp, _vp]),
+    "st_mg_block_solve": (_i, [_vp, _i, _i, _i, _vp, _vp, _vp]),
+    "st_mg_smooth": (_i, [_vp, _i, _i, _i, _vp, _vp, _vp]),
+    "st_mg_restrict": (_i, [_vp, _i, _i, _vp, _vp, _vp]),
+    "st_mg_prolong_add": (_i, [_vp, _i, _i, _vp, _vp, _vp]),
+    "st_mg_vcycle": (_i, [_vp, _vp, _vp, _dp, _vp]),
+    "st_mg_solve": (_i, [_vp, _vp, _vp, _d, _i, _ip, _dp, _vp]),
+    "st_mg_adjoint": (_i, [_vp, _vp, _vp, _vp, _vp, _d, _i, _ip, _dp, _vp]),
+    "st_mg_set_graph": (_i, [_vp, _i]),
+    "st_mg_profile_start": (_i, [_vp]),
+    "st_mg_profile_stop": (_i, [_vp]),
+    "st_mg_profile_read": (_i, [_vp, _i, _i, _dp, _ip]),
+}
+
+PROF_KINDS = {"residual": 0, "dst_x": 1, "dst_y": 2, "dst_z": 3, "tsolve": 4, "restrict": 5,
+              "prolong": 6, "other": 7}
+
+
+def lib():
+    """Load libstmg.so (raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Solver:
+    """One space-time multigrid hierarchy on one GPU.
+
+    dim, n, N, pt, T: Omega = (0,1)^dim with n interior nodes per dimension,
+    N slabs on (0, T), DG order pt.  omega, nu1, nu2, coarsen ('auto' = the
+    mu >= mu* rule, 'semi', 'full'), precision ('fp64', 'fp32', 'mixed'),
+    batch = number of right-hand sides.
+    """
+
+    def __init__(self, dim, n, N, pt=1, T=1.0, omega=0.5, nu1=2, nu2=2, coarsen="auto",
+                 mu_star=0.0, precision="fp64", batch=1, device="cuda:0", workspace=True):
+        if not torch.cuda.is_available():
+            raise RuntimeError("stmg needs a ROCm GPU (torch.cuda.is_available() is False)")
+        self.device = torch.device(device)
+        self._h = ctypes.c_void_p(0)
+        L = lib()
+        p = Params(dim, n, float(T), N, pt, float(omega), nu1, nu2, COARSEN[coarsen], float(mu_star),
+                   PRECISION[precision], batch)
+        with torch.cuda.device(self.device):
+            rc = L.st_mg_setup(ctypes.byref(p), ctypes.byref(self._h))
+        if rc != ST_OK:
+            msg = L.st_mg_last_error(self._h).decode() if self._h.value else "setup failed"
+            if self._h.value:
+                L.st_mg_destroy(self._h)
+                self._h = ctypes.c_void_p(0)
+            raise STMGError(rc, msg)
+        self.params = dict(dim=dim, n=n, N=N, pt=pt, T=T, omega=omega, nu1=nu1, nu2=nu2,
+                           coarsen=coarsen, precision=precision, batch=batch)
+        self.dim, self.n, self.N, self.pt, self.batch = dim, n, N, pt, batch
+        self.nt = pt + 1
+        self.precision = precision
+        self.dtype = torch.float32 if precision == "fp32" else torch.float64
+        dof, flen, ulen = ctypes.c_longlong(), ctypes.c_longlong(), ctypes.c_longlong()
+        self._check(L.st_mg_sizes(self._h, ctypes.byref(dof), ctypes.byref(flen), ctypes.byref(ulen)))
+        self.dof, self.f_len, self.u0_len = dof.value, flen.value, ulen.value
+        nl = ctypes.c_int()
+        buf = ctypes.create_string_buffer(64)
+        self._check(L.st_mg_levels(self._h, ctypes.byref(nl), buf, 64))
+        self.nlev = nl.value
+        self.schedule = buf.value.decode()
+        self.levels = []
+        for k in range(self.nlev):
+            nn, NN, tau, mu = ctypes.c_int(), ctypes.c_int(), ctypes.c_double(), ctypes.c_double()
+            self._check(L.st_mg_level_info(self._h, k, ctypes.byref(nn), ctypes.byref(NN),
+                                           ctypes.byref(tau), ctypes.byref(mu)))
+            self.levels.append(dict(n=nn.value, N=NN.value, tau=tau.value, mu=mu.value))
+        self._ws = None
+        if workspace:
+            self.bind_workspace()
+
+    # ------------------------------------------------------------------ basics
+    def _check(self, rc, allow=()):
+        if rc != ST_OK and rc not in allow:
+            raise STMGError(rc, lib().st_mg_last_error(self._h).decode())
+        return rc
+
+    def workspace_bytes(self):
+        b = ctypes.c_size_t()
+        self._check(lib().st_mg_workspace_bytes(self._h, ctypes.byref(b)))
+        return b.value
+
+    def bind_workspace(self):
+        nbytes = self.workspace_bytes()
+        ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-ws.data_ptr()) % 256
+        self._ws = ws
+        self._check(lib().st_mg_bind_workspace(self._h, ctypes.c_void_p(ws.data_ptr() + off), nbytes))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().st_mg_destroy(self._h)
+            self._h = ctypes.c_void_p(0)
+        self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def level_dof(self, level):
+        if not 0 <= level < self.nlev:
+            raise ValueError(f"level {level} out of range 0..{self.nlev - 1}")
+        lv = self.levels[level]
+        return self.batch * lv["N"] * self.nt * lv["n"] ** self.dim
+
+    def _vec(self, t, numel, dtype, name):
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{name} must be a torch.Tensor")
+        if t.device != self.device:
+            raise ValueError(f"{name} must live on {self.device}")
+        if t.dtype != dtype:
+            raise TypeError(f"{name} must have dtype {dtype}, got {t.dtype}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        if t.numel() != numel:
+            raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
+        return t
+
+    def empty(self, level=0, dtype=None):
+        return torch.empty(self.level_dof(level), dtype=dtype or self.dtype, device=self.device)
+
+    def zeros(self, level=0, dtype=None):
+        return torch.zeros(self.level_dof(level), dtype=dtype or self.dtype, device=self.device)
+
+    # ------------------------------------------------------------- right-hand side
+    def rhs(self, f, u0=None, out=None):
+        """F from nodal data f [b][N][n^d] and u0 [b][n^d] (Sec. 1 load vector)."""
+        f = self._vec(f, self.batch * self.f_len, self.dtype, "f")
+        if u0 is not None:
+            u0 = self._vec(u0, self.batch * self.u0_len, self.dtype, "u0")
+        F = out if out is not None else self.empty()
+        self._check(lib().st_mg_rhs(self._h, _ptr(f), _ptr(u0), _ptr(F), _stream(self.device)))
+        return F
+
+    def rhs_adjoint(self, lam):
+        lam = self._vec(lam, self.dof * self.batch, self.dtype, "lam")
+        gf = torch.empty(self.batch * self.f_len, dtype=self.dtype, device=self.device)
+        gu0 = torch.empty(self.batch * self.u0_len, dtype=self.dtype, device=self.device)
+        self._check(lib().st_mg_rhs_adjoint(self._h, _ptr(lam), _ptr(gf), _ptr(gu0), _stream(self.device)))
+        return gf, gu0
+
+    # ------------------------------------------------------------- level operators
+    def _prec(self, prec):
+        if prec is None:
+            return FP64 if self.precision == "fp64" else FP32
+        return {"fp64": FP64, "fp32": FP32}[prec] if isinstance(prec, str) else prec
+
+    def _pdtype(self, prec):
+        return torch.float64 if prec == FP64 else torch.float32
+
+    def residual(self, u, F, level=0, prec=None, transpose=False, out=None, norms=False):
+        p = self._prec(prec)
+        dt = self._pdtype(p)
+        nd = self.level_dof(level)
+        u = self._vec(u, nd, dt, "u")
+        F = self._vec(F, nd, dt, "F")
+        r = out if out is not None else torch.empty(nd, dtype=dt, device=self.device)
+        nrm = (ctypes.c_double * self.batch)() if norms else None
+        self._check(lib().st_mg_residual(self._h, level, p, int(transpose), _ptr(u), _ptr(F), _ptr(r),
+                                         nrm, _stream(self.device)))
+        return (r, [x ** 0.5 for x in nrm]) if norms else r
+
+    def block_solve(self, r, level=0, prec=None, transpose=False, out=None):
+        p = self._prec(prec)
+        dt = self._pdtype(p)
+        nd = self.level_dof(level)
+        r = self._vec(r, nd, dt, "r")
+        x = out if out is not None else torch.empty(nd, dtype=dt, device=self.device)
+        self._check(lib().st_mg_block_solve(self._h, level, p, int(transpose), _ptr(r), _ptr(x),
+                                            _stream(self.device)))
+        return x
+
+    def smooth(self, u, F, level=0, prec=None, transpose=False):
+        p = self._prec(prec)
+        dt = self._pdtype(p)
+        nd = self.level_dof(level)
+        self._check(lib().st_mg_smooth(self._h, level, p, int(transpose),
+                                       _ptr(self._vec(u, nd, dt, "u")), _ptr(self._vec(F, nd, dt, "F")),
+                                       _stream(self.device)))
+        return u
+
+    def restrict(self, r, level=0, prec=None, out=None):
+        p = self._prec(prec)
+        dt = self._pdtype(p)
+        r = self._vec(r, self.level_dof(level), dt, "r")
+        Fc = out if out is not None else torch.empty(self.level_dof(level + 1), dtype=dt, device=self.device)
+        self._check(lib().st_mg_restrict(self._h, level, p, _ptr(r), _ptr(Fc), _stream(self.device)))
+        return Fc
+
+    def prolong_add(self, e, u, level=0, prec=None):
+        p = self._prec(prec)
+        dt = self._pdtype(p)
+        e = self._vec(e, self.level_dof(level + 1), dt, "e")
+        u = self._vec(u, self.level_dof(level), dt, "u")
+        self._check(lib().st_mg_prolong_add(self._h, level, p, _ptr(e), _ptr(u), _stream(self.device)))
+        return u
+
+    # ------------------------------------------------------------------ cycles
+    def vcycle(self, u, F):
+        nd = self.level_dof(0)
+        u = self._vec(u, nd, self.dtype, "u")
+        F = self._vec(F, nd, self.dtype, "F")
+        rel = (ctypes.c_double * self.batch)()
+        self._check(lib().st_mg_vcycle(self._h, _ptr(u), _ptr(F), rel, _stream(self.device)))
+        return list(rel)
+
+    def solve(self, F, u=None, rtol=1e-10, maxit=100, raise_on_noconv=True):
+        """Returns (u, iterations, history[iters+1][batch])."""
+        nd = self.level_dof(0)
+        F = self._vec(F, nd, self.dtype, "F")
+        if u is None:
+            u = torch.zeros(nd, dtype=self.dtype, device=self.device)
+        u = self._vec(u, nd, self.dtype, "u")
+        its = ctypes.c_int()
+        hist = (ctypes.c_double * ((maxit + 1) * self.batch))()
+        rc = lib().st_mg_solve(self._h, _ptr(u), _ptr(F), float(rtol), int(maxit), ctypes.byref(its),
+                               hist, _stream(self.device))
+        self._check(rc, allow=() if raise_on_noconv else (ST_ENOCONV,))
+        k = its.value
+        h = [list(hist[i * self.batch:(i + 1) * self.batch]) for i in range(k + 1)]
+        return u, k, h
+
+    def adjoint(self, g, lam=None, rtol=1e-10, maxit=100, gradients=True, raise_on_noconv=True):
+        """Solve L^T lam = g; returns (lam, grad_f, grad_u0, iterations, history)."""
+        nd = self.level_dof(0)
+        g = self._vec(g, nd, self.dtype, "g")
+        if lam is None:
+            lam = torch.zeros(nd, dtype=self.dtype, device=self.device)
+        lam = self._vec(lam, nd, self.dtype, "lam")
+        gf = gu0 = None
+        if gradients:
+            gf = torch.empty(self.batch * self.f_len, dtype=self.dtype, device=self.device)
+            gu0 = torch.empty(self.batch * self.u0_len, dtype=self.dtype, device=self.device)
+        its = ctypes.c_int()
+        hist = (ctypes.c_double * ((maxit + 1) * self.batch))()
+        rc = lib().st_mg_adjoint(self._h, _ptr(g), _ptr(lam), _ptr(gf), _ptr(gu0), float(rtol),
+                                 int(maxit), ctypes.byref(its), hist, _stream(self.device))
+        self._check(rc, allow=() if raise_on_noconv else (ST_ENOCONV,))
+        k = its.value
+        h = [list(hist[i * self.batch:(i + 1) * self.batch]) for i in range(k + 1)]
+        return lam, gf, gu0, k, h
+
+    def set_graph(self, enable=True):
+        self._check(lib().st_mg_set_graph(self._h, int(bool(enable))))
+
+    # --------------------------------------------------------------- profiling
+    def profile_start(self):
+        self._check(lib().st_mg_profile_start(self._h))
+
+    def profile_stop(self):
+        self._check(lib().st_mg_profile_stop(self._h))
+
+    def profile_read(self, kind, level=-1):
+        """(total_ms, launches) of one kernel kind on one level (-1 = all)."""
+        ms, cnt = ctypes.c_double(), ctypes.c_int()
+        k = PROF_KINDS[kind] if isinstance(kind, str) else kind
+        self._check(lib().st_mg_profile_read(self._h, k, level, ctypes.byref(ms), ctypes.byref(cnt)))
+        return ms.value, cnt.value
