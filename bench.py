@@ -130,9 +130,7 @@ def main():
         S.profile_start()
         S.solve(F, u=u2, rtol=0.0, maxit=args.steps, raise_on_noconv=False)
         torch.cuda.synchronize()
-        kinds = ["residual", "dst_x", "dst_y", "tsolve", "restrict", "prolong", "other"]
-        if d == 3:
-            kinds.insert(3, "dst_z")
+        kinds = ["residual", "pass_fwd", "pass_inv", "fused", "restrict", "prolong", "other"]
         prof = {}
         for k in kinds:
             tot, cnt = S.profile_read(k, level=-1)
@@ -156,21 +154,26 @@ def main():
         tm = time.perf_counter() - t0
         err_mixed = (torch.linalg.vector_norm(um - u64) / torch.linalg.vector_norm(u64)).item()
 
-    # roofline of the dominant kernel on the fine level
+    # roofline of the dominant transform kernel on the fine level.  Algorithmic
+    # work is the dense sine transform's: a length-n dot product (2n flop) per
+    # value per transform; the folded kernels execute about half of that on the
+    # matrix cores.  The fused kernel does a forward and an inverse transform.
     L0 = S.levels[0]
     nvals = b * L0["N"] * S.nt * L0["n"] ** d
-    cand = {k: v for k, v in prof.items() if k.startswith("dst") and v["fine_launches"] > 0}
+    cand = {k: v for k, v in prof.items() if k in ("pass_fwd", "pass_inv", "fused") and v["fine_launches"] > 0}
     dom = max(cand, key=lambda k: cand[k]["fine_ms_total"])
     avg_ms = cand[dom]["fine_ms_total"] / cand[dom]["fine_launches"]
-    flops = 2.0 * L0["n"] * nvals                      # one length-n dot product per output value
+    transforms = 2 if dom == "fused" else 1
+    flops = transforms * 2.0 * L0["n"] * nvals
+    hbm_bytes = (24 if dom == "pass_inv" else 16) * nvals
     achieved = flops / (avg_ms * 1e-3) / 1e12
-    npad = 16
-    while npad < L0["n"]:
-        npad *= 2
-    roof = {"kernel": f"k_dst<double, {npad // 16}, {'true' if dom == 'dst_x' else 'false'}> ({dom}, fine level)",
-            "bound": "mfma", "achieved": achieved, "peak": FP64_MFMA_PEAK_TFS, "unit": "TFLOP/s",
-            "frac": achieved / FP64_MFMA_PEAK_TFS, "traffic": None,
-            "avg_launch_ms": avg_ms, "flops_per_launch": flops}
+    names = {"pass_fwd": "forward x pass (k_pass_reg<4,false>)", "pass_inv": "inverse x pass + update (k_pass_reg<4,true>)",
+             "fused": "fused y pass: forward + time solve + inverse (k_dst_fused<double,4,2>)"}
+    roof = {"kernel": names[dom] + ", fine level", "bound": "mfma", "achieved": achieved,
+            "peak": FP64_MFMA_PEAK_TFS, "unit": "TFLOP/s", "frac": achieved / FP64_MFMA_PEAK_TFS, "traffic": None,
+            "avg_launch_ms": avg_ms, "launches": cand[dom]["fine_launches"], "flops_per_launch": flops,
+            "executed_mfma_flops_per_launch": flops * (L0["n"] + 1) / (2.0 * L0["n"]),
+            "hbm_bytes_per_launch": hbm_bytes, "hbm_gbs": hbm_bytes / (avg_ms * 1e-3) / 1e9}
     r0 = prof["residual"]
     res_avg = r0["fine_ms_total"] / max(r0["fine_launches"], 1)
     res_bytes = 3 * 8 * nvals                           # read u, F; write r

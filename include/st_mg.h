@@ -168,9 +168,12 @@ int st_mg_set_graph(st_mg_t h, int enable);
  * summed duration (ms) and launch count of one kernel kind on one level
  * (level -1 = all levels). */
 enum {
-  ST_PROF_RESIDUAL = 0, ST_PROF_DST_X = 1, ST_PROF_DST_Y = 2, ST_PROF_DST_Z = 3,
-  ST_PROF_TSOLVE = 4, ST_PROF_RESTRICT = 5, ST_PROF_PROLONG = 6, ST_PROF_OTHER = 7,
-  ST_PROF_KINDS = 8
+  ST_PROF_RESIDUAL = 0,   /* r = F - L u                                          */
+  ST_PROF_PASS_FWD = 1,   /* forward sine-transform pass along x (and y in 3-D)   */
+  ST_PROF_PASS_INV = 2,   /* inverse pass (the last one applies the update)       */
+  ST_PROF_FUSED = 3,      /* forward + per-mode time solve + inverse, slowest axis */
+  ST_PROF_RESTRICT = 4, ST_PROF_PROLONG = 5, ST_PROF_OTHER = 6,
+  ST_PROF_KINDS = 7
 };
 int st_mg_profile_start(st_mg_t h);
 int st_mg_profile_stop(st_mg_t h);

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -93,8 +94,8 @@ struct Level {
   long long nx = 0;
   double tau = 0, h = 0, mu = 0;
   char kind = 0;          // transition to the next coarser level: 'f' or 's'; 0 on the coarsest
-  int np = 0;             // padded transform size (16..256)
-  double* S64 = nullptr;  // DST-I in MFMA fragment order
+  int hb = 0;             // folded transform: 16-row blocks per half
+  double* S64 = nullptr;  // folded DST-I in MFMA fragment order
   float* S32 = nullptr;
   double* G64 = nullptr;  // per-mode inverse blocks [nx][nt][nt]
   float* G32 = nullptr;
@@ -139,6 +140,7 @@ struct st_mg {
   long long partial_per_batch = 0;
   double* norm_dev = nullptr;
   int graph = 0;
+  int impl = TRANSFORM_AUTO;
   GraphCache gc;
   // per-launch event pairs while profiling is on
   bool prof = false;
@@ -279,38 +281,47 @@ double critical_mu(const st_mg* h) {
   return 0.5 * (lo + hi);
 }
 
-int padded_size(int n) {
-  int np = 16;
-  while (np < n) np *= 2;
-  return np;
+// Spectral order along one axis: the h odd sine modes first, then the h-1 even
+// ones.  Returns the 1-based mode number k of spectral index s.
+int spectral_mode(int s, int n) {
+  const int h = (n + 1) / 2;
+  return s < h ? 2 * s + 1 : 2 * (s - h) + 2;
 }
 
-// Upload the level's DST matrix (fragment order) and per-mode blocks G_k.
+// Upload the level's folded DST fragments and the per-mode blocks G.
 int build_level_tables(st_mg* h, Level& L) {
-  const int n = L.n, np = L.np, nt = h->nt, d = h->p.dim;
-  // orthonormal DST-I, S[k][i] = sqrt(2/(n+1)) sin(pi (k+1)(i+1)/(n+1)), zero padded
-  std::vector<double> S((size_t)np * np, 0.0);
+  const int n = L.n, nt = h->nt, d = h->p.dim;
+  const int HB = L.hb, HP = 16 * HB, half = (n + 1) / 2;
   const double sc = std::sqrt(2.0 / (n + 1));
-  for (int k = 0; k < n; ++k)
-    for (int i = 0; i < n; ++i) S[(size_t)k * np + i] = sc * std::sin(PI * (k + 1.0) * (i + 1.0) / (n + 1));
-  const int nb = np / 16, ni = np / 4;
-  std::vector<double> frag((size_t)np * np);
-  std::vector<float> frag32((size_t)np * np);
-  for (int kb = 0; kb < nb; ++kb)
-    for (int ib = 0; ib < ni; ++ib)
-      for (int lane = 0; lane < 64; ++lane) {
-        const size_t o = ((size_t)kb * ni + ib) * 64 + lane;
-        frag[o] = S[(size_t)(kb * 16 + (lane & 15)) * np + ib * 4 + (lane >> 4)];
-        frag32[o] = (float)frag[o];
-      }
+  // folded blocks: fwd_odd[s][i] = S[2s+1][i+1] (s, i < h), fwd_even[s][i] = S[2s+2][i+1] (s, i < h-1);
+  // the inverse blocks are their transposes.
+  auto blk = [&](int dir, int hf, int r, int c) -> double {
+    const int lim = hf == 0 ? half : half - 1;
+    if (r >= lim || c >= lim) return 0.0;
+    const int s = dir == 0 ? r : c, i = dir == 0 ? c : r;
+    const int k = hf == 0 ? 2 * s + 1 : 2 * s + 2;
+    return sc * std::sin(PI * (double)k * (i + 1.0) / (n + 1));
+  };
+  const size_t per = (size_t)HB * (HP / 4) * 64;
+  std::vector<double> frag(4 * per);
+  std::vector<float> frag32(4 * per);
+  for (int dir = 0; dir < 2; ++dir)
+    for (int hf = 0; hf < 2; ++hf)
+      for (int kb = 0; kb < HB; ++kb)
+        for (int ib = 0; ib < HP / 4; ++ib)
+          for (int lane = 0; lane < 64; ++lane) {
+            const size_t o = (size_t)(dir * 2 + hf) * per + ((size_t)kb * (HP / 4) + ib) * 64 + lane;
+            frag[o] = blk(dir, hf, kb * 16 + (lane & 15), ib * 4 + (lane >> 4));
+            frag32[o] = (float)frag[o];
+          }
   // per-mode blocks: mu_k K + nu_k M with mu_k = prod m, nu_k = sum_a kappa_a prod_{b!=a} m_b,
   // m = h/3 (2 + cos), kappa = 2/h (1 - cos) at angle (k+1) pi h
   const double hh = L.h;
   std::vector<double> m1(n), k1(n);
-  for (int k = 0; k < n; ++k) {
-    const double c = std::cos((k + 1) * PI * hh);
-    m1[k] = hh / 3.0 * (2.0 + c);
-    k1[k] = 2.0 / hh * (1.0 - c);
+  for (int s = 0; s < n; ++s) {
+    const double c = std::cos(spectral_mode(s, n) * PI * hh);
+    m1[s] = hh / 3.0 * (2.0 + c);
+    k1[s] = 2.0 / hh * (1.0 - c);
   }
   const long long nx = L.nx;
   std::vector<double> G((size_t)nx * nt * nt);
@@ -425,57 +436,52 @@ int op_residual(st_mg* h, int l, bool transpose, const Tin* u, const Tin* F, Tou
   }
   if (norms) {
     ProfScope ps(h, ST_PROF_OTHER, l, s);
-    const long long per = (long long)residual_blocks_per_slab(L.nx) * L.N;
+    const long long per = (long long)residual_blocks_per_slab(h->p.dim, L.n, L.nx, h->nt) * L.N;
     HIPCHK(h, launch_norm_final(h->partial, per, h->p.batch, h->norm_dev, s));
   }
   return ST_OK;
 }
 
-// x = D^{-1} src written into dst with `mode` (store / += omega x / = omega x).
-// Passes alternate between the buffers A and B; src is only read.
+// x = D^{-1} src written into dst with `mode` (store / += omega x / = omega x):
+// folded DST passes along the leading axes, the fused forward/time-solve/inverse
+// pass along the slowest axis, then the inverse passes.  Intermediate data
+// alternate between the buffers A and B; src is only read.
 template <typename T>
 int op_block_solve(st_mg* h, int l, bool transpose, const T* src, T* dst, int mode, T omega, T* A,
                    T* B, hipStream_t s) {
   const Level& L = h->lv[l];
   const int d = h->p.dim, n = L.n, nt = h->nt;
-  const long long outer = (long long)h->p.batch * L.N * nt;
+  const long long slabs = (long long)h->p.batch * L.N;
   const long long nn = n;
-  // axis a: view [outer * n^(d-1-a)][n][n^a]
-  auto pass = [&](int axis, const T* in, T* out, int md, T om) -> int {
+  auto pass = [&](int axis, bool inv, const T* in, T* out, int md, T om) -> int {
     long long inner = 1;
     for (int i = 0; i < axis; ++i) inner *= nn;
     long long rest = 1;
     for (int i = axis + 1; i < d; ++i) rest *= nn;
-    const long long ncols = outer * rest * inner;
-    ProfScope ps(h, ST_PROF_DST_X + axis, l, s);
-    HIPCHK(h, launch_dst<T>(L.np, axis == 0, in, out, Sof<T>(L), n, inner, ncols, om, md, s));
+    const long long ncols = slabs * nt * rest * inner;
+    ProfScope ps(h, inv ? ST_PROF_PASS_INV : ST_PROF_PASS_FWD, l, s);
+    HIPCHK(h, launch_dst_pass<T>(h->impl, L.hb, axis == 0, inv, in, out, Sof<T>(L), n, inner, ncols, om, md, s));
     return ST_OK;
   };
-  const T* cur = src;
-  T* bufs[2] = {A, B};
-  int nb = 0;
-  for (int axis = 0; axis < d; ++axis) {
-    T* out = bufs[nb];
-    CHK(pass(axis, cur, out, MODE_STORE, T(1)));
-    cur = out;
-    nb ^= 1;
+  auto fused = [&](const T* in, T* out, int md, T om) -> int {
+    long long inner = 1;
+    for (int i = 0; i < d - 1; ++i) inner *= nn;
+    ProfScope ps(h, ST_PROF_FUSED, l, s);
+    HIPCHK(h, launch_dst_fused<T>(h->impl, L.hb, nt, in, out, Sof<T>(L), Gof<T>(L), n, inner, slabs,
+                                  transpose ? 1 : 0, om, md, s));
+    return ST_OK;
+  };
+  if (d == 1) return fused(src, dst, mode, omega);
+  if (d == 2) {
+    CHK(pass(0, false, src, A, MODE_STORE, T(1)));
+    CHK(fused(A, A, MODE_STORE, T(1)));
+    return pass(0, true, A, dst, mode, omega);
   }
-  {
-    ProfScope ps(h, ST_PROF_TSOLVE, l, s);
-    HIPCHK(h, launch_tsolve<T>(nt, const_cast<T*>(cur), Gof<T>(L), L.nx, (long long)h->p.batch * L.N,
-                               transpose ? 1 : 0, s));
-  }
-  for (int axis = d - 1; axis >= 0; --axis) {
-    if (axis == 0) {
-      CHK(pass(axis, cur, dst, mode, omega));
-    } else {
-      T* out = bufs[nb];
-      CHK(pass(axis, cur, out, MODE_STORE, T(1)));
-      cur = out;
-      nb ^= 1;
-    }
-  }
-  return ST_OK;
+  CHK(pass(0, false, src, A, MODE_STORE, T(1)));
+  CHK(pass(1, false, A, B, MODE_STORE, T(1)));
+  CHK(fused(B, B, MODE_STORE, T(1)));
+  CHK(pass(1, true, B, A, MODE_STORE, T(1)));
+  return pass(0, true, A, dst, mode, omega);
 }
 
 template <typename T>
@@ -708,7 +714,7 @@ size_t layout(st_mg* h, char* base) {
     h->ct64 = (double*)take(cl * 8);
   }
   const Level& L0 = h->lv[0];
-  h->partial_per_batch = std::max<long long>((long long)residual_blocks_per_slab(L0.nx) * L0.N, 1024);
+  h->partial_per_batch = std::max<long long>((long long)residual_blocks_per_slab(h->p.dim, L0.n, L0.nx, h->nt) * L0.N, 1024);
   h->partial = (double*)take(sizeof(double) * h->partial_per_batch * b);
   h->norm_dev = (double*)take(sizeof(double) * b);
   return off;
@@ -775,6 +781,11 @@ int st_mg_setup(const st_mg_params* p, st_mg_t* out) {
     return rc;
   }
   h->nt = p->pt + 1;
+  // tuning knob: STMG_TRANSFORM=1 forces the LDS-staged transforms, =2 the register ones
+  if (const char* ti = std::getenv("STMG_TRANSFORM")) {
+    const int v = std::atoi(ti);
+    h->impl = (v >= TRANSFORM_AUTO && v <= TRANSFORM_REG) ? v : TRANSFORM_AUTO;
+  }
   time_basis(h);
   h->mu_star = p->mu_star > 0.0 ? p->mu_star : critical_mu(h);
   if (!std::isfinite(h->mu_star)) {
@@ -794,7 +805,7 @@ int st_mg_setup(const st_mg_params* p, st_mg_t* out) {
     L.tau = tau;
     L.h = 1.0 / (n + 1);
     L.mu = tau / (L.h * L.h);
-    L.np = padded_size(n);
+    L.hb = transform_half_blocks(n);
     if (N == 1) {
       h->lv.push_back(L);
       break;

@@ -58,14 +58,22 @@ enum { MODE_STORE = 0, MODE_ADD_SCALED = 1, MODE_SET_SCALED = 2 };
 template <typename Tin, typename Tout>
 hipError_t launch_residual(int dim, int nt, const Tin* u, const Tin* F, Tout* r,
                            const ResidArgs<Tin>& a, double* partial, hipStream_t s);
-unsigned residual_blocks_per_slab(long long nx);
+unsigned residual_blocks_per_slab(int dim, int n, long long nx, int nt);
 
+// Folded DST-I transforms (stmg_transform.hip).  hb = transform_half_blocks(n);
+// Sfrag = [dir fwd/inv][half odd/even][kb < hb][ib < 4 hb][64 lanes] fragments.
+int transform_half_blocks(int n);
+// Transform implementation: automatic choice, LDS-staged kernels only, or the
+// FP64 register-resident kernels wherever their state fits.
+enum { TRANSFORM_AUTO = 0, TRANSFORM_LDS = 1, TRANSFORM_REG = 2 };
 template <typename T>
-hipError_t launch_dst(int np, bool xaxis, const T* in, T* out, const T* Sfrag, int n,
-                      long long inner, long long ncols, T omega, int mode, hipStream_t s);
+hipError_t launch_dst_pass(int impl, int hb, bool xaxis, bool inverse, const T* in, T* out, const T* Sfrag,
+                           int n, long long inner, long long ncols, T omega, int mode,
+                           hipStream_t s);
 template <typename T>
-hipError_t launch_tsolve(int nt, T* buf, const T* G, long long nx, long long nslab, int transpose,
-                         hipStream_t s);
+hipError_t launch_dst_fused(int impl, int hb, int nt, const T* in, T* out, const T* Sfrag, const T* G, int n,
+                            long long inner, long long outer, int transpose, T omega, int mode,
+                            hipStream_t s);
 template <typename T>
 hipError_t launch_restrict(int dim, int nt, bool full, const T* rf, T* Fc, const TransferArgs<T>& a,
                            hipStream_t s);

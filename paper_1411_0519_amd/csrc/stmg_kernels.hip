@@ -7,59 +7,21 @@
 //               separably), N_t x N_t time mixing, upwind coupling to the
 //               neighbouring slab (eq. chap4_generalLinearSystem).  Fused
 //               per-block partial sums of r^2 for the norm.
-//   k_dst       one sine-transform pass along one axis as a tall GEMM on the
-//               matrix cores (v_mfma_f64_16x16x4f64 / v_mfma_f32_16x16x4f32):
-//               out[o][k][c] = sum_i S[k][i] in[o][i][c], S the orthonormal
-//               DST-I (S = S^T = S^{-1}); epilogue store / u += omega out.
-//   k_tsolve    per sine mode k the N_t x N_t solve G_k = (mu_k K + nu_k M)^{-1}
-//               (fast diagonalisation of the slab block A = K (x) M_h + M (x) K_h).
+//   (the slab solves by fast diagonalisation live in stmg_transform.hip)
 //   k_restrict  F_c[m] = R1 r[2m] + R2 r[2m+1], optional full weighting in space
 //               (eq. chap4_restrictionTime, eq. chap4_spaceRestrictionProlongation).
 //   k_prolong   u[2m] += R1^T e_c[m], u[2m+1] += R2^T e_c[m], optional
 //               (bi/tri)linear interpolation in space.
 #include <hip/hip_runtime.h>
 
+#include "stmg_device.h"
 #include "stmg_internal.h"
 
 namespace stmg {
 
 namespace {
 
-typedef double v4d __attribute__((ext_vector_type(4)));
-typedef float v4f __attribute__((ext_vector_type(4)));
-
-template <typename T>
-struct Mfma;
-// 16x16x4 MFMA: lane l supplies A[l%16][l/16] and B[l/16][l%16]; accumulator
-// element j of lane l is D[row(l/16, j)][l%16].  The row mapping differs between
-// the two instructions (measured on gfx950): f64 interleaves, f32 is blocked.
-template <>
-struct Mfma<double> {
-  typedef v4d acc_t;
-  static __device__ inline acc_t op(double a, double b, acc_t c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-  static __device__ inline int row(int g, int j) { return g + 4 * j; }
-};
-template <>
-struct Mfma<float> {
-  typedef v4f acc_t;
-  static __device__ inline acc_t op(float a, float b, acc_t c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-  static __device__ inline int row(int g, int j) { return 4 * g + j; }
-};
-
-__device__ inline long long slab_index() {
-  return (long long)blockIdx.y + (long long)gridDim.y * blockIdx.z;
-}
-
-inline dim3 slab_grid(unsigned gx, long long slabs) {
-  const long long ymax = 65535;
-  unsigned gy = (unsigned)(slabs < ymax ? slabs : ymax);
-  unsigned gz = (unsigned)((slabs + ymax - 1) / ymax);
-  return dim3(gx, gy, gz);
-}
+using namespace dev;
 
 // Mass and stiffness stencils of all N_t time components at interior node
 // (x, y, z):  mu[l] = (M_h u_l), ku[l] = (K_h u_l).  Separable: 1-D row sums
@@ -213,145 +175,93 @@ __global__ __launch_bounds__(256) void k_residual(const Tin* __restrict__ u,
   }
 }
 
-// ------------------------------------------------------------- DST contraction
-// One workgroup (4 waves) owns TILE_COLS = 64 columns and all n rows of the
-// contracted axis.  The data tile is staged in LDS (row stride 65 to spread
-// banks); the transform matrix is read from global memory in MFMA fragment
-// order (Sfrag[(kb*(NP/4) + ib)*64 + lane] = S[16 kb + lane%16][4 ib + lane/16]),
-// which makes every fragment load one coalesced 64-lane access.
-template <typename T, int NB, bool XAXIS>
-__global__ __launch_bounds__(256) void k_dst(const T* __restrict__ in, T* __restrict__ out,
-                                             const T* __restrict__ Sfrag, int n, long long inner,
-                                             long long ncols, T omega, int mode) {
-  constexpr int NP = 16 * NB;
-  constexpr int LD = TILE_COLS + 1;
-  constexpr int KPW = (NB >= 4) ? NB / 4 : NB;   // k-blocks per wave
-  constexpr int CPW = (NB >= 4) ? 4 : 1;         // 16-column blocks per wave
-  typedef typename Mfma<T>::acc_t acc_t;
-  __shared__ T tile[NP * LD];
-
-  const int tid = threadIdx.x;
-  const long long col0 = (long long)blockIdx.x * TILE_COLS;
-  const long long ncol_here = (ncols - col0) < TILE_COLS ? (ncols - col0) : TILE_COLS;
-
-  // ---- stage the input tile: tile[i][c] = X[i][col0 + c]
-  if (XAXIS) {
-    const long long base = col0 * n;
-    const int total = TILE_COLS * n;
-    const long long maxe = ncol_here * n;
-    for (int e = tid; e < total; e += 256) {
-      const int c = e / n;
-      const int i = e - c * n;
-      tile[i * LD + c] = (e < maxe) ? in[base + e] : T(0);
+// 2-D residual on an LDS tile: one workgroup owns one slab and TY rows
+// (all x).  It stages the N_t components of u and the coupling combination
+// w = sum_k cb[k] u_{n+dir,k} for rows y0-1 .. y0+TY (zero outside the
+// domain), then applies the separable 9-point mass/stiffness stencils from
+// LDS.  Dynamic LDS: (NT + 1) * (TY + 2) * n elements.
+template <typename Tin, typename Tout, int NT>
+__global__ __launch_bounds__(256) void k_residual_tile2d(const Tin* __restrict__ u,
+                                                         const Tin* __restrict__ F,
+                                                         Tout* __restrict__ r, ResidArgs<Tin> a,
+                                                         double* __restrict__ partial, int TY) {
+  typedef Tin T;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  T* U = reinterpret_cast<T*>(lds_raw);
+  const long long slab = slab_index();
+  const long long nslab = (long long)a.batch * a.N;
+  if (slab >= nslab) return;
+  const int n = a.n;
+  const long long nx = a.nx;
+  const int y0 = blockIdx.x * TY;
+  const int rows = TY + 2;
+  const int plane = rows * n;                 // one component's tile
+  const int sn = (int)(slab % a.N);
+  const bool couple = (sn + a.dir >= 0) && (sn + a.dir < a.N);
+  const long long slabsz = (long long)NT * nx;
+  const T* un = u + slab * slabsz;
+  const T* up = u + (slab + a.dir) * slabsz;
+  const float inv_n = 1.0f / (float)n;
+  // ---- stage
+  for (int e = threadIdx.x; e < plane; e += 256) {
+    const int rr = div_small(e, n, inv_n);
+    const int x = e - rr * n;
+    const int y = y0 - 1 + rr;
+    const bool in = (y >= 0) && (y < n);
+    const long long off = (long long)y * n + x;
+    T w = T(0);
+#pragma unroll
+    for (int k = 0; k < NT; ++k) {
+      U[k * plane + e] = in ? un[k * nx + off] : T(0);
+      if (couple && in) w += a.cb[k] * up[k * nx + off];
     }
-  } else {
-    const int c = tid & (TILE_COLS - 1);
-    const long long col = col0 + c;
-    const bool valid = c < ncol_here;
-    const long long o = valid ? col / inner : 0;
-    const long long cc = valid ? col - o * inner : 0;
-    const T* src = in + o * (long long)n * inner + cc;
-    for (int i = tid >> 6; i < n; i += 4) tile[i * LD + c] = valid ? src[(long long)i * inner] : T(0);
-  }
-  for (int e = tid; e < (NP - n) * TILE_COLS; e += 256) {
-    const int i = n + e / TILE_COLS;
-    tile[i * LD + (e % TILE_COLS)] = T(0);
+    U[NT * plane + e] = w;
   }
   __syncthreads();
-
-  // ---- contraction on the matrix cores
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
-  acc_t acc[KPW][CPW];
+  // ---- stencils
+  double ss = 0.0;
+  const T* Fn = F + slab * slabsz;
+  Tout* rn = r + slab * slabsz;
+  const int nout = TY * n;
+  for (int e = threadIdx.x; e < nout; e += 256) {
+    const int yy = div_small(e, n, inv_n);
+    const int x = e - yy * n;
+    const int y = y0 + yy;
+    if (y >= n) continue;
+    const bool hl = x > 0, hr = x < n - 1;
+    T mu[NT + 1], ku[NT];
 #pragma unroll
-  for (int q = 0; q < KPW; ++q)
+    for (int c = 0; c <= NT; ++c) {
+      T m = T(0), kk = T(0);
 #pragma unroll
-    for (int p = 0; p < CPW; ++p) acc[q][p] = acc_t{0, 0, 0, 0};
-  const int ibmax = (n + 3) >> 2;
-  const int brow = lane >> 4, bcol = lane & 15;
-  for (int ib = 0; ib < ibmax; ++ib) {
-    T bf[CPW];
-#pragma unroll
-    for (int p = 0; p < CPW; ++p) {
-      const int cb = (NB >= 4) ? p : wave;
-      bf[p] = tile[(ib * 4 + brow) * LD + cb * 16 + bcol];
-    }
-#pragma unroll
-    for (int q = 0; q < KPW; ++q) {
-      const int kb = (NB >= 4) ? wave + 4 * q : q;
-      const T af = Sfrag[((long long)kb * (NP / 4) + ib) * 64 + lane];
-#pragma unroll
-      for (int p = 0; p < CPW; ++p) acc[q][p] = Mfma<T>::op(af, bf[p], acc[q][p]);
-    }
-  }
-  __syncthreads();
-  // ---- accumulators back to LDS
-#pragma unroll
-  for (int q = 0; q < KPW; ++q) {
-    const int kb = (NB >= 4) ? wave + 4 * q : q;
-#pragma unroll
-    for (int p = 0; p < CPW; ++p) {
-      const int cb = (NB >= 4) ? p : wave;
-#pragma unroll
-      for (int jj = 0; jj < 4; ++jj) {
-        const int k = kb * 16 + Mfma<T>::row(brow, jj);
-        tile[k * LD + cb * 16 + bcol] = acc[q][p][jj];
+      for (int dr = 0; dr < 3; ++dr) {
+        const T* row = U + c * plane + (yy + dr) * n + x;
+        const T l = hl ? row[-1] : T(0);
+        const T m0 = row[0];
+        const T rt = hr ? row[1] : T(0);
+        const T sm = a.wm[0] * l + a.wm[1] * m0 + a.wm[2] * rt;
+        m += a.wm[dr] * sm;
+        if (c < NT) {
+          const T sk = a.wk[0] * l + a.wk[1] * m0 + a.wk[2] * rt;
+          kk += a.wk[dr] * sm + a.wm[dr] * sk;
+        }
       }
+      mu[c] = m;
+      if (c < NT) ku[c] = kk;
+    }
+    const long long off = (long long)y * n + x;
+#pragma unroll
+    for (int l = 0; l < NT; ++l) {
+      T acc = Fn[l * nx + off] + a.ca[l] * mu[NT];
+#pragma unroll
+      for (int k = 0; k < NT; ++k) acc -= a.K[l * NT + k] * mu[k] + a.M[l * NT + k] * ku[k];
+      rn[l * nx + off] = (Tout)acc;
+      ss += (double)acc * (double)acc;
     }
   }
-  __syncthreads();
-
-  // ---- store with epilogue
-  if (XAXIS) {
-    const long long base = col0 * n;
-    const long long maxe = ncol_here * n;
-    const int total = TILE_COLS * n;
-    for (int e = tid; e < total && e < maxe; e += 256) {
-      const int c = e / n;
-      const int i = e - c * n;
-      const T v = tile[i * LD + c];
-      T* dst = out + base + e;
-      if (mode == MODE_STORE) *dst = v;
-      else if (mode == MODE_ADD_SCALED) *dst += omega * v;
-      else *dst = omega * v;
-    }
-  } else {
-    const int c = tid & (TILE_COLS - 1);
-    if (c < ncol_here) {
-      const long long col = col0 + c;
-      const long long o = col / inner;
-      const long long cc = col - o * inner;
-      T* dstb = out + o * (long long)n * inner + cc;
-      for (int i = tid >> 6; i < n; i += 4) {
-        const T v = tile[i * LD + c];
-        T* dst = dstb + (long long)i * inner;
-        if (mode == MODE_STORE) *dst = v;
-        else if (mode == MODE_ADD_SCALED) *dst += omega * v;
-        else *dst = omega * v;
-      }
-    }
-  }
-}
-
-// ------------------------------------------------------------- per-mode solve
-template <typename T, int NT>
-__global__ __launch_bounds__(256) void k_tsolve(T* __restrict__ buf, const T* __restrict__ G,
-                                                long long nx, long long nslab, int transpose) {
-  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= nx * nslab) return;
-  const long long s = idx / nx;
-  const long long j = idx - s * nx;
-  T* p = buf + s * NT * nx + j;
-  T v[NT];
-#pragma unroll
-  for (int k = 0; k < NT; ++k) v[k] = p[k * nx];
-  const T* g = G + j * NT * NT;
-#pragma unroll
-  for (int l = 0; l < NT; ++l) {
-    T acc = T(0);
-#pragma unroll
-    for (int k = 0; k < NT; ++k) acc += (transpose ? g[k * NT + l] : g[l * NT + k]) * v[k];
-    p[l * nx] = acc;
+  if (partial != nullptr) {
+    const double s2 = block_sum(ss);
+    if (threadIdx.x == 0) partial[slab * gridDim.x + blockIdx.x] = s2;
   }
 }
 
@@ -574,13 +484,34 @@ inline unsigned blocks_for(long long total) { return (unsigned)((total + 255) / 
 
 // ================================================================ launchers
 
-unsigned residual_blocks_per_slab(long long nx) { return (unsigned)((nx + 255) / 256); }
+int residual_tile_rows(int nt) { return nt <= 2 ? 8 : (nt == 3 ? 6 : 4); }
+
+unsigned residual_blocks_per_slab(int dim, int n, long long nx, int nt) {
+  if (dim == 2) {
+    const int ty = residual_tile_rows(nt);
+    return (unsigned)((n + ty - 1) / ty);
+  }
+  return (unsigned)((nx + 255) / 256);
+}
 
 template <typename Tin, typename Tout>
 hipError_t launch_residual(int dim, int nt, const Tin* u, const Tin* F, Tout* r,
                            const ResidArgs<Tin>& a, double* partial, hipStream_t s) {
-  const unsigned gx = residual_blocks_per_slab(a.nx);
+  const unsigned gx = residual_blocks_per_slab(dim, a.n, a.nx, nt);
   const dim3 grid = slab_grid(gx, (long long)a.batch * a.N);
+  if (dim == 2) {
+    const int ty = residual_tile_rows(nt);
+    const size_t lds = (size_t)(nt + 1) * (ty + 2) * a.n * sizeof(Tin);
+#define RES2_CASE(NT)                                                                        \
+  if (nt == NT) {                                                                            \
+    hipLaunchKernelGGL((k_residual_tile2d<Tin, Tout, NT>), grid, dim3(256), lds, s, u, F, r, a, \
+                       partial, ty);                                                         \
+    return hipGetLastError();                                                                \
+  }
+    RES2_CASE(1) RES2_CASE(2) RES2_CASE(3) RES2_CASE(4)
+#undef RES2_CASE
+    return hipErrorInvalidValue;
+  }
 #define RES_CASE(D, NT)                                                                \
   if (dim == D && nt == NT) {                                                          \
     hipLaunchKernelGGL((k_residual<Tin, Tout, D, NT>), grid, dim3(256), 0, s, u, F, r, a, \
@@ -588,43 +519,9 @@ hipError_t launch_residual(int dim, int nt, const Tin* u, const Tin* F, Tout* r,
     return hipGetLastError();                                                          \
   }
   RES_CASE(1, 1) RES_CASE(1, 2) RES_CASE(1, 3) RES_CASE(1, 4)
-  RES_CASE(2, 1) RES_CASE(2, 2) RES_CASE(2, 3) RES_CASE(2, 4)
   RES_CASE(3, 1) RES_CASE(3, 2) RES_CASE(3, 3) RES_CASE(3, 4)
 #undef RES_CASE
   return hipErrorInvalidValue;
-}
-
-template <typename T>
-hipError_t launch_dst(int np, bool xaxis, const T* in, T* out, const T* Sfrag, int n,
-                      long long inner, long long ncols, T omega, int mode, hipStream_t s) {
-  const unsigned grid = (unsigned)((ncols + TILE_COLS - 1) / TILE_COLS);
-#define DST_CASE(NB)                                                                       \
-  if (np == 16 * NB) {                                                                     \
-    if (xaxis)                                                                             \
-      hipLaunchKernelGGL((k_dst<T, NB, true>), dim3(grid), dim3(256), 0, s, in, out, Sfrag, \
-                         n, inner, ncols, omega, mode);                                    \
-    else                                                                                   \
-      hipLaunchKernelGGL((k_dst<T, NB, false>), dim3(grid), dim3(256), 0, s, in, out,       \
-                         Sfrag, n, inner, ncols, omega, mode);                             \
-    return hipGetLastError();                                                              \
-  }
-  DST_CASE(1) DST_CASE(2) DST_CASE(4) DST_CASE(8) DST_CASE(16)
-#undef DST_CASE
-  return hipErrorInvalidValue;
-}
-
-template <typename T>
-hipError_t launch_tsolve(int nt, T* buf, const T* G, long long nx, long long nslab, int transpose,
-                         hipStream_t s) {
-  const unsigned grid = blocks_for(nx * nslab);
-  switch (nt) {
-    case 1: hipLaunchKernelGGL((k_tsolve<T, 1>), dim3(grid), dim3(256), 0, s, buf, G, nx, nslab, transpose); break;
-    case 2: hipLaunchKernelGGL((k_tsolve<T, 2>), dim3(grid), dim3(256), 0, s, buf, G, nx, nslab, transpose); break;
-    case 3: hipLaunchKernelGGL((k_tsolve<T, 3>), dim3(grid), dim3(256), 0, s, buf, G, nx, nslab, transpose); break;
-    case 4: hipLaunchKernelGGL((k_tsolve<T, 4>), dim3(grid), dim3(256), 0, s, buf, G, nx, nslab, transpose); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
 }
 
 #define TRANSFER_DISPATCH(KERNEL, TOTAL, ...)                                            \
@@ -735,9 +632,6 @@ template hipError_t launch_residual<double, float>(int, int, const double*, cons
 template hipError_t launch_residual<float, float>(int, int, const float*, const float*, float*,
                                                   const ResidArgs<float>&, double*, hipStream_t);
 #define INST(T)                                                                                     \
-  template hipError_t launch_dst<T>(int, bool, const T*, T*, const T*, int, long long, long long, T, \
-                                    int, hipStream_t);                                              \
-  template hipError_t launch_tsolve<T>(int, T*, const T*, long long, long long, int, hipStream_t);  \
   template hipError_t launch_restrict<T>(int, int, bool, const T*, T*, const TransferArgs<T>&,      \
                                          hipStream_t);                                              \
   template hipError_t launch_prolong<T>(int, int, bool, const T*, T*, const TransferArgs<T>&,       \

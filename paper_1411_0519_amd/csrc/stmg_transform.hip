@@ -1,0 +1,699 @@
+// Exact slab solves by fast diagonalisation on the matrix cores (gfx950).
+//
+// The slab block A = K_tau (x) M_h + M_tau (x) K_h (eq. chap4_generalLinearSystem)
+// is diagonalised in space by the orthonormal DST-I, S[k][j] = c sin(pi k j/(n+1))
+// (1-based, c = sqrt(2/(n+1)), S = S^T = S^{-1}), applied along every axis; per
+// sine mode the N_t x N_t block G = (mu K_tau + nu M_tau)^{-1} remains
+// (eq. chap4_smootherExact is D^{-1} applied exactly).
+//
+// Folding.  With m = n + 1 and h = m/2, S[k][m-j] = (-1)^(k+1) S[k][j], so a
+// length-n transform splits into two half-size products:
+//   odd  k = 2s+1 (s < h):   xhat = sum_{j<=h}   S[k][j] a_j,  a_j = x_j + x_{m-j}, a_h = x_h
+//   even k = 2s+2 (s < h-1): xhat = sum_{j<h}    S[k][j] d_j,  d_j = x_j - x_{m-j}
+// and the inverse y = S xhat is  P = S_odd^T xhat_odd, Q = S_even^T xhat_even,
+// y_j = P_j + Q_j, y_{m-j} = P_j - Q_j, y_h = P_h.  This halves the matrix-core
+// work.  Transformed data are kept in "spectral order" along every axis: the h
+// odd modes first, then the h-1 even modes; the per-mode blocks G use the same
+// order.
+//
+// Kernels (one workgroup = 4 waves = 64 columns of the contracted axis):
+//   k_dst_pass   one forward or inverse folded transform along one axis
+//                (x: rows contiguous; y/z: strided), epilogue store / u += omega y
+//   k_dst_fused  forward transform along the slowest axis, the per-mode time
+//                solve, inverse transform, in one pass over HBM: the tile holds
+//                all N_t time components of 64 / N_t columns.
+#include <hip/hip_runtime.h>
+
+#include "stmg_device.h"
+#include "stmg_internal.h"
+
+namespace stmg {
+
+namespace {
+
+using namespace dev;
+
+constexpr int LDT = TILE_COLS + 1;   // LDS row stride (spreads banks)
+
+// Fragment table offset of (direction, half): [dir][half][kb][ib][lane].
+template <int HB>
+__device__ inline int frag_block(int dir, int half) {
+  constexpr int HP = 16 * HB;
+  return ((dir * 2 + half) * HB) * (HP / 4) * 64;
+}
+
+// Block-diagonal folded product on the tile (rows = contracted axis, 64
+// columns).  INV = false: the tile holds a (rows < h) and d (row n-1-i holds
+// d_{i+1}); INV = true: the tile holds spectral rows (odd s at row s, even s at
+// row h + s).  Results: odd outputs -> acc of odd k-blocks, even -> even.
+template <typename T, int HB, bool INV>
+struct FoldMma {
+  static constexpr int NB = 2 * HB;
+  static constexpr int HP = 16 * HB;
+  static constexpr int KPW = (NB >= 4) ? NB / 4 : NB;
+  static constexpr int CPW = (NB >= 4) ? 4 : 1;
+  typedef typename Mfma<T>::acc_t acc_t;
+
+  static __device__ inline int kbt_of(int wave, int q) { return (NB >= 4) ? wave + 4 * q : q; }
+  static __device__ inline int cb_of(int wave, int p) { return (NB >= 4) ? p : wave; }
+
+  static __device__ inline void run(const T* tile, const T* __restrict__ Sfrag, int n, int h,
+                                    acc_t (&acc)[KPW][CPW]) {
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int brow = lane >> 4, bcol = lane & 15;
+#pragma unroll
+    for (int q = 0; q < KPW; ++q)
+#pragma unroll
+      for (int p = 0; p < CPW; ++p) acc[q][p] = acc_t{0, 0, 0, 0};
+    const T* sf[KPW];
+    bool even[KPW];
+#pragma unroll
+    for (int q = 0; q < KPW; ++q) {
+      const int kbt = kbt_of(wave, q);
+      const int half = kbt / HB, kb = kbt % HB;
+      even[q] = half == 1;
+      sf[q] = Sfrag + frag_block<HB>(INV ? 1 : 0, half) + kb * (HP / 4) * 64 + lane;
+    }
+    const int ibmax = (h + 3) >> 2;
+    T an[KPW];
+#pragma unroll
+    for (int q = 0; q < KPW; ++q) an[q] = sf[q][0];
+    for (int ib = 0; ib < ibmax; ++ib) {
+      T af[KPW];
+#pragma unroll
+      for (int q = 0; q < KPW; ++q) af[q] = an[q];
+      if (ib + 1 < ibmax) {
+#pragma unroll
+        for (int q = 0; q < KPW; ++q) an[q] = sf[q][(ib + 1) * 64];
+      }
+      const int i = ib * 4 + brow;
+      const int rowo = i;                          // odd operand row (valid if i < h)
+      const int rowe = INV ? h + i : n - 1 - i;    // even operand row (valid if i < h - 1)
+      T bo[CPW], be[CPW];
+#pragma unroll
+      for (int p = 0; p < CPW; ++p) {
+        const int col = cb_of(wave, p) * 16 + bcol;
+        bo[p] = (i < h) ? tile[rowo * LDT + col] : T(0);
+        be[p] = (i < h - 1) ? tile[rowe * LDT + col] : T(0);
+      }
+#pragma unroll
+      for (int q = 0; q < KPW; ++q)
+#pragma unroll
+        for (int p = 0; p < CPW; ++p) acc[q][p] = Mfma<T>::op(af[q], even[q] ? be[p] : bo[p], acc[q][p]);
+    }
+  }
+
+  // acc -> tile: odd output r (< h) at row r, even output r (< h-1) at row h + r.
+  static __device__ inline void to_tile(T* tile, int h, const acc_t (&acc)[KPW][CPW]) {
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int brow = lane >> 4, bcol = lane & 15;
+#pragma unroll
+    for (int q = 0; q < KPW; ++q) {
+      const int kbt = kbt_of(wave, q);
+      const int half = kbt / HB, kb = kbt % HB;
+#pragma unroll
+      for (int p = 0; p < CPW; ++p) {
+        const int col = cb_of(wave, p) * 16 + bcol;
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+          const int r = kb * 16 + Mfma<T>::row(brow, jj);
+          if (half == 0) {
+            if (r < h) tile[r * LDT + col] = acc[q][p][jj];
+          } else {
+            if (r < h - 1) tile[(h + r) * LDT + col] = acc[q][p][jj];
+          }
+        }
+      }
+    }
+  }
+};
+
+// In-place butterfly of physical rows: row i <- x_i + x_{n-1-i}, row n-1-i <- x_i - x_{n-1-i}.
+template <typename T>
+__device__ inline void butterfly(T* tile, int n, int h) {
+  for (int e = threadIdx.x; e < (h - 1) * TILE_COLS; e += 256) {
+    const int i = e >> 6, c = e & (TILE_COLS - 1);
+    const T a = tile[i * LDT + c], b = tile[(n - 1 - i) * LDT + c];
+    tile[i * LDT + c] = a + b;
+    tile[(n - 1 - i) * LDT + c] = a - b;
+  }
+}
+
+// Physical value of row p after an inverse product (P at rows < h, Q at h + i).
+template <typename T>
+__device__ inline T unfold(const T* tile, int n, int h, int p, int c) {
+  if (p < h - 1) return tile[p * LDT + c] + tile[(h + p) * LDT + c];
+  if (p == h - 1) return tile[p * LDT + c];
+  const int i = n - 1 - p;
+  return tile[i * LDT + c] - tile[(h + i) * LDT + c];
+}
+
+template <typename T>
+__device__ inline T epilogue(int mode, T old, T v, T omega) {
+  return mode == MODE_STORE ? v : (mode == MODE_ADD_SCALED ? old + omega * v : omega * v);
+}
+
+// ------------------------------------------------------------ single pass
+template <typename T, int HB, bool XAXIS, bool INV>
+__global__ __launch_bounds__(256) void k_dst_pass(const T* __restrict__ in, T* __restrict__ out,
+                                                  const T* __restrict__ Sfrag, int n, long long inner,
+                                                  long long ncols, T omega, int mode) {
+  typedef FoldMma<T, HB, INV> MM;
+  constexpr int NP = 32 * HB;                  // >= n rows
+  constexpr int EPT = NP * TILE_COLS / 256;
+  __shared__ T tile[NP * LDT];
+  const int tid = threadIdx.x;
+  const long long col0 = (long long)blockIdx.x * TILE_COLS;
+  const int ncol_here = (int)((ncols - col0) < TILE_COLS ? (ncols - col0) : TILE_COLS);
+  const float inv_n = 1.0f / (float)n;
+  const int h = (n + 1) >> 1;
+
+  // ---- stage: tile[i][c] = X[i][col0 + c]
+  if (XAXIS) {
+    const T* src = in + col0 * n;
+    const int total = ncol_here * n;
+    T v[EPT];
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+      const int e = tid + 256 * j;
+      v[j] = (e < total) ? src[e] : T(0);
+    }
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+      const int e = tid + 256 * j;
+      if (e < TILE_COLS * n) {
+        const int c = div_small(e, n, inv_n);
+        tile[(e - c * n) * LDT + c] = v[j];
+      }
+    }
+  } else {
+    const int c = tid & (TILE_COLS - 1);
+    const bool valid = c < ncol_here;
+    const long long col = col0 + c;
+    const long long o = valid ? col / inner : 0;
+    const long long cc = valid ? col - o * inner : 0;
+    const T* src = in + o * (long long)n * inner + cc;
+    const int i0 = tid >> 6;
+    T v[EPT];
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+      const int i = i0 + 4 * j;
+      v[j] = (valid && i < n) ? src[(long long)i * inner] : T(0);
+    }
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+      const int i = i0 + 4 * j;
+      if (i < n) tile[i * LDT + c] = v[j];
+    }
+  }
+  __syncthreads();
+  if (!INV) {
+    butterfly(tile, n, h);
+    __syncthreads();
+  }
+  typename MM::acc_t acc[MM::KPW][MM::CPW];
+  MM::run(tile, Sfrag, n, h, acc);
+  __syncthreads();
+  MM::to_tile(tile, h, acc);
+  __syncthreads();
+
+  // ---- store (forward: spectral rows as they are; inverse: unfold)
+  if (XAXIS) {
+    T* dst = out + col0 * n;
+    const int total = ncol_here * n;
+    T o[EPT];
+    if (mode == MODE_ADD_SCALED) {
+#pragma unroll
+      for (int j = 0; j < EPT; ++j) {
+        const int e = tid + 256 * j;
+        o[j] = (e < total) ? dst[e] : T(0);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+      const int e = tid + 256 * j;
+      if (e < total) {
+        const int c = div_small(e, n, inv_n);
+        const int p = e - c * n;
+        const T v = INV ? unfold(tile, n, h, p, c) : tile[p * LDT + c];
+        dst[e] = epilogue(mode, o[j], v, omega);
+      }
+    }
+  } else {
+    const int c = tid & (TILE_COLS - 1);
+    if (c < ncol_here) {
+      const long long col = col0 + c;
+      const long long o = col / inner;
+      const long long cc = col - o * inner;
+      T* dstb = out + o * (long long)n * inner + cc;
+      const int i0 = tid >> 6;
+      T ov[EPT];
+      if (mode == MODE_ADD_SCALED) {
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) {
+          const int i = i0 + 4 * j;
+          ov[j] = (i < n) ? dstb[(long long)i * inner] : T(0);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < EPT; ++j) {
+        const int p = i0 + 4 * j;
+        if (p < n) {
+          const T v = INV ? unfold(tile, n, h, p, c) : tile[p * LDT + c];
+          dstb[(long long)p * inner] = epilogue(mode, ov[j], v, omega);
+        }
+      }
+    }
+  }
+}
+
+// ------------------------------------------------ fused last-axis solve
+// Column c of the tile is (time component l = c / CT, position cc = c % CT) of
+// the linear index lin = blockIdx.x * CT + cc over (slab o, other axes pos):
+// element i sits at o*NT*n*inner + l*n*inner + i*inner + pos.  The sine mode
+// of spectral row s at position pos is j = pos + inner * s.
+template <typename T, int HB, int NT>
+__global__ __launch_bounds__(256) void k_dst_fused(const T* in, T* out,
+                                                   const T* __restrict__ Sfrag,
+                                                   const T* __restrict__ G, int n, long long inner,
+                                                   long long outer, int transpose, T omega,
+                                                   int mode) {
+  typedef FoldMma<T, HB, false> MF;
+  typedef FoldMma<T, HB, true> MI;
+  constexpr int NP = 32 * HB;
+  constexpr int CT = TILE_COLS / NT;
+  constexpr int EPT = NP * TILE_COLS / 256;
+  __shared__ T tile[NP * LDT];
+  __shared__ long long pos_s[TILE_COLS];
+  __shared__ long long base_s[TILE_COLS];
+  const int tid = threadIdx.x;
+  const long long total = outer * inner;
+  const long long lin0 = (long long)blockIdx.x * CT;
+  const int h = (n + 1) >> 1;
+  if (tid < TILE_COLS) {
+    const int l = tid / CT, cc = tid - (tid / CT) * CT;
+    const long long lin = lin0 + cc;
+    if (l < NT && lin < total) {
+      const long long o = lin / inner;
+      const long long pos = lin - o * inner;
+      pos_s[tid] = pos;
+      base_s[tid] = o * NT * (long long)n * inner + (long long)l * n * inner + pos;
+    } else {
+      pos_s[tid] = -1;
+      base_s[tid] = -1;
+    }
+  }
+  __syncthreads();
+  const int c = tid & (TILE_COLS - 1);
+  const long long base = base_s[c];
+  const int i0 = tid >> 6;
+  {
+    T v[EPT];
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+      const int i = i0 + 4 * j;
+      v[j] = (base >= 0 && i < n) ? in[base + (long long)i * inner] : T(0);
+    }
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+      const int i = i0 + 4 * j;
+      if (i < n) tile[i * LDT + c] = v[j];
+    }
+  }
+  __syncthreads();
+  butterfly(tile, n, h);
+  __syncthreads();
+  {
+    typename MF::acc_t acc[MF::KPW][MF::CPW];
+    MF::run(tile, Sfrag, n, h, acc);
+    __syncthreads();
+    MF::to_tile(tile, h, acc);
+  }
+  __syncthreads();
+  // ---- per-mode N_t x N_t solve on the spectral tile
+  for (int e = tid; e < n * CT; e += 256) {
+    const int s = e / CT, cc = e - (e / CT) * CT;
+    const long long pos = pos_s[cc];
+    if (pos < 0) continue;
+    const T* g = G + (pos + inner * s) * (NT * NT);
+    T v[NT];
+#pragma unroll
+    for (int k = 0; k < NT; ++k) v[k] = tile[s * LDT + k * CT + cc];
+#pragma unroll
+    for (int l = 0; l < NT; ++l) {
+      T a = T(0);
+#pragma unroll
+      for (int k = 0; k < NT; ++k) a += (transpose ? g[k * NT + l] : g[l * NT + k]) * v[k];
+      tile[s * LDT + l * CT + cc] = a;
+    }
+  }
+  __syncthreads();
+  {
+    typename MI::acc_t acc[MI::KPW][MI::CPW];
+    MI::run(tile, Sfrag, n, h, acc);
+    __syncthreads();
+    MI::to_tile(tile, h, acc);
+  }
+  __syncthreads();
+  if (base >= 0) {
+    T ov[EPT];
+    if (mode == MODE_ADD_SCALED) {
+#pragma unroll
+      for (int j = 0; j < EPT; ++j) {
+        const int i = i0 + 4 * j;
+        ov[j] = (i < n) ? out[base + (long long)i * inner] : T(0);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+      const int p = i0 + 4 * j;
+      if (p < n) out[base + (long long)p * inner] = epilogue(mode, ov[j], unfold(tile, n, h, p, c), omega);
+    }
+  }
+}
+
+// ------------------------------------------- FP64 register-resident kernels
+// Each wave owns 16 columns (lin = 16 * global_wave + lane % 16) and all rows of
+// the contracted axis; lane (g = lane / 16, r = lane % 16) holds rows g, g+4, ...
+// No LDS and no barriers: the v_mfma_f64_16x16x4f64 accumulator layout (row
+// g + 4j of a 16-row block in element j) is the B-operand layout of the next
+// product (row 4 ib + g with ib = 4 kb + j), so a forward product, the per-mode
+// solve and the inverse product chain in registers.  Element i of column lin
+// sits at o*n*inner*NT + l*n*inner + i*inner + pos with (o, pos) = divmod(lin, inner).
+
+// Forward operands of one column: a (odd half) and d (even half) per 4-row chunk.
+template <int HB>
+__device__ inline void load_folded(const double* __restrict__ src, bool valid, long long inner, int n,
+                                   int h, int g, double (&a)[4 * HB], double (&d)[4 * HB]) {
+#pragma unroll
+  for (int ib = 0; ib < 4 * HB; ++ib) {
+    const int i = 4 * ib + g;
+    const double x1 = (valid && i < h) ? src[(long long)i * inner] : 0.0;
+    const double x2 = (valid && i < h - 1) ? src[(long long)(n - 1 - i) * inner] : 0.0;
+    a[ib] = x1 + x2;
+    d[ib] = x1 - x2;
+  }
+}
+
+// acc[kbt] += S_half(dir) * operand over ib < ceil(h/4); kbt < HB odd, >= HB even.
+// The S fragments of chunk ib+1 are loaded while chunk ib multiplies; a
+// scheduling barrier per chunk stops the compiler from hoisting every fragment
+// load of the unrolled loop (which would exhaust the register file).
+template <int HB, int DIR, typename OpFn>
+__device__ inline void folded_mma_core(const double* __restrict__ Sfrag, int h, int lane, OpFn op,
+                                       v4d (&acc)[2 * HB]) {
+#pragma unroll
+  for (int k = 0; k < 2 * HB; ++k) acc[k] = v4d{0, 0, 0, 0};
+  const int ibmax = (h + 3) >> 2;
+  const double* s0 = Sfrag + frag_block<HB>(DIR, 0) + lane;
+  const double* s1 = Sfrag + frag_block<HB>(DIR, 1) + lane;
+  double no[HB], ne[HB];
+#pragma unroll
+  for (int kb = 0; kb < HB; ++kb) {
+    no[kb] = s0[(kb * 4 * HB) * 64];
+    ne[kb] = s1[(kb * 4 * HB) * 64];
+  }
+#pragma unroll
+  for (int ib = 0; ib < 4 * HB; ++ib) {
+    if (ib < ibmax) {
+      double ao[HB], ae[HB];
+#pragma unroll
+      for (int kb = 0; kb < HB; ++kb) {
+        ao[kb] = no[kb];
+        ae[kb] = ne[kb];
+      }
+      if (ib + 1 < ibmax) {
+#pragma unroll
+        for (int kb = 0; kb < HB; ++kb) {
+          no[kb] = s0[(kb * 4 * HB + ib + 1) * 64];
+          ne[kb] = s1[(kb * 4 * HB + ib + 1) * 64];
+        }
+      }
+      const double bo = op(0, ib), be = op(1, ib);
+#pragma unroll
+      for (int kb = 0; kb < HB; ++kb) {
+        acc[kb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ao[kb], bo, acc[kb], 0, 0, 0);
+        acc[HB + kb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ae[kb], be, acc[HB + kb], 0, 0, 0);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+}
+
+template <int HB, int DIR>
+__device__ inline void folded_mma(const double* __restrict__ Sfrag, int h, int lane,
+                                  const double (&bo)[4 * HB], const double (&be)[4 * HB],
+                                  v4d (&acc)[2 * HB]) {
+  folded_mma_core<HB, DIR>(Sfrag, h, lane, [&](int half, int ib) { return half ? be[ib] : bo[ib]; }, acc);
+}
+
+// Inverse product whose B operands are the accumulators of a forward product:
+// chunk ib = 4 kb + j of the odd (even) half is element j of src[kb] (src[HB + kb]).
+template <int HB>
+__device__ inline void folded_mma_chain(const double* __restrict__ Sfrag, int h, int lane,
+                                        const v4d (&src)[2 * HB], v4d (&acc)[2 * HB]) {
+  folded_mma_core<HB, 1>(Sfrag, h, lane,
+                         [&](int half, int ib) { return src[half * HB + (ib >> 2)][ib & 3]; }, acc);
+}
+
+// Physical outputs of an inverse product: row i gets P_i + Q_i, row n-1-i gets
+// P_i - Q_i (i < h-1), row h-1 gets P_{h-1}; apply the epilogue in place.
+template <int HB>
+__device__ inline void store_unfolded(double* __restrict__ dst, bool valid, long long inner, int n, int h,
+                                      int g, const v4d (&acc)[2 * HB], int mode, double omega) {
+  if (!valid) return;
+#pragma unroll
+  for (int kb = 0; kb < HB; ++kb)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int i = kb * 16 + g + 4 * j;
+      const double P = acc[kb][j], Q = acc[HB + kb][j];
+      if (i < h - 1) {
+        double* p0 = dst + (long long)i * inner;
+        double* p1 = dst + (long long)(n - 1 - i) * inner;
+        const double o0 = (mode == MODE_ADD_SCALED) ? *p0 : 0.0;
+        const double o1 = (mode == MODE_ADD_SCALED) ? *p1 : 0.0;
+        *p0 = epilogue(mode, o0, P + Q, omega);
+        *p1 = epilogue(mode, o1, P - Q, omega);
+      } else if (i == h - 1) {
+        double* p0 = dst + (long long)i * inner;
+        const double o0 = (mode == MODE_ADD_SCALED) ? *p0 : 0.0;
+        *p0 = epilogue(mode, o0, P, omega);
+      }
+    }
+}
+
+template <int HB, bool INV>
+__global__ __launch_bounds__(256) void k_pass_reg(const double* __restrict__ in, double* __restrict__ out,
+                                                  const double* __restrict__ Sfrag, int n, long long inner,
+                                                  long long ncols, double omega, int mode) {
+  const int lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
+  const long long lin = ((long long)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16 + r;
+  const bool valid = lin < ncols;
+  const long long o = valid ? lin / inner : 0;
+  const long long pos = valid ? lin - o * inner : 0;
+  const long long base = o * (long long)n * inner + pos;
+  const int h = (n + 1) >> 1;
+  double bo[4 * HB], be[4 * HB];
+  v4d acc[2 * HB];
+  if (!INV) {
+    load_folded<HB>(in + base, valid, inner, n, h, g, bo, be);
+    folded_mma<HB, 0>(Sfrag, h, lane, bo, be, acc);
+    if (!valid) return;
+#pragma unroll
+    for (int kb = 0; kb < HB; ++kb)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int i = kb * 16 + g + 4 * j;
+        if (i < h) out[base + (long long)i * inner] = acc[kb][j];
+        if (i < h - 1) out[base + (long long)(h + i) * inner] = acc[HB + kb][j];
+      }
+  } else {
+#pragma unroll
+    for (int ib = 0; ib < 4 * HB; ++ib) {
+      const int i = 4 * ib + g;
+      bo[ib] = (valid && i < h) ? in[base + (long long)i * inner] : 0.0;
+      be[ib] = (valid && i < h - 1) ? in[base + (long long)(h + i) * inner] : 0.0;
+    }
+    folded_mma<HB, 1>(Sfrag, h, lane, bo, be, acc);
+    store_unfolded<HB>(out + base, valid, inner, n, h, g, acc, mode, omega);
+  }
+}
+
+template <int HB, int NT>
+__global__ __launch_bounds__(256) void k_fused_reg(const double* in, double* out,
+                                                   const double* __restrict__ Sfrag,
+                                                   const double* __restrict__ G, int n, long long inner,
+                                                   long long outer, int transpose, double omega, int mode) {
+  const int lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
+  const long long lin = ((long long)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16 + r;
+  const bool valid = lin < outer * inner;
+  const long long o = valid ? lin / inner : 0;
+  const long long pos = valid ? lin - o * inner : 0;
+  const long long cstride = (long long)n * inner;           // between time components
+  const long long base = o * NT * cstride + pos;
+  const int h = (n + 1) >> 1;
+  v4d spec[NT][2 * HB];
+#pragma unroll
+  for (int l = 0; l < NT; ++l) {
+    double a[4 * HB], d[4 * HB];
+    load_folded<HB>(in + base + l * cstride, valid, inner, n, h, g, a, d);
+    folded_mma<HB, 0>(Sfrag, h, lane, a, d, spec[l]);
+  }
+  // per-mode N_t x N_t solve; spectral index s: odd rows s < h, even rows h + s
+  if (valid) {
+#pragma unroll
+    for (int k = 0; k < 2 * HB; ++k) {
+      const int half = k / HB, kb = k % HB;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int rr = kb * 16 + g + 4 * j;
+        const bool ok = half == 0 ? rr < h : rr < h - 1;
+        if (!ok) continue;
+        const long long s = half == 0 ? rr : h + rr;
+        const double* gm = G + (pos + inner * s) * (NT * NT);
+        double v[NT], w[NT];
+#pragma unroll
+        for (int l = 0; l < NT; ++l) v[l] = spec[l][k][j];
+#pragma unroll
+        for (int l = 0; l < NT; ++l) {
+          double t = 0.0;
+#pragma unroll
+          for (int m = 0; m < NT; ++m) t += (transpose ? gm[m * NT + l] : gm[l * NT + m]) * v[m];
+          w[l] = t;
+        }
+#pragma unroll
+        for (int l = 0; l < NT; ++l) spec[l][k][j] = w[l];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+#pragma unroll
+  for (int l = 0; l < NT; ++l) {
+    v4d acc[2 * HB];
+    folded_mma_chain<HB>(Sfrag, h, lane, spec[l], acc);
+    store_unfolded<HB>(out + base + l * cstride, valid, inner, n, h, g, acc, mode, omega);
+  }
+}
+
+}  // namespace
+
+// The register-resident kernels serve FP64 while the per-wave state fits
+// (folded half blocks * time components <= 8); larger cases and FP32 use the
+// LDS-staged kernels.
+// nt == 1 selects the single-axis pass; the fused kernel keeps N_t spectral
+// columns per lane and only pays off while that state stays small (measured:
+// half blocks * N_t = 8 spills and runs 1.6x slower than the LDS kernel).
+template <typename T>
+bool reg_path(int impl, int hb, int nt, bool fused) {
+  if (impl == TRANSFORM_LDS || sizeof(T) != 8 || hb > 4) return false;
+  if (!fused) return true;
+  return impl == TRANSFORM_REG ? hb * nt <= 8 : hb * nt <= 4;
+}
+
+hipError_t launch_pass_reg(int hb, bool inverse, const double* in, double* out, const double* Sfrag, int n,
+                           long long inner, long long ncols, double omega, int mode, hipStream_t s) {
+  const unsigned grid = (unsigned)((ncols + 63) / 64);
+#define REG_PASS(HB)                                                                              \
+  if (hb == HB) {                                                                                 \
+    if (inverse)                                                                                  \
+      hipLaunchKernelGGL((k_pass_reg<HB, true>), dim3(grid), dim3(256), 0, s, in, out, Sfrag, n, inner, \
+                         ncols, omega, mode);                                                     \
+    else                                                                                          \
+      hipLaunchKernelGGL((k_pass_reg<HB, false>), dim3(grid), dim3(256), 0, s, in, out, Sfrag, n, inner, \
+                         ncols, omega, mode);                                                     \
+    return hipGetLastError();                                                                     \
+  }
+  REG_PASS(1) REG_PASS(2) REG_PASS(4)
+#undef REG_PASS
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_fused_reg(int hb, int nt, const double* in, double* out, const double* Sfrag,
+                            const double* G, int n, long long inner, long long outer, int transpose,
+                            double omega, int mode, hipStream_t s) {
+  const unsigned grid = (unsigned)((outer * inner + 63) / 64);
+#define REG_FUSED(HB, NT)                                                                          \
+  if (hb == HB && nt == NT) {                                                                      \
+    hipLaunchKernelGGL((k_fused_reg<HB, NT>), dim3(grid), dim3(256), 0, s, in, out, Sfrag, G, n, inner, \
+                       outer, transpose, omega, mode);                                             \
+    return hipGetLastError();                                                                      \
+  }
+  REG_FUSED(1, 1) REG_FUSED(1, 2) REG_FUSED(1, 3) REG_FUSED(1, 4)
+  REG_FUSED(2, 1) REG_FUSED(2, 2) REG_FUSED(2, 3) REG_FUSED(2, 4)
+  REG_FUSED(4, 1) REG_FUSED(4, 2)
+#undef REG_FUSED
+  return hipErrorInvalidValue;
+}
+
+int transform_half_blocks(int n) {
+  const int h = (n + 1) / 2;
+  int hb = 1;
+  while (16 * hb < h) hb *= 2;
+  return hb;
+}
+
+template <typename T>
+hipError_t launch_dst_pass(int impl, int hb, bool xaxis, bool inverse, const T* in, T* out, const T* Sfrag,
+                           int n, long long inner, long long ncols, T omega, int mode,
+                           hipStream_t s) {
+  if (reg_path<T>(impl, hb, 1, false)) return launch_pass_reg(hb, inverse, (const double*)in, (double*)out,
+                                                 (const double*)Sfrag, n, inner, ncols, (double)omega, mode, s);
+  const unsigned grid = (unsigned)((ncols + TILE_COLS - 1) / TILE_COLS);
+#define PASS_CASE(HB)                                                                          \
+  if (hb == HB) {                                                                              \
+    if (xaxis && !inverse)                                                                     \
+      hipLaunchKernelGGL((k_dst_pass<T, HB, true, false>), dim3(grid), dim3(256), 0, s, in, out, \
+                         Sfrag, n, inner, ncols, omega, mode);                                 \
+    else if (xaxis && inverse)                                                                 \
+      hipLaunchKernelGGL((k_dst_pass<T, HB, true, true>), dim3(grid), dim3(256), 0, s, in, out,  \
+                         Sfrag, n, inner, ncols, omega, mode);                                 \
+    else if (!inverse)                                                                         \
+      hipLaunchKernelGGL((k_dst_pass<T, HB, false, false>), dim3(grid), dim3(256), 0, s, in,     \
+                         out, Sfrag, n, inner, ncols, omega, mode);                            \
+    else                                                                                       \
+      hipLaunchKernelGGL((k_dst_pass<T, HB, false, true>), dim3(grid), dim3(256), 0, s, in, out, \
+                         Sfrag, n, inner, ncols, omega, mode);                                 \
+    return hipGetLastError();                                                                  \
+  }
+  PASS_CASE(1) PASS_CASE(2) PASS_CASE(4) PASS_CASE(8)
+#undef PASS_CASE
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t launch_dst_fused(int impl, int hb, int nt, const T* in, T* out, const T* Sfrag, const T* G, int n,
+                            long long inner, long long outer, int transpose, T omega, int mode,
+                            hipStream_t s) {
+  if (reg_path<T>(impl, hb, nt, true))
+    return launch_fused_reg(hb, nt, (const double*)in, (double*)out, (const double*)Sfrag,
+                            (const double*)G, n, inner, outer, transpose, (double)omega, mode, s);
+  const long long ct = TILE_COLS / nt;
+  const unsigned grid = (unsigned)((outer * inner + ct - 1) / ct);
+#define FUSED_CASE(HB, NT)                                                                      \
+  if (hb == HB && nt == NT) {                                                                   \
+    hipLaunchKernelGGL((k_dst_fused<T, HB, NT>), dim3(grid), dim3(256), 0, s, in, out, Sfrag, G, \
+                       n, inner, outer, transpose, omega, mode);                                \
+    return hipGetLastError();                                                                   \
+  }
+  FUSED_CASE(1, 1) FUSED_CASE(1, 2) FUSED_CASE(1, 3) FUSED_CASE(1, 4)
+  FUSED_CASE(2, 1) FUSED_CASE(2, 2) FUSED_CASE(2, 3) FUSED_CASE(2, 4)
+  FUSED_CASE(4, 1) FUSED_CASE(4, 2) FUSED_CASE(4, 3) FUSED_CASE(4, 4)
+  FUSED_CASE(8, 1) FUSED_CASE(8, 2) FUSED_CASE(8, 3) FUSED_CASE(8, 4)
+#undef FUSED_CASE
+  return hipErrorInvalidValue;
+}
+
+template hipError_t launch_dst_pass<double>(int, int, bool, bool, const double*, double*, const double*,
+                                            int, long long, long long, double, int, hipStream_t);
+template hipError_t launch_dst_pass<float>(int, int, bool, bool, const float*, float*, const float*, int,
+                                           long long, long long, float, int, hipStream_t);
+template hipError_t launch_dst_fused<double>(int, int, int, const double*, double*, const double*,
+                                             const double*, int, long long, long long, int, double,
+                                             int, hipStream_t);
+template hipError_t launch_dst_fused<float>(int, int, int, const float*, float*, const float*, const float*,
+                                            int, long long, long long, int, float, int, hipStream_t);
+
+}  // namespace stmg

@@ -65,8 +65,8 @@ SIGNATURES = {
     "st_mg_profile_read": (_i, [_vp, _i, _i, _dp, _ip]),
 }
 
-PROF_KINDS = {"residual": 0, "dst_x": 1, "dst_y": 2, "dst_z": 3, "tsolve": 4, "restrict": 5,
-              "prolong": 6, "other": 7}
+PROF_KINDS = {"residual": 0, "pass_fwd": 1, "pass_inv": 2, "fused": 3, "restrict": 4, "prolong": 5,
+              "other": 6}
 
 
 def lib():

@@ -1,0 +1,158 @@
+"""Full-size workloads in the configuration the benchmark runs: sampled slabs
+checked element by element against the oracle's per-slab formulas (the
+oracle cannot assemble the whole system at these sizes), plus properties
+that hold at any size (convergence to 1e-10, residual of sampled slabs)."""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+import torch
+
+from gpu_util import DEV, nodal_to_gpu
+from oracle import spacetime
+from paper_1411_0519_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+stmg = pytest.importorskip("paper_1411_0519_amd.stmg")
+
+
+class SlabOracle:
+    """Per-slab pieces of the oracle for one (d, n, p_t, tau): A, B = -N (x) M_h."""
+
+    def __init__(self, d, n, N, pt, T=1.0):
+        self.lev = spacetime.SpaceTimeLevel(d, n, 1, pt, T / N)
+        self.N = N
+        self.slab = self.lev.slab
+        self.A = self.lev.A.tocsr()
+        self.B = self.lev.B.tocsr()
+
+    def residual(self, F_n, u_n, u_nb, transpose=False):
+        """Slab residual; u_nb is the neighbour slab (previous, or next for L^T), or None."""
+        A = self.A.T if transpose else self.A
+        B = self.B.T if transpose else self.B
+        r = F_n - A @ u_n
+        if u_nb is not None:
+            r = r - B @ u_nb
+        return r
+
+
+def slab(t, b_i, n_i, S):
+    sz = S.nt * (S.n ** S.dim)
+    off = (b_i * S.N + n_i) * sz
+    return t[off:off + sz].detach().to("cpu", torch.float64).numpy()
+
+
+def test_w2_operators_full_size():
+    w = workloads.WORKLOADS[2]
+    d, n, N, pt = w["dim"], w["n"], w["N"], w["pt"]
+    print("W2 operators full size", flush=True)
+    S = stmg.Solver(d, n, N, pt=pt, device=DEV)
+    O = SlabOracle(d, n, N, pt)
+    g = torch.Generator(device=DEV).manual_seed(7)
+    u = torch.rand(S.level_dof(0), dtype=torch.float64, device=DEV, generator=g) * 2 - 1
+    F = torch.rand(S.level_dof(0), dtype=torch.float64, device=DEV, generator=g) * 2 - 1
+    r = S.residual(u, F)
+    x = S.block_solve(F)
+    torch.cuda.synchronize()
+    lu = spla.splu(O.A.tocsc())
+    for k in (0, 1, 127, N - 1):
+        ref = O.residual(slab(F, 0, k, S), slab(u, 0, k, S), slab(u, 0, k - 1, S) if k > 0 else None)
+        got = slab(r, 0, k, S)
+        assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max(), k
+        xr = lu.solve(slab(F, 0, k, S))
+        assert np.abs(slab(x, 0, k, S) - xr).max() <= 1e-12 * np.abs(xr).max(), k
+
+
+def test_w2_solve_full_size():
+    w, f, u0 = workloads.workload(2)
+    d, n, N, pt = w["dim"], w["n"], w["N"], w["pt"]
+    print("W2 solve full size", flush=True)
+    stream = torch.cuda.Stream(device=DEV)
+    with torch.cuda.stream(stream):
+        S = stmg.Solver(d, n, N, pt=pt, device=DEV)
+        S.set_graph(True)
+        F = S.rhs(nodal_to_gpu(f), nodal_to_gpu(u0))
+        u, its, hist = S.solve(F, rtol=1e-10, maxit=30)
+        torch.cuda.synchronize()
+    assert S.schedule == "ffffffss"
+    assert hist[-1][0] <= 1e-10 and its <= 12
+    rates = [hist[k + 1][0] / hist[k][0] for k in range(its)]
+    assert max(rates[1:]) < 0.15          # LFA two-grid factor at mu = 64, nu = 2 is 0.115
+    O = SlabOracle(d, n, N, pt)
+    nF = torch.linalg.vector_norm(F).item()
+    for k in (0, 5, 128, N - 1):
+        r = O.residual(slab(F, 0, k, S), slab(u, 0, k, S), slab(u, 0, k - 1, S) if k > 0 else None)
+        assert np.linalg.norm(r) <= 1e-10 * nF, k
+
+
+def test_w3_mixed_full_size():
+    w = workloads.WORKLOADS[3]
+    d, n, N, pt = w["dim"], w["n"], w["N"], w["pt"]
+    print("W3 mixed precision full size", flush=True)
+    _, f, u0 = workloads.workload(3)
+    M = stmg.Solver(d, n, N, pt=pt, precision="mixed", device=DEV)
+    assert M.schedule == "ffffsfssss"
+    F = M.rhs(nodal_to_gpu(f), nodal_to_gpu(u0))
+    del f
+    u, its, hist = M.solve(F, rtol=1e-10, maxit=30)
+    torch.cuda.synchronize()
+    assert hist[-1][0] <= 1e-10
+    O = SlabOracle(d, n, N, pt)
+    nF = torch.linalg.vector_norm(F).item()
+    for k in (0, 511, N - 1):
+        r = O.residual(slab(F, 0, k, M), slab(u, 0, k, M), slab(u, 0, k - 1, M) if k > 0 else None)
+        assert np.linalg.norm(r) <= 1e-10 * nF, k
+
+
+def test_w5_adjoint_full_size():
+    w, f, u0 = workloads.workload(5)
+    d, n, N, pt = w["dim"], w["n"], w["N"], w["pt"]
+    print("W5 adjoint full size", flush=True)
+    S = stmg.Solver(d, n, N, pt=pt, device=DEV)
+    F = S.rhs(nodal_to_gpu(f), nodal_to_gpu(u0))
+    u, its, hist = S.solve(F, rtol=1e-10, maxit=30)
+    ud = torch.zeros_like(u).view(N, pt + 1, -1)
+    ud[:, 0, :] = torch.from_numpy(workloads.target_state(d, n, w["target_seed"])).to(DEV)
+    g = (u - ud.view(-1)).contiguous()
+    lam, gf, gu0, its_a, hist_a = S.adjoint(g, rtol=1e-10, maxit=30)
+    torch.cuda.synchronize()
+    assert hist_a[-1][0] <= 1e-10
+    O = SlabOracle(d, n, N, pt)
+    ng = torch.linalg.vector_norm(g).item()
+    for k in (0, 700, N - 1):
+        r = O.residual(slab(g, 0, k, S), slab(lam, 0, k, S), slab(lam, 0, k + 1, S) if k < N - 1 else None,
+                       transpose=True)
+        assert np.linalg.norm(r) <= 1e-10 * ng, k
+    # gradient w.r.t. u0 equals M_h sum_l psi_l(t_0^+) lam_{1,l} (transposed load map) on the oracle
+    lev = O.lev
+    lam0 = slab(lam, 0, 0, S).reshape(pt + 1, -1)
+    ref = lev.Mh @ (lam0[0] - lam0[1])
+    assert np.abs(gu0.cpu().numpy() - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_w4_batched_fp32_full_size():
+    w = workloads.WORKLOADS[4]
+    d, n, N, pt, b = w["dim"], w["n"], w["N"], w["pt"], w["batch"]
+    print("W4 batched FP32 full size", flush=True)
+    S = stmg.Solver(d, n, N, pt=pt, batch=b, precision="fp32", device=DEV)
+    assert S.schedule == "fffffffss"
+    nx = n ** d
+    fg = torch.empty(b * N * nx, dtype=torch.float32, device=DEV)
+    rng = np.random.default_rng(w["seed"])
+    for i in range(b):      # same draw order as workloads.make, one right-hand side at a time
+        fg[i * N * nx:(i + 1) * N * nx] = torch.from_numpy(rng.uniform(-1, 1, N * nx).astype(np.float32)).to(DEV)
+    u0 = np.stack([workloads.sine_series(d, n, rng) for _ in range(b)]).astype(np.float32)
+    F = S.rhs(fg, nodal_to_gpu(u0, torch.float32))
+    del fg
+    stream = torch.cuda.Stream(device=DEV)
+    with torch.cuda.stream(stream):
+        S.set_graph(True)
+        u, its, hist = S.solve(F, rtol=1e-5, maxit=20)
+        torch.cuda.synchronize()
+    assert max(hist[-1]) <= 1e-5 and its <= 10
+    O = SlabOracle(d, n, N, pt)
+    for (bi, k) in ((0, 0), (31, 200), (b - 1, N - 1)):
+        Fk = slab(F, bi, k, S)
+        r = O.residual(Fk, slab(u, bi, k, S), slab(u, bi, k - 1, S) if k > 0 else None)
+        nFb = torch.linalg.vector_norm(F[bi * S.level_dof(0) // b:(bi + 1) * S.level_dof(0) // b].double()).item()
+        assert np.linalg.norm(r) <= 2e-5 * nFb, (bi, k)

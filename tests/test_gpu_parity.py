@@ -60,9 +60,11 @@ def test_residual_parity(case, transpose):
 
 @pytest.mark.parametrize("case", OPERATOR_CASES, ids=case_id)
 @pytest.mark.parametrize("transpose", [False, True])
-def test_block_solve_parity(case, transpose):
+@pytest.mark.parametrize("impl", ["0", "1", "2"], ids=["auto", "lds", "reg"])
+def test_block_solve_parity(case, transpose, impl, monkeypatch):
     d, n, N, pt, b = case
-    print(f"block solve {case} transpose={transpose}", flush=True)
+    print(f"block solve {case} transpose={transpose} impl={impl}", flush=True)
+    monkeypatch.setenv("STMG_TRANSFORM", impl)      # read at setup: transform kernel family
     S = make_solver(d, n, N, pt, b)
     H = multigrid.Hierarchy(d, n, N, pt, transpose=transpose)
     k = len(H.levels) - 1
