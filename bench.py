@@ -130,7 +130,7 @@ def main():
         S.profile_start()
         S.solve(F, u=u2, rtol=0.0, maxit=args.steps, raise_on_noconv=False)
         torch.cuda.synchronize()
-        kinds = ["residual", "pass_fwd", "pass_inv", "fused", "restrict", "prolong", "other"]
+        kinds = ["residual", "pass_fwd", "pass_inv", "fused", "small", "restrict", "prolong", "other"]
         prof = {}
         for k in kinds:
             tot, cnt = S.profile_read(k, level=-1)

@@ -172,8 +172,9 @@ enum {
   ST_PROF_PASS_FWD = 1,   /* forward sine-transform pass along x (and y in 3-D)   */
   ST_PROF_PASS_INV = 2,   /* inverse pass (the last one applies the update)       */
   ST_PROF_FUSED = 3,      /* forward + per-mode time solve + inverse, slowest axis */
-  ST_PROF_RESTRICT = 4, ST_PROF_PROLONG = 5, ST_PROF_OTHER = 6,
-  ST_PROF_KINDS = 7
+  ST_PROF_SMALL = 4,      /* whole smoothing step of a small level, one kernel     */
+  ST_PROF_RESTRICT = 5, ST_PROF_PROLONG = 6, ST_PROF_OTHER = 7,
+  ST_PROF_KINDS = 8
 };
 int st_mg_profile_start(st_mg_t h);
 int st_mg_profile_stop(st_mg_t h);

@@ -65,8 +65,8 @@ SIGNATURES = {
     "st_mg_profile_read": (_i, [_vp, _i, _i, _dp, _ip]),
 }
 
-PROF_KINDS = {"residual": 0, "pass_fwd": 1, "pass_inv": 2, "fused": 3, "restrict": 4, "prolong": 5,
-              "other": 6}
+PROF_KINDS = {"residual": 0, "pass_fwd": 1, "pass_inv": 2, "fused": 3, "small": 4, "restrict": 5,
+              "prolong": 6, "other": 7}
 
 
 def lib():
