@@ -38,6 +38,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="launch kernels eagerly instead of replaying a hipGraph")
     ap.add_argument("--only-timed", action="store_true", help="timed V-cycles only (for profiler runs)")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default kernel families")
     return ap.parse_args()
 
 
@@ -98,6 +99,7 @@ def main():
         F = S.rhs(fg, ug0)
         dof = S.level_dof(0)
         u = torch.zeros(dof, dtype=torch.float64, device=dev)
+        tuning = None if args.no_autotune else S.autotune()
         if not args.no_graph:
             S.set_graph(True)
         # warmup (also records the graph)
@@ -142,6 +144,7 @@ def main():
 
         # mixed precision: FP32 inner V-cycle, FP64 refinement
         M = stmg.Solver(d, n, N, pt=pt, batch=b, device=dev, precision="mixed")
+        tuning_mixed = None if args.no_autotune else M.autotune()
         if not args.no_graph:
             M.set_graph(True)
         um = torch.zeros_like(u)
@@ -194,7 +197,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{w['name']}: {d}-D Q1 {n}^{d} interior, N={N} slabs, DG p_t={pt}, "
                                f"batch {b}, FP64, omega=1/2, nu1=nu2=2, schedule {S.schedule}",
-                   "dof": dof, "levels": S.nlev, "graph": not args.no_graph},
+                   "dof": dof, "levels": S.nlev, "graph": not args.no_graph,
+                   "autotuned_levels": None if tuning is None else [
+                       {"level": k, "n": S.levels[k]["n"], "N": S.levels[k]["N"], "small_step": bool(t[0]),
+                        "transform": ["auto", "lds", "register"][t[1]], "step_ms": round(t[2], 4)}
+                       for k, t in enumerate(tuning[:-1])]},
         "time_to_1e-10": {"fp64_s": t64, "fp64_cycles": its64, "mixed_s": tm, "mixed_cycles": itsm,
                           "speedup_mixed_vs_fp64": t64 / tm,
                           "mixed_rel_error_vs_fp64": err_mixed,

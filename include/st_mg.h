@@ -162,6 +162,16 @@ int st_mg_adjoint(st_mg_t h, const void* g, void* lam, void* grad_f, void* grad_
  * needs a non-NULL stream. */
 int st_mg_set_graph(st_mg_t h, int enable);
 
+/* Autotuner: per level, time one smoothing step with every applicable kernel
+ * family (one-kernel small-level step with the slab in LDS; LDS-staged
+ * transforms; FP64 register-resident transforms) and keep the fastest.
+ * u_scratch, F_scratch: two fine-level device vectors of the handle's vector
+ * type whose contents are overwritten (may be NULL for ST_MIXED).  Needs a
+ * bound workspace; synchronises the stream. */
+int st_mg_autotune(st_mg_t h, void* u_scratch, void* F_scratch, void* stream);
+/* Choice for one level: small (1/0), transform family (0 auto, 1 LDS, 2 register), tuned step ms. */
+int st_mg_level_tuning(st_mg_t h, int level, int* small, int* impl, float* ms);
+
 /* Per-kernel timing with HIP events recorded around every launch on the
  * launch stream (eager mode only; ST_ESTATE in graph mode).  start clears
  * previous records; read synchronises on the last event and returns the

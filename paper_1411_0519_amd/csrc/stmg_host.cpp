@@ -99,7 +99,13 @@ struct Level {
   float* S32 = nullptr;
   double* G64 = nullptr;  // per-mode inverse blocks [nx][nt][nt]
   float* G32 = nullptr;
+  double* Sp64 = nullptr; // plain DST-I (n x n), used by the small-level smoother
+  float* Sp32 = nullptr;
+  int impl = -1;          // transform family chosen for this level (-1: handle default)
+  int small = -1;         // small-level smoother on (1) / off (0) for this level (-1: handle default)
+  float tuned_ms = 0.f;   // autotuned smoothing-step time
   void* u = nullptr;      // workspace vectors (inner precision), coarse levels only
+  void* u2 = nullptr;     // second iterate buffer for the small-level smoother
   void* F = nullptr;
   void* r = nullptr;
   long long dof(int nt, int b) const { return (long long)b * N * nt * nx; }
@@ -141,6 +147,7 @@ struct st_mg {
   double* norm_dev = nullptr;
   int graph = 0;
   int impl = TRANSFORM_AUTO;
+  bool small = true;      // one-kernel smoothing steps on levels whose slabs fit in LDS
   GraphCache gc;
   // per-launch event pairs while profiling is on
   bool prof = false;
@@ -345,6 +352,17 @@ int build_level_tables(st_mg* h, Level& L) {
       G32[(size_t)j * nt * nt + i] = (float)blk[i];
     }
   }
+  std::vector<double> Sp((size_t)n * n);
+  std::vector<float> Sp32((size_t)n * n);
+  for (int k = 0; k < n; ++k)
+    for (int i = 0; i < n; ++i) {
+      Sp[(size_t)k * n + i] = sc * std::sin(PI * (k + 1.0) * (i + 1.0) / (n + 1));
+      Sp32[(size_t)k * n + i] = (float)Sp[(size_t)k * n + i];
+    }
+  HIPCHK(h, hipMalloc(&L.Sp64, Sp.size() * sizeof(double)));
+  HIPCHK(h, hipMalloc(&L.Sp32, Sp32.size() * sizeof(float)));
+  HIPCHK(h, hipMemcpy(L.Sp64, Sp.data(), Sp.size() * sizeof(double), hipMemcpyHostToDevice));
+  HIPCHK(h, hipMemcpy(L.Sp32, Sp32.data(), Sp32.size() * sizeof(float), hipMemcpyHostToDevice));
   HIPCHK(h, hipMalloc(&L.S64, frag.size() * sizeof(double)));
   HIPCHK(h, hipMalloc(&L.S32, frag32.size() * sizeof(float)));
   HIPCHK(h, hipMalloc(&L.G64, G.size() * sizeof(double)));
@@ -360,6 +378,9 @@ int build_level_tables(st_mg* h, Level& L) {
 template <typename T> const T* Sof(const Level& L);
 template <> const double* Sof<double>(const Level& L) { return L.S64; }
 template <> const float* Sof<float>(const Level& L) { return L.S32; }
+template <typename T> const T* SPof(const Level& L);
+template <> const double* SPof<double>(const Level& L) { return L.Sp64; }
+template <> const float* SPof<float>(const Level& L) { return L.Sp32; }
 template <typename T> const T* Gof(const Level& L);
 template <> const double* Gof<double>(const Level& L) { return L.G64; }
 template <> const float* Gof<float>(const Level& L) { return L.G32; }
@@ -460,14 +481,14 @@ int op_block_solve(st_mg* h, int l, bool transpose, const T* src, T* dst, int mo
     for (int i = axis + 1; i < d; ++i) rest *= nn;
     const long long ncols = slabs * nt * rest * inner;
     ProfScope ps(h, inv ? ST_PROF_PASS_INV : ST_PROF_PASS_FWD, l, s);
-    HIPCHK(h, launch_dst_pass<T>(h->impl, L.hb, axis == 0, inv, in, out, Sof<T>(L), n, inner, ncols, om, md, s));
+    HIPCHK(h, launch_dst_pass<T>(L.impl >= 0 ? L.impl : h->impl, L.hb, axis == 0, inv, in, out, Sof<T>(L), n, inner, ncols, om, md, s));
     return ST_OK;
   };
   auto fused = [&](const T* in, T* out, int md, T om) -> int {
     long long inner = 1;
     for (int i = 0; i < d - 1; ++i) inner *= nn;
     ProfScope ps(h, ST_PROF_FUSED, l, s);
-    HIPCHK(h, launch_dst_fused<T>(h->impl, L.hb, nt, in, out, Sof<T>(L), Gof<T>(L), n, inner, slabs,
+    HIPCHK(h, launch_dst_fused<T>(L.impl >= 0 ? L.impl : h->impl, L.hb, nt, in, out, Sof<T>(L), Gof<T>(L), n, inner, slabs,
                                   transpose ? 1 : 0, om, md, s));
     return ST_OK;
   };
@@ -497,6 +518,29 @@ int op_prolong(st_mg* h, int l, const T* ec, T* uf, hipStream_t s) {
   const TransferArgs<T> a = transfer_args<T>(h, l);
   ProfScope ps(h, ST_PROF_PROLONG, l, s);
   HIPCHK(h, launch_prolong<T>(h->p.dim, h->nt, h->lv[l].kind == 'f', ec, uf, a, s));
+  return ST_OK;
+}
+
+// One damped block-Jacobi step of a small level in one kernel: u_out = u_in +
+// omega D^{-1}(F - L u_in), u_in treated as zero when u_zero.
+template <typename T>
+bool small_level(const st_mg* h, int l) {
+  const Level& L = h->lv[l];
+  const bool on = L.small >= 0 ? L.small != 0 : h->small;
+  return on && smooth_small_lds(h->p.dim, L.n, L.nx, h->nt, sizeof(T)) > 0;
+}
+
+template <typename T>
+int op_smooth_small(st_mg* h, int l, bool transpose, const T* u_in, T* u_out, const T* F, bool u_zero,
+                    hipStream_t s) {
+  const Level& L = h->lv[l];
+  SmallArgs<T> a{};
+  a.r = resid_args<T>(h, L, transpose);
+  a.omega = (T)h->p.omega;
+  a.transpose = transpose ? 1 : 0;
+  a.u_zero = u_zero ? 1 : 0;
+  ProfScope ps(h, ST_PROF_SMALL, l, s);
+  HIPCHK(h, launch_smooth_small<T>(h->p.dim, h->nt, u_zero ? F : u_in, u_out, F, SPof<T>(L), Gof<T>(L), a, s));
   return ST_OK;
 }
 
@@ -530,6 +574,46 @@ int coarsest_solve<float>(st_mg* h, bool transpose, float* u, const float* F, hi
                                level_r<float>(h, l), s);
 }
 
+template <typename T>
+int vcycle(st_mg* h, int l, bool transpose, T* u, const T* F, bool u_zero, bool r_ready, hipStream_t s);
+
+// V-cycle on a small level: each smoothing step is one kernel that reads one
+// iterate buffer and writes the other (level 0 borrows the transform buffer);
+// the result is copied back when the step count leaves it in the other buffer.
+template <typename T>
+int vcycle_small(st_mg* h, int l, bool transpose, T* u, const T* F, bool u_zero, hipStream_t s) {
+  const long long len = h->lv[l].dof(h->nt, h->p.batch);
+  T* buf[2] = {u, l == 0 ? (T*)h->tmp : (T*)h->lv[l].u2};
+  int cur = 0;
+  for (int i = 0; i < h->p.nu1; ++i) {
+    CHK(op_smooth_small<T>(h, l, transpose, buf[cur], buf[1 - cur], F, u_zero && i == 0, s));
+    cur ^= 1;
+  }
+  if (cur) {
+    HIPCHK(h, launch_copy<T>(buf[1], u, len, s));
+    cur = 0;
+  }
+  const Level& C = h->lv[l + 1];
+  T* uc = (T*)C.u;
+  T* Fc = (T*)C.F;
+  T* r = level_r<T>(h, l);
+  if (h->p.nu1 == 0 && u_zero) {
+    CHK(op_restrict<T>(h, l, F, Fc, s));
+    HIPCHK(h, launch_fill<T>(u, len, s));
+  } else {
+    CHK((op_residual<T, T>(h, l, transpose, u, F, r, false, s)));
+    CHK(op_restrict<T>(h, l, r, Fc, s));
+  }
+  CHK(vcycle<T>(h, l + 1, transpose, uc, Fc, true, false, s));
+  CHK(op_prolong<T>(h, l, uc, u, s));
+  for (int i = 0; i < h->p.nu2; ++i) {
+    CHK(op_smooth_small<T>(h, l, transpose, buf[cur], buf[1 - cur], F, false, s));
+    cur ^= 1;
+  }
+  if (cur) HIPCHK(h, launch_copy<T>(buf[1], u, len, s));
+  return ST_OK;
+}
+
 // One V-cycle on level l.  u_zero: u holds no valid data and is treated as 0
 // (coarse-level corrections).  r_ready: level_r already holds F - L u.
 template <typename T>
@@ -540,6 +624,7 @@ int vcycle(st_mg* h, int l, bool transpose, T* u, const T* F, bool u_zero, bool 
   const T om = (T)h->p.omega;
   T* r = level_r<T>(h, l);
   T* A = (T*)h->tmp;
+  if (small_level<T>(h, l)) return vcycle_small<T>(h, l, transpose, u, F, u_zero, s);
   for (int i = 0; i < h->p.nu1; ++i) {
     if (i == 0 && u_zero) {
       CHK(op_block_solve<T>(h, l, transpose, F, u, MODE_SET_SCALED, om, A, r, s));
@@ -701,6 +786,7 @@ size_t layout(st_mg* h, char* base) {
     Level& L = h->lv[l];
     const long long len = L.dof(nt, b);
     L.u = take(len * ib);
+    L.u2 = take(len * ib);
     L.F = take(len * ib);
     L.r = take(len * ib);
   }
@@ -730,6 +816,82 @@ int check_level(st_mg* h, int level, int prec, bool need_next) {
     return fail(h, ST_EINVAL, "FP64 level operators need a handle set up with ST_FP64");
   if (prec == ST_FP32 && h->p.precision == ST_FP64)
     return fail(h, ST_EINVAL, "FP32 level operators need a handle set up with ST_FP32 or ST_MIXED");
+  return ST_OK;
+}
+
+// ------------------------------------------------------------------ autotune
+// Time one smoothing step of level l (residual + block solve + update, or the
+// one-kernel small-level step) for every applicable kernel family and keep the
+// fastest.  u, F, r, alt are level-sized scratch buffers; contents are destroyed.
+template <typename T>
+int tune_level(st_mg* h, int l, T* u, T* F, T* r, T* alt, hipStream_t s) {
+  Level& L = h->lv[l];
+  const long long len = L.dof(h->nt, h->p.batch);
+  HIPCHK(h, launch_fill<T>(u, len, s));
+  HIPCHK(h, launch_fill<T>(F, len, s));
+  struct Cand { int small, impl; };
+  std::vector<Cand> cands;
+  const bool can_small = smooth_small_lds(h->p.dim, L.n, L.nx, h->nt, sizeof(T)) > 0;
+  if (can_small) cands.push_back({1, TRANSFORM_AUTO});
+  cands.push_back({0, TRANSFORM_LDS});
+  if (sizeof(T) == 8 && L.hb <= 4) {
+    cands.push_back({0, TRANSFORM_AUTO});
+    cands.push_back({0, TRANSFORM_REG});
+  }
+  hipEvent_t e0, e1;
+  HIPCHK(h, hipEventCreate(&e0));
+  HIPCHK(h, hipEventCreate(&e1));
+  float best = 1e30f;
+  Cand pick = cands.front();
+  const bool prof = h->prof;
+  h->prof = false;
+  for (const Cand& c : cands) {
+    L.small = c.small;
+    L.impl = c.impl;
+    auto step = [&]() -> int {
+      if (c.small) return op_smooth_small<T>(h, l, false, u, alt, F, false, s);
+      CHK((op_residual<T, T>(h, l, false, u, F, r, false, s)));
+      return op_block_solve<T>(h, l, false, r, u, MODE_ADD_SCALED, (T)h->p.omega, (T*)h->tmp, r, s);
+    };
+    int rc = step();
+    float ms = 1e30f;
+    for (int rep = 0; rep < 3 && rc == ST_OK; ++rep) {
+      (void)hipEventRecord(e0, s);
+      rc = step();
+      (void)hipEventRecord(e1, s);
+      (void)hipEventSynchronize(e1);
+      float t = 0.f;
+      (void)hipEventElapsedTime(&t, e0, e1);
+      ms = std::min(ms, t);
+    }
+    if (rc == ST_OK && ms < best) {
+      best = ms;
+      pick = c;
+    }
+  }
+  h->prof = prof;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  L.small = pick.small;
+  L.impl = pick.impl;
+  L.tuned_ms = best;
+  return ST_OK;
+}
+
+template <typename T>
+int autotune_all(st_mg* h, void* u0, void* F0, hipStream_t s) {
+  const int last = (int)h->lv.size() - 1;
+  for (int l = 0; l < last; ++l) {
+    Level& L = h->lv[l];
+    if (l == 0) {
+      T* alt = (T*)h->tmp;
+      // level 0: caller scratch for u and F; the transform buffer doubles as the
+      // second iterate of the small-level step only when the regular path is not timed
+      CHK(tune_level<T>(h, 0, (T*)u0, (T*)F0, (T*)h->r0, alt, s));
+    } else {
+      CHK(tune_level<T>(h, l, (T*)L.u, (T*)L.F, (T*)L.r, (T*)L.u2, s));
+    }
+  }
   return ST_OK;
 }
 
@@ -782,6 +944,8 @@ int st_mg_setup(const st_mg_params* p, st_mg_t* out) {
   }
   h->nt = p->pt + 1;
   // tuning knob: STMG_TRANSFORM=1 forces the LDS-staged transforms, =2 the register ones
+  // tuning knob: STMG_SMALL=0 turns the one-kernel small-level smoother off
+  if (const char* sm = std::getenv("STMG_SMALL")) h->small = std::atoi(sm) != 0;
   if (const char* ti = std::getenv("STMG_TRANSFORM")) {
     const int v = std::atoi(ti);
     h->impl = (v >= TRANSFORM_AUTO && v <= TRANSFORM_REG) ? v : TRANSFORM_AUTO;
@@ -839,6 +1003,8 @@ int st_mg_destroy(st_mg_t h) {
     (void)hipFree(L.S32);
     (void)hipFree(L.G64);
     (void)hipFree(L.G32);
+    (void)hipFree(L.Sp64);
+    (void)hipFree(L.Sp32);
   }
   if (h->ws_owned && h->ws) (void)hipFree(h->ws);
   for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
@@ -1048,6 +1214,32 @@ int st_mg_adjoint(st_mg_t h, const void* g, void* lam, void* grad_f, void* grad_
   if (rc != ST_OK && rc != ST_ENOCONV) return rc;
   const int rc2 = st_mg_rhs_adjoint(h, lam, grad_f, grad_u0, stream);
   return rc2 != ST_OK ? rc2 : rc;
+}
+
+int st_mg_autotune(st_mg_t h, void* u_scratch, void* F_scratch, void* stream) {
+  CHK(check_ready(h));
+  if (h->p.precision == ST_FP64 && (!u_scratch || !F_scratch))
+    return fail(h, ST_EINVAL, "FP64 autotuning needs two fine-level scratch vectors");
+  hipStream_t s = (hipStream_t)stream;
+  if (h->gc.exec) {
+    (void)hipGraphExecDestroy(h->gc.exec);
+    h->gc.exec = nullptr;
+  }
+  if (h->p.precision == ST_FP64) return autotune_all<double>(h, u_scratch, F_scratch, s);
+  // float paths: level 0 of the inner cycle lives in workspace buffers
+  void* u0 = h->p.precision == ST_MIXED ? h->e32 : u_scratch;
+  void* F0 = h->p.precision == ST_MIXED ? h->F32 : F_scratch;
+  if (!u0 || !F0) return fail(h, ST_EINVAL, "FP32 autotuning needs two fine-level scratch vectors");
+  return autotune_all<float>(h, u0, F0, s);
+}
+
+int st_mg_level_tuning(st_mg_t h, int level, int* small, int* impl, float* ms) {
+  if (!h || level < 0 || level >= (int)h->lv.size()) return ST_EINVAL;
+  const Level& L = h->lv[level];
+  if (small) *small = L.small >= 0 ? L.small : (h->small ? 1 : 0);
+  if (impl) *impl = L.impl >= 0 ? L.impl : h->impl;
+  if (ms) *ms = L.tuned_ms;
+  return ST_OK;
 }
 
 int st_mg_set_graph(st_mg_t h, int enable) {

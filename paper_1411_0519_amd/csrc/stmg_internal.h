@@ -98,3 +98,24 @@ hipError_t launch_cast_f64_f32(const double* in, float* out, long long len, hipS
 hipError_t launch_cast_f32_f64(const float* in, double* out, long long len, hipStream_t s);
 
 }  // namespace stmg
+
+namespace stmg {
+
+// One damped block-Jacobi step on a small level, one workgroup per slab with
+// the slab resident in LDS (stmg_smooth_small.hip).
+template <typename T>
+struct SmallArgs {
+  ResidArgs<T> r;   // residual coefficients (direction included)
+  T omega;
+  int transpose;    // apply G^T in the per-mode solve
+  int u_zero;       // u_in is treated as zero (u_in may be null)
+};
+// LDS bytes the small-level kernel needs (0 if the level does not qualify).
+size_t smooth_small_lds(int dim, int n, long long nx, int nt, size_t elem);
+template <typename T>
+hipError_t launch_smooth_small(int dim, int nt, const T* u_in, T* u_out, const T* F, const T* Splain,
+                               const T* G, const SmallArgs<T>& a, hipStream_t s);
+template <typename T>
+hipError_t launch_copy(const T* in, T* out, long long len, hipStream_t s);
+
+}  // namespace stmg

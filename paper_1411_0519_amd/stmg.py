@@ -60,6 +60,8 @@ SIGNATURES = {
     "st_mg_solve": (_i, [_vp, _vp, _vp, _d, _i, _ip, _dp, _vp]),
     "st_mg_adjoint": (_i, [_vp, _vp, _vp, _vp, _vp, _d, _i, _ip, _dp, _vp]),
     "st_mg_set_graph": (_i, [_vp, _i]),
+    "st_mg_autotune": (_i, [_vp, _vp, _vp, _vp]),
+    "st_mg_level_tuning": (_i, [_vp, _i, _ip, _ip, ctypes.POINTER(ctypes.c_float)]),
     "st_mg_profile_start": (_i, [_vp]),
     "st_mg_profile_stop": (_i, [_vp]),
     "st_mg_profile_read": (_i, [_vp, _i, _i, _dp, _ip]),
@@ -317,6 +319,25 @@ class Solver:
 
     def set_graph(self, enable=True):
         self._check(lib().st_mg_set_graph(self._h, int(bool(enable))))
+
+    # ---------------------------------------------------------------- autotune
+    def autotune(self):
+        """Pick the fastest kernel family per level by timing smoothing steps.
+        Returns [(small, impl, ms) per level]."""
+        if self.precision == "mixed":
+            us = fs = None
+        else:
+            us, fs = self.empty(), self.empty()
+        self._check(lib().st_mg_autotune(self._h, _ptr(us), _ptr(fs), _stream(self.device)))
+        return self.tuning()
+
+    def tuning(self):
+        out = []
+        for k in range(self.nlev):
+            sm, im, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_float()
+            self._check(lib().st_mg_level_tuning(self._h, k, ctypes.byref(sm), ctypes.byref(im), ctypes.byref(ms)))
+            out.append((sm.value, im.value, ms.value))
+        return out
 
     # --------------------------------------------------------------- profiling
     def profile_start(self):

@@ -134,8 +134,11 @@ def test_rhs_parity(d, n, N, pt):
     assert rel_err(gu0.cpu().numpy().reshape(gu0_ref.shape), gu0_ref) < 1e-13
 
 
-def run_iterate_parity(d, n, N, pt, b, f_kind, u0_kind, seed, rule="auto", maxit=12, transpose=False):
+def run_iterate_parity(d, n, N, pt, b, f_kind, u0_kind, seed, rule="auto", maxit=12, transpose=False,
+                       autotune=False):
     S = make_solver(d, n, N, pt, b, coarsen=rule)
+    if autotune:
+        S.autotune()
     H = multigrid.Hierarchy(d, n, N, pt, rule={"auto": 0, "semi": 1, "full": 2}[rule], transpose=transpose)
     assert S.schedule == H.schedule
     f, u0 = workloads.make(d, n, N, batch=b, seed=seed, f=f_kind, u0=u0_kind)
@@ -164,15 +167,26 @@ def run_iterate_parity(d, n, N, pt, b, f_kind, u0_kind, seed, rule="auto", maxit
     (2, 15, 16, 2, 3, "uniform", "series16", 4),  # W4 family, reduced, batched
     (1, 15, 64, 0, 1, "uniform", "sine1", 7),     # p_t = 0 with semi steps
 ], ids=lambda c: case_id(c[:5]))
-def test_vcycle_iterate_parity(case):
+@pytest.mark.parametrize("small", ["1", "0"], ids=["small-on", "small-off"])
+def test_vcycle_iterate_parity(case, small, monkeypatch):
     d, n, N, pt, b, fk, uk, seed = case
-    print(f"vcycle iterates {case}", flush=True)
+    print(f"vcycle iterates {case} small={small}", flush=True)
+    monkeypatch.setenv("STMG_SMALL", small)     # one-kernel smoothing on levels that fit in LDS
     worst, its = run_iterate_parity(d, n, N, pt, b, fk, uk, seed)
     assert its >= 5
 
 
-def test_adjoint_iterate_parity():
-    print("adjoint iterates", flush=True)
+@pytest.mark.parametrize("case", [(2, 63, 64, 1, 1), (3, 15, 16, 2, 1), (1, 255, 32, 1, 2)], ids=case_id)
+def test_autotuned_iterate_parity(case):
+    d, n, N, pt, b = case
+    print(f"autotuned iterates {case}", flush=True)
+    run_iterate_parity(d, n, N, pt, b, "uniform", "sine1", 13, autotune=True)
+
+
+@pytest.mark.parametrize("small", ["1", "0"], ids=["small-on", "small-off"])
+def test_adjoint_iterate_parity(small, monkeypatch):
+    print(f"adjoint iterates small={small}", flush=True)
+    monkeypatch.setenv("STMG_SMALL", small)
     run_iterate_parity(2, 31, 32, 1, 1, "uniform", "sine1", 5, transpose=True)
 
 
