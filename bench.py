@@ -170,8 +170,8 @@ def main():
     flops = transforms * 2.0 * L0["n"] * nvals
     hbm_bytes = (24 if dom == "pass_inv" else 16) * nvals
     achieved = flops / (avg_ms * 1e-3) / 1e12
-    names = {"pass_fwd": "forward x pass (k_pass_reg<4,false>)", "pass_inv": "inverse x pass + update (k_pass_reg<4,true>)",
-             "fused": "fused y pass: forward + time solve + inverse (k_dst_fused<double,4,2>)"}
+    names = {"pass_fwd": "forward x pass (k_pass_reg<double,4,false>)", "pass_inv": "inverse x pass + update (k_pass_reg<double,4,true>)",
+             "fused": "fused y pass: forward + time solve + inverse (k_fused_pair<double,4,2>: one wave per time component)"}
     roof = {"kernel": names[dom] + ", fine level", "bound": "mfma", "achieved": achieved,
             "peak": FP64_MFMA_PEAK_TFS, "unit": "TFLOP/s", "frac": achieved / FP64_MFMA_PEAK_TFS, "traffic": None,
             "avg_launch_ms": avg_ms, "launches": cand[dom]["fine_launches"], "flops_per_launch": flops,

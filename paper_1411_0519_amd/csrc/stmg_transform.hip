@@ -374,24 +374,26 @@ __global__ __launch_bounds__(256) void k_dst_fused(const T* in, T* out,
   }
 }
 
-// ------------------------------------------- FP64 register-resident kernels
+// ------------------------------------------------ register-resident kernels
 // Each wave owns 16 columns (lin = 16 * global_wave + lane % 16) and all rows of
-// the contracted axis; lane (g = lane / 16, r = lane % 16) holds rows g, g+4, ...
-// No LDS and no barriers: the v_mfma_f64_16x16x4f64 accumulator layout (row
-// g + 4j of a 16-row block in element j) is the B-operand layout of the next
-// product (row 4 ib + g with ib = 4 kb + j), so a forward product, the per-mode
-// solve and the inverse product chain in registers.  Element i of column lin
-// sits at o*n*inner*NT + l*n*inner + i*inner + pos with (o, pos) = divmod(lin, inner).
+// the contracted axis; lane (g = lane / 16, r = lane % 16) holds the B-operand
+// rows g, g+4, ... and the accumulator rows Mfma<T>::row(g, j) of every
+// 16-row block.  For FP64 the accumulator layout (row g + 4j) equals the
+// B-operand layout of the next product (row 4 ib + g with ib = 4 kb + j), so a
+// forward product, the per-mode solve and the inverse product chain in
+// registers; FP32 (row 4g + j) re-lays out each block through LDS.  Element i
+// of column lin sits at o*n*inner*NT + l*n*inner + i*inner + pos with
+// (o, pos) = divmod(lin, inner).
 
 // Forward operands of one column: a (odd half) and d (even half) per 4-row chunk.
-template <int HB>
-__device__ inline void load_folded(const double* __restrict__ src, bool valid, long long inner, int n,
-                                   int h, int g, double (&a)[4 * HB], double (&d)[4 * HB]) {
+template <typename T, int HB>
+__device__ inline void load_folded(const T* __restrict__ src, bool valid, long long inner, int n, int h,
+                                   int g, T (&a)[4 * HB], T (&d)[4 * HB]) {
 #pragma unroll
   for (int ib = 0; ib < 4 * HB; ++ib) {
     const int i = 4 * ib + g;
-    const double x1 = (valid && i < h) ? src[(long long)i * inner] : 0.0;
-    const double x2 = (valid && i < h - 1) ? src[(long long)(n - 1 - i) * inner] : 0.0;
+    const T x1 = (valid && i < h) ? src[(long long)i * inner] : T(0);
+    const T x2 = (valid && i < h - 1) ? src[(long long)(n - 1 - i) * inner] : T(0);
     a[ib] = x1 + x2;
     d[ib] = x1 - x2;
   }
@@ -401,15 +403,15 @@ __device__ inline void load_folded(const double* __restrict__ src, bool valid, l
 // The S fragments of chunk ib+1 are loaded while chunk ib multiplies; a
 // scheduling barrier per chunk stops the compiler from hoisting every fragment
 // load of the unrolled loop (which would exhaust the register file).
-template <int HB, int DIR, typename OpFn>
-__device__ inline void folded_mma_core(const double* __restrict__ Sfrag, int h, int lane, OpFn op,
-                                       v4d (&acc)[2 * HB]) {
+template <typename T, int HB, int DIR, typename OpFn>
+__device__ inline void folded_mma_core(const T* __restrict__ Sfrag, int h, int lane, OpFn op,
+                                       typename Mfma<T>::acc_t (&acc)[2 * HB]) {
 #pragma unroll
-  for (int k = 0; k < 2 * HB; ++k) acc[k] = v4d{0, 0, 0, 0};
+  for (int k = 0; k < 2 * HB; ++k) acc[k] = typename Mfma<T>::acc_t{0, 0, 0, 0};
   const int ibmax = (h + 3) >> 2;
-  const double* s0 = Sfrag + frag_block<HB>(DIR, 0) + lane;
-  const double* s1 = Sfrag + frag_block<HB>(DIR, 1) + lane;
-  double no[HB], ne[HB];
+  const T* s0 = Sfrag + frag_block<HB>(DIR, 0) + lane;
+  const T* s1 = Sfrag + frag_block<HB>(DIR, 1) + lane;
+  T no[HB], ne[HB];
 #pragma unroll
   for (int kb = 0; kb < HB; ++kb) {
     no[kb] = s0[(kb * 4 * HB) * 64];
@@ -418,7 +420,7 @@ __device__ inline void folded_mma_core(const double* __restrict__ Sfrag, int h, 
 #pragma unroll
   for (int ib = 0; ib < 4 * HB; ++ib) {
     if (ib < ibmax) {
-      double ao[HB], ae[HB];
+      T ao[HB], ae[HB];
 #pragma unroll
       for (int kb = 0; kb < HB; ++kb) {
         ao[kb] = no[kb];
@@ -431,64 +433,65 @@ __device__ inline void folded_mma_core(const double* __restrict__ Sfrag, int h, 
           ne[kb] = s1[(kb * 4 * HB + ib + 1) * 64];
         }
       }
-      const double bo = op(0, ib), be = op(1, ib);
+      const T bo = op(0, ib), be = op(1, ib);
 #pragma unroll
       for (int kb = 0; kb < HB; ++kb) {
-        acc[kb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ao[kb], bo, acc[kb], 0, 0, 0);
-        acc[HB + kb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ae[kb], be, acc[HB + kb], 0, 0, 0);
+        acc[kb] = Mfma<T>::op(ao[kb], bo, acc[kb]);
+        acc[HB + kb] = Mfma<T>::op(ae[kb], be, acc[HB + kb]);
       }
       __builtin_amdgcn_sched_barrier(0);
     }
   }
 }
 
-template <int HB, int DIR>
-__device__ inline void folded_mma(const double* __restrict__ Sfrag, int h, int lane,
-                                  const double (&bo)[4 * HB], const double (&be)[4 * HB],
-                                  v4d (&acc)[2 * HB]) {
-  folded_mma_core<HB, DIR>(Sfrag, h, lane, [&](int half, int ib) { return half ? be[ib] : bo[ib]; }, acc);
+template <typename T, int HB, int DIR>
+__device__ inline void folded_mma(const T* __restrict__ Sfrag, int h, int lane, const T (&bo)[4 * HB],
+                                  const T (&be)[4 * HB], typename Mfma<T>::acc_t (&acc)[2 * HB]) {
+  folded_mma_core<T, HB, DIR>(Sfrag, h, lane, [&](int half, int ib) { return half ? be[ib] : bo[ib]; }, acc);
 }
 
-// Inverse product whose B operands are the accumulators of a forward product:
-// chunk ib = 4 kb + j of the odd (even) half is element j of src[kb] (src[HB + kb]).
-template <int HB>
-__device__ inline void folded_mma_chain(const double* __restrict__ Sfrag, int h, int lane,
-                                        const v4d (&src)[2 * HB], v4d (&acc)[2 * HB]) {
-  folded_mma_core<HB, 1>(Sfrag, h, lane,
-                         [&](int half, int ib) { return src[half * HB + (ib >> 2)][ib & 3]; }, acc);
+// Inverse product whose B operands are held in B-operand order: chunk
+// ib = 4 kb + j of the odd (even) half is element j of src[kb] (src[HB + kb]).
+template <typename T, int HB>
+__device__ inline void folded_mma_chain(const T* __restrict__ Sfrag, int h, int lane,
+                                        const typename Mfma<T>::acc_t (&src)[2 * HB],
+                                        typename Mfma<T>::acc_t (&acc)[2 * HB]) {
+  folded_mma_core<T, HB, 1>(Sfrag, h, lane,
+                            [&](int half, int ib) { return src[half * HB + (ib >> 2)][ib & 3]; }, acc);
 }
 
 // Physical outputs of an inverse product: row i gets P_i + Q_i, row n-1-i gets
 // P_i - Q_i (i < h-1), row h-1 gets P_{h-1}; apply the epilogue in place.
-template <int HB>
-__device__ inline void store_unfolded(double* __restrict__ dst, bool valid, long long inner, int n, int h,
-                                      int g, const v4d (&acc)[2 * HB], int mode, double omega) {
+template <typename T, int HB>
+__device__ inline void store_unfolded(T* __restrict__ dst, bool valid, long long inner, int n, int h, int g,
+                                      const typename Mfma<T>::acc_t (&acc)[2 * HB], int mode, T omega) {
   if (!valid) return;
 #pragma unroll
   for (int kb = 0; kb < HB; ++kb)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int i = kb * 16 + g + 4 * j;
-      const double P = acc[kb][j], Q = acc[HB + kb][j];
+      const int i = kb * 16 + Mfma<T>::row(g, j);
+      const T P = acc[kb][j], Q = acc[HB + kb][j];
       if (i < h - 1) {
-        double* p0 = dst + (long long)i * inner;
-        double* p1 = dst + (long long)(n - 1 - i) * inner;
-        const double o0 = (mode == MODE_ADD_SCALED) ? *p0 : 0.0;
-        const double o1 = (mode == MODE_ADD_SCALED) ? *p1 : 0.0;
+        T* p0 = dst + (long long)i * inner;
+        T* p1 = dst + (long long)(n - 1 - i) * inner;
+        const T o0 = (mode == MODE_ADD_SCALED) ? *p0 : T(0);
+        const T o1 = (mode == MODE_ADD_SCALED) ? *p1 : T(0);
         *p0 = epilogue(mode, o0, P + Q, omega);
         *p1 = epilogue(mode, o1, P - Q, omega);
       } else if (i == h - 1) {
-        double* p0 = dst + (long long)i * inner;
-        const double o0 = (mode == MODE_ADD_SCALED) ? *p0 : 0.0;
+        T* p0 = dst + (long long)i * inner;
+        const T o0 = (mode == MODE_ADD_SCALED) ? *p0 : T(0);
         *p0 = epilogue(mode, o0, P, omega);
       }
     }
 }
 
-template <int HB, bool INV>
-__global__ __launch_bounds__(256) void k_pass_reg(const double* __restrict__ in, double* __restrict__ out,
-                                                  const double* __restrict__ Sfrag, int n, long long inner,
-                                                  long long ncols, double omega, int mode) {
+template <typename T, int HB, bool INV>
+__global__ __launch_bounds__(256) void k_pass_reg(const T* __restrict__ in, T* __restrict__ out,
+                                                  const T* __restrict__ Sfrag, int n, long long inner,
+                                                  long long ncols, T omega, int mode) {
+  typedef typename Mfma<T>::acc_t acc_t;
   const int lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
   const long long lin = ((long long)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16 + r;
   const bool valid = lin < ncols;
@@ -496,17 +499,17 @@ __global__ __launch_bounds__(256) void k_pass_reg(const double* __restrict__ in,
   const long long pos = valid ? lin - o * inner : 0;
   const long long base = o * (long long)n * inner + pos;
   const int h = (n + 1) >> 1;
-  double bo[4 * HB], be[4 * HB];
-  v4d acc[2 * HB];
+  T bo[4 * HB], be[4 * HB];
+  acc_t acc[2 * HB];
   if (!INV) {
-    load_folded<HB>(in + base, valid, inner, n, h, g, bo, be);
-    folded_mma<HB, 0>(Sfrag, h, lane, bo, be, acc);
+    load_folded<T, HB>(in + base, valid, inner, n, h, g, bo, be);
+    folded_mma<T, HB, 0>(Sfrag, h, lane, bo, be, acc);
     if (!valid) return;
 #pragma unroll
     for (int kb = 0; kb < HB; ++kb)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int i = kb * 16 + g + 4 * j;
+        const int i = kb * 16 + Mfma<T>::row(g, j);
         if (i < h) out[base + (long long)i * inner] = acc[kb][j];
         if (i < h - 1) out[base + (long long)(h + i) * inner] = acc[HB + kb][j];
       }
@@ -514,14 +517,16 @@ __global__ __launch_bounds__(256) void k_pass_reg(const double* __restrict__ in,
 #pragma unroll
     for (int ib = 0; ib < 4 * HB; ++ib) {
       const int i = 4 * ib + g;
-      bo[ib] = (valid && i < h) ? in[base + (long long)i * inner] : 0.0;
-      be[ib] = (valid && i < h - 1) ? in[base + (long long)(h + i) * inner] : 0.0;
+      bo[ib] = (valid && i < h) ? in[base + (long long)i * inner] : T(0);
+      be[ib] = (valid && i < h - 1) ? in[base + (long long)(h + i) * inner] : T(0);
     }
-    folded_mma<HB, 1>(Sfrag, h, lane, bo, be, acc);
-    store_unfolded<HB>(out + base, valid, inner, n, h, g, acc, mode, omega);
+    folded_mma<T, HB, 1>(Sfrag, h, lane, bo, be, acc);
+    store_unfolded<T, HB>(out + base, valid, inner, n, h, g, acc, mode, omega);
   }
 }
 
+// Fused slowest-axis solve, all N_t time components in one lane (FP64 only:
+// relies on the chained layout).
 template <int HB, int NT>
 __global__ __launch_bounds__(256) void k_fused_reg(const double* in, double* out,
                                                    const double* __restrict__ Sfrag,
@@ -539,10 +544,9 @@ __global__ __launch_bounds__(256) void k_fused_reg(const double* in, double* out
 #pragma unroll
   for (int l = 0; l < NT; ++l) {
     double a[4 * HB], d[4 * HB];
-    load_folded<HB>(in + base + l * cstride, valid, inner, n, h, g, a, d);
-    folded_mma<HB, 0>(Sfrag, h, lane, a, d, spec[l]);
+    load_folded<double, HB>(in + base + l * cstride, valid, inner, n, h, g, a, d);
+    folded_mma<double, HB, 0>(Sfrag, h, lane, a, d, spec[l]);
   }
-  // per-mode N_t x N_t solve; spectral index s: odd rows s < h, even rows h + s
   if (valid) {
 #pragma unroll
     for (int k = 0; k < 2 * HB; ++k) {
@@ -552,8 +556,8 @@ __global__ __launch_bounds__(256) void k_fused_reg(const double* in, double* out
         const int rr = kb * 16 + g + 4 * j;
         const bool ok = half == 0 ? rr < h : rr < h - 1;
         if (!ok) continue;
-        const long long s = half == 0 ? rr : h + rr;
-        const double* gm = G + (pos + inner * s) * (NT * NT);
+        const long long sidx = half == 0 ? rr : h + rr;
+        const double* gm = G + (pos + inner * sidx) * (NT * NT);
         double v[NT], w[NT];
 #pragma unroll
         for (int l = 0; l < NT; ++l) v[l] = spec[l][k][j];
@@ -573,59 +577,160 @@ __global__ __launch_bounds__(256) void k_fused_reg(const double* in, double* out
 #pragma unroll
   for (int l = 0; l < NT; ++l) {
     v4d acc[2 * HB];
-    folded_mma_chain<HB>(Sfrag, h, lane, spec[l], acc);
-    store_unfolded<HB>(out + base + l * cstride, valid, inner, n, h, g, acc, mode, omega);
+    folded_mma_chain<double, HB>(Sfrag, h, lane, spec[l], acc);
+    store_unfolded<double, HB>(out + base + l * cstride, valid, inner, n, h, g, acc, mode, omega);
   }
+}
+
+// Fused slowest-axis solve with the N_t time components of one 16-column
+// group spread over N_t waves of the workgroup (wave w: column group w / NT,
+// component w % NT).  Each wave keeps only its own component's spectral
+// values; the per-mode time solve exchanges one 16-row block at a time through
+// a double-buffered LDS slot.  FP32 additionally re-lays out each solved block
+// from accumulator order (row 4g + j) into B-operand order (row 4j + g) through
+// a per-wave LDS slot before the inverse product.
+template <typename T, int HB, int NT>
+__global__ __launch_bounds__(256) void k_fused_pair(const T* in, T* out, const T* __restrict__ Sfrag,
+                                                    const T* __restrict__ G, int n, long long inner,
+                                                    long long outer, int transpose, T omega, int mode) {
+  typedef typename Mfma<T>::acc_t acc_t;
+  constexpr bool CHAIN = sizeof(T) == 8;     // accumulator order == B-operand order
+  constexpr int CG = NT >= 3 ? 1 : 4 / NT;   // column groups per workgroup
+  __shared__ T xch[2][CG * NT * 64 * 4];
+  __shared__ T rel[CHAIN ? 1 : CG * NT * 256];
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
+  const int cg = wave / NT, l = wave - (wave / NT) * NT;
+  const long long lin = ((long long)blockIdx.x * CG + cg) * 16 + r;
+  const bool valid = lin < outer * inner;
+  const long long o = valid ? lin / inner : 0;
+  const long long pos = valid ? lin - o * inner : 0;
+  const long long cstride = (long long)n * inner;
+  const long long base = o * NT * cstride + (long long)l * cstride + pos;
+  const int h = (n + 1) >> 1;
+  acc_t spec[2 * HB];
+  {
+    T a[4 * HB], d[4 * HB];
+    load_folded<T, HB>(in + base, valid, inner, n, h, g, a, d);
+    folded_mma<T, HB, 0>(Sfrag, h, lane, a, d, spec);
+  }
+#pragma unroll
+  for (int k = 0; k < 2 * HB; ++k) {
+    T* slot = xch[k & 1];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) slot[((cg * NT + l) * 64 + lane) * 4 + j] = spec[k][j];
+    __syncthreads();
+    const int half = k / HB, kb = k % HB;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int rr = kb * 16 + Mfma<T>::row(g, j);
+      const bool ok = valid && (half == 0 ? rr < h : rr < h - 1);
+      T acc = T(0);
+      if (ok) {
+        const long long sidx = half == 0 ? rr : h + rr;
+        const T* gm = G + (pos + inner * sidx) * (NT * NT);
+#pragma unroll
+        for (int m = 0; m < NT; ++m) {
+          const T v = slot[((cg * NT + m) * 64 + lane) * 4 + j];
+          acc += (transpose ? gm[m * NT + l] : gm[l * NT + m]) * v;
+        }
+      }
+      spec[k][j] = acc;
+    }
+    if (!CHAIN) {
+      // accumulator row 4g + j of column r -> B-operand element (chunk 4k + j', row g' = g)
+      T* rs = rel + (cg * NT + l) * 256;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) rs[(4 * g + j) * 16 + r] = spec[k][j];
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < 4; ++j) spec[k][j] = rs[(4 * j + g) * 16 + r];
+      __syncthreads();
+    }
+  }
+  acc_t acc[2 * HB];
+  folded_mma_chain<T, HB>(Sfrag, h, lane, spec, acc);
+  store_unfolded<T, HB>(out + base, valid, inner, n, h, g, acc, mode, omega);
 }
 
 }  // namespace
 
-// The register-resident kernels serve FP64 while the per-wave state fits
-// (folded half blocks * time components <= 8); larger cases and FP32 use the
-// LDS-staged kernels.
-// nt == 1 selects the single-axis pass; the fused kernel keeps N_t spectral
-// columns per lane and only pays off while that state stays small (measured:
-// half blocks * N_t = 8 spills and runs 1.6x slower than the LDS kernel).
+// Register-resident kernels: FP64 up to 4 half blocks (n <= 127), FP32 up to 8
+// (n <= 255); the LDS-staged kernels cover the rest and the TRANSFORM_LDS choice.
 template <typename T>
-bool reg_path(int impl, int hb, int nt, bool fused) {
-  if (impl == TRANSFORM_LDS || sizeof(T) != 8 || hb > 4) return false;
-  if (!fused) return true;
-  return impl == TRANSFORM_REG ? hb * nt <= 8 : hb * nt <= 4;
+bool reg_path(int impl, int hb) {
+  if (impl == TRANSFORM_LDS) return false;
+  return sizeof(T) == 8 ? hb <= 4 : hb <= 8;
 }
 
-hipError_t launch_pass_reg(int hb, bool inverse, const double* in, double* out, const double* Sfrag, int n,
-                           long long inner, long long ncols, double omega, int mode, hipStream_t s) {
+template <typename T>
+hipError_t launch_pass_reg(int hb, bool inverse, const T* in, T* out, const T* Sfrag, int n,
+                           long long inner, long long ncols, T omega, int mode, hipStream_t s) {
   const unsigned grid = (unsigned)((ncols + 63) / 64);
 #define REG_PASS(HB)                                                                              \
   if (hb == HB) {                                                                                 \
     if (inverse)                                                                                  \
-      hipLaunchKernelGGL((k_pass_reg<HB, true>), dim3(grid), dim3(256), 0, s, in, out, Sfrag, n, inner, \
+      hipLaunchKernelGGL((k_pass_reg<T, HB, true>), dim3(grid), dim3(256), 0, s, in, out, Sfrag, n, inner, \
                          ncols, omega, mode);                                                     \
     else                                                                                          \
-      hipLaunchKernelGGL((k_pass_reg<HB, false>), dim3(grid), dim3(256), 0, s, in, out, Sfrag, n, inner, \
+      hipLaunchKernelGGL((k_pass_reg<T, HB, false>), dim3(grid), dim3(256), 0, s, in, out, Sfrag, n, inner, \
                          ncols, omega, mode);                                                     \
     return hipGetLastError();                                                                     \
   }
   REG_PASS(1) REG_PASS(2) REG_PASS(4)
+  if (sizeof(T) == 4) {
+    REG_PASS(8)
+  }
 #undef REG_PASS
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_fused_reg(int hb, int nt, const double* in, double* out, const double* Sfrag,
-                            const double* G, int n, long long inner, long long outer, int transpose,
-                            double omega, int mode, hipStream_t s) {
-  const unsigned grid = (unsigned)((outer * inner + 63) / 64);
-#define REG_FUSED(HB, NT)                                                                          \
-  if (hb == HB && nt == NT) {                                                                      \
-    hipLaunchKernelGGL((k_fused_reg<HB, NT>), dim3(grid), dim3(256), 0, s, in, out, Sfrag, G, n, inner, \
-                       outer, transpose, omega, mode);                                             \
-    return hipGetLastError();                                                                      \
+template <typename T>
+hipError_t launch_fused_pair(int hb, int nt, const T* in, T* out, const T* Sfrag, const T* G, int n,
+                             long long inner, long long outer, int transpose, T omega, int mode, hipStream_t s) {
+  const int cg = nt >= 3 ? 1 : 4 / nt;
+  const unsigned grid = (unsigned)((outer * inner + 16 * cg - 1) / (16 * cg));
+  const dim3 block(64 * nt * cg);
+#define PAIR(HB, NT)                                                                                 \
+  if (hb == HB && nt == NT) {                                                                        \
+    hipLaunchKernelGGL((k_fused_pair<T, HB, NT>), dim3(grid), block, 0, s, in, out, Sfrag, G, n, inner, outer, \
+                       transpose, omega, mode);                                                      \
+    return hipGetLastError();                                                                        \
   }
-  REG_FUSED(1, 1) REG_FUSED(1, 2) REG_FUSED(1, 3) REG_FUSED(1, 4)
-  REG_FUSED(2, 1) REG_FUSED(2, 2) REG_FUSED(2, 3) REG_FUSED(2, 4)
-  REG_FUSED(4, 1) REG_FUSED(4, 2)
-#undef REG_FUSED
+  PAIR(1, 1) PAIR(1, 2) PAIR(1, 3) PAIR(1, 4)
+  PAIR(2, 1) PAIR(2, 2) PAIR(2, 3) PAIR(2, 4)
+  PAIR(4, 1) PAIR(4, 2) PAIR(4, 3) PAIR(4, 4)
+  if (sizeof(T) == 4) {
+    PAIR(8, 1) PAIR(8, 2) PAIR(8, 3) PAIR(8, 4)
+  }
+#undef PAIR
   return hipErrorInvalidValue;
+}
+
+// Fused solve: TRANSFORM_REG keeps all N_t components in one lane when that
+// state is small (FP64, hb * N_t <= 8); otherwise the wave-per-component kernel.
+template <typename T>
+hipError_t launch_fused_any(int impl, int hb, int nt, const T* in, T* out, const T* Sfrag, const T* G, int n,
+                            long long inner, long long outer, int transpose, T omega, int mode, hipStream_t s) {
+  if (sizeof(T) == 8 && impl == TRANSFORM_REG && hb * nt <= 8) {
+    const unsigned grid = (unsigned)((outer * inner + 63) / 64);
+    const double* ind = (const double*)in;
+    double* outd = (double*)out;
+    const double* Sd = (const double*)Sfrag;
+    const double* Gd = (const double*)G;
+    const double om = (double)omega;
+#define REG_FUSED(HB, NT)                                                                          \
+    if (hb == HB && nt == NT) {                                                                    \
+      hipLaunchKernelGGL((k_fused_reg<HB, NT>), dim3(grid), dim3(256), 0, s, ind, outd, Sd, Gd, n, inner, \
+                         outer, transpose, om, mode);                                              \
+      return hipGetLastError();                                                                    \
+    }
+    REG_FUSED(1, 1) REG_FUSED(1, 2) REG_FUSED(1, 3) REG_FUSED(1, 4)
+    REG_FUSED(2, 1) REG_FUSED(2, 2) REG_FUSED(2, 3) REG_FUSED(2, 4)
+    REG_FUSED(4, 1) REG_FUSED(4, 2)
+#undef REG_FUSED
+  }
+  return launch_fused_pair<T>(hb, nt, in, out, Sfrag, G, n, inner, outer, transpose, omega, mode, s);
 }
 
 int transform_half_blocks(int n) {
@@ -639,8 +744,7 @@ template <typename T>
 hipError_t launch_dst_pass(int impl, int hb, bool xaxis, bool inverse, const T* in, T* out, const T* Sfrag,
                            int n, long long inner, long long ncols, T omega, int mode,
                            hipStream_t s) {
-  if (reg_path<T>(impl, hb, 1, false)) return launch_pass_reg(hb, inverse, (const double*)in, (double*)out,
-                                                 (const double*)Sfrag, n, inner, ncols, (double)omega, mode, s);
+  if (reg_path<T>(impl, hb)) return launch_pass_reg<T>(hb, inverse, in, out, Sfrag, n, inner, ncols, omega, mode, s);
   const unsigned grid = (unsigned)((ncols + TILE_COLS - 1) / TILE_COLS);
 #define PASS_CASE(HB)                                                                          \
   if (hb == HB) {                                                                              \
@@ -667,9 +771,7 @@ template <typename T>
 hipError_t launch_dst_fused(int impl, int hb, int nt, const T* in, T* out, const T* Sfrag, const T* G, int n,
                             long long inner, long long outer, int transpose, T omega, int mode,
                             hipStream_t s) {
-  if (reg_path<T>(impl, hb, nt, true))
-    return launch_fused_reg(hb, nt, (const double*)in, (double*)out, (const double*)Sfrag,
-                            (const double*)G, n, inner, outer, transpose, (double)omega, mode, s);
+  if (reg_path<T>(impl, hb)) return launch_fused_any<T>(impl, hb, nt, in, out, Sfrag, G, n, inner, outer, transpose, omega, mode, s);
   const long long ct = TILE_COLS / nt;
   const unsigned grid = (unsigned)((outer * inner + ct - 1) / ct);
 #define FUSED_CASE(HB, NT)                                                                      \

@@ -40,6 +40,32 @@ def test_fp32_operators(d, n, N, pt):
         assert rel_err(to_oracle(Fc, 1), H.P[k].T @ u) < 1e-6
 
 
+FP32_SOLVE_CASES = [(1, 255, 8, 1, 2), (1, 63, 4, 3, 1), (2, 255, 2, 1, 1), (2, 127, 4, 2, 1),
+                    (2, 31, 8, 0, 2), (3, 15, 4, 1, 1), (3, 31, 2, 2, 1)]
+
+
+@pytest.mark.parametrize("case", FP32_SOLVE_CASES, ids=lambda c: "d{}n{}N{}p{}b{}".format(*c))
+@pytest.mark.parametrize("transpose", [False, True])
+@pytest.mark.parametrize("impl", ["0", "1", "2"], ids=["auto", "lds", "reg"])
+def test_fp32_block_solve_families(case, transpose, impl, monkeypatch):
+    # Every FP32 transform family (LDS-staged, register-resident with the LDS
+    # re-layout between the time solve and the inverse product) against the
+    # oracle's sparse LU, with the FP32 backward-error bound 8 d n u32 per slab.
+    d, n, N, pt, b = case
+    print(f"fp32 block solve {case} transpose={transpose} impl={impl}", flush=True)
+    monkeypatch.setenv("STMG_TRANSFORM", impl)
+    S = stmg.Solver(d, n, N, pt=pt, batch=b, precision="fp32", device=DEV)
+    lev = spacetime.SpaceTimeLevel(d, n, N, pt, 1.0 / N)
+    r = rvec(lev.dof, b, 3).astype(np.float32).astype(np.float64)
+    x = to_oracle(S.block_solve(to_gpu(r, torch.float32), transpose=transpose), b)
+    A = (lev.A.T if transpose else lev.A).tocsr()
+    normA = abs(A).sum(axis=1).max()
+    xs = x.reshape(N, lev.slab, b).transpose(1, 0, 2).reshape(lev.slab, -1)
+    rs = r.reshape(N, lev.slab, b).transpose(1, 0, 2).reshape(lev.slab, -1)
+    be = np.abs(A @ xs - rs).max(axis=0) / (normA * np.abs(xs).max(axis=0))
+    assert np.all(be < 8 * d * n * 2.0 ** -24), be.max()
+
+
 def test_fp32_solve_reaches_float_accuracy():
     d, n, N, pt = 2, 31, 32, 1
     S = stmg.Solver(d, n, N, pt=pt, precision="fp32", device=DEV)
