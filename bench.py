@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--no-graph", action="store_true", help="launch kernels eagerly instead of replaying a hipGraph")
     ap.add_argument("--only-timed", action="store_true", help="timed V-cycles only (for profiler runs)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default kernel families")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only copy a MIB-sized device buffer 5 times (calibrates HBM byte counters) and exit")
     return ap.parse_args()
 
 
@@ -78,7 +80,7 @@ def cpu_baseline(budget_s=20.0):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1",
+        print(json.dumps({"error": "the solver runs on one GPU (one process, one device); multi-GPU runs are not supported, use --gpus 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import numpy as np
@@ -87,6 +89,15 @@ def main():
     from paper_1411_0519_amd import stmg, workloads
 
     dev = "cuda:0"
+    if args.copy_probe:
+        nbytes = args.copy_probe << 20
+        a = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+        c = torch.empty_like(a)
+        for _ in range(5):
+            c.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": nbytes, "copy_probe_bytes_written": nbytes, "copies": 5}))
+        return
     w = workloads.WORKLOADS[args.workload]
     d, n, N, pt, b = w["dim"], w["n"], w["N"], w["pt"], w["batch"]
     _, f, u0 = workloads.workload(args.workload)

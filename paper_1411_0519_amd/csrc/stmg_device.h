@@ -42,6 +42,17 @@ inline dim3 slab_grid(unsigned gx, long long slabs) {
   return dim3(gx, gy, gz);
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.
+// Map dispatch index b (of B) to a logical index so that every XCD processes
+// one contiguous range of logical workgroups: neighbours in memory (halo rows,
+// the previous slab, cache lines split between column groups) then meet in the
+// same L2.  A bijection on [0, B) for any B.
+__device__ inline long long xcd_linear(long long b, long long B) {
+  const long long q = B >> 3, rm = B & 7;
+  const long long x = b & 7, i = b >> 3;
+  return x * q + (x < rm ? x : rm) + i;
+}
+
 // q = e / n for 0 <= e < 2^20 via a float reciprocal and one correction step.
 __device__ inline int div_small(int e, int n, float inv_n) {
   int q = (int)((float)e * inv_n);

@@ -188,12 +188,16 @@ __global__ __launch_bounds__(256) void k_residual_tile2d(const Tin* __restrict__
   typedef Tin T;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   T* U = reinterpret_cast<T*>(lds_raw);
-  const long long slab = slab_index();
+  // logical (slab, row tile) in XCD-contiguous order
+  const long long lg = xcd_linear(blockIdx.x + (long long)gridDim.x * slab_index(),
+                                  (long long)gridDim.x * gridDim.y * gridDim.z);
+  const long long slab = lg / gridDim.x;
+  const int tile = (int)(lg - slab * gridDim.x);
   const long long nslab = (long long)a.batch * a.N;
   if (slab >= nslab) return;
   const int n = a.n;
   const long long nx = a.nx;
-  const int y0 = blockIdx.x * TY;
+  const int y0 = tile * TY;
   const int rows = TY + 2;
   const int plane = rows * n;                 // one component's tile
   const int sn = (int)(slab % a.N);
@@ -261,7 +265,7 @@ __global__ __launch_bounds__(256) void k_residual_tile2d(const Tin* __restrict__
   }
   if (partial != nullptr) {
     const double s2 = block_sum(ss);
-    if (threadIdx.x == 0) partial[slab * gridDim.x + blockIdx.x] = s2;
+    if (threadIdx.x == 0) partial[slab * gridDim.x + tile] = s2;
   }
 }
 

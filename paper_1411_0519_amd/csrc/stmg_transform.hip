@@ -165,7 +165,7 @@ __global__ __launch_bounds__(256) void k_dst_pass(const T* __restrict__ in, T* _
   constexpr int EPT = NP * TILE_COLS / 256;
   __shared__ T tile[NP * LDT];
   const int tid = threadIdx.x;
-  const long long col0 = (long long)blockIdx.x * TILE_COLS;
+  const long long col0 = xcd_linear(blockIdx.x, gridDim.x) * TILE_COLS;
   const int ncol_here = (int)((ncols - col0) < TILE_COLS ? (ncols - col0) : TILE_COLS);
   const float inv_n = 1.0f / (float)n;
   const int h = (n + 1) >> 1;
@@ -290,7 +290,7 @@ __global__ __launch_bounds__(256) void k_dst_fused(const T* in, T* out,
   __shared__ long long base_s[TILE_COLS];
   const int tid = threadIdx.x;
   const long long total = outer * inner;
-  const long long lin0 = (long long)blockIdx.x * CT;
+  const long long lin0 = xcd_linear(blockIdx.x, gridDim.x) * CT;
   const int h = (n + 1) >> 1;
   if (tid < TILE_COLS) {
     const int l = tid / CT, cc = tid - (tid / CT) * CT;
@@ -493,7 +493,7 @@ __global__ __launch_bounds__(256) void k_pass_reg(const T* __restrict__ in, T* _
                                                   long long ncols, T omega, int mode) {
   typedef typename Mfma<T>::acc_t acc_t;
   const int lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
-  const long long lin = ((long long)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16 + r;
+  const long long lin = (xcd_linear(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6)) * 16 + r;
   const bool valid = lin < ncols;
   const long long o = valid ? lin / inner : 0;
   const long long pos = valid ? lin - o * inner : 0;
@@ -533,7 +533,7 @@ __global__ __launch_bounds__(256) void k_fused_reg(const double* in, double* out
                                                    const double* __restrict__ G, int n, long long inner,
                                                    long long outer, int transpose, double omega, int mode) {
   const int lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
-  const long long lin = ((long long)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16 + r;
+  const long long lin = (xcd_linear(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6)) * 16 + r;
   const bool valid = lin < outer * inner;
   const long long o = valid ? lin / inner : 0;
   const long long pos = valid ? lin - o * inner : 0;
@@ -601,7 +601,7 @@ __global__ __launch_bounds__(256) void k_fused_pair(const T* in, T* out, const T
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
   const int cg = wave / NT, l = wave - (wave / NT) * NT;
-  const long long lin = ((long long)blockIdx.x * CG + cg) * 16 + r;
+  const long long lin = (xcd_linear(blockIdx.x, gridDim.x) * CG + cg) * 16 + r;
   const bool valid = lin < outer * inner;
   const long long o = valid ? lin / inner : 0;
   const long long pos = valid ? lin - o * inner : 0;

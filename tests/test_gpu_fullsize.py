@@ -145,6 +145,7 @@ def test_w4_batched_fp32_full_size():
     F = S.rhs(fg, nodal_to_gpu(u0, torch.float32))
     del fg
     stream = torch.cuda.Stream(device=DEV)
+    stream.wait_stream(torch.cuda.current_stream(DEV))     # F was produced on the current stream
     with torch.cuda.stream(stream):
         S.set_graph(True)
         # FP32 stalls near eps_32 * cond(A) ~ 6e-8 * 1e3 relative residual at this mu
