@@ -7,11 +7,19 @@ spectral radii of the 4 N_t x 4 N_t iteration matrices of Theorems
 cahp4_theorem5 / cahp4_theorem6, maximised over the low frequencies with
 theta_x != 0 (Definition of the asymptotic two-grid convergence factors).
 
+The inexact smoother of Remark V-cycleApproxSpace replaces D^{-1} by
+(I - M^x) D^{-1}, M^x the spatial two-grid iteration matrix; on the four
+harmonics it acts as M-tilde(theta_x) on the pair (theta_x, gamma(theta_x))
+for each of the two time frequencies.
+
 Readings where the text is ambiguous:
   * gamma(theta) = theta - sign(theta) pi with sign(0) := +1;
   * the second block of the semi-coarsening coarse symbol is taken at
     (gamma(theta_x), 2 theta_t);
-  * the nonzero eigenvalue of (K + lam M)^{-1} N is R(-lam tau).
+  * the nonzero eigenvalue of (K + lam M)^{-1} N is R(-lam tau);
+  * M-tilde = S^nu2 K^x S^nu1 (post-smoothing applied last; the printed order
+    S^nu1 K^x S^nu2 is the same matrix when nu1 = nu2), R-tilde_x is N_t x 2N_t
+    and P-tilde_x is 2N_t x N_t (the printed shapes are swapped).
 """
 import numpy as np
 
@@ -60,6 +68,51 @@ class Symbols:
         return (1.0 - self.omega) * np.eye(self.nt) + \
             self.omega * np.exp(-1j * tt) * np.linalg.solve(Ablk, self.N)
 
+    def Ahat(self, tx, h=None):
+        """A-hat_{tau,h}(theta_x) = h/3 (2 + cos) K + 2/h (1 - cos) M (Remark V-cycleApproxSpace)."""
+        h = self.h if h is None else h
+        c = np.cos(tx)
+        return (h / 3.0) * (2.0 + c) * self.K + (2.0 / h) * (1.0 - c) * self.M
+
+    def Dx(self):
+        """Block diagonal of A in space: 2h/3 K + 2/h M."""
+        return (2.0 * self.h / 3.0) * self.K + (2.0 / self.h) * self.M
+
+    def Sx(self, tx, omega_x):
+        """Damped block-Jacobi symbol in space, I - omega_x Dx^{-1} A-hat(theta_x)."""
+        return np.eye(self.nt) - omega_x * np.linalg.solve(self.Dx(), self.Ahat(tx))
+
+    def Mx(self, tx, nu1x=2, nu2x=2, omega_x=2.0 / 3.0):
+        """M-tilde(theta_x): spatial two-grid iteration symbol on (theta_x, gamma(theta_x))."""
+        n = self.nt
+        gx = gamma(tx)
+        I = np.eye(n)
+        At = np.zeros((2 * n, 2 * n))
+        At[:n, :n] = self.Ahat(tx)
+        At[n:, n:] = self.Ahat(gx)
+        Rt = np.concatenate([self.Rx(tx) * I, self.Rx(gx) * I], axis=1)
+        Pt = np.concatenate([self.Px(tx) * I, self.Px(gx) * I], axis=0)
+        Ac = self.Ahat(2 * tx, h=2 * self.h)
+        Kx = np.eye(2 * n) - Pt @ np.linalg.solve(Ac, Rt @ At)
+
+        def Sp(nu):
+            out = np.zeros((2 * n, 2 * n))
+            out[:n, :n] = np.linalg.matrix_power(self.Sx(tx, omega_x), nu)
+            out[n:, n:] = np.linalg.matrix_power(self.Sx(gx, omega_x), nu)
+            return out
+        return Sp(nu2x) @ Kx @ Sp(nu1x)
+
+    def S_inexact(self, tx, tt, nu1x=2, nu2x=2, omega_x=2.0 / 3.0):
+        """S-bar = I - omega (I - M) D^{-1} L on the four harmonics (eq. chap4_smootherApprox)."""
+        n = self.nt
+        H = self.harmonics(tx, tt)
+        DinvL = self.blockdiag([np.linalg.solve(self.Ahat(a), self.L(a, b)) for a, b in H])
+        M = np.zeros((4 * n, 4 * n), dtype=complex)
+        Mt = self.Mx(tx, nu1x, nu2x, omega_x)
+        M[:2 * n, :2 * n] = Mt
+        M[2 * n:, 2 * n:] = Mt
+        return np.eye(4 * n) - self.omega * (np.eye(4 * n) - M) @ DinvL
+
     def Rt(self, tt):
         """Time restriction symbol e^{-i theta} R1 + R2 (Lemma chap4_lemma12)."""
         return np.exp(-1j * tt) * self.R1 + self.R2
@@ -88,12 +141,17 @@ class Symbols:
             out[i * n:(i + 1) * n, i * n:(i + 1) * n] = m
         return out
 
-    def two_grid_matrix(self, tx, tt, kind, nu1, nu2):
-        """M-tilde of Theorem cahp4_theorem5 (kind 's') or cahp4_theorem6 (kind 'f')."""
+    def two_grid_matrix(self, tx, tt, kind, nu1, nu2, xopts=None):
+        """M-tilde of Theorem cahp4_theorem5 (kind 's') or cahp4_theorem6 (kind 'f');
+        with xopts (dict nu1x, nu2x, omega_x) the smoother is the inexact one,
+        giving the matrices of eq. chap4_twoGridIterationMatrixApprox."""
         n = self.nt
         H = self.harmonics(tx, tt)
         Lt = self.blockdiag([self.L(a, b) for a, b in H])
-        St = self.blockdiag([self.S(a, b) for a, b in H])
+        if xopts is None:
+            St = self.blockdiag([self.S(a, b) for a, b in H])
+        else:
+            St = self.S_inexact(tx, tt, **xopts)
         gt = gamma(tt)
         if kind == "s":
             Rs = np.zeros((2 * n, 4 * n), dtype=complex)
@@ -153,8 +211,10 @@ def low_frequencies(nl):
     return th[(th > -np.pi / 2) & (th <= np.pi / 2 + 1e-15)]
 
 
-def two_grid_factor(pt, mu, kind, nu1=1, nu2=1, omega=0.5, nx_grid=1024, nt_grid=256, h=1.0 / 1024):
-    """rho(M-hat_mu^{s|f}): max spectral radius over low frequencies, theta_x != 0."""
+def two_grid_factor(pt, mu, kind, nu1=1, nu2=1, omega=0.5, nx_grid=1024, nt_grid=256, h=1.0 / 1024,
+                    xopts=None):
+    """rho(M-hat_mu^{s|f}) (or rho(M-bar) with the inexact smoother when xopts is
+    given): max spectral radius over low frequencies, theta_x != 0."""
     tau = mu * h ** 2
     sym = Symbols(pt, tau, h, omega)
     best = 0.0
@@ -162,7 +222,7 @@ def two_grid_factor(pt, mu, kind, nu1=1, nu2=1, omega=0.5, nx_grid=1024, nt_grid
         if tx == 0.0:
             continue
         for tt in low_frequencies(nt_grid):
-            ev = np.linalg.eigvals(sym.two_grid_matrix(tx, tt, kind, nu1, nu2))
+            ev = np.linalg.eigvals(sym.two_grid_matrix(tx, tt, kind, nu1, nu2, xopts))
             best = max(best, np.abs(ev).max())
     return best
 

@@ -7,12 +7,17 @@ of Sec. 2: nu1 damped block-Jacobi steps (eq. chap4_smoother with the exact
 block inverse, eq. chap4_smootherExact), residual, restriction, recursive
 coarse correction from a zero initial guess, prolongation, nu2 steps; the
 coarsest level (one time slab) is solved exactly by LU.
+
+smoother="inexact" replaces the exact block inverse by one geometric
+multigrid cycle in space per slab (eq. chap4_smootherApprox of Remark
+V-cycleApproxSpace, module spatial_mg); the coarsest level stays exact.
 """
 import numpy as np
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
 from . import dg_time, fe_space
+from .spatial_mg import SpatialCycle
 from .spacetime import SpaceTimeLevel, forward_substitution
 
 AUTO, SEMI, FULL = 0, 1, 2
@@ -79,7 +84,8 @@ class Hierarchy:
     """All levels of the space-time multigrid (index 0 = coarsest)."""
 
     def __init__(self, d, n, N, pt, T=1.0, omega=0.5, nu1=2, nu2=2,
-                 rule=AUTO, mu_star=None, transpose=False):
+                 rule=AUTO, mu_star=None, transpose=False, smoother="exact",
+                 nu1x=2, nu2x=2, omega_x=2.0 / 3.0, depth_x=None):
         lv, kinds = coarsening_schedule(n, N, T, pt, rule, mu_star)
         self.schedule = kinds                                  # fine -> coarse
         self.levels = [SpaceTimeLevel(d, nL, NL, pt, tauL) for (nL, NL, tauL, _) in lv][::-1]
@@ -89,6 +95,11 @@ class Hierarchy:
         self.P = [None] + [transfer(self.levels[k], self.levels[k - 1], self.kinds[k - 1])
                            for k in range(1, len(self.levels))]
         self._lu = [None] * len(self.levels)
+        if smoother not in ("exact", "inexact"):
+            raise ValueError(smoother)
+        self.smoother = smoother
+        self.xopts = dict(nu1=nu1x, nu2=nu2x, omega=omega_x, depth=depth_x)
+        self._sc = [None] * len(self.levels)
 
     @property
     def fine(self):
@@ -112,9 +123,26 @@ class Hierarchy:
         x = self.lu(k).solve(np.ascontiguousarray(cols))
         return x.reshape(lev.slab, lev.N, b).transpose(1, 0, 2).reshape(lev.dof, b)
 
+    def spatial_cycle(self, k):
+        if self._sc[k] is None:
+            lev = self.levels[k]
+            self._sc[k] = SpatialCycle(lev.d, lev.n, lev.pt, lev.tau, transpose=self.transpose, **self.xopts)
+        return self._sc[k]
+
+    def approx_block_solve(self, k, r):
+        """x = (I - M^x) D^{-1} r: one spatial cycle per slab and RHS from zero."""
+        lev = self.levels[k]
+        b = r.shape[1]
+        cols = r.reshape(lev.N, lev.slab, b).transpose(1, 0, 2).reshape(lev.slab, lev.N * b)
+        x = self.spatial_cycle(k).cycle(cols)
+        return x.reshape(lev.slab, lev.N, b).transpose(1, 0, 2).reshape(lev.dof, b)
+
     def smooth(self, k, u, F):
-        """One damped block-Jacobi step, eq. chap4_smoother."""
-        return u + self.omega * self.block_solve(k, self.residual(k, u, F))
+        """One damped block-Jacobi step, eq. chap4_smoother (exact inverse) or
+        eq. chap4_smootherApprox (one spatial cycle per slab)."""
+        r = self.residual(k, u, F)
+        x = self.approx_block_solve(k, r) if self.smoother == "inexact" else self.block_solve(k, r)
+        return u + self.omega * x
 
     def coarsest_solve(self, F):
         """Exact solve on the coarsest level (one slab: L_0 = A_0)."""
