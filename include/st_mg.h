@@ -20,6 +20,10 @@
  * (space); full space-time coarsening iff mu_L = tau_L/h_L^2 >= mu*
  * (Remark chap4_remarkCriticalDiscretizationParameter), otherwise time
  * semi-coarsening; coarsest level = one time slab, solved exactly.
+ * Optionally (Remark V-cycleApproxSpace, eq. chap4_smootherApprox) the exact
+ * block inverse is replaced by one geometric multigrid cycle in space per
+ * slab (damped block Jacobi in space, full weighting, linear interpolation),
+ * the setting of the paper's numerical examples (Sec. 4).
  *
  * Conventions for every entry point:
  *  - return value: ST_OK (0) or a negative ST_E* code; st_mg_last_error()
@@ -68,6 +72,13 @@ enum {
                    double, inner V-cycle in float, coarsest solve in double       */
 };
 
+enum {
+  ST_SMOOTH_EXACT = 0,      /* D^{-1}: exact slab solves by fast diagonalisation  */
+  ST_SMOOTH_SPATIAL_MG = 1  /* (I - M^x) D^{-1}: one spatial multigrid cycle per
+                               slab (eq. chap4_smootherApprox); the coarsest level
+                               and one-node levels stay exact                      */
+};
+
 typedef struct {
   int dim;          /* d in {1,2,3}                                              */
   int n;            /* interior nodes per dimension, n = 2^m - 1, 1 <= n <= 255  */
@@ -80,10 +91,14 @@ typedef struct {
   double mu_star;   /* <= 0: computed from R(-3 mu*) = sqrt(2) - 1               */
   int precision;    /* ST_FP64 | ST_FP32 | ST_MIXED                              */
   int batch;        /* number of right-hand sides b >= 1                         */
+  int smoother;     /* ST_SMOOTH_EXACT | ST_SMOOTH_SPATIAL_MG                    */
+  int nu1x, nu2x;   /* spatial cycle: pre-/post block-Jacobi steps, 0..16        */
+  double omega_x;   /* spatial cycle: Jacobi damping in (0, 1]                   */
 } st_mg_params;
 
 /* Fill defaults: d=1, n=31, T=1, N=16, p_t=1, omega=1/2, nu1=nu2=2 (Sec. 4,
- * Example chap4_example1), AUTO coarsening, FP64, batch 1. */
+ * Example chap4_example1), AUTO coarsening, FP64, batch 1, exact smoother;
+ * spatial cycle (when selected) nu1x=nu2x=2, omega_x=2/3 (Sec. 4). */
 void st_mg_default_params(st_mg_params* p);
 
 /* Validate parameters, build the level hierarchy (Sec. 4 rule) and upload the
@@ -130,7 +145,19 @@ int st_mg_residual(st_mg_t h, int level, int prec, int transpose, const void* u,
 /* x = D^{-1} r, D = diag{A}: exact slab solves by fast diagonalisation. */
 int st_mg_block_solve(st_mg_t h, int level, int prec, int transpose, const void* r, void* x,
                       void* stream);
-/* One damped block-Jacobi step u <- u + omega D^{-1}(F - L u). */
+/* x = (I - M^x) A^{-1} r on every slab: one geometric multigrid cycle in
+ * space from the zero initial guess (Remark V-cycleApproxSpace): nu1x damped
+ * block-Jacobi steps x <- x + omega_x (D^x)^{-1}(r - A x), D^x the N_t x N_t
+ * blocks of A at each spatial node; defect restriction by full weighting
+ * (R_x (x) I); the same cycle on the re-discretised A_{tau,2h} down to one
+ * node, solved exactly; linear interpolation (P_x (x) I); nu2x steps, with
+ * the handle's nu1x, nu2x, omega_x.  Needs a handle set up with
+ * ST_SMOOTH_SPATIAL_MG (its workspace holds the cycle's vectors; ST_ESTATE
+ * otherwise).  x and r must not overlap.  Levels with n = 1 give x = A^{-1} r. */
+int st_mg_spatial_cycle(st_mg_t h, int level, int prec, int transpose, const void* r, void* x,
+                        void* stream);
+/* One damped block-Jacobi step u <- u + omega D^{-1}(F - L u), with D^{-1}
+ * exact or approximated by the spatial cycle, as the handle's smoother says. */
 int st_mg_smooth(st_mg_t h, int level, int prec, int transpose, void* u, const void* F,
                  void* stream);
 /* F_c = R r_f = P^T r_f from level to level+1. */
@@ -164,7 +191,9 @@ int st_mg_set_graph(st_mg_t h, int enable);
 
 /* Autotuner: per level, time one smoothing step with every applicable kernel
  * family (one-kernel small-level step with the slab in LDS; LDS-staged
- * transforms; FP64 register-resident transforms) and keep the fastest.
+ * transforms; register-resident transforms) and keep the fastest.  With the
+ * spatial-cycle smoother the transforms serve only the coarsest level and
+ * nothing is tuned.
  * u_scratch, F_scratch: two fine-level device vectors of the handle's vector
  * type whose contents are overwritten (may be NULL for ST_MIXED).  Needs a
  * bound workspace; synchronises the stream. */
@@ -184,7 +213,9 @@ enum {
   ST_PROF_FUSED = 3,      /* forward + per-mode time solve + inverse, slowest axis */
   ST_PROF_SMALL = 4,      /* whole smoothing step of a small level, one kernel     */
   ST_PROF_RESTRICT = 5, ST_PROF_PROLONG = 6, ST_PROF_OTHER = 7,
-  ST_PROF_KINDS = 8
+  ST_PROF_JACOBI = 8,     /* spatial cycle: block-Jacobi steps and defects        */
+  ST_PROF_XFER_X = 9,     /* spatial cycle: restriction / prolongation in space   */
+  ST_PROF_KINDS = 10
 };
 int st_mg_profile_start(st_mg_t h);
 int st_mg_profile_stop(st_mg_t h);

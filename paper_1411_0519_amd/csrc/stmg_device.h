@@ -60,5 +60,67 @@ __device__ inline int div_small(int e, int n, float inv_n) {
   else if ((q + 1) * n <= e) ++q;
   return q;
 }
+// Mass and stiffness stencils of all N_t time components at interior node
+// (x, y, z):  mu[l] = (M_h u_l), ku[l] = (K_h u_l).  Separable: 1-D row sums
+// along x, then combined with the y/z weights.
+template <typename T, int D, int NT>
+__device__ inline void stencil_mk(const T* __restrict__ base, long long nx, int n, int x, int y,
+                                  int z, const T* wm, const T* wk, T* mu, T* ku) {
+#pragma unroll
+  for (int l = 0; l < NT; ++l) {
+    mu[l] = T(0);
+    ku[l] = T(0);
+  }
+#pragma unroll
+  for (int dz = (D == 3 ? -1 : 0); dz <= (D == 3 ? 1 : 0); ++dz) {
+    const int zz = z + dz;
+    if (zz < 0 || zz >= n) continue;
+#pragma unroll
+    for (int dy = (D >= 2 ? -1 : 0); dy <= (D >= 2 ? 1 : 0); ++dy) {
+      const int yy = y + dy;
+      if (yy < 0 || yy >= n) continue;
+      const long long row = ((long long)zz * n + yy) * n;
+      T sm[NT], sk[NT];
+#pragma unroll
+      for (int l = 0; l < NT; ++l) {
+        sm[l] = T(0);
+        sk[l] = T(0);
+      }
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int xx = x + dx;
+        if (xx < 0 || xx >= n) continue;
+#pragma unroll
+        for (int l = 0; l < NT; ++l) {
+          const T v = base[l * nx + row + xx];
+          sm[l] += wm[dx + 1] * v;
+          sk[l] += wk[dx + 1] * v;
+        }
+      }
+#pragma unroll
+      for (int l = 0; l < NT; ++l) {
+        if (D == 1) {
+          mu[l] += sm[l];
+          ku[l] += sk[l];
+        } else if (D == 2) {
+          mu[l] += wm[dy + 1] * sm[l];
+          ku[l] += wk[dy + 1] * sm[l] + wm[dy + 1] * sk[l];
+        } else {
+          const T mzy = wm[dz + 1] * wm[dy + 1];
+          mu[l] += mzy * sm[l];
+          ku[l] += (wk[dz + 1] * wm[dy + 1] + wm[dz + 1] * wk[dy + 1]) * sm[l] + mzy * sk[l];
+        }
+      }
+    }
+  }
+}
+
+template <int D>
+__device__ inline void node_coords(long long j, int n, int& x, int& y, int& z) {
+  x = (int)(j % n);
+  y = (D >= 2) ? (int)((j / n) % n) : 0;
+  z = (D == 3) ? (int)(j / ((long long)n * n)) : 0;
+}
+
 }  // namespace dev
 }  // namespace stmg

@@ -108,6 +108,16 @@ struct Level {
   void* u2 = nullptr;     // second iterate buffer for the small-level smoother
   void* F = nullptr;
   void* r = nullptr;
+  // spatial cycle of the inexact smoother: sub-level j has n_j = (n_{j-1}-1)/2
+  // interior nodes per dimension down to one; X/Y are the Jacobi ping-pong
+  // iterates, F the restricted defect (j >= 1)
+  struct Sub {
+    int n = 0;
+    long long nx = 0;
+    double h = 0;
+    void *X = nullptr, *Y = nullptr, *F = nullptr;
+  };
+  std::vector<Sub> sub;
   long long dof(int nt, int b) const { return (long long)b * N * nt * nx; }
 };
 
@@ -521,11 +531,134 @@ int op_prolong(st_mg* h, int l, const T* ec, T* uf, hipStream_t s) {
   return ST_OK;
 }
 
+// ------------------------------------------------------ spatial multigrid
+// Coefficients of the slab matrix on spatial sub-level j of level l and the
+// inverse of its N_t x N_t node block D^x = M_jj K + K_jj M (M_jj = (2h/3)^d,
+// K_jj = d (2/h) (2h/3)^(d-1): the diagonals of the Q1 matrices), transposed
+// for the adjoint.  On a one-node sub-level D^x is the whole of A.
+template <typename T>
+SpatialArgs<T> spatial_args(const st_mg* h, const Level& L, const Level::Sub& S, bool transpose, int op,
+                            int upd, T scale, bool x_zero, T omega) {
+  SpatialArgs<T> a{};
+  const int nt = h->nt, d = h->p.dim;
+  double K[NT_MAX * NT_MAX], M[NT_MAX * NT_MAX], Dm[NT_MAX * NT_MAX];
+  const double mjj = std::pow(2.0 * S.h / 3.0, d);
+  const double kjj = d * (2.0 / S.h) * std::pow(2.0 * S.h / 3.0, d - 1);
+  for (int l = 0; l < nt; ++l)
+    for (int k = 0; k < nt; ++k) {
+      K[l * nt + k] = transpose ? h->Kt[k * nt + l] : h->Kt[l * nt + k];
+      M[l * nt + k] = L.tau * h->Mh[l * nt + k];
+      Dm[l * nt + k] = mjj * K[l * nt + k] + kjj * M[l * nt + k];
+    }
+  invert(nt, Dm);
+  for (int i = 0; i < nt * nt; ++i) {
+    a.K[i] = (T)K[i];
+    a.M[i] = (T)M[i];
+    a.Dinv[i] = (T)Dm[i];
+  }
+  a.wm[0] = a.wm[2] = (T)(S.h / 6.0);
+  a.wm[1] = (T)(4.0 * S.h / 6.0);
+  a.wk[0] = a.wk[2] = (T)(-1.0 / S.h);
+  a.wk[1] = (T)(2.0 / S.h);
+  a.n = S.n;
+  a.nx = S.nx;
+  a.slabs = (long long)h->p.batch * L.N;
+  a.omega = omega;
+  a.scale = scale;
+  a.op = op;
+  a.upd = upd;
+  a.x_zero = x_zero ? 1 : 0;
+  return a;
+}
+
+template <typename T>
+int op_spatial(st_mg* h, int l, int j, bool transpose, const T* x, const T* f, const T* base, T* out, int op,
+               int upd, T scale, bool x_zero, T omega, hipStream_t s) {
+  const Level& L = h->lv[l];
+  const SpatialArgs<T> a = spatial_args<T>(h, L, L.sub[j], transpose, op, upd, scale, x_zero, omega);
+  ProfScope ps(h, ST_PROF_JACOBI, l, s);
+  HIPCHK(h, launch_spatial<T>(h->p.dim, h->nt, x, f, base, out, a, s));
+  return ST_OK;
+}
+
+// One spatial cycle on sub-level j of level l for every slab, from x = 0:
+// x = (I - M^x) A_j^{-1} f.  When `dst` is given (j = 0) the result is written
+// there as dst = x (MODE_STORE), dst = omega x (MODE_SET_SCALED) or
+// dst += omega x (MODE_ADD_SCALED), fused into the last Jacobi step;
+// otherwise *res points at the sub-level buffer holding x.
+template <typename T>
+int spatial_cycle(st_mg* h, int l, int j, bool transpose, const T* f, T* dst, int mode, T omega_t, T** res,
+                  hipStream_t s) {
+  Level& L = h->lv[l];
+  const Level::Sub& S = L.sub[j];
+  const int d = h->p.dim, nt = h->nt;
+  const T om = (T)h->p.omega_x;
+  const long long slabs = (long long)h->p.batch * L.N;
+  const long long len = slabs * nt * S.nx;
+  const int upd_last = mode == MODE_ADD_SCALED ? UPD_ADD : UPD_SET;
+  const T sc_last = mode == MODE_STORE ? T(1) : omega_t;
+  if (S.n == 1) {   // one node: exact N_t x N_t solve per slab
+    if (dst) return op_spatial<T>(h, l, j, transpose, nullptr, f, dst, dst, SP_JACOBI, upd_last, sc_last, true, T(1), s);
+    CHK(op_spatial<T>(h, l, j, transpose, nullptr, f, nullptr, (T*)S.X, SP_JACOBI, UPD_NONE, T(1), true, T(1), s));
+    *res = (T*)S.X;
+    return ST_OK;
+  }
+  T* cur = (T*)S.X;
+  T* oth = (T*)S.Y;
+  const int nu1 = h->p.nu1x, nu2 = h->p.nu2x;
+  for (int i = 0; i < nu1; ++i) {
+    CHK(op_spatial<T>(h, l, j, transpose, cur, f, nullptr, i == 0 ? cur : oth, SP_JACOBI, UPD_NONE, T(1), i == 0,
+                      om, s));
+    if (i > 0) std::swap(cur, oth);
+  }
+  const Level::Sub& C = L.sub[j + 1];
+  if (nu1 == 0) {
+    HIPCHK(h, launch_fill<T>(cur, len, s));
+    ProfScope ps(h, ST_PROF_XFER_X, l, s);
+    HIPCHK(h, launch_restrict_space<T>(d, nt, f, (T*)C.F, S.n, C.n, slabs, s));
+  } else {
+    CHK(op_spatial<T>(h, l, j, transpose, cur, f, nullptr, oth, SP_DEFECT, UPD_NONE, T(1), false, om, s));
+    ProfScope ps(h, ST_PROF_XFER_X, l, s);
+    HIPCHK(h, launch_restrict_space<T>(d, nt, oth, (T*)C.F, S.n, C.n, slabs, s));
+  }
+  T* ec = nullptr;
+  CHK(spatial_cycle<T>(h, l, j + 1, transpose, (const T*)C.F, nullptr, MODE_STORE, T(1), &ec, s));
+  {
+    ProfScope ps(h, ST_PROF_XFER_X, l, s);
+    HIPCHK(h, launch_prolong_space<T>(d, nt, ec, cur, S.n, C.n, slabs, s));
+  }
+  for (int i = 0; i < nu2; ++i) {
+    if (dst && i == nu2 - 1)
+      return op_spatial<T>(h, l, j, transpose, cur, f, dst, dst, SP_JACOBI, upd_last, sc_last, false, om, s);
+    CHK(op_spatial<T>(h, l, j, transpose, cur, f, nullptr, oth, SP_JACOBI, UPD_NONE, T(1), false, om, s));
+    std::swap(cur, oth);
+  }
+  if (dst) {   // no post-smoothing: combine the prolongated iterate into dst
+    return op_spatial<T>(h, l, j, transpose, cur, cur, dst, dst, SP_JACOBI, upd_last, sc_last, false, T(0), s);
+  }
+  *res = cur;
+  return ST_OK;
+}
+
+bool inexact_level(const st_mg* h, int l) {
+  return h->p.smoother == ST_SMOOTH_SPATIAL_MG && h->lv[l].n > 1;
+}
+
+// x = D^{-1} src (exact) or (I - M^x) D^{-1} src (spatial cycle), written into
+// dst with `mode` as op_block_solve does.
+template <typename T>
+int op_smoother_solve(st_mg* h, int l, bool transpose, const T* src, T* dst, int mode, T omega, T* A, T* B,
+                      hipStream_t s) {
+  if (inexact_level(h, l)) return spatial_cycle<T>(h, l, 0, transpose, src, dst, mode, omega, nullptr, s);
+  return op_block_solve<T>(h, l, transpose, src, dst, mode, omega, A, B, s);
+}
+
 // One damped block-Jacobi step of a small level in one kernel: u_out = u_in +
 // omega D^{-1}(F - L u_in), u_in treated as zero when u_zero.
 template <typename T>
 bool small_level(const st_mg* h, int l) {
   const Level& L = h->lv[l];
+  if (inexact_level(h, l)) return false;
   const bool on = L.small >= 0 ? L.small != 0 : h->small;
   return on && smooth_small_lds(h->p.dim, L.n, L.nx, h->nt, sizeof(T)) > 0;
 }
@@ -627,10 +760,10 @@ int vcycle(st_mg* h, int l, bool transpose, T* u, const T* F, bool u_zero, bool 
   if (small_level<T>(h, l)) return vcycle_small<T>(h, l, transpose, u, F, u_zero, s);
   for (int i = 0; i < h->p.nu1; ++i) {
     if (i == 0 && u_zero) {
-      CHK(op_block_solve<T>(h, l, transpose, F, u, MODE_SET_SCALED, om, A, r, s));
+      CHK(op_smoother_solve<T>(h, l, transpose, F, u, MODE_SET_SCALED, om, A, r, s));
     } else {
       if (!(i == 0 && r_ready)) CHK((op_residual<T, T>(h, l, transpose, u, F, r, false, s)));
-      CHK(op_block_solve<T>(h, l, transpose, r, u, MODE_ADD_SCALED, om, A, r, s));
+      CHK(op_smoother_solve<T>(h, l, transpose, r, u, MODE_ADD_SCALED, om, A, r, s));
     }
   }
   const Level& C = h->lv[l + 1];
@@ -652,7 +785,7 @@ int vcycle(st_mg* h, int l, bool transpose, T* u, const T* F, bool u_zero, bool 
   CHK(op_prolong<T>(h, l, uc, u, s));
   for (int i = 0; i < h->p.nu2; ++i) {
     CHK((op_residual<T, T>(h, l, transpose, u, F, r, false, s)));
-    CHK(op_block_solve<T>(h, l, transpose, r, u, MODE_ADD_SCALED, om, A, r, s));
+    CHK(op_smoother_solve<T>(h, l, transpose, r, u, MODE_ADD_SCALED, om, A, r, s));
   }
   return ST_OK;
 }
@@ -790,6 +923,17 @@ size_t layout(st_mg* h, char* base) {
     L.F = take(len * ib);
     L.r = take(len * ib);
   }
+  for (size_t l = 0; l < h->lv.size(); ++l) {
+    Level& L = h->lv[l];
+    if (h->p.smoother != ST_SMOOTH_SPATIAL_MG || L.n == 1) continue;
+    for (size_t j = 0; j < L.sub.size(); ++j) {
+      Level::Sub& S = L.sub[j];
+      const long long len = (long long)b * L.N * nt * S.nx;
+      S.X = take(len * ib);
+      S.Y = S.n > 1 ? take(len * ib) : nullptr;
+      S.F = j > 0 ? take(len * ib) : nullptr;
+    }
+  }
   if (h->p.precision == ST_MIXED) {
     h->F32 = take(fine * 4);
     h->e32 = take(fine * 4);
@@ -914,6 +1058,10 @@ void st_mg_default_params(st_mg_params* p) {
   p->mu_star = 0.0;
   p->precision = ST_FP64;
   p->batch = 1;
+  p->smoother = ST_SMOOTH_EXACT;
+  p->nu1x = 2;
+  p->nu2x = 2;
+  p->omega_x = 2.0 / 3.0;
 }
 
 int st_mg_setup(const st_mg_params* p, st_mg_t* out) {
@@ -937,6 +1085,10 @@ int st_mg_setup(const st_mg_params* p, st_mg_t* out) {
   else if (p->coarsen < ST_COARSEN_AUTO || p->coarsen > ST_COARSEN_FULL) rc = bad("unknown coarsening rule");
   else if (p->precision < ST_FP64 || p->precision > ST_MIXED) rc = bad("unknown precision");
   else if (p->batch < 1) rc = bad("batch must be >= 1");
+  else if (p->smoother != ST_SMOOTH_EXACT && p->smoother != ST_SMOOTH_SPATIAL_MG) rc = bad("unknown smoother");
+  else if (p->smoother == ST_SMOOTH_SPATIAL_MG &&
+           (p->nu1x < 0 || p->nu2x < 0 || p->nu1x > 16 || p->nu2x > 16 || !(p->omega_x > 0.0 && p->omega_x <= 1.0)))
+    rc = bad("spatial cycle needs 0 <= nu1x, nu2x <= 16 and omega_x in (0, 1]");
   if (rc != ST_OK) {
     // keep the handle alive only to report the message: return it so the caller can read it
     *out = h;
@@ -983,6 +1135,19 @@ int st_mg_setup(const st_mg_params* p, st_mg_t* out) {
     if (full) n = (n - 1) / 2;
     N /= 2;
     tau *= 2.0;
+  }
+  if (p->smoother == ST_SMOOTH_SPATIAL_MG) {
+    for (auto& L : h->lv) {
+      for (int m = L.n; m >= 1; m = (m - 1) / 2) {
+        Level::Sub S;
+        S.n = m;
+        S.nx = 1;
+        for (int i = 0; i < p->dim; ++i) S.nx *= m;
+        S.h = 1.0 / (m + 1);
+        L.sub.push_back(S);
+        if (m == 1) break;
+      }
+    }
   }
   for (auto& L : h->lv) {
     rc = build_level_tables(h, L);
@@ -1140,6 +1305,20 @@ int st_mg_block_solve(st_mg_t h, int level, int prec, int transpose, const void*
                                (float*)h->tmp, level_r<float>(h, level), s);
 }
 
+int st_mg_spatial_cycle(st_mg_t h, int level, int prec, int transpose, const void* r, void* x,
+                        void* stream) {
+  CHK(check_level(h, level, prec, false));
+  if (!r || !x) return fail(h, ST_EINVAL, "null vector");
+  if (h->p.smoother != ST_SMOOTH_SPATIAL_MG)
+    return fail(h, ST_ESTATE, "the spatial cycle needs a handle set up with ST_SMOOTH_SPATIAL_MG");
+  hipStream_t s = (hipStream_t)stream;
+  if (prec == ST_FP64)
+    return spatial_cycle<double>(h, level, 0, transpose != 0, (const double*)r, (double*)x, MODE_STORE, 1.0,
+                                 nullptr, s);
+  return spatial_cycle<float>(h, level, 0, transpose != 0, (const float*)r, (float*)x, MODE_STORE, 1.0f,
+                              nullptr, s);
+}
+
 int st_mg_smooth(st_mg_t h, int level, int prec, int transpose, void* u, const void* F, void* stream) {
   CHK(check_level(h, level, prec, false));
   if (!u || !F) return fail(h, ST_EINVAL, "null vector");
@@ -1147,13 +1326,13 @@ int st_mg_smooth(st_mg_t h, int level, int prec, int transpose, void* u, const v
   if (prec == ST_FP64) {
     double* r = level_r<double>(h, level);
     CHK((op_residual<double, double>(h, level, transpose != 0, (const double*)u, (const double*)F, r, false, s)));
-    return op_block_solve<double>(h, level, transpose != 0, r, (double*)u, MODE_ADD_SCALED, h->p.omega,
-                                  (double*)h->tmp, r, s);
+    return op_smoother_solve<double>(h, level, transpose != 0, r, (double*)u, MODE_ADD_SCALED, h->p.omega,
+                                     (double*)h->tmp, r, s);
   }
   float* r = level_r<float>(h, level);
   CHK((op_residual<float, float>(h, level, transpose != 0, (const float*)u, (const float*)F, r, false, s)));
-  return op_block_solve<float>(h, level, transpose != 0, r, (float*)u, MODE_ADD_SCALED, (float)h->p.omega,
-                               (float*)h->tmp, r, s);
+  return op_smoother_solve<float>(h, level, transpose != 0, r, (float*)u, MODE_ADD_SCALED, (float)h->p.omega,
+                                  (float*)h->tmp, r, s);
 }
 
 int st_mg_restrict(st_mg_t h, int level, int prec, const void* r_fine, void* F_coarse, void* stream) {
@@ -1225,6 +1404,7 @@ int st_mg_autotune(st_mg_t h, void* u_scratch, void* F_scratch, void* stream) {
     (void)hipGraphExecDestroy(h->gc.exec);
     h->gc.exec = nullptr;
   }
+  if (h->p.smoother == ST_SMOOTH_SPATIAL_MG) return ST_OK;   // transforms only on the coarsest level
   if (h->p.precision == ST_FP64) return autotune_all<double>(h, u_scratch, F_scratch, s);
   // float paths: level 0 of the inner cycle lives in workspace buffers
   void* u0 = h->p.precision == ST_MIXED ? h->e32 : u_scratch;

@@ -97,6 +97,42 @@ hipError_t launch_axpy_f32_f64(double* u, const float* e, long long len, hipStre
 hipError_t launch_cast_f64_f32(const double* in, float* out, long long len, hipStream_t s);
 hipError_t launch_cast_f32_f64(const float* in, double* out, long long len, hipStream_t s);
 
+// ------------------------------------------------- spatial multigrid cycle
+// Kernels of the inexact smoother (one geometric multigrid cycle in space per
+// slab, no coupling between slabs).  The slab matrix A = K (x) M_h + M (x) K_h
+// with K = K_tau (or K_tau^T for the adjoint) and M = M_tau; Dinv is the
+// inverse N_t x N_t block of A at one spatial node (its transpose for the
+// adjoint), which on a one-node level is A^{-1} itself.
+enum { SP_JACOBI = 0, SP_DEFECT = 1 };
+enum { UPD_NONE = 0, UPD_ADD = 1, UPD_SET = 2 };
+template <typename T>
+struct SpatialArgs {
+  T K[NT_MAX * NT_MAX];
+  T M[NT_MAX * NT_MAX];
+  T Dinv[NT_MAX * NT_MAX];
+  T wm[3];                // 1-D mass stencil  h/6 * (1, 4, 1)
+  T wk[3];                // 1-D stiffness stencil  1/h * (-1, 2, -1)
+  int n;                  // interior nodes per dimension
+  long long nx;           // n^d
+  long long slabs;        // batch * N
+  T omega;                // Jacobi damping omega_x
+  T scale;                // weight of the result in the output (UPD_ADD / UPD_SET)
+  int op;                 // SP_JACOBI: y = x + omega Dinv (f - A x);  SP_DEFECT: y = f - A x
+  int upd;                // UPD_NONE: out = y;  UPD_ADD: out = base + scale y;  UPD_SET: out = scale y
+  int x_zero;             // x is treated as zero (x may be null)
+};
+template <typename T>
+hipError_t launch_spatial(int dim, int nt, const T* x, const T* f, const T* base, T* out,
+                          const SpatialArgs<T>& a, hipStream_t s);
+// Full weighting in space on every slab (time untouched): fc = (R_x (x) I) rf.
+template <typename T>
+hipError_t launch_restrict_space(int dim, int nt, const T* rf, T* fc, int nf, int nc, long long slabs,
+                                 hipStream_t s);
+// (Bi/tri)linear interpolation in space on every slab, added: uf += (P_x (x) I) ec.
+template <typename T>
+hipError_t launch_prolong_space(int dim, int nt, const T* ec, T* uf, int nf, int nc, long long slabs,
+                                hipStream_t s);
+
 }  // namespace stmg
 
 namespace stmg {

@@ -13,6 +13,7 @@ import torch
 ST_OK, ST_EINVAL, ST_ENOMEM, ST_EHIP, ST_ENOCONV, ST_ESTATE, ST_EWORKSPACE, ST_ENAN = 0, -1, -2, -3, -4, -5, -6, -7
 COARSEN = {"auto": 0, "semi": 1, "full": 2}
 PRECISION = {"fp64": 0, "fp32": 1, "mixed": 2}
+SMOOTHER = {"exact": 0, "spatial_mg": 1}
 FP64, FP32 = 0, 1
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libstmg.so")
@@ -23,7 +24,8 @@ class Params(ctypes.Structure):
         ("dim", ctypes.c_int), ("n", ctypes.c_int), ("T", ctypes.c_double), ("N", ctypes.c_int),
         ("pt", ctypes.c_int), ("omega", ctypes.c_double), ("nu1", ctypes.c_int), ("nu2", ctypes.c_int),
         ("coarsen", ctypes.c_int), ("mu_star", ctypes.c_double), ("precision", ctypes.c_int),
-        ("batch", ctypes.c_int),
+        ("batch", ctypes.c_int), ("smoother", ctypes.c_int), ("nu1x", ctypes.c_int), ("nu2x", ctypes.c_int),
+        ("omega_x", ctypes.c_double),
     ]
 
 
@@ -53,6 +55,7 @@ SIGNATURES = {
     "st_mg_rhs_adjoint": (_i, [_vp, _vp, _vp, _vp, _vp]),
     "st_mg_residual": (_i, [_vp, _i, _i, _i, _vp, _vp, _vp, _dp, _vp]),
     "st_mg_block_solve": (_i, [_vp, _i, _i, _i, _vp, _vp, _vp]),
+    "st_mg_spatial_cycle": (_i, [_vp, _i, _i, _i, _vp, _vp, _vp]),
     "st_mg_smooth": (_i, [_vp, _i, _i, _i, _vp, _vp, _vp]),
     "st_mg_restrict": (_i, [_vp, _i, _i, _vp, _vp, _vp]),
     "st_mg_prolong_add": (_i, [_vp, _i, _i, _vp, _vp, _vp]),
@@ -68,7 +71,7 @@ SIGNATURES = {
 }
 
 PROF_KINDS = {"residual": 0, "pass_fwd": 1, "pass_inv": 2, "fused": 3, "small": 4, "restrict": 5,
-              "prolong": 6, "other": 7}
+              "prolong": 6, "other": 7, "jacobi": 8, "xfer_x": 9}
 
 
 def lib():
@@ -100,18 +103,21 @@ class Solver:
     dim, n, N, pt, T: Omega = (0,1)^dim with n interior nodes per dimension,
     N slabs on (0, T), DG order pt.  omega, nu1, nu2, coarsen ('auto' = the
     mu >= mu* rule, 'semi', 'full'), precision ('fp64', 'fp32', 'mixed'),
-    batch = number of right-hand sides.
+    batch = number of right-hand sides.  smoother: 'exact' (fast
+    diagonalisation) or 'spatial_mg' (one spatial multigrid cycle per slab with
+    nu1x/nu2x damped block-Jacobi steps, damping omega_x).
     """
 
     def __init__(self, dim, n, N, pt=1, T=1.0, omega=0.5, nu1=2, nu2=2, coarsen="auto",
-                 mu_star=0.0, precision="fp64", batch=1, device="cuda:0", workspace=True):
+                 mu_star=0.0, precision="fp64", batch=1, device="cuda:0", workspace=True,
+                 smoother="exact", nu1x=2, nu2x=2, omega_x=2.0 / 3.0):
         if not torch.cuda.is_available():
             raise RuntimeError("stmg needs a ROCm GPU (torch.cuda.is_available() is False)")
         self.device = torch.device(device)
         self._h = ctypes.c_void_p(0)
         L = lib()
         p = Params(dim, n, float(T), N, pt, float(omega), nu1, nu2, COARSEN[coarsen], float(mu_star),
-                   PRECISION[precision], batch)
+                   PRECISION[precision], batch, SMOOTHER[smoother], nu1x, nu2x, float(omega_x))
         with torch.cuda.device(self.device):
             rc = L.st_mg_setup(ctypes.byref(p), ctypes.byref(self._h))
         if rc != ST_OK:
@@ -121,7 +127,8 @@ class Solver:
                 self._h = ctypes.c_void_p(0)
             raise STMGError(rc, msg)
         self.params = dict(dim=dim, n=n, N=N, pt=pt, T=T, omega=omega, nu1=nu1, nu2=nu2,
-                           coarsen=coarsen, precision=precision, batch=batch)
+                           coarsen=coarsen, precision=precision, batch=batch, smoother=smoother,
+                           nu1x=nu1x, nu2x=nu2x, omega_x=omega_x)
         self.dim, self.n, self.N, self.pt, self.batch = dim, n, N, pt, batch
         self.nt = pt + 1
         self.precision = precision
@@ -245,6 +252,17 @@ class Solver:
         x = out if out is not None else torch.empty(nd, dtype=dt, device=self.device)
         self._check(lib().st_mg_block_solve(self._h, level, p, int(transpose), _ptr(r), _ptr(x),
                                             _stream(self.device)))
+        return x
+
+    def spatial_cycle(self, r, level=0, prec=None, transpose=False, out=None):
+        """x = (I - M^x) A^{-1} r per slab: one spatial multigrid cycle from zero."""
+        p = self._prec(prec)
+        dt = self._pdtype(p)
+        nd = self.level_dof(level)
+        r = self._vec(r, nd, dt, "r")
+        x = out if out is not None else torch.empty(nd, dtype=dt, device=self.device)
+        self._check(lib().st_mg_spatial_cycle(self._h, level, p, int(transpose), _ptr(r), _ptr(x),
+                                              _stream(self.device)))
         return x
 
     def smooth(self, u, F, level=0, prec=None, transpose=False):

@@ -52,11 +52,13 @@ def test_default_params():
     L.st_mg_default_params(ctypes.byref(p))
     assert (p.dim, p.n, p.N, p.pt, p.nu1, p.nu2, p.batch) == (1, 31, 16, 1, 2, 2, 1)
     assert p.omega == 0.5 and p.precision == 0
+    assert (p.smoother, p.nu1x, p.nu2x) == (0, 2, 2) and abs(p.omega_x - 2.0 / 3.0) < 1e-15
 
 
 @pytest.mark.parametrize("field,value,msg", [
     ("dim", 4, "dim"), ("n", 30, "n must"), ("N", 12, "N must"), ("pt", 4, "p_t"),
     ("omega", 0.0, "omega"), ("batch", 0, "batch"), ("T", -1.0, "T must"), ("nu1", -1, "nu1"),
+    ("smoother", 2, "smoother"),
 ])
 def test_setup_rejects_invalid_parameters(field, value, msg):
     L = stmg.lib()
@@ -69,3 +71,35 @@ def test_setup_rejects_invalid_parameters(field, value, msg):
     assert h.value
     assert msg in L.st_mg_last_error(h).decode()
     assert L.st_mg_destroy(h) == 0
+
+
+@pytest.mark.parametrize("field,value", [("nu1x", -1), ("nu2x", 17), ("omega_x", 0.0), ("omega_x", 1.5)])
+def test_setup_rejects_invalid_spatial_cycle(field, value):
+    L = stmg.lib()
+    p = stmg.Params()
+    L.st_mg_default_params(ctypes.byref(p))
+    p.smoother = 1
+    setattr(p, field, value)
+    h = ctypes.c_void_p(0)
+    assert L.st_mg_setup(ctypes.byref(p), ctypes.byref(h)) == stmg.ST_EINVAL
+    assert "spatial cycle" in L.st_mg_last_error(h).decode()
+    assert L.st_mg_destroy(h) == 0
+
+
+@pytest.mark.gpu
+def test_spatial_cycle_workspace_is_counted():
+    # the spatial-cycle smoother needs its own vectors on every level with n > 1
+    # (setup uploads the level tables, so this needs a device)
+    L = stmg.lib()
+    sizes = []
+    for sm in (0, 1):
+        p = stmg.Params()
+        L.st_mg_default_params(ctypes.byref(p))
+        p.smoother = sm
+        h = ctypes.c_void_p(0)
+        assert L.st_mg_setup(ctypes.byref(p), ctypes.byref(h)) == 0
+        b = ctypes.c_size_t()
+        assert L.st_mg_workspace_bytes(h, ctypes.byref(b)) == 0
+        sizes.append(b.value)
+        assert L.st_mg_destroy(h) == 0
+    assert sizes[1] > sizes[0]
