@@ -12,7 +12,7 @@
  * L u = F (eq. chap4_generalLinearSystem) has diagonal blocks
  * A = K_tau (x) M_h + M_tau (x) K_h and sub-diagonal blocks -N_tau (x) M_h.
  *
- * Solver (Sec. 2, Sec. 4): V-cycles (gamma = 1) with nu1/nu2 damped
+ * Solver (Sec. 2, Sec. 4): V-cycles (gamma = 1; W-cycles with gamma = 2) with nu1/nu2 damped
  * block-Jacobi steps u <- u + omega D^{-1}(F - L u) (eq. chap4_smoother),
  * D = diag{A} inverted exactly (eq. chap4_smootherExact) by fast
  * diagonalisation; restriction R = P^T with P from eq.
@@ -94,11 +94,12 @@ typedef struct {
   int smoother;     /* ST_SMOOTH_EXACT | ST_SMOOTH_SPATIAL_MG                    */
   int nu1x, nu2x;   /* spatial cycle: pre-/post block-Jacobi steps, 0..16        */
   double omega_x;   /* spatial cycle: Jacobi damping in (0, 1]                   */
+  int gamma;        /* cycle index (Sec. 2): 1 = V-cycle, 2 = W-cycle            */
 } st_mg_params;
 
 /* Fill defaults: d=1, n=31, T=1, N=16, p_t=1, omega=1/2, nu1=nu2=2 (Sec. 4,
  * Example chap4_example1), AUTO coarsening, FP64, batch 1, exact smoother;
- * spatial cycle (when selected) nu1x=nu2x=2, omega_x=2/3 (Sec. 4). */
+ * spatial cycle (when selected) nu1x=nu2x=2, omega_x=2/3 (Sec. 4); V-cycle. */
 void st_mg_default_params(st_mg_params* p);
 
 /* Validate parameters, build the level hierarchy (Sec. 4 rule) and upload the
@@ -167,6 +168,7 @@ int st_mg_prolong_add(st_mg_t h, int level, int prec, const void* e_coarse, void
                       void* stream);
 
 /* ---- cycles and solves on the finest level ----
+ * (V stands for the handle's cycle: gamma coarse-grid cycles per level.)
  * One V-cycle u <- MG(u, F) (ST_MIXED: one refinement step: FP64 residual,
  * FP32 V-cycle for the correction, FP64 update).  relres (nullable, host,
  * batch doubles) receives ||F - L u_new|| / ||F - L u_old|| per RHS. */

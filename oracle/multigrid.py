@@ -85,12 +85,13 @@ class Hierarchy:
 
     def __init__(self, d, n, N, pt, T=1.0, omega=0.5, nu1=2, nu2=2,
                  rule=AUTO, mu_star=None, transpose=False, smoother="exact",
-                 nu1x=2, nu2x=2, omega_x=2.0 / 3.0, depth_x=None):
+                 nu1x=2, nu2x=2, omega_x=2.0 / 3.0, depth_x=None, gamma=1):
         lv, kinds = coarsening_schedule(n, N, T, pt, rule, mu_star)
         self.schedule = kinds                                  # fine -> coarse
         self.levels = [SpaceTimeLevel(d, nL, NL, pt, tauL) for (nL, NL, tauL, _) in lv][::-1]
         self.kinds = kinds[::-1]                               # kinds[k-1]: level k-1 -> k
         self.omega, self.nu1, self.nu2 = omega, nu1, nu2
+        self.gamma = gamma
         self.transpose = transpose
         self.P = [None] + [transfer(self.levels[k], self.levels[k - 1], self.kinds[k - 1])
                            for k in range(1, len(self.levels))]
@@ -152,7 +153,9 @@ class Hierarchy:
         return forward_substitution(lev, F, self.transpose)
 
     def vcycle(self, k, u, F):
-        """One multigrid V-cycle (gamma = 1) on level k (Sec. 2)."""
+        """One multigrid cycle on level k (Sec. 2): gamma = 1 is the V-cycle,
+        gamma = 2 the W-cycle (the coarse problem is approximated by gamma
+        cycles from a zero initial guess)."""
         if k == 0:
             return self.coarsest_solve(F)
         for _ in range(self.nu1):
@@ -160,7 +163,9 @@ class Hierarchy:
         r = self.residual(k, u, F)
         P = self.P[k]
         Fc = P.T @ r                                   # R = P^T
-        ec = self.vcycle(k - 1, np.zeros((self.levels[k - 1].dof, F.shape[1])), Fc)
+        ec = np.zeros((self.levels[k - 1].dof, F.shape[1]))
+        for _ in range(self.gamma):
+            ec = self.vcycle(k - 1, ec, Fc)
         u = u + P @ ec
         for _ in range(self.nu2):
             u = self.smooth(k, u, F)

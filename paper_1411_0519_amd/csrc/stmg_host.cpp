@@ -737,7 +737,7 @@ int vcycle_small(st_mg* h, int l, bool transpose, T* u, const T* F, bool u_zero,
     CHK((op_residual<T, T>(h, l, transpose, u, F, r, false, s)));
     CHK(op_restrict<T>(h, l, r, Fc, s));
   }
-  CHK(vcycle<T>(h, l + 1, transpose, uc, Fc, true, false, s));
+  for (int g = 0; g < h->p.gamma; ++g) CHK(vcycle<T>(h, l + 1, transpose, uc, Fc, g == 0, false, s));
   CHK(op_prolong<T>(h, l, uc, u, s));
   for (int i = 0; i < h->p.nu2; ++i) {
     CHK(op_smooth_small<T>(h, l, transpose, buf[cur], buf[1 - cur], F, false, s));
@@ -747,7 +747,7 @@ int vcycle_small(st_mg* h, int l, bool transpose, T* u, const T* F, bool u_zero,
   return ST_OK;
 }
 
-// One V-cycle on level l.  u_zero: u holds no valid data and is treated as 0
+// One cycle on level l (gamma coarse-grid cycles: V or W).  u_zero: u holds no valid data and is treated as 0
 // (coarse-level corrections).  r_ready: level_r already holds F - L u.
 template <typename T>
 int vcycle(st_mg* h, int l, bool transpose, T* u, const T* F, bool u_zero, bool r_ready,
@@ -775,7 +775,7 @@ int vcycle(st_mg* h, int l, bool transpose, T* u, const T* F, bool u_zero, bool 
     if (!(h->p.nu1 == 0 && r_ready)) CHK((op_residual<T, T>(h, l, transpose, u, F, r, false, s)));
     CHK(op_restrict<T>(h, l, r, Fc, s));
   }
-  CHK(vcycle<T>(h, l + 1, transpose, uc, Fc, true, false, s));
+  for (int g = 0; g < h->p.gamma; ++g) CHK(vcycle<T>(h, l + 1, transpose, uc, Fc, g == 0, false, s));
   if (h->p.nu1 == 0 && u_zero) {
     const long long len = h->lv[l].dof(h->nt, h->p.batch);
     // u has no defined content yet: start the correction from zero (a fill
@@ -1062,6 +1062,7 @@ void st_mg_default_params(st_mg_params* p) {
   p->nu1x = 2;
   p->nu2x = 2;
   p->omega_x = 2.0 / 3.0;
+  p->gamma = 1;
 }
 
 int st_mg_setup(const st_mg_params* p, st_mg_t* out) {
@@ -1089,6 +1090,7 @@ int st_mg_setup(const st_mg_params* p, st_mg_t* out) {
   else if (p->smoother == ST_SMOOTH_SPATIAL_MG &&
            (p->nu1x < 0 || p->nu2x < 0 || p->nu1x > 16 || p->nu2x > 16 || !(p->omega_x > 0.0 && p->omega_x <= 1.0)))
     rc = bad("spatial cycle needs 0 <= nu1x, nu2x <= 16 and omega_x in (0, 1]");
+  else if (p->gamma != 1 && p->gamma != 2) rc = bad("gamma must be 1 (V-cycle) or 2 (W-cycle)");
   if (rc != ST_OK) {
     // keep the handle alive only to report the message: return it so the caller can read it
     *out = h;

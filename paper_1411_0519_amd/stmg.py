@@ -25,7 +25,7 @@ class Params(ctypes.Structure):
         ("pt", ctypes.c_int), ("omega", ctypes.c_double), ("nu1", ctypes.c_int), ("nu2", ctypes.c_int),
         ("coarsen", ctypes.c_int), ("mu_star", ctypes.c_double), ("precision", ctypes.c_int),
         ("batch", ctypes.c_int), ("smoother", ctypes.c_int), ("nu1x", ctypes.c_int), ("nu2x", ctypes.c_int),
-        ("omega_x", ctypes.c_double),
+        ("omega_x", ctypes.c_double), ("gamma", ctypes.c_int),
     ]
 
 
@@ -105,19 +105,20 @@ class Solver:
     mu >= mu* rule, 'semi', 'full'), precision ('fp64', 'fp32', 'mixed'),
     batch = number of right-hand sides.  smoother: 'exact' (fast
     diagonalisation) or 'spatial_mg' (one spatial multigrid cycle per slab with
-    nu1x/nu2x damped block-Jacobi steps, damping omega_x).
+    nu1x/nu2x damped block-Jacobi steps, damping omega_x).  gamma: cycle index
+    (1 = V-cycle, 2 = W-cycle).
     """
 
     def __init__(self, dim, n, N, pt=1, T=1.0, omega=0.5, nu1=2, nu2=2, coarsen="auto",
                  mu_star=0.0, precision="fp64", batch=1, device="cuda:0", workspace=True,
-                 smoother="exact", nu1x=2, nu2x=2, omega_x=2.0 / 3.0):
+                 smoother="exact", nu1x=2, nu2x=2, omega_x=2.0 / 3.0, gamma=1):
         if not torch.cuda.is_available():
             raise RuntimeError("stmg needs a ROCm GPU (torch.cuda.is_available() is False)")
         self.device = torch.device(device)
         self._h = ctypes.c_void_p(0)
         L = lib()
         p = Params(dim, n, float(T), N, pt, float(omega), nu1, nu2, COARSEN[coarsen], float(mu_star),
-                   PRECISION[precision], batch, SMOOTHER[smoother], nu1x, nu2x, float(omega_x))
+                   PRECISION[precision], batch, SMOOTHER[smoother], nu1x, nu2x, float(omega_x), gamma)
         with torch.cuda.device(self.device):
             rc = L.st_mg_setup(ctypes.byref(p), ctypes.byref(self._h))
         if rc != ST_OK:
@@ -128,7 +129,7 @@ class Solver:
             raise STMGError(rc, msg)
         self.params = dict(dim=dim, n=n, N=N, pt=pt, T=T, omega=omega, nu1=nu1, nu2=nu2,
                            coarsen=coarsen, precision=precision, batch=batch, smoother=smoother,
-                           nu1x=nu1x, nu2x=nu2x, omega_x=omega_x)
+                           nu1x=nu1x, nu2x=nu2x, omega_x=omega_x, gamma=gamma)
         self.dim, self.n, self.N, self.pt, self.batch = dim, n, N, pt, batch
         self.nt = pt + 1
         self.precision = precision

@@ -52,13 +52,13 @@ def test_default_params():
     L.st_mg_default_params(ctypes.byref(p))
     assert (p.dim, p.n, p.N, p.pt, p.nu1, p.nu2, p.batch) == (1, 31, 16, 1, 2, 2, 1)
     assert p.omega == 0.5 and p.precision == 0
-    assert (p.smoother, p.nu1x, p.nu2x) == (0, 2, 2) and abs(p.omega_x - 2.0 / 3.0) < 1e-15
+    assert (p.smoother, p.nu1x, p.nu2x, p.gamma) == (0, 2, 2, 1) and abs(p.omega_x - 2.0 / 3.0) < 1e-15
 
 
 @pytest.mark.parametrize("field,value,msg", [
     ("dim", 4, "dim"), ("n", 30, "n must"), ("N", 12, "N must"), ("pt", 4, "p_t"),
     ("omega", 0.0, "omega"), ("batch", 0, "batch"), ("T", -1.0, "T must"), ("nu1", -1, "nu1"),
-    ("smoother", 2, "smoother"),
+    ("smoother", 2, "smoother"), ("gamma", 3, "gamma"), ("gamma", 0, "gamma"),
 ])
 def test_setup_rejects_invalid_parameters(field, value, msg):
     L = stmg.lib()

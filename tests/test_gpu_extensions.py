@@ -215,3 +215,38 @@ def test_autograd_gradients_match_finite_differences():
             fd = (jp - jm) / (2 * eps)
             an = (torch.sum(gf * df) + torch.sum(gu0 * du)).item()
             assert abs(fd - an) <= 1e-7 * max(1.0, abs(an)), (fd, an)
+
+
+# ------------------------------------------------------------------ W-cycle
+@pytest.mark.parametrize("smoother", ["exact", "spatial_mg"])
+@pytest.mark.parametrize("case", [(1, 31, 32, 1, 1), (2, 15, 16, 2, 2), (3, 7, 8, 1, 1)],
+                         ids=lambda c: "d{}n{}N{}p{}b{}".format(*c))
+def test_w_cycle_iterates_match_oracle(case, smoother):
+    d, n, N, pt, b = case
+    print(f"W-cycle {case} {smoother}", flush=True)
+    S = stmg.Solver(d, n, N, pt=pt, batch=b, gamma=2, smoother=smoother, device=DEV)
+    H = multigrid.Hierarchy(d, n, N, pt, gamma=2, smoother="inexact" if smoother == "spatial_mg" else "exact")
+    f, u0 = workloads.make(d, n, N, batch=b, seed=15, f="uniform", u0="sine1")
+    F = spacetime.rhs(H.fine, f, u0)
+    _, _, its = H.solve(F, rtol=0.0, maxit=3, keep_iterates=True)
+    ug = torch.zeros(S.level_dof(0), dtype=torch.float64, device=DEV)
+    for k in range(1, 4):
+        S.solve(to_gpu(F), u=ug, rtol=0.0, maxit=1, raise_on_noconv=False)
+        assert rel_err(to_oracle(ug, b), its[k]) < 1e-12, k
+
+
+def test_w_cycle_graph_replay_matches_eager():
+    d, n, N, pt = 2, 31, 16, 1
+    f, u0 = workloads.make(d, n, N, seed=16, f="uniform", u0="sine1")
+    stream = torch.cuda.Stream(device=DEV)
+    with torch.cuda.stream(stream):
+        E = stmg.Solver(d, n, N, pt=pt, gamma=2, device=DEV)
+        G = stmg.Solver(d, n, N, pt=pt, gamma=2, device=DEV)
+        G.set_graph(True)
+        F = E.rhs(nodal_to_gpu(f), nodal_to_gpu(u0))
+        ue, ug = torch.zeros_like(F), torch.zeros_like(F)
+        for rep in range(3):
+            E.solve(F, u=ue, rtol=0.0, maxit=2, raise_on_noconv=False)
+            G.solve(F, u=ug, rtol=0.0, maxit=2, raise_on_noconv=False)
+            torch.cuda.synchronize()
+            assert torch.equal(ue, ug), rep

@@ -195,3 +195,45 @@ def test_measured_two_grid_matches_lfa(mu, kind):
     theory = lfa.two_grid_factor(pt, mu, kind, 1, 1, nx_grid=256, nt_grid=64)
     assert abs(meas - theory) <= 0.05 * theory, (meas, theory)
     assert meas <= 0.5
+
+
+# ----------------------------------------------------------------- W-cycle
+def test_w_cycle_two_levels_equals_v_cycle():
+    # Sec. 2: the coarsest level is solved exactly, so with one coarsening the
+    # gamma = 2 cycle repeats an exact solve and equals the V-cycle
+    d, n, N, pt = 1, 15, 2, 1
+    V = multigrid.Hierarchy(d, n, N, pt)
+    W = multigrid.Hierarchy(d, n, N, pt, gamma=2)
+    assert len(V.levels) == 2
+    rng = np.random.default_rng(1)
+    u = rng.uniform(-1, 1, (V.fine.dof, 1))
+    F = rng.uniform(-1, 1, (V.fine.dof, 1))
+    assert np.abs(V.vcycle(1, u, F) - W.vcycle(1, u, F)).max() < 1e-14
+
+
+@pytest.mark.parametrize("smoother", ["exact", "inexact"])
+def test_w_cycle_is_closer_to_two_grid_than_v_cycle(smoother):
+    # gamma = 2 squares the coarse-level iteration error, so one W-cycle lands
+    # nearer the two-grid iterate (exact coarse solve) than one V-cycle
+    d, n, N, pt = 1, 31, 32, 1
+    kw = dict(T=64.0 * N / (n + 1) ** 2, rule=multigrid.SEMI, smoother=smoother)
+    V = multigrid.Hierarchy(d, n, N, pt, **kw)
+    W = multigrid.Hierarchy(d, n, N, pt, gamma=2, **kw)
+    assert len(V.levels) >= 4
+    rng = np.random.default_rng(2)
+    u = rng.uniform(0, 1, (V.fine.dof, 1))
+    F = np.zeros_like(u)
+    k = len(V.levels) - 1
+    tg = V.two_grid(u, F)
+    dv = np.linalg.norm(V.vcycle(k, u, F) - tg)
+    dw = np.linalg.norm(W.vcycle(k, u, F) - tg)
+    assert dw <= 0.6 * dv, (dw, dv)
+
+
+def test_w_cycle_converges_to_direct_solution():
+    d, n, N, pt = 2, 15, 16, 1
+    H = multigrid.Hierarchy(d, n, N, pt, gamma=2)
+    F = np.random.default_rng(3).normal(size=(H.fine.dof, 1))
+    u, hist, _ = H.solve(F, rtol=1e-12, maxit=40)
+    ref = spacetime.forward_substitution(H.fine, F)
+    assert np.abs(u - ref).max() <= 1e-9 * np.abs(ref).max()
