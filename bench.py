@@ -125,6 +125,26 @@ def cpu_baseline(budget_s=20.0):
             "host_cpus_available": len(os.sched_getaffinity(0))}
 
 
+def measured_traffic(workload_name, kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    record (FETCH_SIZE / WRITE_SIZE runs, scaled by a device copy of known
+    size), or None when there is no record or the kernel's source changed
+    since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload_name}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    src = os.path.join(ROOT, rec["source"])
+    if rec.get("kernel") != kernel or not os.path.exists(src):
+        return None
+    with open(src, "rb") as fh:
+        if hashlib.sha256(fh.read()).hexdigest() != rec["source_sha256"]:
+            return None
+    return rec
+
+
 def spatial_cycle_bytes(levels, d, nt, b, nu1x=2, nu2x=2, elem=8):
     """Algorithmic HBM bytes of the block-Jacobi/defect launches of one spatial
     cycle per time level (reads of x, f and, for the fused update, u; one
@@ -262,8 +282,14 @@ def main():
     achieved = flops / (avg_ms * 1e-3) / 1e12
     names = {"pass_fwd": "forward x pass (k_pass_reg<double,4,false>)", "pass_inv": "inverse x pass + update (k_pass_reg<double,4,true>)",
              "fused": "fused y pass: forward + time solve + inverse (k_fused_pair<double,4,2>: one wave per time component)"}
+    kernel_ids = {"pass_fwd": "k_pass_reg<double, 4, false, 1, true>", "pass_inv": "k_pass_reg<double, 4, true, 1, true>",
+                  "fused": "k_fused_pair<double, 4, 2>"}
+    rec = measured_traffic(w["name"], kernel_ids[dom])
+    traffic = None if rec is None else rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
     roof = {"kernel": names[dom] + ", fine level", "bound": "mfma", "achieved": achieved,
-            "peak": FP64_MFMA_PEAK_TFS, "unit": "TFLOP/s", "frac": achieved / FP64_MFMA_PEAK_TFS, "traffic": None,
+            "peak": FP64_MFMA_PEAK_TFS, "unit": "TFLOP/s", "frac": achieved / FP64_MFMA_PEAK_TFS, "traffic": traffic,
+            "traffic_read_write_bytes": None if rec is None else [rec["fetch_bytes_per_launch"],
+                                                                  rec["write_bytes_per_launch"]],
             "avg_launch_ms": avg_ms, "launches": cand[dom]["fine_launches"], "flops_per_launch": flops,
             "executed_mfma_flops_per_launch": flops * (L0["n"] + 1) / (2.0 * L0["n"]),
             "hbm_bytes_per_launch": hbm_bytes, "hbm_gbs": hbm_bytes / (avg_ms * 1e-3) / 1e9}

@@ -487,41 +487,70 @@ __device__ inline void store_unfolded(T* __restrict__ dst, bool valid, long long
     }
 }
 
-template <typename T, int HB, bool INV>
+// GPW column groups per wave (loads of every group issued before the first
+// product; scheduling barriers keep the groups' phases apart).  Launched with
+// GPW = 1: with two groups the compiler's register demand drops occupancy to
+// one wave per SIMD.  UNIT: unit stride along the contracted axis (x passes),
+// which lets the loads use immediate offsets from one base address.
+template <typename T, int HB, bool INV, int GPW, bool UNIT>
 __global__ __launch_bounds__(256) void k_pass_reg(const T* __restrict__ in, T* __restrict__ out,
-                                                  const T* __restrict__ Sfrag, int n, long long inner,
+                                                  const T* __restrict__ Sfrag, int n, long long inner_rt,
                                                   long long ncols, T omega, int mode) {
   typedef typename Mfma<T>::acc_t acc_t;
+  const long long inner = UNIT ? 1 : inner_rt;     // UNIT: contiguous columns (x axis)
   const int lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
-  const long long lin = (xcd_linear(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6)) * 16 + r;
-  const bool valid = lin < ncols;
-  const long long o = valid ? lin / inner : 0;
-  const long long pos = valid ? lin - o * inner : 0;
-  const long long base = o * (long long)n * inner + pos;
+  const long long wv = xcd_linear(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
   const int h = (n + 1) >> 1;
-  T bo[4 * HB], be[4 * HB];
-  acc_t acc[2 * HB];
-  if (!INV) {
-    load_folded<T, HB>(in + base, valid, inner, n, h, g, bo, be);
-    folded_mma<T, HB, 0>(Sfrag, h, lane, bo, be, acc);
-    if (!valid) return;
+  bool valid[GPW];
+  long long base[GPW];
+  T bo[GPW][4 * HB], be[GPW][4 * HB];
 #pragma unroll
-    for (int kb = 0; kb < HB; ++kb)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int i = kb * 16 + Mfma<T>::row(g, j);
-        if (i < h) out[base + (long long)i * inner] = acc[kb][j];
-        if (i < h - 1) out[base + (long long)(h + i) * inner] = acc[HB + kb][j];
-      }
-  } else {
+  for (int q = 0; q < GPW; ++q) {
+    const long long lin = (wv * GPW + q) * 16 + r;
+    valid[q] = lin < ncols;
+    const long long o = valid[q] ? lin / inner : 0;
+    const long long pos = valid[q] ? lin - o * inner : 0;
+    base[q] = o * (long long)n * inner + pos;
 #pragma unroll
     for (int ib = 0; ib < 4 * HB; ++ib) {
       const int i = 4 * ib + g;
-      bo[ib] = (valid && i < h) ? in[base + (long long)i * inner] : T(0);
-      be[ib] = (valid && i < h - 1) ? in[base + (long long)(h + i) * inner] : T(0);
+      if (!INV) {          // raw pair loads; folded right before the product
+        bo[q][ib] = (valid[q] && i < h) ? in[base[q] + (long long)i * inner] : T(0);
+        be[q][ib] = (valid[q] && i < h - 1) ? in[base[q] + (long long)(n - 1 - i) * inner] : T(0);
+      } else {
+        bo[q][ib] = (valid[q] && i < h) ? in[base[q] + (long long)i * inner] : T(0);
+        be[q][ib] = (valid[q] && i < h - 1) ? in[base[q] + (long long)(h + i) * inner] : T(0);
+      }
     }
-    folded_mma<T, HB, 1>(Sfrag, h, lane, bo, be, acc);
-    store_unfolded<T, HB>(out + base, valid, inner, n, h, g, acc, mode, omega);
+  }
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int q = 0; q < GPW; ++q) {
+    if (!INV) {
+#pragma unroll
+      for (int ib = 0; ib < 4 * HB; ++ib) {
+        const T x1 = bo[q][ib], x2 = be[q][ib];
+        bo[q][ib] = x1 + x2;
+        be[q][ib] = x1 - x2;
+      }
+    }
+    acc_t acc[2 * HB];
+    folded_mma<T, HB, INV ? 1 : 0>(Sfrag, h, lane, bo[q], be[q], acc);
+    if (!INV) {
+      if (valid[q]) {
+#pragma unroll
+        for (int kb = 0; kb < HB; ++kb)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int i = kb * 16 + Mfma<T>::row(g, j);
+            if (i < h) out[base[q] + (long long)i * inner] = acc[kb][j];
+            if (i < h - 1) out[base[q] + (long long)(h + i) * inner] = acc[HB + kb][j];
+          }
+      }
+    } else {
+      store_unfolded<T, HB>(out + base[q], valid[q], inner, n, h, g, acc, mode, omega);
+    }
+    __builtin_amdgcn_sched_barrier(0);
   }
 }
 
@@ -585,8 +614,8 @@ __global__ __launch_bounds__(256) void k_fused_reg(const double* in, double* out
 // Fused slowest-axis solve with the N_t time components of one 16-column
 // group spread over N_t waves of the workgroup (wave w: column group w / NT,
 // component w % NT).  Each wave keeps only its own component's spectral
-// values; the per-mode time solve exchanges one 16-row block at a time through
-// a double-buffered LDS slot.  FP32 additionally re-lays out each solved block
+// values; for the per-mode time solve all waves write their blocks to LDS,
+// meet at one barrier and read the other components' values.  FP32 additionally re-lays out each solved block
 // from accumulator order (row 4g + j) into B-operand order (row 4j + g) through
 // a per-wave LDS slot before the inverse product.
 template <typename T, int HB, int NT>
@@ -596,7 +625,7 @@ __global__ __launch_bounds__(256) void k_fused_pair(const T* in, T* out, const T
   typedef typename Mfma<T>::acc_t acc_t;
   constexpr bool CHAIN = sizeof(T) == 8;     // accumulator order == B-operand order
   constexpr int CG = NT >= 3 ? 1 : 4 / NT;   // column groups per workgroup
-  __shared__ T xch[2][CG * NT * 64 * 4];
+  __shared__ T xch[2 * HB][CG * NT * 64 * 4];
   __shared__ T rel[CHAIN ? 1 : CG * NT * 256];
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
@@ -614,12 +643,16 @@ __global__ __launch_bounds__(256) void k_fused_pair(const T* in, T* out, const T
     load_folded<T, HB>(in + base, valid, inner, n, h, g, a, d);
     folded_mma<T, HB, 0>(Sfrag, h, lane, a, d, spec);
   }
+  // every 16-row block of every component to LDS, one barrier, then the
+  // per-mode solves read the other components' values without further waits
+#pragma unroll
+  for (int k = 0; k < 2 * HB; ++k)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) xch[k][((cg * NT + l) * 64 + lane) * 4 + j] = spec[k][j];
+  __syncthreads();
 #pragma unroll
   for (int k = 0; k < 2 * HB; ++k) {
-    T* slot = xch[k & 1];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) slot[((cg * NT + l) * 64 + lane) * 4 + j] = spec[k][j];
-    __syncthreads();
+    const T* slot = xch[k];
     const int half = k / HB, kb = k % HB;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -666,22 +699,28 @@ bool reg_path(int impl, int hb) {
 template <typename T>
 hipError_t launch_pass_reg(int hb, bool inverse, const T* in, T* out, const T* Sfrag, int n,
                            long long inner, long long ncols, T omega, int mode, hipStream_t s) {
-  const unsigned grid = (unsigned)((ncols + 63) / 64);
-#define REG_PASS(HB)                                                                              \
-  if (hb == HB) {                                                                                 \
+  const int gpw = 1;
+  const unsigned grid = (unsigned)((ncols + 64 * gpw - 1) / (64 * gpw));
+#define REG_PASS_GU(HB, G, U)                                                                     \
+  if (hb == HB && gpw == G && (inner == 1) == U) {                                                \
     if (inverse)                                                                                  \
-      hipLaunchKernelGGL((k_pass_reg<T, HB, true>), dim3(grid), dim3(256), 0, s, in, out, Sfrag, n, inner, \
+      hipLaunchKernelGGL((k_pass_reg<T, HB, true, G, U>), dim3(grid), dim3(256), 0, s, in, out, Sfrag, n, inner, \
                          ncols, omega, mode);                                                     \
     else                                                                                          \
-      hipLaunchKernelGGL((k_pass_reg<T, HB, false>), dim3(grid), dim3(256), 0, s, in, out, Sfrag, n, inner, \
+      hipLaunchKernelGGL((k_pass_reg<T, HB, false, G, U>), dim3(grid), dim3(256), 0, s, in, out, Sfrag, n, inner, \
                          ncols, omega, mode);                                                     \
     return hipGetLastError();                                                                     \
   }
+#define REG_PASS_G(HB, G) REG_PASS_GU(HB, G, true) REG_PASS_GU(HB, G, false)
+#define REG_PASS(HB) REG_PASS_G(HB, 1)
+
   REG_PASS(1) REG_PASS(2) REG_PASS(4)
   if (sizeof(T) == 4) {
     REG_PASS(8)
   }
 #undef REG_PASS
+#undef REG_PASS_G
+#undef REG_PASS_GU
   return hipErrorInvalidValue;
 }
 
