@@ -597,6 +597,40 @@ int spatial_cycle(st_mg* h, int l, int j, bool transpose, const T* f, T* dst, in
   const long long len = slabs * nt * S.nx;
   const int upd_last = mode == MODE_ADD_SCALED ? UPD_ADD : UPD_SET;
   const T sc_last = mode == MODE_STORE ? T(1) : omega_t;
+  // The one-kernel tail runs only with nu1x, nu2x >= 2: with nu1x = 1, nu2x = 0
+  // it once ended in a memory-aperture fault whose cause is not understood, so
+  // the other step counts keep the kernel-per-step path below.
+  const bool tail_ok = h->p.nu1x >= 2 && h->p.nu2x >= 2;
+  if (tail_ok && spatial_tail_lds(d, S.n, nt, sizeof(T)) > 0 && (int)(L.sub.size() - j) <= TAIL_MAX) {
+    // the rest of the cycle fits in LDS: one kernel, one workgroup per slab
+    TailArgs<T> ta{};
+    const SpatialArgs<T> a0 = spatial_args<T>(h, L, S, transpose, SP_JACOBI, UPD_NONE, T(1), false, om);
+    for (int i = 0; i < nt * nt; ++i) {
+      ta.K[i] = a0.K[i];
+      ta.M[i] = a0.M[i];
+    }
+    ta.levels = (int)L.sub.size() - j;
+    for (int q = 0; q < ta.levels; ++q) {
+      const SpatialArgs<T> aq = spatial_args<T>(h, L, L.sub[j + q], transpose, SP_JACOBI, UPD_NONE, T(1), false, om);
+      for (int i = 0; i < nt * nt; ++i) ta.Dinv[q][i] = aq.Dinv[i];
+      for (int i = 0; i < 3; ++i) {
+        ta.wm[q][i] = aq.wm[i];
+        ta.wk[q][i] = aq.wk[i];
+      }
+      ta.n[q] = L.sub[j + q].n;
+    }
+    ta.slabs = slabs;
+    ta.omega = om;
+    ta.nu1 = h->p.nu1x;
+    ta.nu2 = h->p.nu2x;
+    T* target = dst ? dst : (T*)S.X;
+    ta.upd = dst ? upd_last : UPD_NONE;
+    ta.scale = dst ? sc_last : T(1);
+    ProfScope ps(h, ST_PROF_JACOBI, l, s);
+    HIPCHK(h, launch_spatial_tail<T>(d, nt, f, dst, target, ta, s));
+    if (!dst) *res = (T*)S.X;
+    return ST_OK;
+  }
   if (S.n == 1) {   // one node: exact N_t x N_t solve per slab
     if (dst) return op_spatial<T>(h, l, j, transpose, nullptr, f, dst, dst, SP_JACOBI, upd_last, sc_last, true, T(1), s);
     CHK(op_spatial<T>(h, l, j, transpose, nullptr, f, nullptr, (T*)S.X, SP_JACOBI, UPD_NONE, T(1), true, T(1), s));

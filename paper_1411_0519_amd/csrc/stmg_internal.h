@@ -124,6 +124,32 @@ struct SpatialArgs {
 template <typename T>
 hipError_t launch_spatial(int dim, int nt, const T* x, const T* f, const T* base, T* out,
                           const SpatialArgs<T>& a, hipStream_t s);
+// The coarse end of a spatial cycle in one kernel: one workgroup per slab runs
+// the cycle from sub-level `first` (n_0 = n of that sub-level) down to one node
+// and back with every sub-level vector in LDS.  Per sub-level j (0 = first):
+// Dinv, stencil weights and n.  The result x of the first sub-level is written
+// as out = x, scale*x or base + scale*x (upd as in SpatialArgs).
+constexpr int TAIL_MAX = 8;
+template <typename T>
+struct TailArgs {
+  T K[NT_MAX * NT_MAX];
+  T M[NT_MAX * NT_MAX];
+  T Dinv[TAIL_MAX][NT_MAX * NT_MAX];
+  T wm[TAIL_MAX][3];
+  T wk[TAIL_MAX][3];
+  int n[TAIL_MAX];
+  int levels;             // sub-levels in the tail (last has n = 1)
+  long long slabs;
+  T omega;
+  T scale;
+  int upd;
+  int nu1, nu2;
+};
+// LDS bytes of the tail starting at n (0 if it does not fit the 64 KB budget).
+size_t spatial_tail_lds(int dim, int n, int nt, size_t elem);
+template <typename T>
+hipError_t launch_spatial_tail(int dim, int nt, const T* f, const T* base, T* out, const TailArgs<T>& a,
+                               hipStream_t s);
 // Full weighting in space on every slab (time untouched): fc = (R_x (x) I) rf.
 template <typename T>
 hipError_t launch_restrict_space(int dim, int nt, const T* rf, T* fc, int nf, int nc, long long slabs,

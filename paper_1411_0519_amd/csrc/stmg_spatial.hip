@@ -10,6 +10,9 @@
 //                      smoothed iterate u += omega_t x directly)
 //   k_restrict_space   full weighting in space, time untouched
 //   k_prolong_space    (bi/tri)linear interpolation in space, added
+//   k_spatial_tail     the coarse end of the cycle (from a sub-level whose
+//                      vectors fit in LDS down to one node and back), one
+//                      workgroup per slab
 #include <hip/hip_runtime.h>
 
 #include "stmg_device.h"
@@ -158,7 +161,175 @@ __global__ __launch_bounds__(256) void k_prolong_space(const T* __restrict__ ec,
   }
 }
 
+// Whole spatial cycle from one sub-level down, one workgroup per slab, all
+// vectors in LDS: per sub-level j the iterate pair X_j / Y_j and the right-hand
+// side F_j (NT * n_j^d values each), laid out one sub-level after another.
+template <typename T, int D, int NT>
+__global__ __launch_bounds__(256) void k_spatial_tail(const T* __restrict__ f, const T* base, T* out,
+                                                      TailArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  T* lds = reinterpret_cast<T*>(lds_raw);
+  const long long slab = slab_index();
+  if (slab >= a.slabs) return;
+  T* X[TAIL_MAX];
+  T* Y[TAIL_MAX];
+  T* F[TAIL_MAX];
+  long long nxs[TAIL_MAX];
+  {
+    long long off = 0;
+    for (int j = 0; j < a.levels; ++j) {
+      long long nx = a.n[j];
+      for (int i = 1; i < D; ++i) nx *= a.n[j];
+      nxs[j] = nx;
+      X[j] = lds + off;
+      Y[j] = lds + off + NT * nx;
+      F[j] = lds + off + 2 * NT * nx;
+      off += 3 * NT * nx;
+    }
+  }
+  const long long nx0 = nxs[0];
+  const T* fs = f + slab * NT * nx0;
+  for (long long e = threadIdx.x; e < NT * nx0; e += blockDim.x) F[0][e] = fs[e];
+  __syncthreads();
+  // y = x + w Dinv (f - A x) on sub-level j (x treated as 0 when xz), or the defect
+  auto sweep = [&](int j, const T* x, const T* fj, T* y, bool xz, bool defect, T w) {
+    const long long nx = nxs[j];
+    const int n = a.n[j];
+    for (long long p = threadIdx.x; p < nx; p += blockDim.x) {
+      T mu[NT], ku[NT], xv[NT];
+      if (xz) {
+#pragma unroll
+        for (int l = 0; l < NT; ++l) mu[l] = ku[l] = xv[l] = T(0);
+      } else {
+        int px, py, pz;
+        node_coords<D>(p, n, px, py, pz);
+        stencil_mk<T, D, NT>(x, nx, n, px, py, pz, a.wm[j], a.wk[j], mu, ku);
+#pragma unroll
+        for (int l = 0; l < NT; ++l) xv[l] = x[l * nx + p];
+      }
+      T r[NT];
+#pragma unroll
+      for (int l = 0; l < NT; ++l) {
+        T acc = fj[l * nx + p];
+#pragma unroll
+        for (int k = 0; k < NT; ++k) acc -= a.K[l * NT + k] * mu[k] + a.M[l * NT + k] * ku[k];
+        r[l] = acc;
+      }
+#pragma unroll
+      for (int l = 0; l < NT; ++l) {
+        T v = r[l];
+        if (!defect) {
+          T c = T(0);
+#pragma unroll
+          for (int k = 0; k < NT; ++k) c += a.Dinv[j][l * NT + k] * r[k];
+          v = xv[l] + w * c;
+        }
+        y[l * nx + p] = v;
+      }
+    }
+    __syncthreads();
+  };
+  const int J = a.levels - 1;
+  int cur[TAIL_MAX];          // 0: result in X_j, 1: in Y_j
+  for (int j = 0; j < J; ++j) {
+    T* P[2] = {X[j], Y[j]};
+    int c = 0;
+    if (a.nu1 == 0) {
+      for (long long e = threadIdx.x; e < NT * nxs[j]; e += blockDim.x) X[j][e] = T(0);
+      __syncthreads();
+    }
+    for (int i = 0; i < a.nu1; ++i) {
+      if (i == 0) sweep(j, nullptr, F[j], P[0], true, false, a.omega);
+      else {
+        sweep(j, P[c], F[j], P[1 - c], false, false, a.omega);
+        c ^= 1;
+      }
+    }
+    sweep(j, P[c], F[j], P[1 - c], a.nu1 == 0, true, a.omega);      // defect into the free buffer
+    // full weighting of the defect into F_{j+1}
+    const T* rf = P[1 - c];
+    const int nf = a.n[j], nc = a.n[j + 1];
+    const long long nxf = nxs[j], nxc = nxs[j + 1];
+    for (long long q = threadIdx.x; q < nxc; q += blockDim.x) {
+      int cx, cy, cz;
+      node_coords<D>(q, nc, cx, cy, cz);
+      const int fx = 2 * cx + 1, fy = 2 * cy + 1, fz = 2 * cz + 1;
+#pragma unroll
+      for (int l = 0; l < NT; ++l) {
+        T acc = T(0);
+        for (int dz = (D == 3 ? -1 : 0); dz <= (D == 3 ? 1 : 0); ++dz)
+          for (int dy = (D >= 2 ? -1 : 0); dy <= (D >= 2 ? 1 : 0); ++dy) {
+            const T wzy = (dz == 0 ? T(1) : T(0.5)) * (dy == 0 ? T(1) : T(0.5));
+            const long long zz = (D == 3) ? fz + dz : 0;
+            const long long yy = (D >= 2) ? fy + dy : 0;
+            const T* line = rf + l * nxf + (zz * nf + yy) * nf;
+            acc += wzy * (T(0.5) * line[fx - 1] + line[fx] + T(0.5) * line[fx + 1]);
+          }
+        F[j + 1][l * nxc + q] = acc;
+      }
+    }
+    __syncthreads();
+    cur[j] = c;
+  }
+  // one node: exact N_t x N_t solve
+  sweep(J, nullptr, F[J], X[J], true, false, T(1));
+  cur[J] = 0;
+  for (int j = J - 1; j >= 0; --j) {
+    T* P[2] = {X[j], Y[j]};
+    int c = cur[j];
+    const T* ec = cur[j + 1] ? Y[j + 1] : X[j + 1];
+    const int nf = a.n[j], nc = a.n[j + 1];
+    const long long nxf = nxs[j], nxc = nxs[j + 1];
+    for (long long p = threadIdx.x; p < nxf; p += blockDim.x) {
+      int x, y, z;
+      node_coords<D>(p, nf, x, y, z);
+      int cxs[2], cys[2] = {0, 0}, czs[2] = {0, 0};
+      float wx[2], wy[2] = {1.f, 1.f}, wz[2] = {1.f, 1.f};
+      const int kx = coarse_taps(x, nc, cxs, wx);
+      const int ky = (D >= 2) ? coarse_taps(y, nc, cys, wy) : 1;
+      const int kz = (D == 3) ? coarse_taps(z, nc, czs, wz) : 1;
+#pragma unroll
+      for (int l = 0; l < NT; ++l) {
+        T acc = T(0);
+        for (int iz = 0; iz < kz; ++iz)
+          for (int iy = 0; iy < ky; ++iy)
+            for (int ix = 0; ix < kx; ++ix)
+              acc += (T)(wz[iz] * wy[iy] * wx[ix]) * ec[l * nxc + ((long long)czs[iz] * nc + cys[iy]) * nc + cxs[ix]];
+        P[c][l * nxf + p] += acc;
+      }
+    }
+    __syncthreads();
+    for (int i = 0; i < a.nu2; ++i) {
+      sweep(j, P[c], F[j], P[1 - c], false, false, a.omega);
+      c ^= 1;
+    }
+    cur[j] = c;
+  }
+  const T* res = cur[0] ? Y[0] : X[0];
+  const long long o0 = slab * NT * nx0;
+  for (long long e = threadIdx.x; e < NT * nx0; e += blockDim.x) {
+    T v = res[e];
+    if (a.upd == UPD_ADD) v = base[o0 + e] + a.scale * v;
+    else if (a.upd == UPD_SET) v = a.scale * v;
+    out[o0 + e] = v;
+  }
+}
+
 }  // namespace
+
+size_t spatial_tail_lds(int dim, int n, int nt, size_t elem) {
+  size_t tot = 0;
+  int levels = 0;
+  for (int m = n; m >= 1; m = (m - 1) / 2) {
+    size_t nx = 1;
+    for (int i = 0; i < dim; ++i) nx *= (size_t)m;
+    tot += 3 * (size_t)nt * nx * elem;
+    ++levels;
+    if (m == 1) break;
+  }
+  if (levels > TAIL_MAX || tot > 65536) return 0;
+  return tot;
+}
 
 #define SPATIAL_DISPATCH(KERNEL, GX, ...)                                                             \
   const dim3 grid = slab_grid(GX, slabs);                                                           \
@@ -201,13 +372,31 @@ hipError_t launch_prolong_space(int dim, int nt, const T* ec, T* uf, int nf, int
                                 hipStream_t s) {
   SPATIAL_DISPATCH(k_prolong_space, blocks_for(ipow(nf, dim)), ec, uf, nf, nc, slabs)
 }
+template <typename T>
+hipError_t launch_spatial_tail(int dim, int nt, const T* f, const T* base, T* out, const TailArgs<T>& a,
+                               hipStream_t s) {
+  const size_t lds = spatial_tail_lds(dim, a.n[0], nt, sizeof(T));
+  if (lds == 0) return hipErrorInvalidValue;
+  const dim3 grid = slab_grid(1, a.slabs);
+#define TAIL_CASE(D, NT)                                                                           \
+  if (dim == D && nt == NT) {                                                                      \
+    hipLaunchKernelGGL((k_spatial_tail<T, D, NT>), grid, dim3(256), lds, s, f, base, out, a);      \
+    return hipGetLastError();                                                                      \
+  }
+  TAIL_CASE(1, 1) TAIL_CASE(1, 2) TAIL_CASE(1, 3) TAIL_CASE(1, 4)
+  TAIL_CASE(2, 1) TAIL_CASE(2, 2) TAIL_CASE(2, 3) TAIL_CASE(2, 4)
+  TAIL_CASE(3, 1) TAIL_CASE(3, 2) TAIL_CASE(3, 3) TAIL_CASE(3, 4)
+#undef TAIL_CASE
+  return hipErrorInvalidValue;
+}
 #undef SPATIAL_DISPATCH
 
 #define INST(T)                                                                                       \
   template hipError_t launch_spatial<T>(int, int, const T*, const T*, const T*, T*, const SpatialArgs<T>&, \
                                         hipStream_t);                                                 \
   template hipError_t launch_restrict_space<T>(int, int, const T*, T*, int, int, long long, hipStream_t); \
-  template hipError_t launch_prolong_space<T>(int, int, const T*, T*, int, int, long long, hipStream_t);
+  template hipError_t launch_prolong_space<T>(int, int, const T*, T*, int, int, long long, hipStream_t); \
+  template hipError_t launch_spatial_tail<T>(int, int, const T*, const T*, T*, const TailArgs<T>&, hipStream_t);
 INST(double)
 INST(float)
 #undef INST

@@ -65,6 +65,13 @@ def test_spatial_cycle_parameters(nu, omega_x):
     assert rel_err(to_oracle(x, b), ref) < 1e-13
 
 
+@pytest.mark.skip(reason="the one-kernel LDS tail of the spatial cycle ended in a GPU memory-aperture fault "
+                         "with nu1x = 1, nu2x = 0 (2-D n = 31); the cause was not found, so the library runs the "
+                         "tail only for nu1x, nu2x >= 2 and this configuration takes the kernel-per-step path")
+def test_spatial_tail_with_single_pre_step_and_no_post_step():
+    pass
+
+
 def test_spatial_cycle_on_every_level():
     d, n, N, pt, b = 2, 31, 16, 1, 1
     S = stmg.Solver(d, n, N, pt=pt, batch=b, smoother="spatial_mg", device=DEV)
