@@ -68,8 +68,10 @@ enum {
 enum {
   ST_FP64 = 0,  /* every level in double                                          */
   ST_FP32 = 1,  /* every level in float, norms accumulated in double             */
-  ST_MIXED = 2  /* double outer iterative refinement: fine residual and update in
+  ST_MIXED = 2, /* double outer iterative refinement: fine residual and update in
                    double, inner V-cycle in float, coarsest solve in double       */
+  ST_MIXED_BF16 = 3 /* as ST_MIXED, with the inner cycle's sine transforms on the
+                   bf16 matrix cores (FP32 accumulation and storage)              */
 };
 
 enum {
@@ -89,7 +91,7 @@ typedef struct {
   int nu1, nu2;     /* pre-/post-smoothing steps, >= 0                           */
   int coarsen;      /* ST_COARSEN_*                                              */
   double mu_star;   /* <= 0: computed from R(-3 mu*) = sqrt(2) - 1               */
-  int precision;    /* ST_FP64 | ST_FP32 | ST_MIXED                              */
+  int precision;    /* ST_FP64 | ST_FP32 | ST_MIXED | ST_MIXED_BF16             */
   int batch;        /* number of right-hand sides b >= 1                         */
   int smoother;     /* ST_SMOOTH_EXACT | ST_SMOOTH_SPATIAL_MG                    */
   int nu1x, nu2x;   /* spatial cycle: pre-/post block-Jacobi steps, 0..16        */

@@ -89,6 +89,15 @@ bool invert(int n, double* A) {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Nearest bfloat16 (ties to even) of a double, via the nearest float.
+uint16_t bf16_round(double v) {
+  const float f = (float)v;
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
 struct Level {
   int n = 0, N = 0;
   long long nx = 0;
@@ -97,6 +106,7 @@ struct Level {
   int hb = 0;             // folded transform: 16-row blocks per half
   double* S64 = nullptr;  // folded DST-I in MFMA fragment order
   float* S32 = nullptr;
+  void* S16 = nullptr;    // folded DST-I in bf16 16x16x16 operand order [dir][half][kb][c][lane][4]
   double* G64 = nullptr;  // per-mode inverse blocks [nx][nt][nt]
   float* G32 = nullptr;
   double* Sp64 = nullptr; // plain DST-I (n x n), used by the small-level smoother
@@ -195,6 +205,9 @@ int fail(st_mg_t h, int code, const char* fmt, ...) {
   } while (0)
 
 bool is_pow2(long long x) { return x > 0 && (x & (x - 1)) == 0; }
+
+// FP64 outer refinement around an FP32 inner cycle (FP32 or BF16 transforms).
+bool is_mixed(const st_mg* h) { return h->p.precision == ST_MIXED || h->p.precision == ST_MIXED_BF16; }
 
 // ------------------------------------------------------------------ profiling
 // Event pair around one launch: begin() returns a ticket, end() closes it.
@@ -331,6 +344,17 @@ int build_level_tables(st_mg* h, Level& L) {
             frag[o] = blk(dir, hf, kb * 16 + (lane & 15), ib * 4 + (lane >> 4));
             frag32[o] = (float)frag[o];
           }
+  // bf16 operands of v_mfma_f32_16x16x16_bf16: lane supplies A[lane%16][4(lane/16)+q]
+  std::vector<uint16_t> frag16((size_t)4 * HB * HB * 64 * 4);
+  for (int dir = 0; dir < 2; ++dir)
+    for (int hf = 0; hf < 2; ++hf)
+      for (int kb = 0; kb < HB; ++kb)
+        for (int c = 0; c < HB; ++c)
+          for (int lane = 0; lane < 64; ++lane)
+            for (int q = 0; q < 4; ++q) {
+              const size_t o = (((((size_t)dir * 2 + hf) * HB + kb) * HB + c) * 64 + lane) * 4 + q;
+              frag16[o] = bf16_round(blk(dir, hf, kb * 16 + (lane & 15), c * 16 + 4 * (lane >> 4) + q));
+            }
   // per-mode blocks: mu_k K + nu_k M with mu_k = prod m, nu_k = sum_a kappa_a prod_{b!=a} m_b,
   // m = h/3 (2 + cos), kappa = 2/h (1 - cos) at angle (k+1) pi h
   const double hh = L.h;
@@ -373,6 +397,8 @@ int build_level_tables(st_mg* h, Level& L) {
   HIPCHK(h, hipMalloc(&L.Sp32, Sp32.size() * sizeof(float)));
   HIPCHK(h, hipMemcpy(L.Sp64, Sp.data(), Sp.size() * sizeof(double), hipMemcpyHostToDevice));
   HIPCHK(h, hipMemcpy(L.Sp32, Sp32.data(), Sp32.size() * sizeof(float), hipMemcpyHostToDevice));
+  HIPCHK(h, hipMalloc(&L.S16, frag16.size() * sizeof(uint16_t)));
+  HIPCHK(h, hipMemcpy(L.S16, frag16.data(), frag16.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
   HIPCHK(h, hipMalloc(&L.S64, frag.size() * sizeof(double)));
   HIPCHK(h, hipMalloc(&L.S32, frag32.size() * sizeof(float)));
   HIPCHK(h, hipMalloc(&L.G64, G.size() * sizeof(double)));
@@ -473,6 +499,12 @@ int op_residual(st_mg* h, int l, bool transpose, const Tin* u, const Tin* F, Tou
   return ST_OK;
 }
 
+// Inner-cycle levels of ST_MIXED_BF16 run their transforms on the bf16 matrix cores.
+template <typename T>
+bool bf16_level(const st_mg* h, const Level& L) {
+  return sizeof(T) == 4 && h->p.precision == ST_MIXED_BF16 && L.hb <= 8;
+}
+
 // x = D^{-1} src written into dst with `mode` (store / += omega x / = omega x):
 // folded DST passes along the leading axes, the fused forward/time-solve/inverse
 // pass along the slowest axis, then the inverse passes.  Intermediate data
@@ -491,6 +523,10 @@ int op_block_solve(st_mg* h, int l, bool transpose, const T* src, T* dst, int mo
     for (int i = axis + 1; i < d; ++i) rest *= nn;
     const long long ncols = slabs * nt * rest * inner;
     ProfScope ps(h, inv ? ST_PROF_PASS_INV : ST_PROF_PASS_FWD, l, s);
+    if (bf16_level<T>(h, L)) {
+      HIPCHK(h, launch_pass_bf16(L.hb, inv, (const float*)in, (float*)out, L.S16, n, inner, ncols, (float)om, md, s));
+      return ST_OK;
+    }
     HIPCHK(h, launch_dst_pass<T>(L.impl >= 0 ? L.impl : h->impl, L.hb, axis == 0, inv, in, out, Sof<T>(L), n, inner, ncols, om, md, s));
     return ST_OK;
   };
@@ -498,6 +534,11 @@ int op_block_solve(st_mg* h, int l, bool transpose, const T* src, T* dst, int mo
     long long inner = 1;
     for (int i = 0; i < d - 1; ++i) inner *= nn;
     ProfScope ps(h, ST_PROF_FUSED, l, s);
+    if (bf16_level<T>(h, L)) {
+      HIPCHK(h, launch_fused_bf16(L.hb, nt, (const float*)in, (float*)out, L.S16, (const float*)Gof<T>(L), n, inner,
+                                  slabs, transpose ? 1 : 0, (float)om, md, s));
+      return ST_OK;
+    }
     HIPCHK(h, launch_dst_fused<T>(L.impl >= 0 ? L.impl : h->impl, L.hb, nt, in, out, Sof<T>(L), Gof<T>(L), n, inner, slabs,
                                   transpose ? 1 : 0, om, md, s));
     return ST_OK;
@@ -728,7 +769,7 @@ int coarsest_solve<double>(st_mg* h, bool transpose, double* u, const double* F,
 template <>
 int coarsest_solve<float>(st_mg* h, bool transpose, float* u, const float* F, hipStream_t s) {
   const int l = (int)h->lv.size() - 1;
-  if (h->p.precision == ST_MIXED) {
+  if (is_mixed(h)) {
     // exact coarsest solve kept in double
     const long long len = h->lv[l].dof(h->nt, h->p.batch);
     HIPCHK(h, launch_cast_f32_f64(F, h->cF64, len, s));
@@ -835,7 +876,7 @@ int read_norms(st_mg* h, double* out, hipStream_t s) {
 // residual in the buffer the next cycle starts from.
 template <typename T>
 int fine_residual_norm(st_mg* h, bool transpose, const void* u, const void* F, hipStream_t s) {
-  if (h->p.precision == ST_MIXED)
+  if (is_mixed(h))
     return op_residual<double, float>(h, 0, transpose, (const double*)u, (const double*)F,
                                       (float*)h->F32, true, s);
   return op_residual<T, T>(h, 0, transpose, (const T*)u, (const T*)F, level_r<T>(h, 0), true, s);
@@ -845,7 +886,7 @@ int fine_residual_norm(st_mg* h, bool transpose, const void* u, const void* F, h
 // FP64/FP32: V-cycle reusing r; mixed: inner float V-cycle on L e = r, u += e.
 template <typename T>
 int cycle_body(st_mg* h, bool transpose, void* u, const void* F, hipStream_t s) {
-  if (h->p.precision == ST_MIXED) {
+  if (is_mixed(h)) {
     CHK(vcycle<float>(h, 0, transpose, (float*)h->e32, (const float*)h->F32, true, false, s));
     const long long len = h->lv[0].dof(h->nt, h->p.batch);
     HIPCHK(h, launch_axpy_f32_f64((double*)u, (const float*)h->e32, len, s));
@@ -968,7 +1009,7 @@ size_t layout(st_mg* h, char* base) {
       S.F = j > 0 ? take(len * ib) : nullptr;
     }
   }
-  if (h->p.precision == ST_MIXED) {
+  if (is_mixed(h)) {
     h->F32 = take(fine * 4);
     h->e32 = take(fine * 4);
     const long long cl = h->lv.back().dof(nt, b);
@@ -993,7 +1034,7 @@ int check_level(st_mg* h, int level, int prec, bool need_next) {
   if (prec == ST_FP64 && h->p.precision != ST_FP64)
     return fail(h, ST_EINVAL, "FP64 level operators need a handle set up with ST_FP64");
   if (prec == ST_FP32 && h->p.precision == ST_FP64)
-    return fail(h, ST_EINVAL, "FP32 level operators need a handle set up with ST_FP32 or ST_MIXED");
+    return fail(h, ST_EINVAL, "FP32 level operators need a handle set up with ST_FP32 or ST_MIXED(_BF16)");
   return ST_OK;
 }
 
@@ -1118,7 +1159,7 @@ int st_mg_setup(const st_mg_params* p, st_mg_t* out) {
   else if (!(p->omega > 0.0 && p->omega <= 1.0)) rc = bad("omega must be in (0, 1]");
   else if (p->nu1 < 0 || p->nu2 < 0 || p->nu1 + p->nu2 > 64) rc = bad("nu1, nu2 must be >= 0");
   else if (p->coarsen < ST_COARSEN_AUTO || p->coarsen > ST_COARSEN_FULL) rc = bad("unknown coarsening rule");
-  else if (p->precision < ST_FP64 || p->precision > ST_MIXED) rc = bad("unknown precision");
+  else if (p->precision < ST_FP64 || p->precision > ST_MIXED_BF16) rc = bad("unknown precision");
   else if (p->batch < 1) rc = bad("batch must be >= 1");
   else if (p->smoother != ST_SMOOTH_EXACT && p->smoother != ST_SMOOTH_SPATIAL_MG) rc = bad("unknown smoother");
   else if (p->smoother == ST_SMOOTH_SPATIAL_MG &&
@@ -1202,6 +1243,7 @@ int st_mg_destroy(st_mg_t h) {
   for (auto& L : h->lv) {
     (void)hipFree(L.S64);
     (void)hipFree(L.S32);
+    (void)hipFree(L.S16);
     (void)hipFree(L.G64);
     (void)hipFree(L.G32);
     (void)hipFree(L.Sp64);
@@ -1443,8 +1485,8 @@ int st_mg_autotune(st_mg_t h, void* u_scratch, void* F_scratch, void* stream) {
   if (h->p.smoother == ST_SMOOTH_SPATIAL_MG) return ST_OK;   // transforms only on the coarsest level
   if (h->p.precision == ST_FP64) return autotune_all<double>(h, u_scratch, F_scratch, s);
   // float paths: level 0 of the inner cycle lives in workspace buffers
-  void* u0 = h->p.precision == ST_MIXED ? h->e32 : u_scratch;
-  void* F0 = h->p.precision == ST_MIXED ? h->F32 : F_scratch;
+  void* u0 = is_mixed(h) ? h->e32 : u_scratch;
+  void* F0 = is_mixed(h) ? h->F32 : F_scratch;
   if (!u0 || !F0) return fail(h, ST_EINVAL, "FP32 autotuning needs two fine-level scratch vectors");
   return autotune_all<float>(h, u0, F0, s);
 }

@@ -74,6 +74,12 @@ template <typename T>
 hipError_t launch_dst_fused(int impl, int hb, int nt, const T* in, T* out, const T* Sfrag, const T* G, int n,
                             long long inner, long long outer, int transpose, T omega, int mode,
                             hipStream_t s);
+// BF16 matrix-core transforms on FP32 data (stmg_bf16.hip); F is the level's
+// bf16 fragment table [dir][half][kb][c][lane][4], hb <= 8.
+hipError_t launch_pass_bf16(int hb, bool inverse, const float* in, float* out, const void* F, int n, long long inner,
+                            long long ncols, float omega, int mode, hipStream_t s);
+hipError_t launch_fused_bf16(int hb, int nt, const float* in, float* out, const void* F, const float* G, int n,
+                             long long inner, long long outer, int transpose, float omega, int mode, hipStream_t s);
 template <typename T>
 hipError_t launch_restrict(int dim, int nt, bool full, const T* rf, T* Fc, const TransferArgs<T>& a,
                            hipStream_t s);

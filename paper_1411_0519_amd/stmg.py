@@ -12,7 +12,7 @@ import torch
 
 ST_OK, ST_EINVAL, ST_ENOMEM, ST_EHIP, ST_ENOCONV, ST_ESTATE, ST_EWORKSPACE, ST_ENAN = 0, -1, -2, -3, -4, -5, -6, -7
 COARSEN = {"auto": 0, "semi": 1, "full": 2}
-PRECISION = {"fp64": 0, "fp32": 1, "mixed": 2}
+PRECISION = {"fp64": 0, "fp32": 1, "mixed": 2, "mixed_bf16": 3}
 SMOOTHER = {"exact": 0, "spatial_mg": 1}
 FP64, FP32 = 0, 1
 
@@ -102,7 +102,8 @@ class Solver:
 
     dim, n, N, pt, T: Omega = (0,1)^dim with n interior nodes per dimension,
     N slabs on (0, T), DG order pt.  omega, nu1, nu2, coarsen ('auto' = the
-    mu >= mu* rule, 'semi', 'full'), precision ('fp64', 'fp32', 'mixed'),
+    mu >= mu* rule, 'semi', 'full'), precision ('fp64', 'fp32', 'mixed', 'mixed_bf16':
+    FP64 refinement around an FP32 inner cycle whose transforms use bf16 matrix cores),
     batch = number of right-hand sides.  smoother: 'exact' (fast
     diagonalisation) or 'spatial_mg' (one spatial multigrid cycle per slab with
     nu1x/nu2x damped block-Jacobi steps, damping omega_x).  gamma: cycle index
@@ -343,7 +344,7 @@ class Solver:
     def autotune(self):
         """Pick the fastest kernel family per level by timing smoothing steps.
         Returns [(small, impl, ms) per level]."""
-        if self.precision == "mixed":
+        if self.precision in ("mixed", "mixed_bf16"):
             us = fs = None
         else:
             us, fs = self.empty(), self.empty()

@@ -250,3 +250,66 @@ def test_w_cycle_graph_replay_matches_eager():
             G.solve(F, u=ug, rtol=0.0, maxit=2, raise_on_noconv=False)
             torch.cuda.synchronize()
             assert torch.equal(ue, ug), rep
+
+
+# ------------------------------------------------- BF16 inner-cycle transforms
+BF16_CASES = [(1, 31, 8, 1, 1), (2, 31, 4, 1, 2), (2, 127, 2, 2, 1), (2, 255, 2, 1, 1), (3, 15, 2, 1, 1)]
+
+
+@pytest.mark.parametrize("case", BF16_CASES, ids=lambda c: "d{}n{}N{}p{}b{}".format(*c))
+@pytest.mark.parametrize("transpose", [False, True])
+def test_bf16_block_solve_accuracy(case, transpose):
+    # Each folded product rounds its operands (data and sine matrix) to bfloat16
+    # (unit roundoff 2^-9) and accumulates in FP32; a d-dimensional block solve
+    # has 2d products, so its relative error is bounded by about 2d * 2 * 2^-9.
+    d, n, N, pt, b = case
+    print(f"bf16 block solve {case} transpose={transpose}", flush=True)
+    S = stmg.Solver(d, n, N, pt=pt, batch=b, precision="mixed_bf16", device=DEV)
+    lev = spacetime.SpaceTimeLevel(d, n, N, pt, 1.0 / N)
+    r = rvec(lev.dof, b, 3).astype(np.float32).astype(np.float64)
+    x = to_oracle(S.block_solve(to_gpu(r, torch.float32), prec="fp32", transpose=transpose), b)
+    A = (lev.A.T if transpose else lev.A).tocsc()
+    import scipy.sparse.linalg as spla
+    lu = spla.splu(A)
+    rs = r.reshape(N, lev.slab, b).transpose(1, 0, 2).reshape(lev.slab, -1)
+    xs = x.reshape(N, lev.slab, b).transpose(1, 0, 2).reshape(lev.slab, -1)
+    ref = lu.solve(np.ascontiguousarray(rs))
+    err = np.linalg.norm(xs - ref, axis=0) / np.linalg.norm(ref, axis=0)
+    print("bf16 relative errors", err.max(), flush=True)
+    assert np.all(err <= 4 * d * 2.0 ** -9), err.max()
+    assert err.max() > 2.0 ** -24          # the bf16 path really ran (FP32 transforms are far more accurate)
+
+
+@pytest.mark.parametrize("d,n,N,pt,b", [(2, 31, 32, 1, 1), (3, 15, 16, 1, 1), (2, 63, 32, 2, 2)])
+def test_mixed_bf16_reaches_fp64_tolerance(d, n, N, pt, b):
+    print(f"mixed bf16 {(d, n, N, pt, b)}", flush=True)
+    M = stmg.Solver(d, n, N, pt=pt, batch=b, precision="mixed_bf16", device=DEV)
+    S = stmg.Solver(d, n, N, pt=pt, batch=b, device=DEV)
+    lev = spacetime.SpaceTimeLevel(d, n, N, pt, 1.0 / N)
+    f, u0 = workloads.make(d, n, N, batch=b, seed=4, f="uniform", u0="series16")
+    F = spacetime.rhs(lev, f, u0)
+    Fg = to_gpu(F)
+    um, itm, histm = M.solve(Fg, rtol=1e-10, maxit=40)
+    u64, it64, hist64 = S.solve(Fg, rtol=1e-10, maxit=40)
+    assert max(histm[-1]) <= 1e-10
+    assert itm <= it64 + 4, (itm, it64)
+    r = F - lev.L @ to_oracle(um, b)
+    assert np.all(np.linalg.norm(r, axis=0) <= 1.01e-10 * np.linalg.norm(F, axis=0))
+    assert norm_rel(to_oracle(um, b), spacetime.forward_substitution(lev, F)) < 1e-8
+
+
+def test_mixed_bf16_graph_replay_matches_eager():
+    d, n, N, pt = 2, 31, 16, 1
+    f, u0 = workloads.make(d, n, N, seed=17, f="uniform", u0="sine1")
+    stream = torch.cuda.Stream(device=DEV)
+    with torch.cuda.stream(stream):
+        E = stmg.Solver(d, n, N, pt=pt, precision="mixed_bf16", device=DEV)
+        G = stmg.Solver(d, n, N, pt=pt, precision="mixed_bf16", device=DEV)
+        G.set_graph(True)
+        F = E.rhs(nodal_to_gpu(f), nodal_to_gpu(u0))
+        ue, ug = torch.zeros_like(F), torch.zeros_like(F)
+        for rep in range(3):
+            E.solve(F, u=ue, rtol=0.0, maxit=2, raise_on_noconv=False)
+            G.solve(F, u=ug, rtol=0.0, maxit=2, raise_on_noconv=False)
+            torch.cuda.synchronize()
+            assert torch.equal(ue, ug), rep
