@@ -262,6 +262,24 @@ def main():
         torch.cuda.synchronize()
         tm = time.perf_counter() - t0
         err_mixed = (torch.linalg.vector_norm(um - u64) / torch.linalg.vector_norm(u64)).item()
+        M.close()
+
+        # mixed precision with the inner cycle's transforms on the bf16 matrix cores
+        B = stmg.Solver(d, n, N, pt=pt, batch=b, device=dev, precision="mixed_bf16")
+        if not args.no_autotune:
+            B.autotune()
+        if not args.no_graph:
+            B.set_graph(True)
+        ub = torch.zeros_like(u)
+        B.solve(F, u=ub, rtol=0.0, maxit=2, raise_on_noconv=False)
+        ub.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ub, itsb, histb = B.solve(F, u=ub, rtol=1e-10, maxit=100)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+        err_bf16 = (torch.linalg.vector_norm(ub - u64) / torch.linalg.vector_norm(u64)).item()
+        B.close()
 
         inexact = None
         if not args.no_inexact:
@@ -321,7 +339,9 @@ def main():
         "time_to_1e-10": {"fp64_s": t64, "fp64_cycles": its64, "mixed_s": tm, "mixed_cycles": itsm,
                           "speedup_mixed_vs_fp64": t64 / tm,
                           "mixed_rel_error_vs_fp64": err_mixed,
-                          "fp64_final_relres": hist64[-1][0], "mixed_final_relres": histm[-1][0]},
+                          "fp64_final_relres": hist64[-1][0], "mixed_final_relres": histm[-1][0],
+                          "mixed_bf16_s": tb, "mixed_bf16_cycles": itsb, "speedup_mixed_bf16_vs_fp64": t64 / tb,
+                          "mixed_bf16_rel_error_vs_fp64": err_bf16, "mixed_bf16_final_relres": histb[-1][0]},
         "roofline": roof,
         "residual_kernel": {"bound": "hbm", "achieved": res_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                             "frac": res_gbs / HBM_PEAK_GBS, "avg_launch_ms": res_avg,
