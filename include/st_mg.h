@@ -86,7 +86,8 @@ typedef struct {
   int n;            /* interior nodes per dimension, n = 2^m - 1, 1 <= n <= 255  */
   double T;         /* final time > 0                                            */
   int N;            /* number of time slabs, a power of two                      */
-  int pt;           /* DG order p_t, 0 <= p_t <= 3                               */
+  int pt;           /* DG order p_t, 0 <= p_t <= 47 (p_t <= 3: tuned kernels with
+                       compile-time N_t; higher orders: runtime-N_t kernels)    */
   double omega;     /* damping omega_t of the block-Jacobi smoother (0,1]        */
   int nu1, nu2;     /* pre-/post-smoothing steps, >= 0                           */
   int coarsen;      /* ST_COARSEN_*                                              */

@@ -146,13 +146,17 @@ struct st_mg {
   int nt = 0;
   double mu_star = 0;
   std::vector<Level> lv;
-  double Kt[NT_MAX * NT_MAX] = {};   // K_tau (independent of tau for the Legendre basis)
-  double Mh[NT_MAX * NT_MAX] = {};   // M_tau / tau
-  double ca[NT_MAX] = {};            // psi_l(t_{n-1}^+): N_tau = ca cb^T
-  double cb[NT_MAX] = {};            // psi_l(t_n^-)
-  double ints[NT_MAX] = {};          // int_slab psi_l dt / tau
-  double R1T[NT_MAX * NT_MAX] = {};  // time prolongation blocks (independent of tau)
-  double R2T[NT_MAX * NT_MAX] = {};
+  double Kt[NT_BIG * NT_BIG] = {};   // K_tau (independent of tau for the Legendre basis)
+  double Mh[NT_BIG * NT_BIG] = {};   // M_tau / tau
+  double ca[NT_BIG] = {};            // psi_l(t_{n-1}^+): N_tau = ca cb^T
+  double cb[NT_BIG] = {};            // psi_l(t_n^-)
+  double ints[NT_BIG] = {};          // int_slab psi_l dt / tau
+  double R1T[NT_BIG * NT_BIG] = {};  // time prolongation blocks (independent of tau)
+  double R2T[NT_BIG * NT_BIG] = {};
+  // device copies of the time matrices for N_t > NT_MAX:
+  // [K | K^T | M/tau | ca | cb | ints | R1T | R2T], double and float
+  double* gen64 = nullptr;
+  float* gen32 = nullptr;
   // workspace
   void* ws = nullptr;
   size_t ws_bytes = 0;
@@ -208,6 +212,9 @@ bool is_pow2(long long x) { return x > 0 && (x & (x - 1)) == 0; }
 
 // FP64 outer refinement around an FP32 inner cycle (FP32 or BF16 transforms).
 bool is_mixed(const st_mg* h) { return h->p.precision == ST_MIXED || h->p.precision == ST_MIXED_BF16; }
+
+// High DG orders run the runtime-N_t kernels (time matrices in device memory).
+bool high_order(const st_mg* h) { return h->nt > NT_MAX; }
 
 // ------------------------------------------------------------------ profiling
 // Event pair around one launch: begin() returns a ticket, end() closes it.
@@ -276,7 +283,7 @@ void time_basis(st_mg* h) {
 // matrix (K + lam M)^{-1} N with lam tau = -z; Lemma chap4_theorem2).
 double stability(const st_mg* h, double z) {
   const int nt = h->nt;
-  double A[NT_MAX * NT_MAX];
+  double A[NT_BIG * NT_BIG];
   for (int i = 0; i < nt * nt; ++i) A[i] = h->Kt[i] - z * h->Mh[i];
   if (!invert(nt, A)) return NAN;
   double r = 0.0;
@@ -378,7 +385,7 @@ int build_level_tables(st_mg* h, Level& L) {
         if (b != a) t *= m1[idx[b]];
       nu += t;
     }
-    double blk[NT_MAX * NT_MAX];
+    double blk[NT_BIG * NT_BIG];
     for (int i = 0; i < nt * nt; ++i) blk[i] = mu * h->Kt[i] + nu * L.tau * h->Mh[i];
     if (!invert(nt, blk)) return fail(h, ST_EINVAL, "singular slab block at mode %lld", j);
     for (int i = 0; i < nt * nt; ++i) {
@@ -481,19 +488,77 @@ RhsArgs<T> rhs_args(const st_mg* h) {
   return a;
 }
 
+template <typename T>
+const T* gen_table(const st_mg* h);
+template <>
+const double* gen_table<double>(const st_mg* h) { return h->gen64; }
+template <>
+const float* gen_table<float>(const st_mg* h) { return h->gen32; }
+
+template <typename T>
+GenArgs<T> gen_args(const st_mg* h, const Level& L, bool transpose) {
+  const int nt = h->nt, q = nt * nt;
+  const T* t = gen_table<T>(h);
+  GenArgs<T> a{};
+  a.K = t + (transpose ? q : 0);
+  a.M = t + 2 * q;
+  a.ca = t + 3 * q + (transpose ? nt : 0);
+  a.cb = t + 3 * q + (transpose ? 0 : nt);
+  a.ints = t + 3 * q + 2 * nt;
+  a.tau = (T)L.tau;
+  a.wm[0] = a.wm[2] = (T)(L.h / 6.0);
+  a.wm[1] = (T)(4.0 * L.h / 6.0);
+  a.wk[0] = a.wk[2] = (T)(-1.0 / L.h);
+  a.wk[1] = (T)(2.0 / L.h);
+  a.n = L.n;
+  a.nx = L.nx;
+  a.N = L.N;
+  a.batch = h->p.batch;
+  a.dir = transpose ? +1 : -1;
+  a.nt = nt;
+  return a;
+}
+
+template <typename T>
+GenTransfer<T> gen_transfer(const st_mg* h, int lf) {
+  const Level& F = h->lv[lf];
+  const Level& C = h->lv[lf + 1];
+  const int nt = h->nt, q = nt * nt;
+  const T* t = gen_table<T>(h);
+  GenTransfer<T> a{};
+  a.R1T = t + 3 * q + 3 * nt;
+  a.R2T = t + 4 * q + 3 * nt;
+  a.nf = F.n;
+  a.nc = C.n;
+  a.nxf = F.nx;
+  a.nxc = C.nx;
+  a.Nc = C.N;
+  a.batch = h->p.batch;
+  a.nt = nt;
+  return a;
+}
+
+unsigned resid_blocks(const st_mg* h, const Level& L) {
+  return high_order(h) ? residual_gen_blocks_per_slab(L.nx) : residual_blocks_per_slab(h->p.dim, L.n, L.nx, h->nt);
+}
+
 // ------------------------------------------------------------------ operators
 template <typename Tin, typename Tout>
 int op_residual(st_mg* h, int l, bool transpose, const Tin* u, const Tin* F, Tout* r, bool norms,
                 hipStream_t s) {
   const Level& L = h->lv[l];
-  const ResidArgs<Tin> a = resid_args<Tin>(h, L, transpose);
-  {
+  if (high_order(h)) {
+    ProfScope ps(h, ST_PROF_RESIDUAL, l, s);
+    HIPCHK(h, (launch_residual_gen<Tin, Tout>(h->p.dim, u, F, r, gen_args<Tin>(h, L, transpose),
+                                              norms ? h->partial : nullptr, s)));
+  } else {
+    const ResidArgs<Tin> a = resid_args<Tin>(h, L, transpose);
     ProfScope ps(h, ST_PROF_RESIDUAL, l, s);
     HIPCHK(h, (launch_residual<Tin, Tout>(h->p.dim, h->nt, u, F, r, a, norms ? h->partial : nullptr, s)));
   }
   if (norms) {
     ProfScope ps(h, ST_PROF_OTHER, l, s);
-    const long long per = (long long)residual_blocks_per_slab(h->p.dim, L.n, L.nx, h->nt) * L.N;
+    const long long per = (long long)resid_blocks(h, L) * L.N;
     HIPCHK(h, launch_norm_final(h->partial, per, h->p.batch, h->norm_dev, s));
   }
   return ST_OK;
@@ -543,6 +608,29 @@ int op_block_solve(st_mg* h, int l, bool transpose, const T* src, T* dst, int mo
                                   transpose ? 1 : 0, om, md, s));
     return ST_OK;
   };
+  if (high_order(h)) {
+    // N_t > NT_MAX: transform every axis, per-mode time solve, inverse transforms
+    const T* cur = src;
+    T* bufs[2] = {A, B};
+    for (int ax = 0; ax < d; ++ax) {
+      CHK(pass(ax, false, cur, bufs[ax & 1], MODE_STORE, T(1)));
+      cur = bufs[ax & 1];
+    }
+    T* spec = bufs[(d - 1) & 1];
+    {
+      ProfScope ps(h, ST_PROF_FUSED, l, s);
+      HIPCHK(h, launch_time_solve_gen<T>(spec, spec, Gof<T>(L), L.nx, nt, slabs, transpose ? 1 : 0, T(1),
+                                         MODE_STORE, s));
+    }
+    cur = spec;
+    for (int ax = d - 1; ax >= 0; --ax) {
+      if (ax == 0) return pass(0, true, cur, dst, mode, omega);
+      T* nxt = (cur == A) ? B : A;
+      CHK(pass(ax, true, cur, nxt, MODE_STORE, T(1)));
+      cur = nxt;
+    }
+    return ST_OK;
+  }
   if (d == 1) return fused(src, dst, mode, omega);
   if (d == 2) {
     CHK(pass(0, false, src, A, MODE_STORE, T(1)));
@@ -558,16 +646,24 @@ int op_block_solve(st_mg* h, int l, bool transpose, const T* src, T* dst, int mo
 
 template <typename T>
 int op_restrict(st_mg* h, int l, const T* rf, T* Fc, hipStream_t s) {
-  const TransferArgs<T> a = transfer_args<T>(h, l);
   ProfScope ps(h, ST_PROF_RESTRICT, l, s);
+  if (high_order(h)) {
+    HIPCHK(h, launch_restrict_gen<T>(h->p.dim, h->lv[l].kind == 'f', rf, Fc, gen_transfer<T>(h, l), s));
+    return ST_OK;
+  }
+  const TransferArgs<T> a = transfer_args<T>(h, l);
   HIPCHK(h, launch_restrict<T>(h->p.dim, h->nt, h->lv[l].kind == 'f', rf, Fc, a, s));
   return ST_OK;
 }
 
 template <typename T>
 int op_prolong(st_mg* h, int l, const T* ec, T* uf, hipStream_t s) {
-  const TransferArgs<T> a = transfer_args<T>(h, l);
   ProfScope ps(h, ST_PROF_PROLONG, l, s);
+  if (high_order(h)) {
+    HIPCHK(h, launch_prolong_gen<T>(h->p.dim, h->lv[l].kind == 'f', ec, uf, gen_transfer<T>(h, l), s));
+    return ST_OK;
+  }
+  const TransferArgs<T> a = transfer_args<T>(h, l);
   HIPCHK(h, launch_prolong<T>(h->p.dim, h->nt, h->lv[l].kind == 'f', ec, uf, a, s));
   return ST_OK;
 }
@@ -733,7 +829,7 @@ int op_smoother_solve(st_mg* h, int l, bool transpose, const T* src, T* dst, int
 template <typename T>
 bool small_level(const st_mg* h, int l) {
   const Level& L = h->lv[l];
-  if (inexact_level(h, l)) return false;
+  if (inexact_level(h, l) || high_order(h)) return false;
   const bool on = L.small >= 0 ? L.small != 0 : h->small;
   return on && smooth_small_lds(h->p.dim, L.n, L.nx, h->nt, sizeof(T)) > 0;
 }
@@ -1019,7 +1115,7 @@ size_t layout(st_mg* h, char* base) {
     h->ct64 = (double*)take(cl * 8);
   }
   const Level& L0 = h->lv[0];
-  h->partial_per_batch = std::max<long long>((long long)residual_blocks_per_slab(h->p.dim, L0.n, L0.nx, h->nt) * L0.N, 1024);
+  h->partial_per_batch = std::max<long long>((long long)resid_blocks(h, L0) * L0.N, 1024);
   h->partial = (double*)take(sizeof(double) * h->partial_per_batch * b);
   h->norm_dev = (double*)take(sizeof(double) * b);
   return off;
@@ -1050,7 +1146,7 @@ int tune_level(st_mg* h, int l, T* u, T* F, T* r, T* alt, hipStream_t s) {
   HIPCHK(h, launch_fill<T>(F, len, s));
   struct Cand { int small, impl; };
   std::vector<Cand> cands;
-  const bool can_small = smooth_small_lds(h->p.dim, L.n, L.nx, h->nt, sizeof(T)) > 0;
+  const bool can_small = !high_order(h) && smooth_small_lds(h->p.dim, L.n, L.nx, h->nt, sizeof(T)) > 0;
   if (can_small) cands.push_back({1, TRANSFORM_AUTO});
   cands.push_back({0, TRANSFORM_LDS});
   if (sizeof(T) == 8 && L.hb <= 4) {
@@ -1155,7 +1251,7 @@ int st_mg_setup(const st_mg_params* p, st_mg_t* out) {
   else if (p->n < 1 || p->n > 255 || !is_pow2((long long)p->n + 1)) rc = bad("n must be 2^m - 1 with 1 <= n <= 255");
   else if (!(p->T > 0.0) || !std::isfinite(p->T)) rc = bad("T must be positive");
   else if (!is_pow2(p->N) || p->N > (1 << 20)) rc = bad("N must be a power of two (<= 2^20)");
-  else if (p->pt < 0 || p->pt > NT_MAX - 1) rc = bad("p_t must be in 0..3");
+  else if (p->pt < 0 || p->pt > NT_BIG - 1) rc = bad("p_t must be in 0..47");
   else if (!(p->omega > 0.0 && p->omega <= 1.0)) rc = bad("omega must be in (0, 1]");
   else if (p->nu1 < 0 || p->nu2 < 0 || p->nu1 + p->nu2 > 64) rc = bad("nu1, nu2 must be >= 0");
   else if (p->coarsen < ST_COARSEN_AUTO || p->coarsen > ST_COARSEN_FULL) rc = bad("unknown coarsening rule");
@@ -1166,6 +1262,8 @@ int st_mg_setup(const st_mg_params* p, st_mg_t* out) {
            (p->nu1x < 0 || p->nu2x < 0 || p->nu1x > 16 || p->nu2x > 16 || !(p->omega_x > 0.0 && p->omega_x <= 1.0)))
     rc = bad("spatial cycle needs 0 <= nu1x, nu2x <= 16 and omega_x in (0, 1]");
   else if (p->gamma != 1 && p->gamma != 2) rc = bad("gamma must be 1 (V-cycle) or 2 (W-cycle)");
+  else if (p->smoother == ST_SMOOTH_SPATIAL_MG && p->pt > NT_MAX - 1)
+    rc = bad("the spatial-cycle smoother supports p_t <= 3");
   if (rc != ST_OK) {
     // keep the handle alive only to report the message: return it so the caller can read it
     *out = h;
@@ -1180,6 +1278,32 @@ int st_mg_setup(const st_mg_params* p, st_mg_t* out) {
     h->impl = (v >= TRANSFORM_AUTO && v <= TRANSFORM_REG) ? v : TRANSFORM_AUTO;
   }
   time_basis(h);
+  {
+    const int nt = h->nt, q = nt * nt;
+    std::vector<double> t(5 * q + 3 * nt);
+    for (int l = 0; l < nt; ++l)
+      for (int k = 0; k < nt; ++k) {
+        t[l * nt + k] = h->Kt[l * nt + k];
+        t[q + l * nt + k] = h->Kt[k * nt + l];
+        t[2 * q + l * nt + k] = h->Mh[l * nt + k];
+        t[3 * q + 3 * nt + l * nt + k] = h->R1T[l * nt + k];
+        t[4 * q + 3 * nt + l * nt + k] = h->R2T[l * nt + k];
+      }
+    for (int l = 0; l < nt; ++l) {
+      t[3 * q + l] = h->ca[l];
+      t[3 * q + nt + l] = h->cb[l];
+      t[3 * q + 2 * nt + l] = h->ints[l];
+    }
+    std::vector<float> t32(t.begin(), t.end());
+    if (hipMalloc(&h->gen64, t.size() * sizeof(double)) != hipSuccess ||
+        hipMalloc(&h->gen32, t32.size() * sizeof(float)) != hipSuccess ||
+        hipMemcpy(h->gen64, t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(h->gen32, t32.data(), t32.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
+      h->err = "could not upload the time matrices";
+      *out = h;
+      return ST_EHIP;
+    }
+  }
   h->mu_star = p->mu_star > 0.0 ? p->mu_star : critical_mu(h);
   if (!std::isfinite(h->mu_star)) {
     h->err = "could not compute mu*";
@@ -1250,6 +1374,8 @@ int st_mg_destroy(st_mg_t h) {
     (void)hipFree(L.Sp32);
   }
   if (h->ws_owned && h->ws) (void)hipFree(h->ws);
+  (void)hipFree(h->gen64);
+  (void)hipFree(h->gen32);
   for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
   delete h;
   return ST_OK;
@@ -1327,7 +1453,14 @@ int st_mg_sizes(st_mg_t h, long long* dof, long long* f_len, long long* u0_len) 
 int st_mg_rhs(st_mg_t h, const void* f, const void* u0, void* F, void* stream) {
   if (!h || h->lv.empty() || !f || !F) return h ? fail(h, ST_EINVAL, "null argument") : ST_EINVAL;
   hipStream_t s = (hipStream_t)stream;
-  if (h->p.precision == ST_FP32) {
+  if (high_order(h)) {
+    if (h->p.precision == ST_FP32)
+      HIPCHK(h, launch_rhs_gen<float>(h->p.dim, (const float*)f, (const float*)u0, (float*)F,
+                                      gen_args<float>(h, h->lv[0], false), s));
+    else
+      HIPCHK(h, launch_rhs_gen<double>(h->p.dim, (const double*)f, (const double*)u0, (double*)F,
+                                       gen_args<double>(h, h->lv[0], false), s));
+  } else if (h->p.precision == ST_FP32) {
     HIPCHK(h, launch_rhs<float>(h->p.dim, h->nt, (const float*)f, (const float*)u0, (float*)F,
                                 rhs_args<float>(h), s));
   } else {
@@ -1341,7 +1474,14 @@ int st_mg_rhs_adjoint(st_mg_t h, const void* lam, void* grad_f, void* grad_u0, v
   if (!h || h->lv.empty() || !lam) return h ? fail(h, ST_EINVAL, "null argument") : ST_EINVAL;
   if (!grad_f && !grad_u0) return ST_OK;
   hipStream_t s = (hipStream_t)stream;
-  if (h->p.precision == ST_FP32) {
+  if (high_order(h)) {
+    if (h->p.precision == ST_FP32)
+      HIPCHK(h, launch_rhs_adjoint_gen<float>(h->p.dim, (const float*)lam, (float*)grad_f, (float*)grad_u0,
+                                              gen_args<float>(h, h->lv[0], false), s));
+    else
+      HIPCHK(h, launch_rhs_adjoint_gen<double>(h->p.dim, (const double*)lam, (double*)grad_f, (double*)grad_u0,
+                                               gen_args<double>(h, h->lv[0], false), s));
+  } else if (h->p.precision == ST_FP32) {
     HIPCHK(h, launch_rhs_adjoint<float>(h->p.dim, h->nt, (const float*)lam, (float*)grad_f,
                                         (float*)grad_u0, rhs_args<float>(h), s));
   } else {

@@ -7,7 +7,8 @@
 
 namespace stmg {
 
-constexpr int NT_MAX = 4;          // DG order p_t <= 3
+constexpr int NT_MAX = 4;          // compile-time time dofs of the tuned kernels (p_t <= 3)
+constexpr int NT_BIG = 48;         // runtime time dofs of the high-order kernels (p_t <= 47)
 constexpr int TILE_COLS = 64;      // columns per workgroup of the transform kernel
 
 // Residual r = F - L u (or F - L^T u) on one level.  Time coefficients are
@@ -164,6 +165,52 @@ hipError_t launch_restrict_space(int dim, int nt, const T* rf, T* fc, int nf, in
 template <typename T>
 hipError_t launch_prolong_space(int dim, int nt, const T* ec, T* uf, int nf, int nc, long long slabs,
                                 hipStream_t s);
+
+// ------------------------------------------- high DG orders (N_t > NT_MAX)
+// Time matrices in device memory (direction applied: K or K^T; ca/cb swapped
+// for the adjoint).  stmg_generic.hip.
+template <typename T>
+struct GenArgs {
+  const T* K;             // [nt*nt]
+  const T* M;             // [nt*nt] M_tau / tau
+  const T* ca;            // [nt]
+  const T* cb;            // [nt]
+  const T* ints;          // [nt] int_slab psi_l dt / tau
+  T tau;
+  T wm[3];
+  T wk[3];
+  int n;
+  long long nx;
+  int N;
+  int batch;
+  int dir;                // -1 forward, +1 adjoint
+  int nt;
+};
+template <typename T>
+struct GenTransfer {
+  const T* R1T;           // [nt*nt]
+  const T* R2T;
+  int nf, nc;
+  long long nxf, nxc;
+  int Nc;
+  int batch;
+  int nt;
+};
+template <typename Tin, typename Tout>
+hipError_t launch_residual_gen(int dim, const Tin* u, const Tin* F, Tout* r, const GenArgs<Tin>& a, double* partial,
+                               hipStream_t s);
+unsigned residual_gen_blocks_per_slab(long long nx);
+template <typename T>
+hipError_t launch_time_solve_gen(const T* in, T* out, const T* G, long long nx, int nt, long long slabs, int transpose,
+                                 T omega, int mode, hipStream_t s);
+template <typename T>
+hipError_t launch_restrict_gen(int dim, bool full, const T* rf, T* Fc, const GenTransfer<T>& a, hipStream_t s);
+template <typename T>
+hipError_t launch_prolong_gen(int dim, bool full, const T* ec, T* uf, const GenTransfer<T>& a, hipStream_t s);
+template <typename T>
+hipError_t launch_rhs_gen(int dim, const T* f, const T* u0, T* F, const GenArgs<T>& a, hipStream_t s);
+template <typename T>
+hipError_t launch_rhs_adjoint_gen(int dim, const T* lam, T* gf, T* gu0, const GenArgs<T>& a, hipStream_t s);
 
 }  // namespace stmg
 

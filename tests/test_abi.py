@@ -56,8 +56,8 @@ def test_default_params():
 
 
 @pytest.mark.parametrize("field,value,msg", [
-    ("dim", 4, "dim"), ("n", 30, "n must"), ("N", 12, "N must"), ("pt", 4, "p_t"),
-    ("omega", 0.0, "omega"), ("batch", 0, "batch"), ("T", -1.0, "T must"), ("nu1", -1, "nu1"),
+    ("dim", 4, "dim"), ("n", 30, "n must"), ("N", 12, "N must"), ("pt", -1, "p_t"),
+    ("omega", 0.0, "omega"), ("batch", 0, "batch"), ("T", -1.0, "T must"), ("nu1", -1, "nu1"), ("pt", 48, "p_t"),
     ("smoother", 2, "smoother"), ("gamma", 3, "gamma"), ("gamma", 0, "gamma"),
 ])
 def test_setup_rejects_invalid_parameters(field, value, msg):
@@ -103,3 +103,15 @@ def test_spatial_cycle_workspace_is_counted():
         sizes.append(b.value)
         assert L.st_mg_destroy(h) == 0
     assert sizes[1] > sizes[0]
+
+
+def test_spatial_smoother_rejects_high_orders():
+    L = stmg.lib()
+    p = stmg.Params()
+    L.st_mg_default_params(ctypes.byref(p))
+    p.smoother = 1
+    p.pt = 4
+    h = ctypes.c_void_p(0)
+    assert L.st_mg_setup(ctypes.byref(p), ctypes.byref(h)) == stmg.ST_EINVAL
+    assert "p_t <= 3" in L.st_mg_last_error(h).decode()
+    assert L.st_mg_destroy(h) == 0

@@ -237,3 +237,21 @@ def test_w_cycle_converges_to_direct_solution():
     u, hist, _ = H.solve(F, rtol=1e-12, maxit=40)
     ref = spacetime.forward_substitution(H.fine, F)
     assert np.abs(u - ref).max() <= 1e-9 * np.abs(ref).max()
+
+
+
+@pytest.mark.parametrize("pt", [4, 10])
+def test_high_order_iterations_in_table2_range(pt):
+    # Example chap4_example2 / Table chap4_TableExample2: tau = 1, zero right-hand
+    # side, random start in [0, 1], eps_MG = 1e-8, the Example 1 smoother (one
+    # spatial V-cycle per slab): 4..7 iterations for every p_t.  Q1 here, P1
+    # there: a range check with one iteration of slack.
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "iterations.json")) as fh:
+        lo, hi = json.load(fh)["table2_range"]
+    d, n, N = 2, 7, 32
+    H = multigrid.Hierarchy(d, n, N, pt, T=float(N), smoother="inexact")
+    u0 = np.random.default_rng(3).uniform(0, 1, (H.fine.dof, 1))
+    _, hist, _ = H.solve(np.zeros_like(u0), u=u0, rtol=1e-8, maxit=40)
+    assert lo - 1 <= len(hist) - 1 <= hi + 1, len(hist) - 1
