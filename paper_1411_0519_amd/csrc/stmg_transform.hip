@@ -535,7 +535,9 @@ __global__ __launch_bounds__(256) void k_pass_reg(const T* __restrict__ in, T* _
       }
     }
     acc_t acc[2 * HB];
-    folded_mma<T, HB, INV ? 1 : 0>(Sfrag, h, lane, bo[q], be[q], acc);
+    const T* Sf = Sfrag;
+    asm volatile("" : "+s"(Sf));     // no reuse of one group's fragment loads by the next
+    folded_mma<T, HB, INV ? 1 : 0>(Sf, h, lane, bo[q], be[q], acc);
     if (!INV) {
       if (valid[q]) {
 #pragma unroll
@@ -699,7 +701,7 @@ bool reg_path(int impl, int hb) {
 template <typename T>
 hipError_t launch_pass_reg(int hb, bool inverse, const T* in, T* out, const T* Sfrag, int n,
                            long long inner, long long ncols, T omega, int mode, hipStream_t s) {
-  const int gpw = 1;
+  const int gpw = (sizeof(T) == 8 && hb == 4 && inner == 1) ? 2 : 1;
   const unsigned grid = (unsigned)((ncols + 64 * gpw - 1) / (64 * gpw));
 #define REG_PASS_GU(HB, G, U)                                                                     \
   if (hb == HB && gpw == G && (inner == 1) == U) {                                                \
@@ -713,6 +715,9 @@ hipError_t launch_pass_reg(int hb, bool inverse, const T* in, T* out, const T* S
   }
 #define REG_PASS_G(HB, G) REG_PASS_GU(HB, G, true) REG_PASS_GU(HB, G, false)
 #define REG_PASS(HB) REG_PASS_G(HB, 1)
+  if (sizeof(T) == 8) {
+    REG_PASS_GU(4, 2, true)
+  }
 
   REG_PASS(1) REG_PASS(2) REG_PASS(4)
   if (sizeof(T) == 4) {
