@@ -300,7 +300,7 @@ def main():
     achieved = flops / (avg_ms * 1e-3) / 1e12
     names = {"pass_fwd": "forward x pass (k_pass_reg<double,4,false>)", "pass_inv": "inverse x pass + update (k_pass_reg<double,4,true>)",
              "fused": "fused y pass: forward + time solve + inverse (k_fused_pair<double,4,2>: one wave per time component)"}
-    kernel_ids = {"pass_fwd": "k_pass_reg<double, 4, false, 1, true>", "pass_inv": "k_pass_reg<double, 4, true, 1, true>",
+    kernel_ids = {"pass_fwd": "k_pass_reg<double, 4, false, 2, true>", "pass_inv": "k_pass_reg<double, 4, true, 2, true>",
                   "fused": "k_fused_pair<double, 4, 2>"}
     rec = measured_traffic(w["name"], kernel_ids[dom])
     traffic = None if rec is None else rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]

@@ -14,6 +14,9 @@ Modules
   spacetime  block system L u = f and its right-hand side (Sec. 1)
   multigrid  hierarchy, coarsening rule, smoother, V-cycle, solve, adjoint (Sec. 2, Sec. 4)
   lfa        local Fourier analysis: symbols, smoothing and two-grid factors (Sec. 3)
+  spatial_mg one spatial multigrid cycle per slab, the inexact smoother (Remark V-cycleApproxSpace)
+  mesh       red refinement of triangles/tetrahedra, P1 matrices, nested interpolation (Sec. 4 examples)
+  p1         the space-time hierarchy on P1 meshes (Sec. 4 examples)
 
 Every function is pinned by a CPU test against something other than itself
 (values printed in the paper, closed forms, textbook special cases, brute

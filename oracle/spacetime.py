@@ -15,12 +15,17 @@ from . import dg_time, fe_space
 class SpaceTimeLevel:
     """Matrices of one space-time level (d, n interior nodes, N slabs of length tau)."""
 
-    def __init__(self, d, n, N, pt, tau):
+    def __init__(self, d, n, N, pt, tau, space=None):
+        """space = (M_h, K_h, h) replaces the Q1 matrices of the n^d grid (P1 meshes)."""
         self.d, self.n, self.N, self.pt, self.tau = d, n, N, pt, tau
-        self.h = 1.0 / (n + 1)
         self.nt = pt + 1
-        self.nx = n ** d
-        self.Mh, self.Kh = fe_space.q1_matrices(d, n)
+        if space is None:
+            self.h = 1.0 / (n + 1)
+            self.nx = n ** d
+            self.Mh, self.Kh = fe_space.q1_matrices(d, n)
+        else:
+            self.Mh, self.Kh, self.h = space
+            self.nx = self.Mh.shape[0]
         self.Kt, self.Mt, self.Nt = dg_time.time_matrices(pt, tau)
         self.A = (sp.kron(self.Kt, self.Mh) + sp.kron(self.Mt, self.Kh)).tocsc()
         self.B = (-sp.kron(self.Nt, self.Mh)).tocsr()

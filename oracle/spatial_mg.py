@@ -36,15 +36,23 @@ def spatial_sizes(n, depth=None):
 class SpatialCycle:
     """One spatial multigrid cycle for A_{tau,h} on every column of a [l][space] block."""
 
-    def __init__(self, d, n, pt, tau, nu1=2, nu2=2, omega=2.0 / 3.0, transpose=False, depth=None):
+    def __init__(self, d, n, pt, tau, nu1=2, nu2=2, omega=2.0 / 3.0, transpose=False, depth=None, space=None):
+        """space = (mats, prolongations) gives the spatial hierarchy explicitly
+        (P1 meshes): mats[j] = (M_j, K_j) from fine to coarse, prolongations[j-1]
+        the interpolation from sub-level j to j-1."""
         self.d, self.n, self.pt, self.tau = d, n, pt, tau
         self.nu1, self.nu2, self.omega = nu1, nu2, omega
-        self.ns = spatial_sizes(n, depth)
+        if space is None:
+            self.ns = spatial_sizes(n, depth)
+            mats = [fe_space.q1_matrices(d, nj) for nj in self.ns]
+            pros = [fe_space.space_prolongation(d, nj) for nj in self.ns[1:]]
+        else:
+            mats, pros = space
+            self.ns = [M.shape[0] for M, _ in mats]
         Kt, Mt, _ = dg_time.time_matrices(pt, tau)
         nt = pt + 1
         self.A, self.Dlu, self.P = [], [], []
-        for j, nj in enumerate(self.ns):
-            Mh, Kh = fe_space.q1_matrices(d, nj)
+        for j, (Mh, Kh) in enumerate(mats):
             A = sp.kron(Kt, Mh) + sp.kron(Mt, Kh)
             D = sp.kron(Kt, sp.diags(Mh.diagonal())) + sp.kron(Mt, sp.diags(Kh.diagonal()))
             if transpose:
@@ -52,7 +60,7 @@ class SpatialCycle:
             self.A.append(A.tocsr())
             self.Dlu.append(spla.splu(D.tocsc()))
             if j > 0:
-                self.P.append(sp.kron(sp.identity(nt), fe_space.space_prolongation(d, nj), format="csr"))
+                self.P.append(sp.kron(sp.identity(nt), pros[j - 1], format="csr"))
         self.coarse_lu = spla.splu(self.A[-1].tocsc())
 
     def cycle(self, f, j=0):

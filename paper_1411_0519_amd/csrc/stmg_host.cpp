@@ -1152,6 +1152,8 @@ int tune_level(st_mg* h, int l, T* u, T* F, T* r, T* alt, hipStream_t s) {
   if (sizeof(T) == 8 && L.hb <= 4) {
     cands.push_back({0, TRANSFORM_AUTO});
     cands.push_back({0, TRANSFORM_REG});
+  } else if (sizeof(T) == 4 && L.hb <= 8) {
+    cands.push_back({0, TRANSFORM_AUTO});
   }
   hipEvent_t e0, e1;
   HIPCHK(h, hipEventCreate(&e0));
@@ -1170,11 +1172,18 @@ int tune_level(st_mg* h, int l, T* u, T* F, T* r, T* alt, hipStream_t s) {
     };
     int rc = step();
     float ms = 1e30f;
-    for (int rep = 0; rep < 3 && rc == ST_OK; ++rep) {
+    for (int rep = 0; rep < 5 && rc == ST_OK; ++rep) {
+      // the spin holds the stream while the host queues the step, so the
+      // events time the kernels and not the launch latency between them
+      if (launch_spin(200.0, s) != hipSuccess) {
+        rc = ST_EHIP;
+        break;
+      }
       (void)hipEventRecord(e0, s);
       rc = step();
       (void)hipEventRecord(e1, s);
       (void)hipEventSynchronize(e1);
+      if (rc != ST_OK) break;
       float t = 0.f;
       (void)hipEventElapsedTime(&t, e0, e1);
       ms = std::min(ms, t);

@@ -100,6 +100,9 @@ hipError_t launch_norm_final(const double* partial, long long per_batch, int bat
                              hipStream_t s);
 template <typename T>
 hipError_t launch_fill(T* v, long long len, hipStream_t s);
+// Idle one wave for about `microseconds` (capped at 5 ms) so that the launches
+// queued behind it run without host-side gaps; used to time short sequences.
+hipError_t launch_spin(double microseconds, hipStream_t s);
 hipError_t launch_axpy_f32_f64(double* u, const float* e, long long len, hipStream_t s);
 hipError_t launch_cast_f64_f32(const double* in, float* out, long long len, hipStream_t s);
 hipError_t launch_cast_f32_f64(const float* in, double* out, long long len, hipStream_t s);

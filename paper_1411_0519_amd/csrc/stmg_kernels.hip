@@ -404,6 +404,16 @@ __global__ __launch_bounds__(256) void k_fill(T* __restrict__ v, long long len) 
   if (i < len) v[i] = T(0);
 }
 
+// One wave that idles for `ticks` of the constant-rate wall clock (bounded by an
+// iteration cap as well), so that work queued behind it starts back to back.
+__global__ __launch_bounds__(64) void k_spin(long long ticks) {
+  const long long t0 = (long long)wall_clock64();
+  for (int it = 0; it < (1 << 22); ++it) {
+    if ((long long)wall_clock64() - t0 >= ticks) break;
+    __builtin_amdgcn_s_sleep(2);
+  }
+}
+
 __global__ __launch_bounds__(256) void k_axpy_f32_f64(double* __restrict__ u,
                                                       const float* __restrict__ e, long long len) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -550,6 +560,17 @@ hipError_t launch_norm_final(const double* partial, long long per_batch, int bat
 template <typename T>
 hipError_t launch_fill(T* v, long long len, hipStream_t s) {
   hipLaunchKernelGGL((k_fill<T>), dim3(blocks_for(len)), dim3(256), 0, s, v, len);
+  return hipGetLastError();
+}
+
+hipError_t launch_spin(double microseconds, hipStream_t s) {
+  int dev = 0, khz = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
+  if (e != hipSuccess) return e;
+  if (khz <= 0) khz = 100000;
+  const double us = microseconds < 0 ? 0.0 : (microseconds > 5000.0 ? 5000.0 : microseconds);
+  hipLaunchKernelGGL(k_spin, dim3(1), dim3(64), 0, s, (long long)(us * 1e-3 * khz));
   return hipGetLastError();
 }
 

@@ -17,6 +17,14 @@ Workloads (d, n interior nodes per dimension, N slabs on (0,T), DG order p_t):
       (rhs, node, slab), u0 = 16-mode sine series per rhs
   W5  2-D, n=255, N=1024, p_t=1, T=1: f ~ U[-1,1], u0 = sin sin, target u_d =
       16-mode sine series (constant in time)
+
+Coarse simplicial meshes of the numerical examples (Sec. 4), refined by the
+method's own code:
+  square4  (0,1)^2 as 4 triangles around the centre (Example 2)
+  cube12   (0,1)^3 as 12 tetrahedra: every face cut along the diagonal through
+           its corner nearest the origin, each half joined to the centre
+           (Example 1; four uniform refinements give the 49,152 tetrahedra of
+           the parallel example)
 """
 import numpy as np
 
@@ -121,3 +129,43 @@ def target_state(dim, n, seed):
 def random_start(dof, batch, seed):
     """Random initial iterate with values in [0,1] (paper's contraction protocol)."""
     return np.random.default_rng(seed).uniform(0.0, 1.0, size=(batch, dof))
+
+
+def coarse_mesh(kind):
+    """(coords, cells): vertex coordinates (float64, rows x dim) and cells (int32,
+    rows of dim+1 vertex indices) of a built-in coarse mesh."""
+    if kind == "square4":
+        coords = np.array([[0, 0], [1, 0], [1, 1], [0, 1], [0.5, 0.5]], dtype=np.float64)
+        cells = np.array([[0, 1, 4], [1, 2, 4], [2, 3, 4], [3, 0, 4]], dtype=np.int32)
+        return coords, cells
+    if kind == "cube12":
+        corners = [[x, y, z] for z in (0, 1) for y in (0, 1) for x in (0, 1)]   # index x + 2y + 4z
+        coords = np.array(corners + [[0.5, 0.5, 0.5]], dtype=np.float64)
+        faces = [(0, 2, 6), (0, 6, 4), (1, 3, 7), (1, 7, 5), (0, 1, 5), (0, 5, 4),
+                 (2, 3, 7), (2, 7, 6), (0, 1, 3), (0, 3, 2), (4, 5, 7), (4, 7, 6)]
+        cells = np.array([list(f) + [8] for f in faces], dtype=np.int32)
+        return coords, cells
+    raise ValueError(kind)
+
+
+def mesh_data(points, N, batch=1, seed=0, f="uniform", u0="sine1"):
+    """Nodal data at given node coordinates (rows x dim): f of shape (batch, N,
+    nodes), u0 of shape (batch, nodes); the same recipes as `make`."""
+    rng = np.random.default_rng(seed)
+    pts = np.asarray(points, dtype=np.float64)
+    nx = pts.shape[0]
+    if f == "uniform":
+        fa = rng.uniform(-1.0, 1.0, size=(batch, N, nx))
+    elif f == "zero":
+        fa = np.zeros((batch, N, nx))
+    else:
+        raise ValueError(f)
+    if u0 == "sine1":
+        ua = np.broadcast_to(np.prod(np.sin(np.pi * pts), axis=1), (batch, nx)).copy()
+    elif u0 == "uniform01":
+        ua = rng.uniform(0.0, 1.0, size=(batch, nx))
+    elif u0 == "zero":
+        ua = np.zeros((batch, nx))
+    else:
+        raise ValueError(u0)
+    return fa, ua
