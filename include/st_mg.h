@@ -110,6 +110,52 @@ void st_mg_default_params(st_mg_params* p);
  * only the constant tables; no vector workspace.  *out owned by the caller
  * until st_mg_destroy. */
 int st_mg_setup(const st_mg_params* p, st_mg_t* out);
+
+/* ---- P1 simplicial meshes (Sec. 4, Examples chap4_example1 and chap4_example2) ----
+ * Space is discretised with conforming P1 elements on a coarse triangle (d = 2)
+ * or tetrahedron (d = 3) mesh refined `refinements` times by red refinement
+ * (every edge halved; a tetrahedron's inner octahedron cut along its shortest
+ * diagonal, ties broken by the lexicographically smallest endpoint
+ * coordinates).  Nodes on boundary faces (faces of one cell) carry the
+ * homogeneous Dirichlet condition; the unknowns are the interior nodes in node
+ * order, old vertices first, then edge midpoints in the order a sweep over the
+ * cells (local edges (0,1),(0,2),(0,3),(1,2),(1,3),(2,3)) meets them.  Level
+ * transfers: nested interpolation in space (an edge node takes the mean of its
+ * edge's ends), eq. chap4_restrictionTime in time, R = P^T.  The mesh size in
+ * mu = tau/h^2 is h_L = h0 2^-L on refinement level L. */
+typedef struct {
+  int dim;              /* 2: triangles, 3: tetrahedra                            */
+  int nnodes;           /* vertices of the coarse mesh, >= dim + 1                */
+  int ncells;           /* cells of the coarse mesh, >= 1                         */
+  const double* coords; /* HOST, nnodes x dim, row-major                          */
+  const int* cells;     /* HOST, ncells x (dim + 1) vertex indices, each cell of
+                           positive volume                                        */
+  double h0;            /* coarse mesh size for the coarsening rule; <= 0: its
+                           longest edge                                           */
+} st_mesh;
+
+/* Host-only query (no GPU needed): refinement level `level` (0..refinements)
+ * of `coarse`.  nx = interior nodes, nnz = stored entries of the interior
+ * M_h / K_h (CSR, one shared pattern, columns ascending).  Each output array
+ * may be NULL; otherwise points (nx x dim), rowptr (nx + 1), col (nnz),
+ * mval / kval (nnz) are filled.  ST_EINVAL for an invalid mesh (index out of
+ * range, degenerate cell, dim mismatch) or level < 0; ST_ENOMEM when the
+ * refined mesh would exceed 2^31 - 1 nodes or entries. */
+int st_mesh_level(const st_mesh* coarse, int level, long long* nx, long long* nnz, double* points,
+                  int* rowptr, int* col, double* mval, double* kval);
+
+/* st_mg_setup for the P1 mesh `coarse` refined `refinements` (0..10) times:
+ * the paper's inexact smoother is required (p->smoother = ST_SMOOTH_SPATIAL_MG:
+ * node-block Jacobi in space, nu1x/nu2x steps damped by omega_x, down to the
+ * coarse mesh, where each slab is solved exactly); p->n is ignored; p->dim must
+ * equal coarse->dim; 0 <= p_t <= 3; precision ST_FP64 or ST_FP32.  The exact
+ * slab solves of the coarse mesh and of the coarsest level use dense inverses
+ * built at setup: N_t x (interior nodes) <= 1024 on both, else ST_EINVAL (refine
+ * less, or use more time slabs so that space is coarsened further).  In the
+ * per-level queries n_L reports the refinement level.  Vectors use the layout
+ * [batch][slab][time dof l][interior node]. */
+int st_mg_setup_mesh(const st_mg_params* p, const st_mesh* coarse, int refinements, st_mg_t* out);
+
 int st_mg_destroy(st_mg_t h);
 const char* st_mg_last_error(st_mg_t h);
 
@@ -128,6 +174,9 @@ int st_mg_level_info(st_mg_t h, int level, int* n, int* N, double* tau, double* 
 /* Fine-level sizes: vector length per right-hand side (N N_t n^d) and the
  * nodal lengths of f (N n^d) and u0 (n^d) per right-hand side. */
 int st_mg_sizes(st_mg_t h, long long* dof, long long* f_len, long long* u0_len);
+/* Spatial unknowns per time dof on a level: n_L^d on the grid, the interior
+ * nodes of the level's refinement on a P1 mesh. */
+int st_mg_level_nx(st_mg_t h, int level, long long* nx);
 
 /* Right-hand side from nodal data (Sec. 1 load vector; u0 enters slab 1
  * through N_tau (x) M_h, eq. (equation1) with n = 0):

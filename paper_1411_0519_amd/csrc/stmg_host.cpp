@@ -14,6 +14,7 @@
 
 #include "st_mg.h"
 #include "stmg_internal.h"
+#include "stmg_mesh.h"
 
 using namespace stmg;
 
@@ -128,7 +129,26 @@ struct Level {
     void *X = nullptr, *Y = nullptr, *F = nullptr;
   };
   std::vector<Sub> sub;
+  // P1 meshes: n is the refinement level; D = dense inverse of the slab matrix
+  // on the coarse mesh at this level's tau (m = N_t x its interior nodes), C =
+  // the same for this level's own mesh on the coarsest level
+  double* D64 = nullptr;
+  float* D32 = nullptr;
+  int dm = 0;
+  double* C64 = nullptr;
+  float* C32 = nullptr;
+  int cm = 0;
   long long dof(int nt, int b) const { return (long long)b * N * nt * nx; }
+};
+
+// One refinement level of a P1 mesh on the device (CSR of M_h / K_h with their
+// diagonals; interpolation from the next coarser level when level > 0).
+struct MeshDev {
+  long long nx = 0, nnz = 0, nxc = 0;
+  int *rowptr = nullptr, *col = nullptr;
+  double *mv64 = nullptr, *kv64 = nullptr, *dg64 = nullptr, *w64 = nullptr;
+  float *mv32 = nullptr, *kv32 = nullptr, *dg32 = nullptr, *w32 = nullptr;
+  int *p = nullptr, *rrow = nullptr, *rcol = nullptr;
 };
 
 struct GraphCache {
@@ -146,6 +166,9 @@ struct st_mg {
   int nt = 0;
   double mu_star = 0;
   std::vector<Level> lv;
+  bool mesh = false;                 // P1 mesh in space (st_mg_setup_mesh)
+  std::vector<stmg::MeshLevel> mh;   // host meshes, refinement levels 0..R
+  std::vector<MeshDev> md;           // their device copies
   double Kt[NT_BIG * NT_BIG] = {};   // K_tau (independent of tau for the Legendre basis)
   double Mh[NT_BIG * NT_BIG] = {};   // M_tau / tau
   double ca[NT_BIG] = {};            // psi_l(t_{n-1}^+): N_tau = ca cb^T
@@ -489,6 +512,9 @@ RhsArgs<T> rhs_args(const st_mg* h) {
 }
 
 template <typename T>
+MeshRhsArgs<T> mesh_rhs_args(const st_mg* h);
+
+template <typename T>
 const T* gen_table(const st_mg* h);
 template <>
 const double* gen_table<double>(const st_mg* h) { return h->gen64; }
@@ -539,7 +565,53 @@ GenTransfer<T> gen_transfer(const st_mg* h, int lf) {
 }
 
 unsigned resid_blocks(const st_mg* h, const Level& L) {
+  if (h->mesh) return mesh_blocks_per_slab(L.nx);
   return high_order(h) ? residual_gen_blocks_per_slab(L.nx) : residual_blocks_per_slab(h->p.dim, L.n, L.nx, h->nt);
+}
+
+// ------------------------------------------------------------ P1 mesh data
+template <typename T>
+MeshOp<T> mesh_op(const st_mg* h, int rx);
+template <>
+MeshOp<double> mesh_op<double>(const st_mg* h, int rx) {
+  const MeshDev& m = h->md[(size_t)rx];
+  return {m.rowptr, m.col, m.mv64, m.kv64, m.dg64, m.nx};
+}
+template <>
+MeshOp<float> mesh_op<float>(const st_mg* h, int rx) {
+  const MeshDev& m = h->md[(size_t)rx];
+  return {m.rowptr, m.col, m.mv32, m.kv32, m.dg32, m.nx};
+}
+template <typename T>
+const T* mesh_w(const st_mg* h, int rx);
+template <>
+const double* mesh_w<double>(const st_mg* h, int rx) { return h->md[(size_t)rx].w64; }
+template <>
+const float* mesh_w<float>(const st_mg* h, int rx) { return h->md[(size_t)rx].w32; }
+// interpolation from refinement level rx - 1 to rx
+MeshXfer mesh_xfer(const st_mg* h, int rx) {
+  const MeshDev& m = h->md[(size_t)rx];
+  return {m.p, m.rrow, m.rcol, m.nx, m.nxc};
+}
+template <typename T>
+const T* dense_inv(const Level& L, bool own);
+template <>
+const double* dense_inv<double>(const Level& L, bool own) { return own && L.C64 ? L.C64 : L.D64; }
+template <>
+const float* dense_inv<float>(const Level& L, bool own) { return own && L.C32 ? L.C32 : L.D32; }
+
+template <typename T>
+MeshRhsArgs<T> mesh_rhs_args(const st_mg* h) {
+  const Level& L = h->lv[0];
+  MeshRhsArgs<T> a{};
+  a.op = mesh_op<T>(h, L.n);
+  for (int l = 0; l < h->nt; ++l) {
+    a.ints[l] = (T)(L.tau * h->ints[l]);
+    a.ca[l] = (T)h->ca[l];
+  }
+  a.N = L.N;
+  a.batch = h->p.batch;
+  return a;
 }
 
 // ------------------------------------------------------------------ operators
@@ -547,7 +619,24 @@ template <typename Tin, typename Tout>
 int op_residual(st_mg* h, int l, bool transpose, const Tin* u, const Tin* F, Tout* r, bool norms,
                 hipStream_t s) {
   const Level& L = h->lv[l];
-  if (high_order(h)) {
+  if (h->mesh) {
+    const ResidArgs<Tin> ra = resid_args<Tin>(h, L, transpose);
+    MeshResidArgs<Tin> a{};
+    a.op = mesh_op<Tin>(h, L.n);
+    for (int i = 0; i < NT_MAX * NT_MAX; ++i) {
+      a.K[i] = ra.K[i];
+      a.M[i] = ra.M[i];
+    }
+    for (int i = 0; i < NT_MAX; ++i) {
+      a.ca[i] = ra.ca[i];
+      a.cb[i] = ra.cb[i];
+    }
+    a.N = L.N;
+    a.batch = h->p.batch;
+    a.dir = ra.dir;
+    ProfScope ps(h, ST_PROF_RESIDUAL, l, s);
+    HIPCHK(h, (launch_mesh_residual<Tin, Tout>(h->nt, u, F, r, a, norms ? h->partial : nullptr, s)));
+  } else if (high_order(h)) {
     ProfScope ps(h, ST_PROF_RESIDUAL, l, s);
     HIPCHK(h, (launch_residual_gen<Tin, Tout>(h->p.dim, u, F, r, gen_args<Tin>(h, L, transpose),
                                               norms ? h->partial : nullptr, s)));
@@ -644,9 +733,37 @@ int op_block_solve(st_mg* h, int l, bool transpose, const T* src, T* dst, int mo
   return pass(0, true, A, dst, mode, omega);
 }
 
+// Space-time transfer between level lf and lf + 1 on a mesh: the mesh
+// interpolation in space for full coarsening, none for semi-coarsening.
+template <typename T>
+MeshTransferArgs<T> mesh_transfer(const st_mg* h, int lf) {
+  const Level& F = h->lv[lf];
+  const Level& C = h->lv[lf + 1];
+  MeshTransferArgs<T> a{};
+  for (int i = 0; i < h->nt * h->nt; ++i) {
+    a.R1T[i] = (T)h->R1T[i];
+    a.R2T[i] = (T)h->R2T[i];
+  }
+  a.full = F.kind == 'f' ? 1 : 0;
+  if (a.full) {
+    a.x = mesh_xfer(h, F.n);
+    a.w = mesh_w<T>(h, F.n);
+  } else {
+    a.x = MeshXfer{nullptr, nullptr, nullptr, F.nx, F.nx};
+    a.w = nullptr;
+  }
+  a.Nc = C.N;
+  a.batch = h->p.batch;
+  return a;
+}
+
 template <typename T>
 int op_restrict(st_mg* h, int l, const T* rf, T* Fc, hipStream_t s) {
   ProfScope ps(h, ST_PROF_RESTRICT, l, s);
+  if (h->mesh) {
+    HIPCHK(h, launch_mesh_restrict<T>(h->nt, rf, Fc, mesh_transfer<T>(h, l), s));
+    return ST_OK;
+  }
   if (high_order(h)) {
     HIPCHK(h, launch_restrict_gen<T>(h->p.dim, h->lv[l].kind == 'f', rf, Fc, gen_transfer<T>(h, l), s));
     return ST_OK;
@@ -659,6 +776,10 @@ int op_restrict(st_mg* h, int l, const T* rf, T* Fc, hipStream_t s) {
 template <typename T>
 int op_prolong(st_mg* h, int l, const T* ec, T* uf, hipStream_t s) {
   ProfScope ps(h, ST_PROF_PROLONG, l, s);
+  if (h->mesh) {
+    HIPCHK(h, launch_mesh_prolong<T>(h->nt, ec, uf, mesh_transfer<T>(h, l), s));
+    return ST_OK;
+  }
   if (high_order(h)) {
     HIPCHK(h, launch_prolong_gen<T>(h->p.dim, h->lv[l].kind == 'f', ec, uf, gen_transfer<T>(h, l), s));
     return ST_OK;
@@ -812,7 +933,108 @@ int spatial_cycle(st_mg* h, int l, int j, bool transpose, const T* f, T* dst, in
 }
 
 bool inexact_level(const st_mg* h, int l) {
+  if (h->mesh) return true;
   return h->p.smoother == ST_SMOOTH_SPATIAL_MG && h->lv[l].n > 1;
+}
+
+// Exact slab solves on a mesh level by its dense inverse (the coarse mesh, or
+// the coarsest level's own mesh), written with `mode` as op_block_solve does.
+template <typename T>
+int mesh_exact_solve(st_mg* h, int l, bool transpose, const T* src, T* dst, int mode, T omega, hipStream_t s) {
+  const Level& L = h->lv[l];
+  const bool own = l + 1 == (int)h->lv.size();
+  if (L.n != 0 && !own)
+    return fail(h, ST_EINVAL, "exact slab solves on a mesh exist on refinement level 0 and on the coarsest level");
+  const int m = own && L.cm > 0 ? L.cm : L.dm;
+  const int upd = mode == MODE_ADD_SCALED ? UPD_ADD : UPD_SET;
+  const T sc = mode == MODE_STORE ? T(1) : omega;
+  ProfScope ps(h, ST_PROF_OTHER, l, s);
+  HIPCHK(h, launch_mesh_dense<T>(dense_inv<T>(L, own), m, transpose ? 1 : 0, src, dst, dst, upd, sc,
+                                 (long long)h->p.batch * L.N, s));
+  return ST_OK;
+}
+
+// One spatial cycle on a mesh level (sub-level j = refinement level L.n - j),
+// from x = 0, with the conventions of spatial_cycle: node-block Jacobi steps,
+// P^T / P between refinement levels, the dense slab inverse on the coarse mesh.
+template <typename T>
+int mesh_spatial_cycle(st_mg* h, int l, int j, bool transpose, const T* f, T* dst, int mode, T omega_t, T** res,
+                       hipStream_t s) {
+  Level& L = h->lv[l];
+  const Level::Sub& S = L.sub[j];
+  const int nt = h->nt, rx = S.n;
+  const long long slabs = (long long)h->p.batch * L.N;
+  const long long len = slabs * nt * S.nx;
+  const int upd_last = mode == MODE_ADD_SCALED ? UPD_ADD : UPD_SET;
+  const T sc_last = mode == MODE_STORE ? T(1) : omega_t;
+  if (rx == 0) {
+    ProfScope ps(h, ST_PROF_JACOBI, l, s);
+    if (dst) {
+      HIPCHK(h, launch_mesh_dense<T>(dense_inv<T>(L, false), L.dm, transpose ? 1 : 0, f, dst, dst, upd_last, sc_last,
+                                     slabs, s));
+      return ST_OK;
+    }
+    HIPCHK(h, launch_mesh_dense<T>(dense_inv<T>(L, false), L.dm, transpose ? 1 : 0, f, nullptr, (T*)S.X, UPD_NONE,
+                                   T(1), slabs, s));
+    *res = (T*)S.X;
+    return ST_OK;
+  }
+  const T om = (T)h->p.omega_x;
+  MeshSmoothArgs<T> a{};
+  a.op = mesh_op<T>(h, rx);
+  for (int l2 = 0; l2 < nt; ++l2)
+    for (int k = 0; k < nt; ++k) {
+      a.K[l2 * nt + k] = (T)(transpose ? h->Kt[k * nt + l2] : h->Kt[l2 * nt + k]);
+      a.M[l2 * nt + k] = (T)(L.tau * h->Mh[l2 * nt + k]);
+    }
+  a.slabs = slabs;
+  auto smooth = [&](const T* x, const T* ff, const T* base, T* out, int op, int upd, T scale, bool x_zero,
+                    T omega) -> int {
+    MeshSmoothArgs<T> b = a;
+    b.omega = omega;
+    b.scale = scale;
+    b.op_kind = op;
+    b.upd = upd;
+    b.x_zero = x_zero ? 1 : 0;
+    ProfScope ps(h, ST_PROF_JACOBI, l, s);
+    HIPCHK(h, launch_mesh_smooth<T>(nt, x, ff, base, out, b, s));
+    return ST_OK;
+  };
+  T* cur = (T*)S.X;
+  T* oth = (T*)S.Y;
+  const int nu1 = h->p.nu1x, nu2 = h->p.nu2x;
+  for (int i = 0; i < nu1; ++i) {
+    CHK(smooth(cur, f, nullptr, i == 0 ? cur : oth, SP_JACOBI, UPD_NONE, T(1), i == 0, om));
+    if (i > 0) std::swap(cur, oth);
+  }
+  const Level::Sub& C = L.sub[j + 1];
+  const MeshXfer xf = mesh_xfer(h, rx);
+  const T* w = mesh_w<T>(h, rx);
+  if (nu1 == 0) {
+    HIPCHK(h, launch_fill<T>(cur, len, s));
+    ProfScope ps(h, ST_PROF_XFER_X, l, s);
+    HIPCHK(h, launch_mesh_restrict_space<T>(nt, f, (T*)C.F, xf, w, slabs, s));
+  } else {
+    CHK(smooth(cur, f, nullptr, oth, SP_DEFECT, UPD_NONE, T(1), false, om));
+    ProfScope ps(h, ST_PROF_XFER_X, l, s);
+    HIPCHK(h, launch_mesh_restrict_space<T>(nt, oth, (T*)C.F, xf, w, slabs, s));
+  }
+  T* ec = nullptr;
+  CHK(mesh_spatial_cycle<T>(h, l, j + 1, transpose, (const T*)C.F, nullptr, MODE_STORE, T(1), &ec, s));
+  {
+    ProfScope ps(h, ST_PROF_XFER_X, l, s);
+    HIPCHK(h, launch_mesh_prolong_space<T>(nt, ec, cur, xf, w, slabs, s));
+  }
+  for (int i = 0; i < nu2; ++i) {
+    if (dst && i == nu2 - 1) return smooth(cur, f, dst, dst, SP_JACOBI, upd_last, sc_last, false, om);
+    CHK(smooth(cur, f, nullptr, oth, SP_JACOBI, UPD_NONE, T(1), false, om));
+    std::swap(cur, oth);
+  }
+  if (dst) {   // no post-smoothing: combine the prolongated iterate into dst
+    return smooth(cur, cur, dst, dst, SP_JACOBI, upd_last, sc_last, false, T(0));
+  }
+  *res = cur;
+  return ST_OK;
 }
 
 // x = D^{-1} src (exact) or (I - M^x) D^{-1} src (spatial cycle), written into
@@ -820,6 +1042,7 @@ bool inexact_level(const st_mg* h, int l) {
 template <typename T>
 int op_smoother_solve(st_mg* h, int l, bool transpose, const T* src, T* dst, int mode, T omega, T* A, T* B,
                       hipStream_t s) {
+  if (h->mesh) return mesh_spatial_cycle<T>(h, l, 0, transpose, src, dst, mode, omega, nullptr, s);
   if (inexact_level(h, l)) return spatial_cycle<T>(h, l, 0, transpose, src, dst, mode, omega, nullptr, s);
   return op_block_solve<T>(h, l, transpose, src, dst, mode, omega, A, B, s);
 }
@@ -829,7 +1052,7 @@ int op_smoother_solve(st_mg* h, int l, bool transpose, const T* src, T* dst, int
 template <typename T>
 bool small_level(const st_mg* h, int l) {
   const Level& L = h->lv[l];
-  if (inexact_level(h, l) || high_order(h)) return false;
+  if (h->mesh || inexact_level(h, l) || high_order(h)) return false;
   const bool on = L.small >= 0 ? L.small != 0 : h->small;
   return on && smooth_small_lds(h->p.dim, L.n, L.nx, h->nt, sizeof(T)) > 0;
 }
@@ -858,6 +1081,7 @@ int coarsest_solve(st_mg* h, bool transpose, T* u, const T* F, hipStream_t s);
 template <>
 int coarsest_solve<double>(st_mg* h, bool transpose, double* u, const double* F, hipStream_t s) {
   const int l = (int)h->lv.size() - 1;
+  if (h->mesh) return mesh_exact_solve<double>(h, l, transpose, F, u, MODE_SET_SCALED, 1.0, s);
   return op_block_solve<double>(h, l, transpose, F, u, MODE_SET_SCALED, 1.0, (double*)h->tmp,
                                 level_r<double>(h, l), s);
 }
@@ -865,6 +1089,7 @@ int coarsest_solve<double>(st_mg* h, bool transpose, double* u, const double* F,
 template <>
 int coarsest_solve<float>(st_mg* h, bool transpose, float* u, const float* F, hipStream_t s) {
   const int l = (int)h->lv.size() - 1;
+  if (h->mesh) return mesh_exact_solve<float>(h, l, transpose, F, u, MODE_SET_SCALED, 1.0f, s);
   if (is_mixed(h)) {
     // exact coarsest solve kept in double
     const long long len = h->lv[l].dof(h->nt, h->p.batch);
@@ -1096,12 +1321,12 @@ size_t layout(st_mg* h, char* base) {
   }
   for (size_t l = 0; l < h->lv.size(); ++l) {
     Level& L = h->lv[l];
-    if (h->p.smoother != ST_SMOOTH_SPATIAL_MG || L.n == 1) continue;
+    if (h->p.smoother != ST_SMOOTH_SPATIAL_MG || (h->mesh ? L.n == 0 : L.n == 1)) continue;
     for (size_t j = 0; j < L.sub.size(); ++j) {
       Level::Sub& S = L.sub[j];
       const long long len = (long long)b * L.N * nt * S.nx;
       S.X = take(len * ib);
-      S.Y = S.n > 1 ? take(len * ib) : nullptr;
+      S.Y = (h->mesh ? j + 1 < L.sub.size() : S.n > 1) ? take(len * ib) : nullptr;
       S.F = j > 0 ? take(len * ib) : nullptr;
     }
   }
@@ -1219,33 +1444,131 @@ int autotune_all(st_mg* h, void* u0, void* F0, hipStream_t s) {
   return ST_OK;
 }
 
-}  // namespace
-
-// ================================================================== C ABI
-extern "C" {
-
-void st_mg_default_params(st_mg_params* p) {
-  if (!p) return;
-  p->dim = 1;
-  p->n = 31;
-  p->T = 1.0;
-  p->N = 16;
-  p->pt = 1;
-  p->omega = 0.5;
-  p->nu1 = 2;
-  p->nu2 = 2;
-  p->coarsen = ST_COARSEN_AUTO;
-  p->mu_star = 0.0;
-  p->precision = ST_FP64;
-  p->batch = 1;
-  p->smoother = ST_SMOOTH_EXACT;
-  p->nu1x = 2;
-  p->nu2x = 2;
-  p->omega_x = 2.0 / 3.0;
-  p->gamma = 1;
+// Device copy of a host array (nullptr for an empty one).
+template <typename D, typename S>
+int upload(st_mg* h, D** dst, const std::vector<S>& src) {
+  *dst = nullptr;
+  if (src.empty()) return ST_OK;
+  std::vector<D> tmp(src.begin(), src.end());
+  if (hipMalloc((void**)dst, tmp.size() * sizeof(D)) != hipSuccess)
+    return fail(h, ST_ENOMEM, "hipMalloc of %zu bytes failed", tmp.size() * sizeof(D));
+  HIPCHK(h, hipMemcpy(*dst, tmp.data(), tmp.size() * sizeof(D), hipMemcpyHostToDevice));
+  return ST_OK;
 }
 
-int st_mg_setup(const st_mg_params* p, st_mg_t* out) {
+// Dense inverse of the slab matrix A = K_tau (x) M_h + M_tau (x) K_h of mesh
+// level `rx` (rows l * nx + i), uploaded in double and float.
+int dense_slab_inverse(st_mg* h, int rx, double tau, double** d64, float** d32, int* m_out) {
+  const stmg::MeshLevel& M = h->mh[(size_t)rx];
+  const int nt = h->nt;
+  const long long nx = M.nx(), m = nt * nx;
+  if (m > 1024)
+    return fail(h, ST_EINVAL,
+                "an exact slab solve on refinement level %d needs a dense %lld x %lld inverse (limit 1024): "
+                "refine less or use more time slabs so that space is coarsened further",
+                rx, m, m);
+  std::vector<double> A((size_t)(m * m), 0.0);
+  for (long long i = 0; i < nx; ++i)
+    for (int e = M.rowptr[(size_t)i]; e < M.rowptr[(size_t)i + 1]; ++e) {
+      const long long c = M.col[(size_t)e];
+      for (int l = 0; l < nt; ++l)
+        for (int k = 0; k < nt; ++k)
+          A[(size_t)((l * nx + i) * m + k * nx + c)] =
+              h->Kt[l * nt + k] * M.mval[(size_t)e] + tau * h->Mh[l * nt + k] * M.kval[(size_t)e];
+    }
+  if (!invert((int)m, A.data())) return fail(h, ST_EINVAL, "singular slab matrix on refinement level %d", rx);
+  CHK(upload(h, d64, A));
+  CHK(upload(h, d32, A));
+  *m_out = (int)m;
+  return ST_OK;
+}
+
+// Levels on a P1 mesh: the Sec. 4 rule with the refinement level in place of
+// the grid size (space coarsens while the level is above 0) and h_L = h0 2^-L;
+// the spatial cycle of a level runs over its refinement levels down to 0.
+int setup_mesh_levels(st_mg* h, const st_mesh* mesh, int refinements) {
+  const st_mg_params* p = &h->p;
+  std::string err;
+  int rc = stmg::mesh_hierarchy(mesh, refinements, h->mh, err);
+  if (rc != ST_OK) return fail(h, rc, "%s", err.c_str());
+  h->mesh = true;
+  const double h0 = mesh->h0 > 0.0 ? mesh->h0 : h->mh[0].longest_edge;
+  for (size_t r = 0; r < h->mh.size(); ++r)
+    if (h->mh[r].nx() < 1)
+      return fail(h, ST_EINVAL, "refinement level %zu of the mesh has no interior node", r);
+  int rx = refinements, N = p->N;
+  double tau = p->T / p->N;
+  while (true) {
+    Level L;
+    L.n = rx;
+    L.N = N;
+    L.nx = h->mh[(size_t)rx].nx();
+    L.tau = tau;
+    L.h = h0 * std::ldexp(1.0, -rx);
+    L.mu = tau / (L.h * L.h);
+    for (int j = rx; j >= 0; --j) {
+      Level::Sub S;
+      S.n = j;
+      S.nx = h->mh[(size_t)j].nx();
+      S.h = h0 * std::ldexp(1.0, -j);
+      L.sub.push_back(S);
+    }
+    if (N == 1) {
+      h->lv.push_back(L);
+      break;
+    }
+    bool full;
+    if (p->coarsen == ST_COARSEN_FULL) full = rx > 0;
+    else if (p->coarsen == ST_COARSEN_SEMI) full = false;
+    else full = rx > 0 && L.mu >= h->mu_star * (1.0 - 1e-12);
+    L.kind = full ? 'f' : 's';
+    h->lv.push_back(L);
+    if (full) rx -= 1;
+    N /= 2;
+    tau *= 2.0;
+  }
+  h->md.resize(h->mh.size());
+  for (size_t r = 0; r < h->mh.size(); ++r) {
+    const stmg::MeshLevel& M = h->mh[r];
+    MeshDev& D = h->md[r];
+    D.nx = M.nx();
+    D.nnz = (long long)M.col.size();
+    std::vector<double> dg((size_t)D.nx * 2, 0.0);
+    for (long long i = 0; i < D.nx; ++i)
+      for (int e = M.rowptr[(size_t)i]; e < M.rowptr[(size_t)i + 1]; ++e)
+        if (M.col[(size_t)e] == i) {
+          dg[(size_t)i * 2] = M.mval[(size_t)e];
+          dg[(size_t)i * 2 + 1] = M.kval[(size_t)e];
+        }
+    CHK(upload(h, &D.rowptr, M.rowptr));
+    CHK(upload(h, &D.col, M.col));
+    CHK(upload(h, &D.mv64, M.mval));
+    CHK(upload(h, &D.kv64, M.kval));
+    CHK(upload(h, &D.mv32, M.mval));
+    CHK(upload(h, &D.kv32, M.kval));
+    CHK(upload(h, &D.dg64, dg));
+    CHK(upload(h, &D.dg32, dg));
+    if (r > 0) {
+      std::vector<int> pp, rrow, rcol;
+      std::vector<double> w;
+      stmg::mesh_interpolation(h->mh[r - 1], M, pp, w, rrow, rcol);
+      D.nxc = h->mh[r - 1].nx();
+      CHK(upload(h, &D.p, pp));
+      CHK(upload(h, &D.rrow, rrow));
+      CHK(upload(h, &D.rcol, rcol));
+      CHK(upload(h, &D.w64, w));
+      CHK(upload(h, &D.w32, w));
+    }
+  }
+  for (size_t l = 0; l < h->lv.size(); ++l) {
+    Level& L = h->lv[l];
+    CHK(dense_slab_inverse(h, 0, L.tau, &L.D64, &L.D32, &L.dm));
+    if (l + 1 == h->lv.size() && L.n > 0) CHK(dense_slab_inverse(h, L.n, L.tau, &L.C64, &L.C32, &L.cm));
+  }
+  return ST_OK;
+}
+
+int setup_impl(const st_mg_params* p, st_mg_t* out, const st_mesh* mesh, int refinements) {
   if (!p || !out) return ST_EINVAL;
   *out = nullptr;
   st_mg* h = new (std::nothrow) st_mg();
@@ -1257,7 +1580,13 @@ int st_mg_setup(const st_mg_params* p, st_mg_t* out) {
   };
   int rc = ST_OK;
   if (p->dim < 1 || p->dim > 3) rc = bad("dim must be 1, 2 or 3");
-  else if (p->n < 1 || p->n > 255 || !is_pow2((long long)p->n + 1)) rc = bad("n must be 2^m - 1 with 1 <= n <= 255");
+  else if (!mesh && (p->n < 1 || p->n > 255 || !is_pow2((long long)p->n + 1)))
+    rc = bad("n must be 2^m - 1 with 1 <= n <= 255");
+  else if (mesh && mesh->dim != p->dim) rc = bad("params dim and mesh dim differ");
+  else if (mesh && p->smoother != ST_SMOOTH_SPATIAL_MG)
+    rc = bad("P1 meshes need the spatial-cycle smoother (ST_SMOOTH_SPATIAL_MG)");
+  else if (mesh && p->precision != ST_FP64 && p->precision != ST_FP32)
+    rc = bad("P1 meshes run in ST_FP64 or ST_FP32");
   else if (!(p->T > 0.0) || !std::isfinite(p->T)) rc = bad("T must be positive");
   else if (!is_pow2(p->N) || p->N > (1 << 20)) rc = bad("N must be a power of two (<= 2^20)");
   else if (p->pt < 0 || p->pt > NT_BIG - 1) rc = bad("p_t must be in 0..47");
@@ -1319,6 +1648,11 @@ int st_mg_setup(const st_mg_params* p, st_mg_t* out) {
     *out = h;
     return ST_EINVAL;
   }
+  if (mesh) {
+    rc = setup_mesh_levels(h, mesh, refinements);
+    *out = h;
+    return rc;
+  }
   // hierarchy: Sec. 4 rule; space down to one node, time down to one slab
   int n = p->n, N = p->N;
   double tau = p->T / p->N;
@@ -1370,6 +1704,39 @@ int st_mg_setup(const st_mg_params* p, st_mg_t* out) {
   return ST_OK;
 }
 
+}  // namespace
+
+// ================================================================== C ABI
+extern "C" {
+
+void st_mg_default_params(st_mg_params* p) {
+  if (!p) return;
+  p->dim = 1;
+  p->n = 31;
+  p->T = 1.0;
+  p->N = 16;
+  p->pt = 1;
+  p->omega = 0.5;
+  p->nu1 = 2;
+  p->nu2 = 2;
+  p->coarsen = ST_COARSEN_AUTO;
+  p->mu_star = 0.0;
+  p->precision = ST_FP64;
+  p->batch = 1;
+  p->smoother = ST_SMOOTH_EXACT;
+  p->nu1x = 2;
+  p->nu2x = 2;
+  p->omega_x = 2.0 / 3.0;
+  p->gamma = 1;
+}
+
+int st_mg_setup(const st_mg_params* p, st_mg_t* out) { return setup_impl(p, out, nullptr, 0); }
+
+int st_mg_setup_mesh(const st_mg_params* p, const st_mesh* coarse, int refinements, st_mg_t* out) {
+  if (!coarse) return ST_EINVAL;
+  return setup_impl(p, out, coarse, refinements);
+}
+
 int st_mg_destroy(st_mg_t h) {
   if (!h) return ST_OK;
   if (h->gc.exec) (void)hipGraphExecDestroy(h->gc.exec);
@@ -1381,6 +1748,16 @@ int st_mg_destroy(st_mg_t h) {
     (void)hipFree(L.G32);
     (void)hipFree(L.Sp64);
     (void)hipFree(L.Sp32);
+    (void)hipFree(L.D64);
+    (void)hipFree(L.D32);
+    (void)hipFree(L.C64);
+    (void)hipFree(L.C32);
+  }
+  for (auto& D : h->md) {
+    for (void* q : {(void*)D.rowptr, (void*)D.col, (void*)D.mv64, (void*)D.kv64, (void*)D.dg64, (void*)D.w64,
+                    (void*)D.mv32, (void*)D.kv32, (void*)D.dg32, (void*)D.w32, (void*)D.p, (void*)D.rrow,
+                    (void*)D.rcol})
+      (void)hipFree(q);
   }
   if (h->ws_owned && h->ws) (void)hipFree(h->ws);
   (void)hipFree(h->gen64);
@@ -1450,6 +1827,12 @@ int st_mg_level_info(st_mg_t h, int level, int* n, int* N, double* tau, double* 
   return ST_OK;
 }
 
+int st_mg_level_nx(st_mg_t h, int level, long long* nx) {
+  if (!h || !nx || level < 0 || level >= (int)h->lv.size()) return ST_EINVAL;
+  *nx = h->lv[level].nx;
+  return ST_OK;
+}
+
 int st_mg_sizes(st_mg_t h, long long* dof, long long* f_len, long long* u0_len) {
   if (!h || h->lv.empty()) return ST_EINVAL;
   const Level& L = h->lv[0];
@@ -1462,6 +1845,14 @@ int st_mg_sizes(st_mg_t h, long long* dof, long long* f_len, long long* u0_len) 
 int st_mg_rhs(st_mg_t h, const void* f, const void* u0, void* F, void* stream) {
   if (!h || h->lv.empty() || !f || !F) return h ? fail(h, ST_EINVAL, "null argument") : ST_EINVAL;
   hipStream_t s = (hipStream_t)stream;
+  if (h->mesh) {
+    if (h->p.precision == ST_FP32)
+      HIPCHK(h, launch_mesh_rhs<float>(h->nt, (const float*)f, (const float*)u0, (float*)F, mesh_rhs_args<float>(h), s));
+    else
+      HIPCHK(h, launch_mesh_rhs<double>(h->nt, (const double*)f, (const double*)u0, (double*)F,
+                                        mesh_rhs_args<double>(h), s));
+    return ST_OK;
+  }
   if (high_order(h)) {
     if (h->p.precision == ST_FP32)
       HIPCHK(h, launch_rhs_gen<float>(h->p.dim, (const float*)f, (const float*)u0, (float*)F,
@@ -1483,6 +1874,15 @@ int st_mg_rhs_adjoint(st_mg_t h, const void* lam, void* grad_f, void* grad_u0, v
   if (!h || h->lv.empty() || !lam) return h ? fail(h, ST_EINVAL, "null argument") : ST_EINVAL;
   if (!grad_f && !grad_u0) return ST_OK;
   hipStream_t s = (hipStream_t)stream;
+  if (h->mesh) {
+    if (h->p.precision == ST_FP32)
+      HIPCHK(h, launch_mesh_rhs_adjoint<float>(h->nt, (const float*)lam, (float*)grad_f, (float*)grad_u0,
+                                               mesh_rhs_args<float>(h), s));
+    else
+      HIPCHK(h, launch_mesh_rhs_adjoint<double>(h->nt, (const double*)lam, (double*)grad_f, (double*)grad_u0,
+                                                mesh_rhs_args<double>(h), s));
+    return ST_OK;
+  }
   if (high_order(h)) {
     if (h->p.precision == ST_FP32)
       HIPCHK(h, launch_rhs_adjoint_gen<float>(h->p.dim, (const float*)lam, (float*)grad_f, (float*)grad_u0,
@@ -1525,6 +1925,11 @@ int st_mg_block_solve(st_mg_t h, int level, int prec, int transpose, const void*
   CHK(check_level(h, level, prec, false));
   if (!r || !x) return fail(h, ST_EINVAL, "null vector");
   hipStream_t s = (hipStream_t)stream;
+  if (h->mesh) {
+    if (prec == ST_FP64)
+      return mesh_exact_solve<double>(h, level, transpose != 0, (const double*)r, (double*)x, MODE_STORE, 1.0, s);
+    return mesh_exact_solve<float>(h, level, transpose != 0, (const float*)r, (float*)x, MODE_STORE, 1.0f, s);
+  }
   if (prec == ST_FP64)
     return op_block_solve<double>(h, level, transpose != 0, (const double*)r, (double*)x, MODE_STORE,
                                   1.0, (double*)h->tmp, level_r<double>(h, level), s);
@@ -1539,6 +1944,13 @@ int st_mg_spatial_cycle(st_mg_t h, int level, int prec, int transpose, const voi
   if (h->p.smoother != ST_SMOOTH_SPATIAL_MG)
     return fail(h, ST_ESTATE, "the spatial cycle needs a handle set up with ST_SMOOTH_SPATIAL_MG");
   hipStream_t s = (hipStream_t)stream;
+  if (h->mesh) {
+    if (prec == ST_FP64)
+      return mesh_spatial_cycle<double>(h, level, 0, transpose != 0, (const double*)r, (double*)x, MODE_STORE, 1.0,
+                                        nullptr, s);
+    return mesh_spatial_cycle<float>(h, level, 0, transpose != 0, (const float*)r, (float*)x, MODE_STORE, 1.0f,
+                                     nullptr, s);
+  }
   if (prec == ST_FP64)
     return spatial_cycle<double>(h, level, 0, transpose != 0, (const double*)r, (double*)x, MODE_STORE, 1.0,
                                  nullptr, s);

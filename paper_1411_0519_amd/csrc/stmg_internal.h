@@ -237,3 +237,104 @@ template <typename T>
 hipError_t launch_copy(const T* in, T* out, long long len, hipStream_t s);
 
 }  // namespace stmg
+
+namespace stmg {
+
+// ------------------------------------------------- P1 meshes (stmg_mesh.hip)
+// One refinement level on the device: the interior M_h and K_h in CSR with one
+// shared pattern, and their diagonals [nx][2] = (M_ii, K_ii).
+template <typename T>
+struct MeshOp {
+  const int* rowptr;
+  const int* col;
+  const T* mv;
+  const T* kv;
+  const T* diag;
+  long long nx;
+};
+// Interpolation from the next coarser level: fine node i takes
+// w[i] (e[p[2i]] + e[p[2i+1]]) over parents >= 0; its transpose as CSR over the
+// coarse nodes (rrow, rcol: fine indices; weights w[rcol]).
+struct MeshXfer {
+  const int* p;
+  const int* rrow;
+  const int* rcol;
+  long long nxf, nxc;
+};
+// Residual r = F - L u on a mesh level; time coefficients as in ResidArgs.
+template <typename T>
+struct MeshResidArgs {
+  MeshOp<T> op;
+  T K[NT_MAX * NT_MAX];
+  T M[NT_MAX * NT_MAX];
+  T ca[NT_MAX];
+  T cb[NT_MAX];
+  int N;
+  int batch;
+  int dir;
+};
+template <typename Tin, typename Tout>
+hipError_t launch_mesh_residual(int nt, const Tin* u, const Tin* F, Tout* r, const MeshResidArgs<Tin>& a,
+                                double* partial, hipStream_t s);
+unsigned mesh_blocks_per_slab(long long nx);
+// Node-block Jacobi step or defect on every slab of a mesh level:
+// y = x + omega D_i^{-1} (f - A x)_i with D_i = M_ii K + K_ii M (SP_JACOBI), or
+// y = f - A x (SP_DEFECT); written as in SpatialArgs (upd, scale, base).
+template <typename T>
+struct MeshSmoothArgs {
+  MeshOp<T> op;
+  T K[NT_MAX * NT_MAX];
+  T M[NT_MAX * NT_MAX];
+  long long slabs;
+  T omega;
+  T scale;
+  int op_kind;
+  int upd;
+  int x_zero;
+};
+template <typename T>
+hipError_t launch_mesh_smooth(int nt, const T* x, const T* f, const T* base, T* out, const MeshSmoothArgs<T>& a,
+                              hipStream_t s);
+// fc = (P^T (x) I) rf per slab; uf += (P (x) I) ec per slab.
+template <typename T>
+hipError_t launch_mesh_restrict_space(int nt, const T* rf, T* fc, const MeshXfer& x, const T* w, long long slabs,
+                                      hipStream_t s);
+template <typename T>
+hipError_t launch_mesh_prolong_space(int nt, const T* ec, T* uf, const MeshXfer& x, const T* w, long long slabs,
+                                     hipStream_t s);
+// Exact slab solve with a dense inverse (m = N_t nx <= 1024): y = Ainv f
+// (Ainv^T f when trans), written as out = y, scale y or base + scale y.
+template <typename T>
+hipError_t launch_mesh_dense(const T* Ainv, int m, int trans, const T* f, const T* base, T* out, int upd, T scale,
+                             long long slabs, hipStream_t s);
+// Space-time transfers (eq. chap4_restrictionTime in time; space by the mesh
+// interpolation when full, identity when semi).
+template <typename T>
+struct MeshTransferArgs {
+  T R1T[NT_MAX * NT_MAX];
+  T R2T[NT_MAX * NT_MAX];
+  MeshXfer x;             // nxf == nxc for semi-coarsening
+  const T* w;
+  int full;
+  int Nc;
+  int batch;
+};
+template <typename T>
+hipError_t launch_mesh_restrict(int nt, const T* rf, T* Fc, const MeshTransferArgs<T>& a, hipStream_t s);
+template <typename T>
+hipError_t launch_mesh_prolong(int nt, const T* ec, T* uf, const MeshTransferArgs<T>& a, hipStream_t s);
+// Load vector and its transpose on the finest mesh level.
+template <typename T>
+struct MeshRhsArgs {
+  MeshOp<T> op;
+  T ints[NT_MAX];
+  T ca[NT_MAX];
+  int N;
+  int batch;
+};
+template <typename T>
+hipError_t launch_mesh_rhs(int nt, const T* f, const T* u0, T* F, const MeshRhsArgs<T>& a, hipStream_t s);
+template <typename T>
+hipError_t launch_mesh_rhs_adjoint(int nt, const T* lam, T* gf, T* gu0, const MeshRhsArgs<T>& a, hipStream_t s);
+
+}  // namespace stmg

@@ -29,6 +29,13 @@ class Params(ctypes.Structure):
     ]
 
 
+class Mesh(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int), ("nnodes", ctypes.c_int), ("ncells", ctypes.c_int),
+        ("coords", ctypes.POINTER(ctypes.c_double)), ("cells", ctypes.POINTER(ctypes.c_int)), ("h0", ctypes.c_double),
+    ]
+
+
 class STMGError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"st_mg error {code}: {msg}")
@@ -44,6 +51,9 @@ _llp = ctypes.POINTER(ctypes.c_longlong)
 SIGNATURES = {
     "st_mg_default_params": (None, [ctypes.POINTER(Params)]),
     "st_mg_setup": (_i, [ctypes.POINTER(Params), ctypes.POINTER(_vp)]),
+    "st_mg_setup_mesh": (_i, [ctypes.POINTER(Params), ctypes.POINTER(Mesh), _i, ctypes.POINTER(_vp)]),
+    "st_mesh_level": (_i, [ctypes.POINTER(Mesh), _i, _llp, _llp, _dp, _ip, _ip, _dp, _dp]),
+    "st_mg_level_nx": (_i, [_vp, _i, _llp]),
     "st_mg_destroy": (_i, [_vp]),
     "st_mg_last_error": (ctypes.c_char_p, [_vp]),
     "st_mg_workspace_bytes": (_i, [_vp, ctypes.POINTER(_sz)]),
@@ -89,6 +99,39 @@ def lib():
     return _lib
 
 
+def _mesh_struct(coords, cells, h0=0.0):
+    """(Mesh, keep-alive arrays) for a coarse mesh given as numpy arrays."""
+    import numpy as np
+    c = np.ascontiguousarray(coords, dtype=np.float64)
+    t = np.ascontiguousarray(cells, dtype=np.int32)
+    if c.ndim != 2 or t.ndim != 2 or t.shape[1] != c.shape[1] + 1:
+        raise ValueError("coords must be (nodes, dim) and cells (cells, dim + 1)")
+    m = Mesh(c.shape[1], c.shape[0], t.shape[0], c.ctypes.data_as(_dp), t.ctypes.data_as(_ip), float(h0))
+    return m, (c, t)
+
+
+def mesh_level(coords, cells, level):
+    """Refinement `level` of a coarse P1 mesh as the library builds it (host
+    only, no GPU): interior node coordinates and the interior M_h, K_h in CSR."""
+    import numpy as np
+    m, keep = _mesh_struct(coords, cells)
+    L = lib()
+    nx, nnz = ctypes.c_longlong(), ctypes.c_longlong()
+    rc = L.st_mesh_level(ctypes.byref(m), level, ctypes.byref(nx), ctypes.byref(nnz), None, None, None, None, None)
+    if rc != ST_OK:
+        raise STMGError(rc, "st_mesh_level failed")
+    pts = np.zeros((nx.value, m.dim))
+    rowptr = np.zeros(nx.value + 1, dtype=np.int32)
+    col = np.zeros(nnz.value, dtype=np.int32)
+    mval = np.zeros(nnz.value)
+    kval = np.zeros(nnz.value)
+    rc = L.st_mesh_level(ctypes.byref(m), level, None, None, pts.ctypes.data_as(_dp), rowptr.ctypes.data_as(_ip),
+                         col.ctypes.data_as(_ip), mval.ctypes.data_as(_dp), kval.ctypes.data_as(_dp))
+    if rc != ST_OK:
+        raise STMGError(rc, "st_mesh_level failed")
+    return dict(points=pts, rowptr=rowptr, col=col, mval=mval, kval=kval)
+
+
 def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
 
@@ -108,11 +151,15 @@ class Solver:
     diagonalisation) or 'spatial_mg' (one spatial multigrid cycle per slab with
     nu1x/nu2x damped block-Jacobi steps, damping omega_x).  gamma: cycle index
     (1 = V-cycle, 2 = W-cycle).
+
+    mesh = (coords, cells): P1 elements on that coarse triangle/tetrahedron mesh
+    refined n times (n then counts refinements; smoother 'spatial_mg', precision
+    'fp64' or 'fp32'); h0 = its mesh size in mu = tau/h^2 (0: longest edge).
     """
 
     def __init__(self, dim, n, N, pt=1, T=1.0, omega=0.5, nu1=2, nu2=2, coarsen="auto",
                  mu_star=0.0, precision="fp64", batch=1, device="cuda:0", workspace=True,
-                 smoother="exact", nu1x=2, nu2x=2, omega_x=2.0 / 3.0, gamma=1):
+                 smoother="exact", nu1x=2, nu2x=2, omega_x=2.0 / 3.0, gamma=1, mesh=None, h0=0.0):
         if not torch.cuda.is_available():
             raise RuntimeError("stmg needs a ROCm GPU (torch.cuda.is_available() is False)")
         self.device = torch.device(device)
@@ -121,7 +168,11 @@ class Solver:
         p = Params(dim, n, float(T), N, pt, float(omega), nu1, nu2, COARSEN[coarsen], float(mu_star),
                    PRECISION[precision], batch, SMOOTHER[smoother], nu1x, nu2x, float(omega_x), gamma)
         with torch.cuda.device(self.device):
-            rc = L.st_mg_setup(ctypes.byref(p), ctypes.byref(self._h))
+            if mesh is None:
+                rc = L.st_mg_setup(ctypes.byref(p), ctypes.byref(self._h))
+            else:
+                ms, keep = _mesh_struct(*mesh, h0=h0)
+                rc = L.st_mg_setup_mesh(ctypes.byref(p), ctypes.byref(ms), n, ctypes.byref(self._h))
         if rc != ST_OK:
             msg = L.st_mg_last_error(self._h).decode() if self._h.value else "setup failed"
             if self._h.value:
@@ -132,6 +183,7 @@ class Solver:
                            coarsen=coarsen, precision=precision, batch=batch, smoother=smoother,
                            nu1x=nu1x, nu2x=nu2x, omega_x=omega_x, gamma=gamma)
         self.dim, self.n, self.N, self.pt, self.batch = dim, n, N, pt, batch
+        self.mesh = mesh
         self.nt = pt + 1
         self.precision = precision
         self.dtype = torch.float32 if precision == "fp32" else torch.float64
@@ -148,7 +200,9 @@ class Solver:
             nn, NN, tau, mu = ctypes.c_int(), ctypes.c_int(), ctypes.c_double(), ctypes.c_double()
             self._check(L.st_mg_level_info(self._h, k, ctypes.byref(nn), ctypes.byref(NN),
                                            ctypes.byref(tau), ctypes.byref(mu)))
-            self.levels.append(dict(n=nn.value, N=NN.value, tau=tau.value, mu=mu.value))
+            nx = ctypes.c_longlong()
+            self._check(L.st_mg_level_nx(self._h, k, ctypes.byref(nx)))
+            self.levels.append(dict(n=nn.value, N=NN.value, tau=tau.value, mu=mu.value, nx=nx.value))
         self._ws = None
         if workspace:
             self.bind_workspace()
@@ -187,7 +241,7 @@ class Solver:
         if not 0 <= level < self.nlev:
             raise ValueError(f"level {level} out of range 0..{self.nlev - 1}")
         lv = self.levels[level]
-        return self.batch * lv["N"] * self.nt * lv["n"] ** self.dim
+        return self.batch * lv["N"] * self.nt * lv["nx"]
 
     def _vec(self, t, numel, dtype, name):
         if not isinstance(t, torch.Tensor):

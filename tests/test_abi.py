@@ -16,7 +16,7 @@ HEADER = os.path.join(ROOT, "include", "st_mg.h")
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(st_mg_[a-z0-9_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(st_(?:mg|mesh)_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_header_declares_the_boundary():
