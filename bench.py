@@ -40,6 +40,7 @@ def parse():
     ap.add_argument("--only-timed", action="store_true", help="timed V-cycles only (for profiler runs)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default kernel families")
     ap.add_argument("--no-inexact", action="store_true", help="skip the spatial-multigrid smoother measurement")
+    ap.add_argument("--no-mesh", action="store_true", help="skip the P1 tetrahedral-mesh measurement")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized device buffer 5 times (calibrates HBM byte counters) and exit")
     return ap.parse_args()
@@ -90,6 +91,64 @@ def measure_inexact(stmg, torch, d, n, N, pt, b, F, u_ref, dev, args):
                                           "avg_launch_ms": jac0_ms / max(jac0_cnt, 1),
                                           "bytes_total": jac_bytes},
             "kernel_breakdown_ms_per_step": {k: v[0] / steps for k, v in prof.items()}}
+
+
+def measure_p1(stmg, torch, dev, args):
+    """The parallel example's setting on a P1 mesh: the unit cube of 49,152
+    tetrahedra (12 refined four times), p_t = 3, tau = 0.1, nu1 = nu2 = 1,
+    omega_t = 1, one spatial cycle per slab (node-block Jacobi, nu_x = 2,
+    omega_x = 2/3) on N = 1024 slabs.  V-cycle throughput, time to the
+    examples' reduction 1e-8 and the HBM rate of the CSR residual kernel."""
+    from paper_1411_0519_amd import workloads
+    coarse = workloads.coarse_mesh("cube12")
+    R, N, pt = 4, 1024, 3
+    X = stmg.Solver(3, R, N, pt=pt, T=0.1 * N, omega=1.0, nu1=1, nu2=1, smoother="spatial_mg", mesh=coarse,
+                    device=dev)
+    lv = stmg.mesh_level(*coarse, R)
+    f, u0 = workloads.mesh_data(lv["points"], N, seed=21)
+    F = X.rhs(torch.from_numpy(f.ravel()).to(dev), torch.from_numpy(u0.ravel()).to(dev))
+    steps = max(args.steps // 2, 5)
+    u = torch.zeros_like(F)
+    if not args.no_graph:
+        X.set_graph(True)
+    X.solve(F, u=u, rtol=0.0, maxit=2, raise_on_noconv=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    X.solve(F, u=u, rtol=0.0, maxit=steps, raise_on_noconv=False)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    u.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, its, hist = X.solve(F, u=u, rtol=1e-8, maxit=100)
+    torch.cuda.synchronize()
+    tsolve = time.perf_counter() - t0
+    X.set_graph(False)
+    u2 = torch.zeros_like(F)
+    X.solve(F, u=u2, rtol=0.0, maxit=1, raise_on_noconv=False)
+    X.profile_start()
+    X.solve(F, u=u2, rtol=0.0, maxit=steps, raise_on_noconv=False)
+    torch.cuda.synchronize()
+    kinds = ["residual", "jacobi", "xfer_x", "restrict", "prolong", "other"]
+    prof = {k: X.profile_read(k, level=-1) for k in kinds}
+    res_ms, res_cnt = X.profile_read("residual", level=0)
+    X.profile_stop()
+    dof = X.level_dof(0)
+    nnz = len(lv["col"])
+    # u and F read once, r written once, the CSR pattern and both value arrays
+    res_bytes = 24.0 * dof + 20.0 * nnz + 4.0 * (len(lv["rowptr"]))
+    gbs = res_bytes * res_cnt / (res_ms * 1e-3) / 1e9
+    out = {"workload": "heat3d_p1_cube12_R4_N1024_p3: unit cube of 49,152 P1 tetrahedra (12 refined 4 times, "
+                       f"{X.levels[0]['nx']} interior nodes), N=1024 slabs, tau=0.1, DG p_t=3, FP64, "
+                       "nu1=nu2=1, omega_t=1, spatial cycle nu_x=2 omega_x=2/3, schedule " + X.schedule,
+           "dof": dof, "value": dof * steps / el, "unit": "DoF*V-cycles/s", "ms_per_step": 1e3 * el / steps,
+           "steps": steps, "time_to_1e-8_s": tsolve, "cycles_to_1e-8": its, "final_relres": hist[-1][0],
+           "residual_kernel_fine_level": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                          "frac": gbs / HBM_PEAK_GBS, "launches": res_cnt,
+                                          "avg_launch_ms": res_ms / max(res_cnt, 1), "bytes_per_launch": res_bytes},
+           "kernel_breakdown_ms_per_step": {k: v[0] / steps for k, v in prof.items()}}
+    X.close()
+    return out
 
 
 def cpu_baseline(budget_s=20.0):
@@ -284,6 +343,9 @@ def main():
         inexact = None
         if not args.no_inexact:
             inexact = measure_inexact(stmg, torch, d, n, N, pt, b, F, u64, dev, args)
+        p1_mesh = None
+        if not args.no_mesh:
+            p1_mesh = measure_p1(stmg, torch, dev, args)
 
     # roofline of the dominant transform kernel on the fine level.  Algorithmic
     # work is the dense sine transform's: a length-n dot product (2n flop) per
@@ -351,6 +413,8 @@ def main():
     }
     if inexact is not None:
         out["inexact_smoother"] = inexact
+    if p1_mesh is not None:
+        out["p1_mesh"] = p1_mesh
     if not args.no_cpu_baseline:
         cb = cpu_baseline()
         out["cpu_baseline"] = cb

@@ -117,9 +117,12 @@ int st_mg_setup(const st_mg_params* p, st_mg_t* out);
  * (every edge halved; a tetrahedron's inner octahedron cut along its shortest
  * diagonal, ties broken by the lexicographically smallest endpoint
  * coordinates).  Nodes on boundary faces (faces of one cell) carry the
- * homogeneous Dirichlet condition; the unknowns are the interior nodes in node
- * order, old vertices first, then edge midpoints in the order a sweep over the
- * cells (local edges (0,1),(0,2),(0,3),(1,2),(1,3),(2,3)) meets them.  Level
+ * homogeneous Dirichlet condition; the unknowns are the interior nodes ordered
+ * along the Z-order (Morton) curve of their coordinates (each coordinate scaled
+ * to the coarse mesh's bounding box and quantised to 21 bits in 3-D, 31 bits in
+ * 2-D; bits interleaved with x lowest; ties by node number, where old vertices
+ * come first and edge midpoints follow in the order a sweep over the cells,
+ * local edges (0,1),(0,2),(0,3),(1,2),(1,3),(2,3), meets them).  Level
  * transfers: nested interpolation in space (an edge node takes the mean of its
  * edge's ends), eq. chap4_restrictionTime in time, R = P^T.  The mesh size in
  * mu = tau/h^2 is h_L = h0 2^-L on refinement level L. */

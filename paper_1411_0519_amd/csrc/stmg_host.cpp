@@ -146,6 +146,13 @@ struct Level {
 struct MeshDev {
   long long nx = 0, nnz = 0, nxc = 0;
   int *rowptr = nullptr, *col = nullptr;
+  int ew = 0;                                   // ELL width (longest row)
+  int* ecol = nullptr;                          // [ew][nx]
+  double* emk64 = nullptr;                      // [ew][nx][2] (M_h, K_h)
+  float* emk32 = nullptr;
+  int hmax = 0;                                 // largest tile halo
+  int *hoff = nullptr, *hcol = nullptr;         // tile halos (256-row tiles)
+  unsigned short* lcol = nullptr;               // [ew][nx] halo-local columns
   double *mv64 = nullptr, *kv64 = nullptr, *dg64 = nullptr, *w64 = nullptr;
   float *mv32 = nullptr, *kv32 = nullptr, *dg32 = nullptr, *w32 = nullptr;
   int *p = nullptr, *rrow = nullptr, *rcol = nullptr;
@@ -575,12 +582,12 @@ MeshOp<T> mesh_op(const st_mg* h, int rx);
 template <>
 MeshOp<double> mesh_op<double>(const st_mg* h, int rx) {
   const MeshDev& m = h->md[(size_t)rx];
-  return {m.rowptr, m.col, m.mv64, m.kv64, m.dg64, m.nx};
+  return {m.rowptr, m.col, m.mv64, m.kv64, m.dg64, m.nx, m.ecol, m.emk64, m.ew, m.hoff, m.hcol, m.lcol, m.hmax};
 }
 template <>
 MeshOp<float> mesh_op<float>(const st_mg* h, int rx) {
   const MeshDev& m = h->md[(size_t)rx];
-  return {m.rowptr, m.col, m.mv32, m.kv32, m.dg32, m.nx};
+  return {m.rowptr, m.col, m.mv32, m.kv32, m.dg32, m.nx, m.ecol, m.emk32, m.ew, m.hoff, m.hcol, m.lcol, m.hmax};
 }
 template <typename T>
 const T* mesh_w(const st_mg* h, int rx);
@@ -1548,6 +1555,49 @@ int setup_mesh_levels(st_mg* h, const st_mesh* mesh, int refinements) {
     CHK(upload(h, &D.kv32, M.kval));
     CHK(upload(h, &D.dg64, dg));
     CHK(upload(h, &D.dg32, dg));
+    for (long long i = 0; i < D.nx; ++i) D.ew = std::max(D.ew, M.rowptr[(size_t)i + 1] - M.rowptr[(size_t)i]);
+    std::vector<int> ecol((size_t)D.ew * D.nx);
+    std::vector<double> emk((size_t)D.ew * D.nx * 2, 0.0);
+    for (long long i = 0; i < D.nx; ++i)
+      for (int e = 0; e < D.ew; ++e) {
+        const int q = M.rowptr[(size_t)i] + e;
+        const size_t at = (size_t)e * D.nx + i;
+        if (q < M.rowptr[(size_t)i + 1]) {
+          ecol[at] = M.col[(size_t)q];
+          emk[2 * at] = M.mval[(size_t)q];
+          emk[2 * at + 1] = M.kval[(size_t)q];
+        } else {
+          ecol[at] = (int)i;
+        }
+      }
+    CHK(upload(h, &D.ecol, ecol));
+    CHK(upload(h, &D.emk64, emk));
+    CHK(upload(h, &D.emk32, emk));
+    {
+      const long long tiles = (D.nx + MESH_TILE - 1) / MESH_TILE;
+      std::vector<int> hoff((size_t)tiles + 1, 0), hcol;
+      std::vector<unsigned short> lcol((size_t)D.ew * D.nx, 0);
+      for (long long t = 0; t < tiles; ++t) {
+        const long long i0 = t * MESH_TILE, i1 = std::min(D.nx, i0 + MESH_TILE);
+        std::vector<int> cols;
+        for (long long i = i0; i < i1; ++i)
+          for (int e = 0; e < D.ew; ++e) cols.push_back(ecol[(size_t)e * D.nx + i]);
+        std::sort(cols.begin(), cols.end());
+        cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
+        if (cols.size() > 65535) return fail(h, ST_EINVAL, "mesh rows touch too many distinct nodes");
+        for (long long i = i0; i < i1; ++i)
+          for (int e = 0; e < D.ew; ++e) {
+            const size_t at = (size_t)e * D.nx + i;
+            lcol[at] = (unsigned short)(std::lower_bound(cols.begin(), cols.end(), ecol[at]) - cols.begin());
+          }
+        D.hmax = std::max(D.hmax, (int)cols.size());
+        hcol.insert(hcol.end(), cols.begin(), cols.end());
+        hoff[(size_t)t + 1] = (int)hcol.size();
+      }
+      CHK(upload(h, &D.hoff, hoff));
+      CHK(upload(h, &D.hcol, hcol));
+      CHK(upload(h, &D.lcol, lcol));
+    }
     if (r > 0) {
       std::vector<int> pp, rrow, rcol;
       std::vector<double> w;
@@ -1754,7 +1804,7 @@ int st_mg_destroy(st_mg_t h) {
     (void)hipFree(L.C32);
   }
   for (auto& D : h->md) {
-    for (void* q : {(void*)D.rowptr, (void*)D.col, (void*)D.mv64, (void*)D.kv64, (void*)D.dg64, (void*)D.w64,
+    for (void* q : {(void*)D.hoff, (void*)D.hcol, (void*)D.lcol, (void*)D.ecol, (void*)D.emk64, (void*)D.emk32, (void*)D.rowptr, (void*)D.col, (void*)D.mv64, (void*)D.kv64, (void*)D.dg64, (void*)D.w64,
                     (void*)D.mv32, (void*)D.kv32, (void*)D.dg32, (void*)D.w32, (void*)D.p, (void*)D.rrow,
                     (void*)D.rcol})
       (void)hipFree(q);

@@ -241,6 +241,7 @@ hipError_t launch_copy(const T* in, T* out, long long len, hipStream_t s);
 namespace stmg {
 
 // ------------------------------------------------- P1 meshes (stmg_mesh.hip)
+constexpr int MESH_TILE = 256;   // rows per workgroup of the mesh kernels
 // One refinement level on the device: the interior M_h and K_h in CSR with one
 // shared pattern, and their diagonals [nx][2] = (M_ii, K_ii).
 template <typename T>
@@ -251,6 +252,19 @@ struct MeshOp {
   const T* kv;
   const T* diag;
   long long nx;
+  // the same matrices column-major in ELL form for the hot kernels: entry e of
+  // row i at e * nx + i (ecol, and emk holding (M_h, K_h) pairs), rows padded
+  // to ew entries with column i and zero values
+  const int* ecol;
+  const T* emk;
+  int ew;
+  // halo of each 256-row tile: the distinct columns its rows touch (sorted),
+  // hcol[hoff[t] .. hoff[t+1]), at most hmax per tile; lcol[e * nx + i] is the
+  // position of ecol[e * nx + i] in the halo of i's tile
+  const int* hoff;
+  const int* hcol;
+  const unsigned short* lcol;
+  int hmax;
 };
 // Interpolation from the next coarser level: fine node i takes
 // w[i] (e[p[2i]] + e[p[2i+1]]) over parents >= 0; its transpose as CSR over the

@@ -25,7 +25,16 @@ namespace {
 
 using namespace dev;
 
-constexpr int MB = 256;
+constexpr int MB = MESH_TILE;   // one thread per row of a tile (the host builds the tile halos)
+
+// Blocks run over (slab, node tile) with the tiles of a slab adjacent and the
+// dispatch order remapped so that each XCD works through a contiguous range of
+// slabs: the gathers of a row then hit the slab vectors its own L2 holds.
+__device__ inline void slab_tile(long long tiles, long long& slab, long long& tile) {
+  const long long b = xcd_linear(blockIdx.x, gridDim.x);
+  slab = b / tiles;
+  tile = b - slab * tiles;
+}
 
 __device__ inline double block_sum(double v) {
   __shared__ double red[MB / 64];
@@ -39,16 +48,17 @@ __device__ inline double block_sum(double v) {
   return s;
 }
 
-// (M_h x_k)_i and (K_h x_k)_i for the N_t components of one slab.
+// (M_h x_k)_i and (K_h x_k)_i for the N_t components of one slab, over the
+// ELL copy (consecutive lanes read consecutive matrix entries).
 template <typename T, int NT>
 __device__ inline void row_mk(const MeshOp<T>& op, const T* __restrict__ x, long long nx, long long i, T* mu,
                               T* ku) {
 #pragma unroll
   for (int k = 0; k < NT; ++k) mu[k] = ku[k] = T(0);
-  const int e1 = op.rowptr[i + 1];
-  for (int e = op.rowptr[i]; e < e1; ++e) {
-    const long long c = op.col[e];
-    const T m = op.mv[e], kk = op.kv[e];
+  for (int e = 0; e < op.ew; ++e) {
+    const long long q = (long long)e * nx + i;
+    const long long c = op.ecol[q];
+    const T m = op.emk[2 * q], kk = op.emk[2 * q + 1];
 #pragma unroll
     for (int k = 0; k < NT; ++k) {
       const T v = x[k * nx + c];
@@ -62,26 +72,37 @@ template <typename Tin, typename Tout, int NT>
 __global__ __launch_bounds__(MB) void k_mesh_residual(const Tin* __restrict__ u, const Tin* __restrict__ F,
                                                       Tout* __restrict__ r, MeshResidArgs<Tin> a,
                                                       double* __restrict__ partial) {
-  const long long slab = slab_index();
   const long long nx = a.op.nx;
-  const long long i = (long long)blockIdx.x * MB + threadIdx.x;
+  long long slab, tile;
+  slab_tile((nx + MB - 1) / MB, slab, tile);
+  const long long i = tile * MB + threadIdx.x;
   const int s = (int)(slab % a.N);
   double ss = 0.0;
   if (i < nx && slab < (long long)a.batch * a.N) {
     const long long off = slab * NT * nx;
+    const Tin* us = u + off;
     Tin mu[NT], ku[NT];
-    row_mk<Tin, NT>(a.op, u + off, nx, i, mu, ku);
-    Tin mw = Tin(0);
-    if (s + a.dir >= 0 && s + a.dir < a.N) {   // coupling to the neighbouring slab: ca (M_h w), w = sum cb_k u_k
+    Tin mw = Tin(0);   // coupling to the neighbouring slab: ca (M_h w), w = sum cb_k u_k
+    if (s + a.dir >= 0 && s + a.dir < a.N) {
       const Tin* un = u + (slab + a.dir) * NT * nx;
-      const int e1 = a.op.rowptr[i + 1];
-      for (int e = a.op.rowptr[i]; e < e1; ++e) {
-        const long long c = a.op.col[e];
+#pragma unroll
+      for (int k = 0; k < NT; ++k) mu[k] = ku[k] = Tin(0);
+      for (int e = 0; e < a.op.ew; ++e) {
+        const long long q = (long long)e * nx + i;
+        const long long c = a.op.ecol[q];
+        const Tin m = a.op.emk[2 * q], kk = a.op.emk[2 * q + 1];
         Tin w = Tin(0);
 #pragma unroll
-        for (int k = 0; k < NT; ++k) w += a.cb[k] * un[k * nx + c];
-        mw += a.op.mv[e] * w;
+        for (int k = 0; k < NT; ++k) {
+          const Tin v = us[k * nx + c];
+          mu[k] += m * v;
+          ku[k] += kk * v;
+          w += a.cb[k] * un[k * nx + c];
+        }
+        mw += m * w;
       }
+    } else {
+      row_mk<Tin, NT>(a.op, us, nx, i, mu, ku);
     }
 #pragma unroll
     for (int l = 0; l < NT; ++l) {
@@ -94,7 +115,86 @@ __global__ __launch_bounds__(MB) void k_mesh_residual(const Tin* __restrict__ u,
   }
   if (partial != nullptr) {
     const double t = block_sum(ss);
-    if (threadIdx.x == 0 && slab < (long long)a.batch * a.N) partial[slab * gridDim.x + blockIdx.x] = t;
+    if (threadIdx.x == 0 && slab < (long long)a.batch * a.N) partial[slab * ((nx + MB - 1) / MB) + tile] = t;
+  }
+}
+
+// Halo-staged variants: the workgroup first copies the values its rows touch
+// (the tile's halo, mostly contiguous thanks to the Z-order numbering) into
+// LDS, once per time component, together with the neighbouring slab's
+// coupling combination w = sum_k cb_k u_k; the rows are then formed from LDS.
+template <typename T, int NT>
+__device__ inline void stage_halo(const MeshOp<T>& op, long long tile, const T* __restrict__ xs,
+                                  const T* __restrict__ xn, const T* cb, T* lx, T* lw) {
+  const long long nx = op.nx;
+  const int h0 = op.hoff[tile], hn = op.hoff[tile + 1] - h0;
+  for (int j = threadIdx.x; j < hn; j += MB) {
+    const long long c = op.hcol[h0 + j];
+#pragma unroll
+    for (int k = 0; k < NT; ++k) lx[k * op.hmax + j] = xs[k * nx + c];
+    if (xn != nullptr) {
+      T w = T(0);
+#pragma unroll
+      for (int k = 0; k < NT; ++k) w += cb[k] * xn[k * nx + c];
+      lw[j] = w;
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, int NT>
+__device__ inline void row_mk_lds(const MeshOp<T>& op, const T* lx, const T* lw, long long i, T* mu, T* ku,
+                                  T& mw) {
+  const long long nx = op.nx;
+#pragma unroll
+  for (int k = 0; k < NT; ++k) mu[k] = ku[k] = T(0);
+  mw = T(0);
+  for (int e = 0; e < op.ew; ++e) {
+    const long long q = (long long)e * nx + i;
+    const int lc = op.lcol[q];
+    const T m = op.emk[2 * q], kk = op.emk[2 * q + 1];
+#pragma unroll
+    for (int k = 0; k < NT; ++k) {
+      const T v = lx[k * op.hmax + lc];
+      mu[k] += m * v;
+      ku[k] += kk * v;
+    }
+    if (lw != nullptr) mw += m * lw[lc];
+  }
+}
+
+template <typename Tin, typename Tout, int NT>
+__global__ __launch_bounds__(MB) void k_mesh_residual_lds(const Tin* __restrict__ u, const Tin* __restrict__ F,
+                                                          Tout* __restrict__ r, MeshResidArgs<Tin> a,
+                                                          double* __restrict__ partial) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  Tin* lx = reinterpret_cast<Tin*>(lds_raw);
+  Tin* lw = lx + NT * a.op.hmax;
+  const long long nx = a.op.nx;
+  const long long tiles = (nx + MB - 1) / MB;
+  long long slab, tile;
+  slab_tile(tiles, slab, tile);
+  const long long i = tile * MB + threadIdx.x;
+  const int s = (int)(slab % a.N);
+  const bool couple = s + a.dir >= 0 && s + a.dir < a.N;
+  const long long off = slab * NT * nx;
+  stage_halo<Tin, NT>(a.op, tile, u + off, couple ? u + (slab + a.dir) * NT * nx : nullptr, a.cb, lx, lw);
+  double ss = 0.0;
+  if (i < nx) {
+    Tin mu[NT], ku[NT], mw;
+    row_mk_lds<Tin, NT>(a.op, lx, couple ? lw : nullptr, i, mu, ku, mw);
+#pragma unroll
+    for (int l = 0; l < NT; ++l) {
+      Tin acc = F[off + l * nx + i] + a.ca[l] * mw;
+#pragma unroll
+      for (int k = 0; k < NT; ++k) acc -= a.K[l * NT + k] * mu[k] + a.M[l * NT + k] * ku[k];
+      r[off + l * nx + i] = (Tout)acc;
+      ss += (double)acc * (double)acc;
+    }
+  }
+  if (partial != nullptr) {
+    const double t = block_sum(ss);
+    if (threadIdx.x == 0) partial[slab * tiles + tile] = t;
   }
 }
 
@@ -132,9 +232,10 @@ __device__ inline void node_solve(const T* K, const T* M, T m, T k, T* r) {
 template <typename T, int NT>
 __global__ __launch_bounds__(MB) void k_mesh_smooth(const T* __restrict__ x, const T* __restrict__ f,
                                                     const T* base, T* out, MeshSmoothArgs<T> a) {
-  const long long slab = slab_index();
   const long long nx = a.op.nx;
-  const long long i = (long long)blockIdx.x * MB + threadIdx.x;
+  long long slab, tile;
+  slab_tile((nx + MB - 1) / MB, slab, tile);
+  const long long i = tile * MB + threadIdx.x;
   if (slab >= a.slabs || i >= nx) return;
   const long long off = slab * NT * nx + i;
   T r[NT], xv[NT];
@@ -155,6 +256,42 @@ __global__ __launch_bounds__(MB) void k_mesh_smooth(const T* __restrict__ x, con
       r[l] = acc;
       xv[l] = x[off + l * nx];
     }
+  }
+  if (a.op_kind == SP_JACOBI) {
+    node_solve<T, NT>(a.K, a.M, a.op.diag[2 * i], a.op.diag[2 * i + 1], r);
+#pragma unroll
+    for (int l = 0; l < NT; ++l) r[l] = xv[l] + a.omega * r[l];
+  }
+#pragma unroll
+  for (int l = 0; l < NT; ++l) {
+    T o = r[l];
+    if (a.upd == UPD_ADD) o = base[off + l * nx] + a.scale * o;
+    else if (a.upd == UPD_SET) o = a.scale * o;
+    out[off + l * nx] = o;
+  }
+}
+
+template <typename T, int NT>
+__global__ __launch_bounds__(MB) void k_mesh_smooth_lds(const T* __restrict__ x, const T* __restrict__ f,
+                                                        const T* base, T* out, MeshSmoothArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  T* lx = reinterpret_cast<T*>(lds_raw);
+  const long long nx = a.op.nx;
+  long long slab, tile;
+  slab_tile((nx + MB - 1) / MB, slab, tile);
+  const long long i = tile * MB + threadIdx.x;
+  stage_halo<T, NT>(a.op, tile, x + slab * NT * nx, nullptr, nullptr, lx, nullptr);
+  if (i >= nx) return;
+  const long long off = slab * NT * nx + i;
+  T mu[NT], ku[NT], mw, r[NT], xv[NT];
+  row_mk_lds<T, NT>(a.op, lx, nullptr, i, mu, ku, mw);
+#pragma unroll
+  for (int l = 0; l < NT; ++l) {
+    T acc = f[off + l * nx];
+#pragma unroll
+    for (int k = 0; k < NT; ++k) acc -= a.K[l * NT + k] * mu[k] + a.M[l * NT + k] * ku[k];
+    r[l] = acc;
+    xv[l] = x[off + l * nx];
   }
   if (a.op_kind == SP_JACOBI) {
     node_solve<T, NT>(a.K, a.M, a.op.diag[2 * i], a.op.diag[2 * i + 1], r);
@@ -387,7 +524,16 @@ unsigned mesh_blocks_per_slab(long long nx) { return blocks_for(nx); }
 template <typename Tin, typename Tout>
 hipError_t launch_mesh_residual(int nt, const Tin* u, const Tin* F, Tout* r, const MeshResidArgs<Tin>& a,
                                 double* partial, hipStream_t s) {
-  const dim3 grid = slab_grid(blocks_for(a.op.nx), (long long)a.batch * a.N);
+  const long long blocks = (long long)blocks_for(a.op.nx) * a.batch * a.N;
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)blocks);
+  const size_t lds = (size_t)(nt + 1) * a.op.hmax * sizeof(Tin);
+  if (lds <= 65536) {
+#define L_(NT) hipLaunchKernelGGL((k_mesh_residual_lds<Tin, Tout, NT>), grid, dim3(MB), lds, s, u, F, r, a, partial)
+    NT_SWITCH(L_)
+#undef L_
+    return hipGetLastError();
+  }
 #define L_(NT) hipLaunchKernelGGL((k_mesh_residual<Tin, Tout, NT>), grid, dim3(MB), 0, s, u, F, r, a, partial)
   NT_SWITCH(L_)
 #undef L_
@@ -397,7 +543,16 @@ hipError_t launch_mesh_residual(int nt, const Tin* u, const Tin* F, Tout* r, con
 template <typename T>
 hipError_t launch_mesh_smooth(int nt, const T* x, const T* f, const T* base, T* out, const MeshSmoothArgs<T>& a,
                               hipStream_t s) {
-  const dim3 grid = slab_grid(blocks_for(a.op.nx), a.slabs);
+  const long long blocks = (long long)blocks_for(a.op.nx) * a.slabs;
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)blocks);
+  const size_t lds = (size_t)nt * a.op.hmax * sizeof(T);
+  if (!a.x_zero && lds <= 65536) {
+#define L_(NT) hipLaunchKernelGGL((k_mesh_smooth_lds<T, NT>), grid, dim3(MB), lds, s, x, f, base, out, a)
+    NT_SWITCH(L_)
+#undef L_
+    return hipGetLastError();
+  }
 #define L_(NT) hipLaunchKernelGGL((k_mesh_smooth<T, NT>), grid, dim3(MB), 0, s, x, f, base, out, a)
   NT_SWITCH(L_)
 #undef L_

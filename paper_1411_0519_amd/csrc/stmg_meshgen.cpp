@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <array>
+#include <cstdint>
 #include <cmath>
 #include <cstring>
 #include <limits>
@@ -148,8 +149,28 @@ MeshLevel refine(const MeshLevel& C) {
   return F;
 }
 
-// Boundary faces are faces of exactly one cell; their vertices are Dirichlet nodes.
-void number_interior(MeshLevel& L) {
+// Z-order (Morton) key of a point: each coordinate scaled to the box [lo, hi]
+// and quantised to 21 bits (d = 3) or 31 bits (d = 2), bits interleaved with
+// the first coordinate lowest.
+uint64_t morton_key(const double* x, int d, const double* lo, const double* hi) {
+  const int bits = d == 3 ? 21 : 31;
+  const double top = (double)((1ull << bits) - 1);
+  uint64_t q[3] = {0, 0, 0};
+  for (int i = 0; i < d; ++i) {
+    const double w = hi[i] > lo[i] ? (x[i] - lo[i]) / (hi[i] - lo[i]) : 0.0;
+    q[i] = (uint64_t)std::llround(std::min(std::max(w, 0.0), 1.0) * top);
+  }
+  uint64_t key = 0;
+  for (int b = bits - 1; b >= 0; --b)
+    for (int i = d - 1; i >= 0; --i) key = (key << 1) | ((q[i] >> b) & 1ull);
+  return key;
+}
+
+// Boundary faces are faces of exactly one cell; their vertices are Dirichlet
+// nodes.  The interior nodes are numbered along the Z-order curve of their
+// coordinates (ties by node number), so that a node's matrix row gathers
+// from nearby entries of a vector.
+void number_interior(MeshLevel& L, const double* lo, const double* hi) {
   const int d = L.d, nv = d + 1;
   std::vector<std::array<int, 3>> faces;
   faces.reserve((size_t)L.cells() * nv);
@@ -173,13 +194,16 @@ void number_interior(MeshLevel& L) {
       for (int k = 0; k < d; ++k) bnd[(size_t)faces[i][k]] = 1;
     i = j;
   }
+  std::vector<std::pair<uint64_t, int>> order;
+  for (long long v = 0; v < L.nodes(); ++v)
+    if (!bnd[(size_t)v]) order.push_back({morton_key(&L.xyz[(size_t)v * d], d, lo, hi), (int)v});
+  std::sort(order.begin(), order.end());
   L.pos.assign((size_t)L.nodes(), -1);
   L.interior.clear();
-  for (long long v = 0; v < L.nodes(); ++v)
-    if (!bnd[(size_t)v]) {
-      L.pos[(size_t)v] = (int)L.interior.size();
-      L.interior.push_back((int)v);
-    }
+  for (const auto& o : order) {
+    L.pos[(size_t)o.second] = (int)L.interior.size();
+    L.interior.push_back(o.second);
+  }
 }
 
 // M_e = |T| (1 + delta_ij) / ((d+1)(d+2)), K_e = |T| G G^T with G the
@@ -240,8 +264,8 @@ void assemble(MeshLevel& L) {
   for (long long r = 0; r < nx; ++r) L.rowptr[(size_t)r + 1] += L.rowptr[(size_t)r];
 }
 
-void finish(MeshLevel& L) {
-  number_interior(L);
+void finish(MeshLevel& L, const double* lo, const double* hi) {
+  number_interior(L, lo, hi);
   assemble(L);
 }
 
@@ -309,12 +333,20 @@ int mesh_hierarchy(const st_mesh* m, int refinements, std::vector<MeshLevel>& ou
         }
         L.longest_edge = std::max(L.longest_edge, std::sqrt(l2));
       }
-  finish(L);
+  double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};   // bounding box of the coarse mesh
+  for (int i = 0; i < d; ++i) {
+    lo[i] = hi[i] = L.xyz[(size_t)i];
+    for (long long v = 0; v < L.nodes(); ++v) {
+      lo[i] = std::min(lo[i], L.xyz[(size_t)v * d + i]);
+      hi[i] = std::max(hi[i], L.xyz[(size_t)v * d + i]);
+    }
+  }
+  finish(L, lo, hi);
   out.push_back(std::move(L));
   for (int r = 0; r < refinements; ++r) {
     MeshLevel F = refine(out.back());
     F.longest_edge = 0.5 * out.back().longest_edge;
-    finish(F);
+    finish(F, lo, hi);
     out.push_back(std::move(F));
   }
   return ST_OK;

@@ -1,7 +1,8 @@
 """GPU parity of the P1 mesh path (numerical examples of Sec. 4: P1 elements on
 uniformly refined triangle/tetrahedron meshes, one spatial multigrid cycle per
 slab) against the oracle's P1Hierarchy on the same seeded inputs, through the
-C ABI."""
+C ABI.  The library numbers the interior nodes along a Z-order curve, the
+oracle in node order; vectors are mapped between the two by node coordinates."""
 import numpy as np
 import pytest
 import torch
@@ -27,6 +28,34 @@ def meshes(kind, R):
     return _MESHES[(kind, R)]
 
 
+_PERMS = {}
+
+
+def perm(kind, rx):
+    """perm[j] = oracle index of the library's interior node j on refinement rx."""
+    if (kind, rx) not in _PERMS:
+        pts = stmg.mesh_level(*workloads.coarse_mesh(kind), rx)["points"]
+        opts = meshes(kind, rx)[rx].points
+        index = {tuple(p): i for i, p in enumerate(opts)}
+        _PERMS[(kind, rx)] = np.array([index[tuple(p)] for p in pts])
+    return _PERMS[(kind, rx)]
+
+
+def g(x, kind, rx, N, nt, dtype=torch.float64):
+    """Oracle vector (dof, b) -> library device vector."""
+    b = x.shape[1]
+    y = x.reshape(N, nt, -1, b)[:, :, perm(kind, rx), :]
+    return to_gpu(y.reshape(-1, b), dtype)
+
+
+def o(t, kind, rx, N, nt, b):
+    """Library device vector -> oracle layout (dof, b)."""
+    y = to_oracle(t, b).reshape(N, nt, -1, b)
+    out = np.empty_like(y)
+    out[:, :, perm(kind, rx), :] = y
+    return out.reshape(-1, b)
+
+
 def cid(c):
     return "{}R{}N{}p{}b{}".format(*c)
 
@@ -45,98 +74,112 @@ def rvec(dof, b, seed):
     return np.random.default_rng(seed).uniform(-1, 1, (dof, b))
 
 
+def lvl_info(S, H, lvl):
+    """(oracle level index k, oracle level, refinement level) of library level lvl."""
+    k = len(H.levels) - 1 - lvl
+    return k, H.levels[k], S.levels[lvl]["n"]
+
+
 @pytest.mark.parametrize("case", CASES, ids=cid)
 @pytest.mark.parametrize("transpose", [False, True])
 def test_mesh_residual(case, transpose):
     print(f"mesh residual {case} transpose={transpose}", flush=True)
+    kind, R, N, pt, b = case
     S, H = pair(case)
-    b = case[4]
     assert S.schedule == H.schedule
     lev = H.fine
     u = rvec(lev.dof, b, 1)
     F = rvec(lev.dof, b, 2)
-    r, nrm = S.residual(to_gpu(u), to_gpu(F), transpose=transpose, norms=True)
+    r, nrm = S.residual(g(u, kind, R, N, pt + 1), g(F, kind, R, N, pt + 1), transpose=transpose, norms=True)
     ref = F - lev.apply(u, transpose)
-    assert rel_err(to_oracle(r, b), ref) < 1e-13
+    assert rel_err(o(r, kind, R, N, pt + 1, b), ref) < 1e-13
     assert np.allclose(nrm, np.linalg.norm(ref, axis=0), rtol=1e-12)
+
+
+def spatial_ref(H, k, r, b):
+    lev = H.levels[k]
+    cols = r.reshape(lev.N, lev.slab, b).transpose(1, 0, 2).reshape(lev.slab, lev.N * b)
+    return H.spatial_cycle(k).cycle(cols).reshape(lev.slab, lev.N, b).transpose(1, 0, 2).reshape(lev.dof, b)
 
 
 @pytest.mark.parametrize("case", CASES, ids=cid)
 @pytest.mark.parametrize("transpose", [False, True])
 def test_mesh_spatial_cycle(case, transpose):
     print(f"mesh spatial cycle {case} transpose={transpose}", flush=True)
+    kind, R, N, pt, b = case
     S, H = pair(case, transpose=transpose)
-    b = case[4]
     for lvl in range(S.nlev):
-        k = len(H.levels) - 1 - lvl
-        lev = H.levels[k]
+        k, lev, rx = lvl_info(S, H, lvl)
         r = rvec(lev.dof, b, 3 + lvl)
-        x = S.spatial_cycle(to_gpu(r), level=lvl, transpose=transpose)
-        cols = r.reshape(lev.N, lev.slab, b).transpose(1, 0, 2).reshape(lev.slab, lev.N * b)
-        ref = H.spatial_cycle(k).cycle(cols).reshape(lev.slab, lev.N, b).transpose(1, 0, 2).reshape(lev.dof, b)
-        assert rel_err(to_oracle(x, b), ref) < 1e-12, lvl
+        x = S.spatial_cycle(g(r, kind, rx, lev.N, pt + 1), level=lvl, transpose=transpose)
+        assert rel_err(o(x, kind, rx, lev.N, pt + 1, b), spatial_ref(H, k, r, b)) < 1e-12, lvl
 
 
 @pytest.mark.parametrize("nu", [(1, 0), (0, 1), (0, 0), (3, 1)])
 def test_mesh_spatial_cycle_parameters(nu):
     case = ("square4", 3, 4, 1, 1)
+    kind, R, N, pt, b = case
     S, H = pair(case, nu1x=nu[0], nu2x=nu[1], omega_x=0.8)
-    lev = H.fine
-    r = rvec(lev.dof, 1, 4)
-    x = S.spatial_cycle(to_gpu(r))
-    cols = r.reshape(lev.N, lev.slab, 1).transpose(1, 0, 2).reshape(lev.slab, lev.N)
-    ref = H.spatial_cycle(len(H.levels) - 1).cycle(cols).reshape(lev.slab, lev.N, 1).transpose(1, 0, 2)
-    assert rel_err(to_oracle(x, 1), ref.reshape(lev.dof, 1)) < 1e-12
+    r = rvec(H.fine.dof, 1, 4)
+    x = S.spatial_cycle(g(r, kind, R, N, pt + 1))
+    assert rel_err(o(x, kind, R, N, pt + 1, 1), spatial_ref(H, len(H.levels) - 1, r, 1)) < 1e-12
 
 
 @pytest.mark.parametrize("case", CASES[:3], ids=cid)
 def test_mesh_transfers(case):
+    kind, R, N, pt, b = case
     S, H = pair(case)
-    b = case[4]
     for lvl in range(S.nlev - 1):
-        k = len(H.levels) - 1 - lvl
+        k, lev, rx = lvl_info(S, H, lvl)
+        _, levc, rxc = lvl_info(S, H, lvl + 1)
         P = H.P[k]
-        rf = rvec(H.levels[k].dof, b, 10 + lvl)
-        ec = rvec(H.levels[k - 1].dof, b, 20 + lvl)
-        uf = rvec(H.levels[k].dof, b, 30 + lvl)
-        Fc = S.restrict(to_gpu(rf), level=lvl)
-        ug = to_gpu(uf)
-        S.prolong_add(to_gpu(ec), ug, level=lvl)
-        assert rel_err(to_oracle(Fc, b), P.T @ rf) < 1e-13, lvl
-        assert rel_err(to_oracle(ug, b), uf + P @ ec) < 1e-13, lvl
+        rf = rvec(lev.dof, b, 10 + lvl)
+        ec = rvec(levc.dof, b, 20 + lvl)
+        uf = rvec(lev.dof, b, 30 + lvl)
+        Fc = S.restrict(g(rf, kind, rx, lev.N, pt + 1), level=lvl)
+        ug = g(uf, kind, rx, lev.N, pt + 1)
+        S.prolong_add(g(ec, kind, rxc, levc.N, pt + 1), ug, level=lvl)
+        assert rel_err(o(Fc, kind, rxc, levc.N, pt + 1, b), P.T @ rf) < 1e-13, lvl
+        assert rel_err(o(ug, kind, rx, lev.N, pt + 1, b), uf + P @ ec) < 1e-13, lvl
 
 
 def test_mesh_smoothing_step():
     case = ("cube12", 2, 4, 1, 2)
-    b = 2
+    kind, R, N, pt, b = case
     for transpose in (False, True):
         S, H = pair(case, transpose=transpose)
         k = len(H.levels) - 1
         rng = np.random.default_rng(7)
         u = rng.uniform(-1, 1, (H.fine.dof, b))
         F = rng.uniform(-1, 1, (H.fine.dof, b))
-        ug = to_gpu(u)
-        S.smooth(ug, to_gpu(F), transpose=transpose)
-        assert rel_err(to_oracle(ug, b), H.smooth(k, u, F)) < 1e-12
+        ug = g(u, kind, R, N, pt + 1)
+        S.smooth(ug, g(F, kind, R, N, pt + 1), transpose=transpose)
+        assert rel_err(o(ug, kind, R, N, pt + 1, b), H.smooth(k, u, F)) < 1e-12
 
 
 def test_mesh_exact_slab_solves():
     # dense inverses: the coarse mesh on every level, the coarsest level's own mesh
     case = ("square4", 2, 2, 1, 1)
+    kind = case[0]
     S, H = pair(case)
     for lvl in range(S.nlev):
-        k = len(H.levels) - 1 - lvl
-        lev = H.levels[k]
+        k, lev, rx = lvl_info(S, H, lvl)
         r = rvec(lev.dof, 1, 40 + lvl)
-        if H.space_level[k] == 0 or k == 0:
+        if rx == 0 or k == 0:
             for transpose in (False, True):
-                Ht = p1.P1Hierarchy(*workloads.coarse_mesh("square4"), 2, 2, 1, transpose=transpose,
-                                    meshes=meshes("square4", 2))
-                x = S.block_solve(to_gpu(r), level=lvl, transpose=transpose)
-                assert rel_err(to_oracle(x, 1), Ht.block_solve(k, r)) < 1e-12
+                Ht = p1.P1Hierarchy(*workloads.coarse_mesh(kind), 2, 2, 1, transpose=transpose,
+                                    meshes=meshes(kind, 2))
+                x = S.block_solve(g(r, kind, rx, lev.N, 2), level=lvl, transpose=transpose)
+                assert rel_err(o(x, kind, rx, lev.N, 2, 1), Ht.block_solve(k, r)) < 1e-12
         else:
             with pytest.raises(stmg.STMGError):
-                S.block_solve(to_gpu(r), level=lvl)
+                S.block_solve(g(r, kind, rx, lev.N, 2), level=lvl)
+
+
+def nodal(f, u0, kind, R):
+    """Nodal arrays in oracle node order -> library order (last axis)."""
+    pm = perm(kind, R)
+    return f[..., pm], u0[..., pm]
 
 
 @pytest.mark.parametrize("case", [("square4", 3, 16, 1, 1), ("cube12", 2, 16, 1, 2), ("square4", 2, 8, 3, 1)],
@@ -144,74 +187,75 @@ def test_mesh_exact_slab_solves():
 @pytest.mark.parametrize("gamma", [1, 2])
 def test_mesh_iterates_match_oracle(case, gamma):
     print(f"mesh iterates {case} gamma={gamma}", flush=True)
+    kind, R, N, pt, b = case
     S, H = pair(case, gamma=gamma)
-    b = case[4]
     assert S.schedule == H.schedule
-    pts = H.meshes[-1].points
-    f, u0 = workloads.mesh_data(pts, case[2], batch=b, seed=8)
+    f, u0 = workloads.mesh_data(H.meshes[-1].points, N, batch=b, seed=8)
     F = spacetime.rhs(H.fine, f, u0)
     _, _, its = H.solve(F, rtol=0.0, maxit=3, keep_iterates=True)
     ug = torch.zeros(S.level_dof(0), dtype=torch.float64, device=DEV)
-    Fg = to_gpu(F)
+    Fg = g(F, kind, R, N, pt + 1)
     for k in range(1, 4):
         S.solve(Fg, u=ug, rtol=0.0, maxit=1, raise_on_noconv=False)
-        assert rel_err(to_oracle(ug, b), its[k]) < 1e-11, k
+        assert rel_err(o(ug, kind, R, N, pt + 1, b), its[k]) < 1e-11, k
 
 
 def test_mesh_adjoint_iterates():
     case = ("cube12", 2, 8, 1, 1)
+    kind, R, N, pt, b = case
     S, H = pair(case, transpose=True)
-    g = rvec(H.fine.dof, 1, 11)
-    Ht = p1.P1Hierarchy(*workloads.coarse_mesh("cube12"), 2, 8, 1, transpose=True, meshes=meshes("cube12", 2))
-    _, _, its = Ht.solve(g, rtol=0.0, maxit=3, keep_iterates=True)
+    gv = rvec(H.fine.dof, 1, 11)
+    _, _, its = H.solve(gv, rtol=0.0, maxit=3, keep_iterates=True)
     lam = torch.zeros(S.level_dof(0), dtype=torch.float64, device=DEV)
     for k in range(1, 4):
-        S.adjoint(to_gpu(g), lam=lam, rtol=0.0, maxit=1, gradients=False, raise_on_noconv=False)
-        assert rel_err(to_oracle(lam, 1), its[k]) < 1e-11, k
+        S.adjoint(g(gv, kind, R, N, pt + 1), lam=lam, rtol=0.0, maxit=1, gradients=False, raise_on_noconv=False)
+        assert rel_err(o(lam, kind, R, N, pt + 1, 1), its[k]) < 1e-11, k
 
 
 def test_mesh_rhs_and_adjoint_map():
     case = ("cube12", 2, 4, 2, 2)
+    kind, R, N, pt, b = case
     S, H = pair(case)
-    b = 2
-    pts = H.meshes[-1].points
-    f, u0 = workloads.mesh_data(pts, 4, batch=b, seed=5)
-    F = S.rhs(nodal_to_gpu(f), nodal_to_gpu(u0))
-    assert rel_err(to_oracle(F, b), spacetime.rhs(H.fine, f, u0)) < 1e-13
+    f, u0 = workloads.mesh_data(H.meshes[-1].points, N, batch=b, seed=5)
+    fl, u0l = nodal(f, u0, kind, R)
+    F = S.rhs(nodal_to_gpu(fl), nodal_to_gpu(u0l))
+    assert rel_err(o(F, kind, R, N, pt + 1, b), spacetime.rhs(H.fine, f, u0)) < 1e-13
     lam = rvec(H.fine.dof, b, 6)
-    gf, gu0 = S.rhs_adjoint(to_gpu(lam))
+    gf, gu0 = S.rhs_adjoint(g(lam, kind, R, N, pt + 1))
     gf_ref, gu0_ref = spacetime.rhs_adjoint(H.fine, lam)
-    assert rel_err(gf.cpu().numpy().reshape(gf_ref.shape), gf_ref) < 1e-13
-    assert rel_err(gu0.cpu().numpy().reshape(gu0_ref.shape), gu0_ref) < 1e-13
+    pm = perm(kind, R)
+    assert rel_err(gf.cpu().numpy().reshape(gf_ref.shape), gf_ref[..., pm]) < 1e-13
+    assert rel_err(gu0.cpu().numpy().reshape(gu0_ref.shape), gu0_ref[..., pm]) < 1e-13
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_mesh_solve_reaches_direct_solution(precision):
     case = ("cube12", 2, 32, 1, 1)
+    kind, R, N, pt, b = case
     S, H = pair(case, precision=precision)
-    pts = H.meshes[-1].points
-    f, u0 = workloads.mesh_data(pts, 32, seed=13)
+    f, u0 = workloads.mesh_data(H.meshes[-1].points, N, seed=13)
     F = spacetime.rhs(H.fine, f, u0)
     dt = torch.float32 if precision == "fp32" else torch.float64
     rtol = 1e-5 if precision == "fp32" else 1e-10
-    u, its, hist = S.solve(to_gpu(F, dt), rtol=rtol, maxit=40)
+    u, its, hist = S.solve(g(F, kind, R, N, pt + 1, dt), rtol=rtol, maxit=40)
     assert max(hist[-1]) <= rtol and its <= 20
     ref = spacetime.forward_substitution(H.fine, F)
-    assert norm_rel(to_oracle(u, 1), ref) < (1e-3 if precision == "fp32" else 1e-8)
+    assert norm_rel(o(u, kind, R, N, pt + 1, 1), ref) < (1e-3 if precision == "fp32" else 1e-8)
 
 
 def test_mesh_table1_iteration_counts():
     # Example chap4_example1 on the GPU: 12-tetrahedron cube refined twice,
     # T = 1, N = 2^L_t, f = 0, random start in [0,1], reduction 1e-8; the same
     # counts as the oracle (which are within two of Table chap4_TableExample1)
-    coarse = workloads.coarse_mesh("cube12")
+    kind = "cube12"
+    coarse = workloads.coarse_mesh(kind)
     for lt in (2, 4, 6):
         N = 2 ** lt
         S = stmg.Solver(3, 2, N, pt=1, smoother="spatial_mg", mesh=coarse, device=DEV)
-        H = p1.P1Hierarchy(*coarse, 2, N, 1, meshes=meshes("cube12", 2))
+        H = p1.P1Hierarchy(*coarse, 2, N, 1, meshes=meshes(kind, 2))
         u0 = np.random.default_rng(0).uniform(0, 1, (H.fine.dof, 1))
         _, hist_o, _ = H.solve(np.zeros_like(u0), u=u0, rtol=1e-8, maxit=30)
-        u = to_gpu(u0)
+        u = g(u0, kind, 2, N, 2)
         u, its, hist = S.solve(torch.zeros_like(u), u=u, rtol=1e-8, maxit=30)
         assert its == len(hist_o) - 1, (lt, its, len(hist_o) - 1)
 
@@ -223,8 +267,8 @@ def test_mesh_graph_replay_matches_eager():
         E = stmg.Solver(2, 3, 16, pt=1, smoother="spatial_mg", mesh=coarse, device=DEV)
         G = stmg.Solver(2, 3, 16, pt=1, smoother="spatial_mg", mesh=coarse, device=DEV)
         G.set_graph(True)
-        H = meshes("square4", 3)
-        f, u0 = workloads.mesh_data(H[-1].points, 16, seed=12)
+        pts = stmg.mesh_level(*coarse, 3)["points"]
+        f, u0 = workloads.mesh_data(pts, 16, seed=12)
         F = E.rhs(nodal_to_gpu(f), nodal_to_gpu(u0))
         ue = torch.zeros_like(F)
         ug = torch.zeros_like(F)

@@ -12,6 +12,31 @@ from oracle import mesh
 from paper_1411_0519_amd import stmg, workloads
 
 
+def node_map(lib_points, oracle_points):
+    """pm[j] = oracle index of the library's node j (coordinates match exactly)."""
+    index = {tuple(p): i for i, p in enumerate(oracle_points)}
+    assert len(index) == len(lib_points)
+    return np.array([index[tuple(p)] for p in lib_points])
+
+
+def z_order(points, coarse_coords):
+    """Morton keys of the points in the coarse mesh's bounding box, written out
+    bit by bit (first coordinate lowest; 21 bits in 3-D, 31 in 2-D); the
+    position in the node list breaks ties."""
+    d = points.shape[1]
+    bits = 21 if d == 3 else 31
+    lo, hi = coarse_coords.min(axis=0), coarse_coords.max(axis=0)
+    q = np.rint((points - lo) / (hi - lo) * (2 ** bits - 1)).astype(np.int64)
+    keys = []
+    for j, row in enumerate(q):
+        key = 0
+        for b in range(bits - 1, -1, -1):
+            for i in range(d - 1, -1, -1):
+                key = (key << 1) | int((row[i] >> b) & 1)
+        keys.append(key * len(q) + j)
+    return np.array(keys, dtype=object)
+
+
 @pytest.mark.parametrize("kind,levels", [("square4", 4), ("cube12", 2)])
 def test_library_mesh_matches_oracle(kind, levels):
     c, t = workloads.coarse_mesh(kind)
@@ -19,11 +44,12 @@ def test_library_mesh_matches_oracle(kind, levels):
     for L in range(levels + 1):
         g = stmg.mesh_level(c, t, L)
         o = ms[L]
-        assert np.array_equal(g["points"], o.points), L            # same nodes in the same order
+        pm = node_map(g["points"], o.points)                        # the same node set
         M = sp.csr_matrix((g["mval"], g["col"], g["rowptr"]), shape=(o.nx, o.nx))
         K = sp.csr_matrix((g["kval"], g["col"], g["rowptr"]), shape=(o.nx, o.nx))
-        assert abs(M - o.Mh).max() <= 1e-15 * abs(o.Mh).max()
-        assert abs(K - o.Kh).max() <= 1e-14 * abs(o.Kh).max()
+        assert abs(M - o.Mh[pm][:, pm]).max() <= 1e-15 * abs(o.Mh).max()
+        assert abs(K - o.Kh[pm][:, pm]).max() <= 1e-14 * abs(o.Kh).max()
+        assert np.all(np.diff(z_order(g["points"], c)) > 0)          # numbered along the Z-order curve
         assert np.all(np.diff(g["rowptr"]) > 0)
         for i in range(o.nx):                                       # columns ascending per row
             row = g["col"][g["rowptr"][i]:g["rowptr"][i + 1]]
@@ -37,9 +63,9 @@ def test_library_mesh_on_an_unstructured_coarse_mesh():
     ms = mesh.hierarchy(c, t, 3)
     g = stmg.mesh_level(c, t, 3)
     o = ms[3]
-    assert np.array_equal(g["points"], o.points)
+    pm = node_map(g["points"], o.points)
     K = sp.csr_matrix((g["kval"], g["col"], g["rowptr"]), shape=(o.nx, o.nx))
-    assert abs(K - o.Kh).max() <= 1e-14 * abs(o.Kh).max()
+    assert abs(K - o.Kh[pm][:, pm]).max() <= 1e-14 * abs(o.Kh).max()
 
 
 def _mesh(coords, cells):
