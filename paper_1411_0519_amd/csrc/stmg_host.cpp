@@ -156,6 +156,8 @@ struct MeshDev {
   double *mv64 = nullptr, *kv64 = nullptr, *dg64 = nullptr, *w64 = nullptr;
   float *mv32 = nullptr, *kv32 = nullptr, *dg32 = nullptr, *w32 = nullptr;
   int *p = nullptr, *rrow = nullptr, *rcol = nullptr;
+  int* rell = nullptr;                          // [rw][nxc] transpose of the interpolation, ELL
+  int rw = 0;
 };
 
 struct GraphCache {
@@ -598,7 +600,7 @@ const float* mesh_w<float>(const st_mg* h, int rx) { return h->md[(size_t)rx].w3
 // interpolation from refinement level rx - 1 to rx
 MeshXfer mesh_xfer(const st_mg* h, int rx) {
   const MeshDev& m = h->md[(size_t)rx];
-  return {m.p, m.rrow, m.rcol, m.nx, m.nxc};
+  return {m.p, m.rrow, m.rcol, m.nx, m.nxc, m.rell, m.rw};
 }
 template <typename T>
 const T* dense_inv(const Level& L, bool own);
@@ -756,7 +758,7 @@ MeshTransferArgs<T> mesh_transfer(const st_mg* h, int lf) {
     a.x = mesh_xfer(h, F.n);
     a.w = mesh_w<T>(h, F.n);
   } else {
-    a.x = MeshXfer{nullptr, nullptr, nullptr, F.nx, F.nx};
+    a.x = MeshXfer{nullptr, nullptr, nullptr, F.nx, F.nx, nullptr, 0};
     a.w = nullptr;
   }
   a.Nc = C.N;
@@ -1608,6 +1610,12 @@ int setup_mesh_levels(st_mg* h, const st_mesh* mesh, int refinements) {
       CHK(upload(h, &D.rcol, rcol));
       CHK(upload(h, &D.w64, w));
       CHK(upload(h, &D.w32, w));
+      for (long long I = 0; I < D.nxc; ++I) D.rw = std::max(D.rw, rrow[(size_t)I + 1] - rrow[(size_t)I]);
+      std::vector<int> rell((size_t)D.rw * D.nxc, -1);
+      for (long long I = 0; I < D.nxc; ++I)
+        for (int e = rrow[(size_t)I]; e < rrow[(size_t)I + 1]; ++e)
+          rell[(size_t)(e - rrow[(size_t)I]) * D.nxc + I] = rcol[(size_t)e];
+      CHK(upload(h, &D.rell, rell));
     }
   }
   for (size_t l = 0; l < h->lv.size(); ++l) {
@@ -1804,7 +1812,7 @@ int st_mg_destroy(st_mg_t h) {
     (void)hipFree(L.C32);
   }
   for (auto& D : h->md) {
-    for (void* q : {(void*)D.hoff, (void*)D.hcol, (void*)D.lcol, (void*)D.ecol, (void*)D.emk64, (void*)D.emk32, (void*)D.rowptr, (void*)D.col, (void*)D.mv64, (void*)D.kv64, (void*)D.dg64, (void*)D.w64,
+    for (void* q : {(void*)D.rell, (void*)D.hoff, (void*)D.hcol, (void*)D.lcol, (void*)D.ecol, (void*)D.emk64, (void*)D.emk32, (void*)D.rowptr, (void*)D.col, (void*)D.mv64, (void*)D.kv64, (void*)D.dg64, (void*)D.w64,
                     (void*)D.mv32, (void*)D.kv32, (void*)D.dg32, (void*)D.w32, (void*)D.p, (void*)D.rrow,
                     (void*)D.rcol})
       (void)hipFree(q);

@@ -274,6 +274,10 @@ struct MeshXfer {
   const int* rrow;
   const int* rcol;
   long long nxf, nxc;
+  // the transpose column-major in ELL form: entry e of coarse row I at
+  // e * nxc + I (fine index, -1 for padding), rw entries per row
+  const int* rell;
+  int rw;
 };
 // Residual r = F - L u on a mesh level; time coefficients as in ResidArgs.
 template <typename T>

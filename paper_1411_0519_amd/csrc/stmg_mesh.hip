@@ -310,16 +310,17 @@ __global__ __launch_bounds__(MB) void k_mesh_smooth_lds(const T* __restrict__ x,
 template <typename T, int NT>
 __global__ __launch_bounds__(MB) void k_mesh_restrict_space(const T* __restrict__ rf, T* __restrict__ fc,
                                                             MeshXfer x, const T* __restrict__ w, long long slabs) {
-  const long long slab = slab_index();
-  const long long I = (long long)blockIdx.x * MB + threadIdx.x;
+  long long slab, tile;
+  slab_tile((x.nxc + MB - 1) / MB, slab, tile);
+  const long long I = tile * MB + threadIdx.x;
   if (slab >= slabs || I >= x.nxc) return;
   const T* src = rf + slab * NT * x.nxf;
   T acc[NT];
 #pragma unroll
   for (int l = 0; l < NT; ++l) acc[l] = T(0);
-  const int e1 = x.rrow[I + 1];
-  for (int e = x.rrow[I]; e < e1; ++e) {
-    const long long c = x.rcol[e];
+  for (int e = 0; e < x.rw; ++e) {
+    const long long c = x.rell[(long long)e * x.nxc + I];
+    if (c < 0) break;
     const T wc = w[c];
 #pragma unroll
     for (int l = 0; l < NT; ++l) acc[l] += wc * src[l * x.nxf + c];
@@ -332,8 +333,9 @@ __global__ __launch_bounds__(MB) void k_mesh_restrict_space(const T* __restrict_
 template <typename T, int NT>
 __global__ __launch_bounds__(MB) void k_mesh_prolong_space(const T* __restrict__ ec, T* __restrict__ uf,
                                                            MeshXfer x, const T* __restrict__ w, long long slabs) {
-  const long long slab = slab_index();
-  const long long i = (long long)blockIdx.x * MB + threadIdx.x;
+  long long slab, tile;
+  slab_tile((x.nxf + MB - 1) / MB, slab, tile);
+  const long long i = tile * MB + threadIdx.x;
   if (slab >= slabs || i >= x.nxf) return;
   const int p0 = x.p[2 * i], p1 = x.p[2 * i + 1];
   const T wi = w[i];
@@ -378,9 +380,10 @@ __global__ __launch_bounds__(MB) void k_mesh_dense(const T* __restrict__ Ainv, i
 template <typename T, int NT>
 __global__ __launch_bounds__(MB) void k_mesh_restrict(const T* __restrict__ rf, T* __restrict__ Fc,
                                                       MeshTransferArgs<T> a) {
-  const long long cs = slab_index();   // b * Nc + m
-  const long long I = (long long)blockIdx.x * MB + threadIdx.x;
   const long long nxc = a.x.nxc, nxf = a.x.nxf;
+  long long cs, tile;   // cs = b * Nc + m
+  slab_tile((nxc + MB - 1) / MB, cs, tile);
+  const long long I = tile * MB + threadIdx.x;
   if (cs >= (long long)a.batch * a.Nc || I >= nxc) return;
   const long long b = cs / a.Nc, m = cs % a.Nc;
   T out[NT];
@@ -394,9 +397,9 @@ __global__ __launch_bounds__(MB) void k_mesh_restrict(const T* __restrict__ rf, 
     if (a.full) {
 #pragma unroll
       for (int l = 0; l < NT; ++l) g[l] = T(0);
-      const int e1 = a.x.rrow[I + 1];
-      for (int e = a.x.rrow[I]; e < e1; ++e) {
-        const long long c = a.x.rcol[e];
+      for (int e = 0; e < a.x.rw; ++e) {
+        const long long c = a.x.rell[(long long)e * nxc + I];
+        if (c < 0) break;
         const T wc = a.w[c];
 #pragma unroll
         for (int l = 0; l < NT; ++l) g[l] += wc * src[l * nxf + c];
@@ -419,9 +422,10 @@ __global__ __launch_bounds__(MB) void k_mesh_restrict(const T* __restrict__ rf, 
 template <typename T, int NT>
 __global__ __launch_bounds__(MB) void k_mesh_prolong(const T* __restrict__ ec, T* __restrict__ uf,
                                                      MeshTransferArgs<T> a) {
-  const long long fsl = slab_index();   // b * 2Nc + fs
-  const long long i = (long long)blockIdx.x * MB + threadIdx.x;
   const long long nxc = a.x.nxc, nxf = a.x.nxf;
+  long long fsl, tile;   // fsl = b * 2Nc + fs
+  slab_tile((nxf + MB - 1) / MB, fsl, tile);
+  const long long i = tile * MB + threadIdx.x;
   const long long Nf = 2LL * a.Nc;
   if (fsl >= (long long)a.batch * Nf || i >= nxf) return;
   const long long b = fsl / Nf, fs = fsl % Nf, m = fs >> 1;
@@ -562,7 +566,9 @@ hipError_t launch_mesh_smooth(int nt, const T* x, const T* f, const T* base, T* 
 template <typename T>
 hipError_t launch_mesh_restrict_space(int nt, const T* rf, T* fc, const MeshXfer& x, const T* w, long long slabs,
                                       hipStream_t s) {
-  const dim3 grid = slab_grid(blocks_for(x.nxc), slabs);
+  const long long blocks = (long long)blocks_for(x.nxc) * slabs;
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)blocks);
 #define L_(NT) hipLaunchKernelGGL((k_mesh_restrict_space<T, NT>), grid, dim3(MB), 0, s, rf, fc, x, w, slabs)
   NT_SWITCH(L_)
 #undef L_
@@ -572,7 +578,9 @@ hipError_t launch_mesh_restrict_space(int nt, const T* rf, T* fc, const MeshXfer
 template <typename T>
 hipError_t launch_mesh_prolong_space(int nt, const T* ec, T* uf, const MeshXfer& x, const T* w, long long slabs,
                                      hipStream_t s) {
-  const dim3 grid = slab_grid(blocks_for(x.nxf), slabs);
+  const long long blocks = (long long)blocks_for(x.nxf) * slabs;
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)blocks);
 #define L_(NT) hipLaunchKernelGGL((k_mesh_prolong_space<T, NT>), grid, dim3(MB), 0, s, ec, uf, x, w, slabs)
   NT_SWITCH(L_)
 #undef L_
@@ -590,7 +598,9 @@ hipError_t launch_mesh_dense(const T* Ainv, int m, int trans, const T* f, const 
 
 template <typename T>
 hipError_t launch_mesh_restrict(int nt, const T* rf, T* Fc, const MeshTransferArgs<T>& a, hipStream_t s) {
-  const dim3 grid = slab_grid(blocks_for(a.x.nxc), (long long)a.batch * a.Nc);
+  const long long blocks = (long long)blocks_for(a.x.nxc) * a.batch * a.Nc;
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)blocks);
 #define L_(NT) hipLaunchKernelGGL((k_mesh_restrict<T, NT>), grid, dim3(MB), 0, s, rf, Fc, a)
   NT_SWITCH(L_)
 #undef L_
@@ -599,7 +609,9 @@ hipError_t launch_mesh_restrict(int nt, const T* rf, T* Fc, const MeshTransferAr
 
 template <typename T>
 hipError_t launch_mesh_prolong(int nt, const T* ec, T* uf, const MeshTransferArgs<T>& a, hipStream_t s) {
-  const dim3 grid = slab_grid(blocks_for(a.x.nxf), (long long)a.batch * 2 * a.Nc);
+  const long long blocks = (long long)blocks_for(a.x.nxf) * a.batch * 2 * a.Nc;
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)blocks);
 #define L_(NT) hipLaunchKernelGGL((k_mesh_prolong<T, NT>), grid, dim3(MB), 0, s, ec, uf, a)
   NT_SWITCH(L_)
 #undef L_
