@@ -204,6 +204,11 @@ struct st_mg {
   int graph = 0;
   int impl = TRANSFORM_AUTO;
   bool small = true;      // one-kernel smoothing steps on levels whose slabs fit in LDS
+  // coarse end of every cycle in one workgroup from level `tail` down (-1: off);
+  // argument blocks in device memory for the forward and the adjoint cycle
+  int tail = -1;
+  size_t tail_lds = 0;
+  void* tail_args[2] = {nullptr, nullptr};
   GraphCache gc;
   // per-launch event pairs while profiling is on
   bool prof = false;
@@ -1158,6 +1163,12 @@ template <typename T>
 int vcycle(st_mg* h, int l, bool transpose, T* u, const T* F, bool u_zero, bool r_ready,
            hipStream_t s) {
   const int last = (int)h->lv.size() - 1;
+  if (l == h->tail && l > 0) {
+    ProfScope ps(h, ST_PROF_SMALL, l, s);
+    HIPCHK(h, launch_coarse_cycle<T>(h->p.dim, h->nt, (const CoarseArgs<T>*)h->tail_args[transpose ? 1 : 0],
+                                     h->tail_lds, F, u, h->p.batch, u_zero ? 1 : 0, s));
+    return ST_OK;
+  }
   if (l == last) return coarsest_solve<T>(h, transpose, u, F, s);
   const T om = (T)h->p.omega;
   T* r = level_r<T>(h, l);
@@ -1451,6 +1462,98 @@ int autotune_all(st_mg* h, void* u0, void* F0, hipStream_t s) {
     }
   }
   return ST_OK;
+}
+
+// The coarse end of the cycle in one workgroup: the first level l >= 1 from
+// which every level's iterate, right-hand side and tables, plus two scratch
+// vectors, fit in 64 KB of LDS (exact smoother, N_t <= 4, FP64 or FP32 handles;
+// STMG_COARSE_TAIL=0 turns it off).
+template <typename T>
+int setup_coarse_tail_t(st_mg* h) {
+  const int last = (int)h->lv.size() - 1, nt = h->nt, b = h->p.batch;
+  auto need = [&](int top) -> size_t {
+    size_t e = 0, mx = 0;
+    for (int l = top; l <= last; ++l) {
+      const Level& L = h->lv[l];
+      const size_t dof = (size_t)b * L.N * nt * L.nx;
+      e += (size_t)L.n * L.n + (size_t)L.nx * nt * nt + 2 * dof;
+      mx = std::max(mx, dof);
+    }
+    return (e + 2 * mx) * sizeof(T);
+  };
+  int top = -1;
+  for (int l = 1; l < last; ++l)
+    if (last - l + 1 <= CT_MAX && need(l) <= 65536) {
+      top = l;
+      break;
+    }
+  if (top < 0) return ST_OK;
+  for (int tr = 0; tr < 2; ++tr) {
+    CoarseArgs<T> a{};
+    int off = 0;
+    a.levels = last - top + 1;
+    for (int q = 0; q < a.levels; ++q) {
+      const Level& L = h->lv[top + q];
+      const ResidArgs<T> ra = resid_args<T>(h, L, tr != 0);
+      CoarseLevel<T>& c = a.lv[q];
+      for (int i = 0; i < NT_MAX * NT_MAX; ++i) {
+        c.K[i] = ra.K[i];
+        c.M[i] = ra.M[i];
+      }
+      for (int i = 0; i < NT_MAX; ++i) {
+        c.ca[i] = ra.ca[i];
+        c.cb[i] = ra.cb[i];
+      }
+      for (int i = 0; i < 3; ++i) {
+        c.wm[i] = ra.wm[i];
+        c.wk[i] = ra.wk[i];
+      }
+      c.gS = SPof<T>(L);
+      c.gG = Gof<T>(L);
+      c.n = L.n;
+      c.N = L.N;
+      c.nx = (int)L.nx;
+      c.rn = 1.0f / (float)L.n;
+      c.rN = 1.0f / (float)L.N;
+      c.rnx = 1.0f / (float)L.nx;
+      c.full = L.kind == 'f' ? 1 : 0;
+      const int dof = b * L.N * nt * (int)L.nx;
+      c.offS = off;
+      off += L.n * L.n;
+      c.offG = off;
+      off += (int)L.nx * nt * nt;
+      c.offU = off;
+      off += dof;
+      c.offF = off;
+      off += dof;
+    }
+    int mx = 0;
+    for (int q = 0; q < a.levels; ++q) mx = std::max(mx, b * a.lv[q].N * nt * a.lv[q].nx);
+    a.offR = off;
+    a.offQ = off + mx;
+    for (int i = 0; i < nt * nt; ++i) {
+      a.R1T[i] = (T)h->R1T[i];
+      a.R2T[i] = (T)h->R2T[i];
+    }
+    a.omega = (T)h->p.omega;
+    a.nu1 = h->p.nu1;
+    a.nu2 = h->p.nu2;
+    a.gamma = h->p.gamma;
+    a.transpose = tr;
+    a.dir = tr ? +1 : -1;
+    HIPCHK(h, hipMalloc(&h->tail_args[tr], sizeof(a)));
+    HIPCHK(h, hipMemcpy(h->tail_args[tr], &a, sizeof(a), hipMemcpyHostToDevice));
+  }
+  h->tail = top;
+  h->tail_lds = need(top);
+  return ST_OK;
+}
+
+int setup_coarse_tail(st_mg* h) {
+  if (const char* e = std::getenv("STMG_COARSE_TAIL"))
+    if (std::atoi(e) == 0) return ST_OK;
+  if (h->mesh || high_order(h) || h->p.smoother != ST_SMOOTH_EXACT || is_mixed(h)) return ST_OK;
+  return h->p.precision == ST_FP32 ? setup_coarse_tail_t<float>(h) : setup_coarse_tail_t<double>(h);
 }
 
 // Device copy of a host array (nullptr for an empty one).
@@ -1758,8 +1861,9 @@ int setup_impl(const st_mg_params* p, st_mg_t* out, const st_mesh* mesh, int ref
       return rc;
     }
   }
+  rc = setup_coarse_tail(h);
   *out = h;
-  return ST_OK;
+  return rc;
 }
 
 }  // namespace
@@ -1818,6 +1922,8 @@ int st_mg_destroy(st_mg_t h) {
       (void)hipFree(q);
   }
   if (h->ws_owned && h->ws) (void)hipFree(h->ws);
+  (void)hipFree(h->tail_args[0]);
+  (void)hipFree(h->tail_args[1]);
   (void)hipFree(h->gen64);
   (void)hipFree(h->gen32);
   for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);

@@ -356,3 +356,43 @@ template <typename T>
 hipError_t launch_mesh_rhs_adjoint(int nt, const T* lam, T* gf, T* gu0, const MeshRhsArgs<T>& a, hipStream_t s);
 
 }  // namespace stmg
+
+namespace stmg {
+
+// ------------------------------------ coarse end of a cycle in one workgroup
+// (stmg_coarse.hip).  Level 0 of the tail is the level the cycle is called on.
+constexpr int CT_MAX = 10;
+template <typename T>
+struct CoarseLevel {
+  T K[NT_MAX * NT_MAX];   // as ResidArgs (direction applied)
+  T M[NT_MAX * NT_MAX];
+  T ca[NT_MAX];
+  T cb[NT_MAX];
+  T wm[3];
+  T wk[3];
+  const T* gS;            // plain DST-I, n x n (device)
+  const T* gG;            // per-mode inverse blocks in spectral order (device)
+  int n, N, nx;
+  float rn, rN, rnx;      // 1/n, 1/N, 1/nx for the index arithmetic
+  int full;               // transition to the next tail level is full coarsening
+  int offS, offG, offU, offF;   // LDS offsets in elements
+};
+template <typename T>
+struct CoarseArgs {
+  CoarseLevel<T> lv[CT_MAX];
+  T R1T[NT_MAX * NT_MAX];
+  T R2T[NT_MAX * NT_MAX];
+  T omega;
+  int levels;
+  int nu1, nu2, gamma;
+  int transpose;          // apply G^T
+  int dir;                // -1 forward, +1 adjoint
+  int offR, offQ;         // two scratch vectors of the largest tail level
+};
+// One cycle (with gamma coarse cycles below) on the tail's top level:
+// u = cycle(u, F) (u treated as zero when u_zero), one workgroup, lds bytes.
+template <typename T>
+hipError_t launch_coarse_cycle(int dim, int nt, const CoarseArgs<T>* args, size_t lds, const T* F, T* u, int batch,
+                               int u_zero, hipStream_t s);
+
+}  // namespace stmg
