@@ -123,6 +123,20 @@ def measure_p1(stmg, torch, dev, args):
     _, its, hist = X.solve(F, u=u, rtol=1e-8, maxit=100)
     torch.cuda.synchronize()
     tsolve = time.perf_counter() - t0
+    # the same solve with FP64 refinement around an FP32 inner cycle
+    Xm = stmg.Solver(3, R, N, pt=pt, T=0.1 * N, omega=1.0, nu1=1, nu2=1, smoother="spatial_mg", mesh=coarse,
+                     device=dev, precision="mixed")
+    if not args.no_graph:
+        Xm.set_graph(True)
+    um = torch.zeros_like(F)
+    Xm.solve(F, u=um, rtol=0.0, maxit=2, raise_on_noconv=False)
+    um.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    um, itsm, histm = Xm.solve(F, u=um, rtol=1e-8, maxit=100)
+    torch.cuda.synchronize()
+    tmixed = time.perf_counter() - t0
+    Xm.close()
     X.set_graph(False)
     u2 = torch.zeros_like(F)
     X.solve(F, u=u2, rtol=0.0, maxit=1, raise_on_noconv=False)
@@ -143,6 +157,8 @@ def measure_p1(stmg, torch, dev, args):
                        "nu1=nu2=1, omega_t=1, spatial cycle nu_x=2 omega_x=2/3, schedule " + X.schedule,
            "dof": dof, "value": dof * steps / el, "unit": "DoF*V-cycles/s", "ms_per_step": 1e3 * el / steps,
            "steps": steps, "time_to_1e-8_s": tsolve, "cycles_to_1e-8": its, "final_relres": hist[-1][0],
+           "mixed_time_to_1e-8_s": tmixed, "mixed_cycles_to_1e-8": itsm, "mixed_final_relres": histm[-1][0],
+           "mixed_rel_diff_vs_fp64": (torch.linalg.vector_norm(um - u) / torch.linalg.vector_norm(u)).item(),
            "residual_kernel_fine_level": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                           "frac": gbs / HBM_PEAK_GBS, "launches": res_cnt,
                                           "avg_launch_ms": res_ms / max(res_cnt, 1), "bytes_per_launch": res_bytes},

@@ -151,7 +151,7 @@ int st_mesh_level(const st_mesh* coarse, int level, long long* nx, long long* nn
  * the paper's inexact smoother is required (p->smoother = ST_SMOOTH_SPATIAL_MG:
  * node-block Jacobi in space, nu1x/nu2x steps damped by omega_x, down to the
  * coarse mesh, where each slab is solved exactly); p->n is ignored; p->dim must
- * equal coarse->dim; 0 <= p_t <= 3; precision ST_FP64 or ST_FP32.  The exact
+ * equal coarse->dim; 0 <= p_t <= 3; precision ST_FP64, ST_FP32 or ST_MIXED.  The exact
  * slab solves of the coarse mesh and of the coarsest level use dense inverses
  * built at setup: N_t x (interior nodes) <= 1024 on both, else ST_EINVAL (refine
  * less, or use more time slabs so that space is coarsened further).  In the

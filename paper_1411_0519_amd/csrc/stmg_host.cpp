@@ -1103,13 +1103,16 @@ int coarsest_solve<double>(st_mg* h, bool transpose, double* u, const double* F,
 template <>
 int coarsest_solve<float>(st_mg* h, bool transpose, float* u, const float* F, hipStream_t s) {
   const int l = (int)h->lv.size() - 1;
-  if (h->mesh) return mesh_exact_solve<float>(h, l, transpose, F, u, MODE_SET_SCALED, 1.0f, s);
+  if (h->mesh && !is_mixed(h)) return mesh_exact_solve<float>(h, l, transpose, F, u, MODE_SET_SCALED, 1.0f, s);
   if (is_mixed(h)) {
     // exact coarsest solve kept in double
     const long long len = h->lv[l].dof(h->nt, h->p.batch);
     HIPCHK(h, launch_cast_f32_f64(F, h->cF64, len, s));
-    CHK(op_block_solve<double>(h, l, transpose, h->cF64, h->cu64, MODE_SET_SCALED, 1.0, h->ct64,
-                               h->cr64, s));
+    if (h->mesh)
+      CHK(mesh_exact_solve<double>(h, l, transpose, h->cF64, h->cu64, MODE_SET_SCALED, 1.0, s));
+    else
+      CHK(op_block_solve<double>(h, l, transpose, h->cF64, h->cu64, MODE_SET_SCALED, 1.0, h->ct64,
+                                 h->cr64, s));
     HIPCHK(h, launch_cast_f64_f32(h->cu64, u, len, s));
     return ST_OK;
   }
@@ -1746,8 +1749,8 @@ int setup_impl(const st_mg_params* p, st_mg_t* out, const st_mesh* mesh, int ref
   else if (mesh && mesh->dim != p->dim) rc = bad("params dim and mesh dim differ");
   else if (mesh && p->smoother != ST_SMOOTH_SPATIAL_MG)
     rc = bad("P1 meshes need the spatial-cycle smoother (ST_SMOOTH_SPATIAL_MG)");
-  else if (mesh && p->precision != ST_FP64 && p->precision != ST_FP32)
-    rc = bad("P1 meshes run in ST_FP64 or ST_FP32");
+  else if (mesh && p->precision == ST_MIXED_BF16)
+    rc = bad("P1 meshes have no sine transforms: use ST_FP64, ST_FP32 or ST_MIXED");
   else if (!(p->T > 0.0) || !std::isfinite(p->T)) rc = bad("T must be positive");
   else if (!is_pow2(p->N) || p->N > (1 << 20)) rc = bad("N must be a power of two (<= 2^20)");
   else if (p->pt < 0 || p->pt > NT_BIG - 1) rc = bad("p_t must be in 0..47");

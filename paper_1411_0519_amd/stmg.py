@@ -154,7 +154,7 @@ class Solver:
 
     mesh = (coords, cells): P1 elements on that coarse triangle/tetrahedron mesh
     refined n times (n then counts refinements; smoother 'spatial_mg', precision
-    'fp64' or 'fp32'); h0 = its mesh size in mu = tau/h^2 (0: longest edge).
+    'fp64', 'fp32' or 'mixed'); h0 = its mesh size in mu = tau/h^2 (0: longest edge).
     """
 
     def __init__(self, dim, n, N, pt=1, T=1.0, omega=0.5, nu1=2, nu2=2, coarsen="auto",

@@ -228,7 +228,7 @@ def test_mesh_rhs_and_adjoint_map():
     assert rel_err(gu0.cpu().numpy().reshape(gu0_ref.shape), gu0_ref[..., pm]) < 1e-13
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "mixed"])
 def test_mesh_solve_reaches_direct_solution(precision):
     case = ("cube12", 2, 32, 1, 1)
     kind, R, N, pt, b = case
@@ -241,6 +241,11 @@ def test_mesh_solve_reaches_direct_solution(precision):
     assert max(hist[-1]) <= rtol and its <= 20
     ref = spacetime.forward_substitution(H.fine, F)
     assert norm_rel(o(u, kind, R, N, pt + 1, 1), ref) < (1e-3 if precision == "fp32" else 1e-8)
+    if precision == "mixed":
+        # FP64 refinement around the FP32 inner cycle: as many outer steps as the FP64 solve, within two
+        S64, _ = pair(case)
+        _, its64, _ = S64.solve(g(F, kind, R, N, pt + 1), rtol=rtol, maxit=40)
+        assert its <= its64 + 2
 
 
 def test_mesh_table1_iteration_counts():

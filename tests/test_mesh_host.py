@@ -94,7 +94,7 @@ def test_mesh_setup_validates_before_device_work():
     L = stmg.lib()
     c, t = workloads.coarse_mesh("cube12")
     m, keep = _mesh(c, t)
-    for field, value in (("smoother", 0), ("dim", 2), ("precision", stmg.PRECISION["mixed"]), ("pt", 4)):
+    for field, value in (("smoother", 0), ("dim", 2), ("precision", stmg.PRECISION["mixed_bf16"]), ("pt", 4)):
         p = stmg.Params()
         L.st_mg_default_params(ctypes.byref(p))
         p.dim, p.N, p.smoother = 3, 8, 1
