@@ -41,6 +41,7 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true", help="keep the default kernel families")
     ap.add_argument("--no-inexact", action="store_true", help="skip the spatial-multigrid smoother measurement")
     ap.add_argument("--no-mesh", action="store_true", help="skip the P1 tetrahedral-mesh measurement")
+    ap.add_argument("--only-mesh", action="store_true", help="only the P1 tetrahedral-mesh measurement (for profiler runs)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized device buffer 5 times (calibrates HBM byte counters) and exit")
     return ap.parse_args()
@@ -267,6 +268,10 @@ def main():
             c.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_read": nbytes, "copy_probe_bytes_written": nbytes, "copies": 5}))
+        return
+    if args.only_mesh:
+        with torch.cuda.stream(torch.cuda.Stream(device=dev)):
+            print(json.dumps({"p1_mesh": measure_p1(stmg, torch, dev, args)}))
         return
     w = workloads.WORKLOADS[args.workload]
     d, n, N, pt, b = w["dim"], w["n"], w["N"], w["pt"], w["batch"]

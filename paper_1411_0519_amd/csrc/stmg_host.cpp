@@ -153,11 +153,15 @@ struct MeshDev {
   int hmax = 0;                                 // largest tile halo
   int *hoff = nullptr, *hcol = nullptr;         // tile halos (256-row tiles)
   unsigned short* lcol = nullptr;               // [ew][nx] halo-local columns
+
   double *mv64 = nullptr, *kv64 = nullptr, *dg64 = nullptr, *w64 = nullptr;
   float *mv32 = nullptr, *kv32 = nullptr, *dg32 = nullptr, *w32 = nullptr;
   int *p = nullptr, *rrow = nullptr, *rcol = nullptr;
   int* rell = nullptr;                          // [rw][nxc] transpose of the interpolation, ELL
   int rw = 0;
+  int *rhoff = nullptr, *rhcol = nullptr;       // coarse-tile halos of the transpose
+  unsigned short* rloc = nullptr;
+  int rhmax = 0;
 };
 
 struct GraphCache {
@@ -605,7 +609,7 @@ const float* mesh_w<float>(const st_mg* h, int rx) { return h->md[(size_t)rx].w3
 // interpolation from refinement level rx - 1 to rx
 MeshXfer mesh_xfer(const st_mg* h, int rx) {
   const MeshDev& m = h->md[(size_t)rx];
-  return {m.p, m.rrow, m.rcol, m.nx, m.nxc, m.rell, m.rw};
+  return {m.p, m.rrow, m.rcol, m.nx, m.nxc, m.rell, m.rw, m.rhoff, m.rhcol, m.rloc, m.rhmax};
 }
 template <typename T>
 const T* dense_inv(const Level& L, bool own);
@@ -763,7 +767,7 @@ MeshTransferArgs<T> mesh_transfer(const st_mg* h, int lf) {
     a.x = mesh_xfer(h, F.n);
     a.w = mesh_w<T>(h, F.n);
   } else {
-    a.x = MeshXfer{nullptr, nullptr, nullptr, F.nx, F.nx, nullptr, 0};
+    a.x = MeshXfer{nullptr, nullptr, nullptr, F.nx, F.nx, nullptr, 0, nullptr, nullptr, nullptr, 0};
     a.w = nullptr;
   }
   a.Nc = C.N;
@@ -1722,6 +1726,32 @@ int setup_mesh_levels(st_mg* h, const st_mesh* mesh, int refinements) {
         for (int e = rrow[(size_t)I]; e < rrow[(size_t)I + 1]; ++e)
           rell[(size_t)(e - rrow[(size_t)I]) * D.nxc + I] = rcol[(size_t)e];
       CHK(upload(h, &D.rell, rell));
+      {
+        const long long tiles = (D.nxc + MESH_TILE - 1) / MESH_TILE;
+        std::vector<int> hoff((size_t)tiles + 1, 0), hcol;
+        std::vector<unsigned short> loc((size_t)D.rw * D.nxc, 0);
+        for (long long t = 0; t < tiles; ++t) {
+          const long long i0 = t * MESH_TILE, i1 = std::min(D.nxc, i0 + MESH_TILE);
+          std::vector<int> cols;
+          for (long long I = i0; I < i1; ++I)
+            for (int e = rrow[(size_t)I]; e < rrow[(size_t)I + 1]; ++e) cols.push_back(rcol[(size_t)e]);
+          std::sort(cols.begin(), cols.end());
+          cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
+          if (cols.size() > 65535) return fail(h, ST_EINVAL, "interpolation rows touch too many distinct nodes");
+          for (long long I = i0; I < i1; ++I)
+            for (int e = 0; e < D.rw; ++e) {
+              const size_t at = (size_t)e * D.nxc + I;
+              if (rell[at] >= 0)
+                loc[at] = (unsigned short)(std::lower_bound(cols.begin(), cols.end(), rell[at]) - cols.begin());
+            }
+          D.rhmax = std::max(D.rhmax, (int)cols.size());
+          hcol.insert(hcol.end(), cols.begin(), cols.end());
+          hoff[(size_t)t + 1] = (int)hcol.size();
+        }
+        CHK(upload(h, &D.rhoff, hoff));
+        CHK(upload(h, &D.rhcol, hcol));
+        CHK(upload(h, &D.rloc, loc));
+      }
     }
   }
   for (size_t l = 0; l < h->lv.size(); ++l) {
@@ -1919,7 +1949,7 @@ int st_mg_destroy(st_mg_t h) {
     (void)hipFree(L.C32);
   }
   for (auto& D : h->md) {
-    for (void* q : {(void*)D.rell, (void*)D.hoff, (void*)D.hcol, (void*)D.lcol, (void*)D.ecol, (void*)D.emk64, (void*)D.emk32, (void*)D.rowptr, (void*)D.col, (void*)D.mv64, (void*)D.kv64, (void*)D.dg64, (void*)D.w64,
+    for (void* q : {(void*)D.rhoff, (void*)D.rhcol, (void*)D.rloc, (void*)D.rell, (void*)D.hoff, (void*)D.hcol, (void*)D.lcol, (void*)D.ecol, (void*)D.emk64, (void*)D.emk32, (void*)D.rowptr, (void*)D.col, (void*)D.mv64, (void*)D.kv64, (void*)D.dg64, (void*)D.w64,
                     (void*)D.mv32, (void*)D.kv32, (void*)D.dg32, (void*)D.w32, (void*)D.p, (void*)D.rrow,
                     (void*)D.rcol})
       (void)hipFree(q);

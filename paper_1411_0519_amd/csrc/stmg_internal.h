@@ -278,6 +278,13 @@ struct MeshXfer {
   // e * nxc + I (fine index, -1 for padding), rw entries per row
   const int* rell;
   int rw;
+  // halo of each 256-row coarse tile: the distinct fine nodes its rows of the
+  // transpose touch (sorted), rhcol[rhoff[t] .. rhoff[t+1]), at most rhmax;
+  // rloc[e * nxc + I] is the position of rell[e * nxc + I] in that halo
+  const int* rhoff;
+  const int* rhcol;
+  const unsigned short* rloc;
+  int rhmax;
 };
 // Residual r = F - L u on a mesh level; time coefficients as in ResidArgs.
 template <typename T>

@@ -330,6 +330,48 @@ __global__ __launch_bounds__(MB) void k_mesh_restrict_space(const T* __restrict_
   for (int l = 0; l < NT; ++l) dst[l * x.nxc + I] = acc[l];
 }
 
+// (P^T v)_I for the coarse rows of this workgroup's tile from the tile's halo
+// of v staged in LDS (one component at a time, the interpolation weight of the
+// fine node folded in).  All threads of the workgroup must call it.
+template <typename T>
+__device__ inline T restrict_row_lds(const MeshXfer& x, const T* __restrict__ w, long long tile, long long I,
+                                     const T* __restrict__ v, T* lx) {
+  const int h0 = x.rhoff[tile], hn = x.rhoff[tile + 1] - h0;
+  for (int j = threadIdx.x; j < hn; j += MB) {
+    const long long c = x.rhcol[h0 + j];
+    lx[j] = w[c] * v[c];
+  }
+  __syncthreads();
+  T acc = T(0);
+  if (I < x.nxc)
+    for (int e = 0; e < x.rw; ++e) {
+      const long long q = (long long)e * x.nxc + I;
+      if (x.rell[q] < 0) break;
+      acc += lx[x.rloc[q]];
+    }
+  __syncthreads();
+  return acc;
+}
+
+template <typename T, int NT>
+__global__ __launch_bounds__(MB) void k_mesh_restrict_space_lds(const T* __restrict__ rf, T* __restrict__ fc,
+                                                                MeshXfer x, const T* __restrict__ w,
+                                                                long long slabs) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  T* lx = reinterpret_cast<T*>(lds_raw);
+  long long slab, tile;
+  slab_tile((x.nxc + MB - 1) / MB, slab, tile);
+  const long long I = tile * MB + threadIdx.x;
+  const T* src = rf + slab * NT * x.nxf;
+  T acc[NT];
+#pragma unroll
+  for (int l = 0; l < NT; ++l) acc[l] = restrict_row_lds<T>(x, w, tile, I, src + l * x.nxf, lx);
+  if (I >= x.nxc) return;
+  T* dst = fc + slab * NT * x.nxc;
+#pragma unroll
+  for (int l = 0; l < NT; ++l) dst[l * x.nxc + I] = acc[l];
+}
+
 template <typename T, int NT>
 __global__ __launch_bounds__(MB) void k_mesh_prolong_space(const T* __restrict__ ec, T* __restrict__ uf,
                                                            MeshXfer x, const T* __restrict__ w, long long slabs) {
@@ -413,6 +455,37 @@ __global__ __launch_bounds__(MB) void k_mesh_restrict(const T* __restrict__ rf, 
 #pragma unroll
       for (int l = 0; l < NT; ++l) out[k] += blk[l * NT + k] * g[l];
   }
+  T* dst = Fc + cs * NT * nxc + I;
+#pragma unroll
+  for (int k = 0; k < NT; ++k) dst[k * nxc] = out[k];
+}
+
+// the same with full coarsening, the space part from LDS-staged halos
+template <typename T, int NT>
+__global__ __launch_bounds__(MB) void k_mesh_restrict_lds(const T* __restrict__ rf, T* __restrict__ Fc,
+                                                          MeshTransferArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  T* lx = reinterpret_cast<T*>(lds_raw);
+  const long long nxc = a.x.nxc, nxf = a.x.nxf;
+  long long cs, tile;   // cs = b * Nc + m
+  slab_tile((nxc + MB - 1) / MB, cs, tile);
+  const long long I = tile * MB + threadIdx.x;
+  const long long b = cs / a.Nc, m = cs % a.Nc;
+  T out[NT];
+#pragma unroll
+  for (int k = 0; k < NT; ++k) out[k] = T(0);
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    const T* src = rf + ((b * 2 * a.Nc) + 2 * m + s) * NT * nxf;
+    const T* blk = s ? a.R2T : a.R1T;
+#pragma unroll
+    for (int l = 0; l < NT; ++l) {
+      const T g = restrict_row_lds<T>(a.x, a.w, tile, I, src + l * nxf, lx);
+#pragma unroll
+      for (int k = 0; k < NT; ++k) out[k] += blk[l * NT + k] * g;
+    }
+  }
+  if (I >= nxc) return;
   T* dst = Fc + cs * NT * nxc + I;
 #pragma unroll
   for (int k = 0; k < NT; ++k) dst[k * nxc] = out[k];
@@ -569,6 +642,13 @@ hipError_t launch_mesh_restrict_space(int nt, const T* rf, T* fc, const MeshXfer
   const long long blocks = (long long)blocks_for(x.nxc) * slabs;
   if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
   const dim3 grid((unsigned)blocks);
+  const size_t lds = (size_t)x.rhmax * sizeof(T);
+  if (x.rhoff != nullptr && lds <= 65536) {
+#define L_(NT) hipLaunchKernelGGL((k_mesh_restrict_space_lds<T, NT>), grid, dim3(MB), lds, s, rf, fc, x, w, slabs)
+    NT_SWITCH(L_)
+#undef L_
+    return hipGetLastError();
+  }
 #define L_(NT) hipLaunchKernelGGL((k_mesh_restrict_space<T, NT>), grid, dim3(MB), 0, s, rf, fc, x, w, slabs)
   NT_SWITCH(L_)
 #undef L_
@@ -601,6 +681,13 @@ hipError_t launch_mesh_restrict(int nt, const T* rf, T* Fc, const MeshTransferAr
   const long long blocks = (long long)blocks_for(a.x.nxc) * a.batch * a.Nc;
   if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
   const dim3 grid((unsigned)blocks);
+  const size_t lds = (size_t)a.x.rhmax * sizeof(T);
+  if (a.full && a.x.rhoff != nullptr && lds <= 65536) {
+#define L_(NT) hipLaunchKernelGGL((k_mesh_restrict_lds<T, NT>), grid, dim3(MB), lds, s, rf, Fc, a)
+    NT_SWITCH(L_)
+#undef L_
+    return hipGetLastError();
+  }
 #define L_(NT) hipLaunchKernelGGL((k_mesh_restrict<T, NT>), grid, dim3(MB), 0, s, rf, Fc, a)
   NT_SWITCH(L_)
 #undef L_
