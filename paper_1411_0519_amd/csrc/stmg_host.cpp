@@ -153,6 +153,7 @@ struct MeshDev {
   int hmax = 0;                                 // largest tile halo
   int *hoff = nullptr, *hcol = nullptr;         // tile halos (256-row tiles)
   unsigned short* lcol = nullptr;               // [ew][nx] halo-local columns
+  unsigned short* ldiag = nullptr;              // [nx] halo-local position of the node itself
 
   double *mv64 = nullptr, *kv64 = nullptr, *dg64 = nullptr, *w64 = nullptr;
   float *mv32 = nullptr, *kv32 = nullptr, *dg32 = nullptr, *w32 = nullptr;
@@ -593,12 +594,12 @@ MeshOp<T> mesh_op(const st_mg* h, int rx);
 template <>
 MeshOp<double> mesh_op<double>(const st_mg* h, int rx) {
   const MeshDev& m = h->md[(size_t)rx];
-  return {m.rowptr, m.col, m.mv64, m.kv64, m.dg64, m.nx, m.ecol, m.emk64, m.ew, m.hoff, m.hcol, m.lcol, m.hmax};
+  return {m.rowptr, m.col, m.mv64, m.kv64, m.dg64, m.nx, m.ecol, m.emk64, m.ew, m.hoff, m.hcol, m.lcol, m.ldiag, m.hmax};
 }
 template <>
 MeshOp<float> mesh_op<float>(const st_mg* h, int rx) {
   const MeshDev& m = h->md[(size_t)rx];
-  return {m.rowptr, m.col, m.mv32, m.kv32, m.dg32, m.nx, m.ecol, m.emk32, m.ew, m.hoff, m.hcol, m.lcol, m.hmax};
+  return {m.rowptr, m.col, m.mv32, m.kv32, m.dg32, m.nx, m.ecol, m.emk32, m.ew, m.hoff, m.hcol, m.lcol, m.ldiag, m.hmax};
 }
 template <typename T>
 const T* mesh_w(const st_mg* h, int rx);
@@ -1688,7 +1689,7 @@ int setup_mesh_levels(st_mg* h, const st_mesh* mesh, int refinements) {
     {
       const long long tiles = (D.nx + MESH_TILE - 1) / MESH_TILE;
       std::vector<int> hoff((size_t)tiles + 1, 0), hcol;
-      std::vector<unsigned short> lcol((size_t)D.ew * D.nx, 0);
+      std::vector<unsigned short> lcol((size_t)D.ew * D.nx, 0), ldiag((size_t)D.nx, 0);
       for (long long t = 0; t < tiles; ++t) {
         const long long i0 = t * MESH_TILE, i1 = std::min(D.nx, i0 + MESH_TILE);
         std::vector<int> cols;
@@ -1697,11 +1698,14 @@ int setup_mesh_levels(st_mg* h, const st_mesh* mesh, int refinements) {
         std::sort(cols.begin(), cols.end());
         cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
         if (cols.size() > 65535) return fail(h, ST_EINVAL, "mesh rows touch too many distinct nodes");
-        for (long long i = i0; i < i1; ++i)
+        for (long long i = i0; i < i1; ++i) {
           for (int e = 0; e < D.ew; ++e) {
             const size_t at = (size_t)e * D.nx + i;
             lcol[at] = (unsigned short)(std::lower_bound(cols.begin(), cols.end(), ecol[at]) - cols.begin());
           }
+          // every row holds its diagonal entry, so the node is in its own tile's halo
+          ldiag[(size_t)i] = (unsigned short)(std::lower_bound(cols.begin(), cols.end(), (int)i) - cols.begin());
+        }
         D.hmax = std::max(D.hmax, (int)cols.size());
         hcol.insert(hcol.end(), cols.begin(), cols.end());
         hoff[(size_t)t + 1] = (int)hcol.size();
@@ -1709,6 +1713,7 @@ int setup_mesh_levels(st_mg* h, const st_mesh* mesh, int refinements) {
       CHK(upload(h, &D.hoff, hoff));
       CHK(upload(h, &D.hcol, hcol));
       CHK(upload(h, &D.lcol, lcol));
+      CHK(upload(h, &D.ldiag, ldiag));
     }
     if (r > 0) {
       std::vector<int> pp, rrow, rcol;
@@ -1949,7 +1954,7 @@ int st_mg_destroy(st_mg_t h) {
     (void)hipFree(L.C32);
   }
   for (auto& D : h->md) {
-    for (void* q : {(void*)D.rhoff, (void*)D.rhcol, (void*)D.rloc, (void*)D.rell, (void*)D.hoff, (void*)D.hcol, (void*)D.lcol, (void*)D.ecol, (void*)D.emk64, (void*)D.emk32, (void*)D.rowptr, (void*)D.col, (void*)D.mv64, (void*)D.kv64, (void*)D.dg64, (void*)D.w64,
+    for (void* q : {(void*)D.ldiag, (void*)D.rhoff, (void*)D.rhcol, (void*)D.rloc, (void*)D.rell, (void*)D.hoff, (void*)D.hcol, (void*)D.lcol, (void*)D.ecol, (void*)D.emk64, (void*)D.emk32, (void*)D.rowptr, (void*)D.col, (void*)D.mv64, (void*)D.kv64, (void*)D.dg64, (void*)D.w64,
                     (void*)D.mv32, (void*)D.kv32, (void*)D.dg32, (void*)D.w32, (void*)D.p, (void*)D.rrow,
                     (void*)D.rcol})
       (void)hipFree(q);

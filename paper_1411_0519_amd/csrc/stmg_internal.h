@@ -241,7 +241,7 @@ hipError_t launch_copy(const T* in, T* out, long long len, hipStream_t s);
 namespace stmg {
 
 // ------------------------------------------------- P1 meshes (stmg_mesh.hip)
-constexpr int MESH_TILE = 256;   // rows per workgroup of the mesh kernels
+constexpr int MESH_TILE = 512;   // rows per workgroup of the mesh kernels
 // One refinement level on the device: the interior M_h and K_h in CSR with one
 // shared pattern, and their diagonals [nx][2] = (M_ii, K_ii).
 template <typename T>
@@ -258,12 +258,14 @@ struct MeshOp {
   const int* ecol;
   const T* emk;
   int ew;
-  // halo of each 256-row tile: the distinct columns its rows touch (sorted),
-  // hcol[hoff[t] .. hoff[t+1]), at most hmax per tile; lcol[e * nx + i] is the
-  // position of ecol[e * nx + i] in the halo of i's tile
+  // halo of each MESH_TILE-row tile: the distinct columns its rows touch
+  // (sorted), hcol[hoff[t] .. hoff[t+1]), at most hmax per tile; lcol[e * nx + i]
+  // is the position of ecol[e * nx + i] in the halo of i's tile, ldiag[i] that
+  // of node i itself
   const int* hoff;
   const int* hcol;
   const unsigned short* lcol;
+  const unsigned short* ldiag;
   int hmax;
 };
 // Interpolation from the next coarser level: fine node i takes
@@ -278,7 +280,7 @@ struct MeshXfer {
   // e * nxc + I (fine index, -1 for padding), rw entries per row
   const int* rell;
   int rw;
-  // halo of each 256-row coarse tile: the distinct fine nodes its rows of the
+  // halo of each MESH_TILE-row coarse tile: the distinct fine nodes its rows of the
   // transpose touch (sorted), rhcol[rhoff[t] .. rhoff[t+1]), at most rhmax;
   // rloc[e * nxc + I] is the position of rell[e * nxc + I] in that halo
   const int* rhoff;

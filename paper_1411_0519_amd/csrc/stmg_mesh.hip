@@ -291,7 +291,7 @@ __global__ __launch_bounds__(MB) void k_mesh_smooth_lds(const T* __restrict__ x,
 #pragma unroll
     for (int k = 0; k < NT; ++k) acc -= a.K[l * NT + k] * mu[k] + a.M[l * NT + k] * ku[k];
     r[l] = acc;
-    xv[l] = x[off + l * nx];
+    xv[l] = lx[l * a.op.hmax + a.op.ldiag[i]];
   }
   if (a.op_kind == SP_JACOBI) {
     node_solve<T, NT>(a.K, a.M, a.op.diag[2 * i], a.op.diag[2 * i + 1], r);
