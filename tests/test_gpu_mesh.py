@@ -294,3 +294,49 @@ def test_mesh_setup_errors():
     bad = (coarse[0], np.array([[0, 1, 2, 9]]))
     with pytest.raises(stmg.STMGError):
         stmg.Solver(3, 1, 4, pt=1, smoother="spatial_mg", mesh=bad, device=DEV)
+
+
+def test_mesh_full_size_parallel_example():
+    # the benchmarked workload: cube of 49,152 tetrahedra (12 refined four times), p_t = 3,
+    # tau = 0.1, N = 1024 slabs, nu = 1, omega_t = 1; solve to 1e-10 and check sampled slabs
+    # against the oracle's slab equations (its own P1 matrices on the refined mesh)
+    kind, R, N, pt = "cube12", 4, 1024, 3
+    print("mesh full size 49,152 tetrahedra", flush=True)
+    coarse = workloads.coarse_mesh(kind)
+    S = stmg.Solver(3, R, N, pt=pt, T=0.1 * N, omega=1.0, nu1=1, nu2=1, smoother="spatial_mg", mesh=coarse,
+                    device=DEV)
+    ms = meshes(kind, R)
+    assert len(ms[R].cells) == 49152
+    pts = stmg.mesh_level(*coarse, R)["points"]
+    f, u0 = workloads.mesh_data(pts, N, seed=21)
+    stream = torch.cuda.Stream(device=DEV)
+    with torch.cuda.stream(stream):
+        S.set_graph(True)
+        F = S.rhs(nodal_to_gpu(f), nodal_to_gpu(u0))
+        u, its, hist = S.solve(F, rtol=1e-10, maxit=30)
+        torch.cuda.synchronize()
+    assert hist[-1][0] <= 1e-10 and its <= 14
+    lev = spacetime.SpaceTimeLevel(3, None, 1, pt, 0.1, space=(ms[R].Mh, ms[R].Kh, 1.0))
+    A, B = lev.A.tocsr(), lev.B.tocsr()
+    nt, nx = pt + 1, ms[R].nx
+    pm = perm(kind, R)
+    Fh = F.cpu().numpy().reshape(N, nt, nx)
+    uh = u.cpu().numpy().reshape(N, nt, nx)
+    Fo = np.empty_like(Fh)
+    uo = np.empty_like(uh)
+    Fo[:, :, pm] = Fh
+    uo[:, :, pm] = uh
+    nF = np.linalg.norm(Fh)
+    for k in (0, 511, N - 1):
+        r = Fo[k].ravel() - A @ uo[k].ravel()
+        if k > 0:
+            r -= B @ uo[k - 1].ravel()
+        assert np.linalg.norm(r) <= 1e-10 * nF, k
+    # the load vector of slab 0 against the oracle's (u0 enters there)
+    fo = np.empty_like(f)
+    fo[..., pm] = f
+    u0o = np.empty_like(u0)
+    u0o[..., pm] = u0
+    lev1 = spacetime.SpaceTimeLevel(3, None, 1, pt, 0.1, space=(ms[R].Mh, ms[R].Kh, 1.0))
+    F0 = spacetime.rhs(lev1, fo[:, :1], u0o).reshape(nt, nx)
+    assert rel_err(Fo[0], F0) < 1e-13
