@@ -340,3 +340,34 @@ def test_mesh_full_size_parallel_example():
     lev1 = spacetime.SpaceTimeLevel(3, None, 1, pt, 0.1, space=(ms[R].Mh, ms[R].Kh, 1.0))
     F0 = spacetime.rhs(lev1, fo[:, :1], u0o).reshape(nt, nx)
     assert rel_err(Fo[0], F0) < 1e-13
+
+
+@pytest.mark.parametrize("pt", [0, 1, 3])
+def test_mesh_table2_iteration_counts(pt):
+    # Example chap4_example2 on the GPU: square of 4 triangles refined once, T = 1024, tau = 1 (N = 1024),
+    # f = 0, random start in [0,1], reduction 1e-8: the oracle's count (within one of the printed 7)
+    kind, R, N = "square4", 1, 1024
+    coarse = workloads.coarse_mesh(kind)
+    S = stmg.Solver(2, R, N, pt=pt, T=float(N), smoother="spatial_mg", mesh=coarse, device=DEV)
+    H = p1.P1Hierarchy(*coarse, R, N, pt, T=float(N), meshes=meshes(kind, R))
+    assert S.schedule == H.schedule
+    u0 = np.random.default_rng(0).uniform(0, 1, (H.fine.dof, 1))
+    _, hist_o, _ = H.solve(np.zeros_like(u0), u=u0, rtol=1e-8, maxit=30)
+    u = g(u0, kind, R, N, pt + 1)
+    u, its, hist = S.solve(torch.zeros_like(u), u=u, rtol=1e-8, maxit=30)
+    assert its == len(hist_o) - 1, (its, len(hist_o) - 1)
+    assert abs(its - 7) <= 1
+
+
+def test_mesh_without_refinement():
+    # the coarse mesh itself (one interior node): every slab solve is the dense one, time coarsening only
+    kind = "cube12"
+    case = (kind, 0, 16, 2, 2)
+    S, H = pair(case)
+    assert S.schedule == H.schedule == "s" * 4
+    F = rvec(H.fine.dof, 2, 31)
+    _, _, its = H.solve(F, rtol=0.0, maxit=3, keep_iterates=True)
+    ug = torch.zeros(S.level_dof(0), dtype=torch.float64, device=DEV)
+    for k in range(1, 4):
+        S.solve(g(F, kind, 0, 16, 3), u=ug, rtol=0.0, maxit=1, raise_on_noconv=False)
+        assert rel_err(o(ug, kind, 0, 16, 3, 2), its[k]) < 1e-12, k
