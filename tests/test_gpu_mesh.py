@@ -371,3 +371,16 @@ def test_mesh_without_refinement():
     for k in range(1, 4):
         S.solve(g(F, kind, 0, 16, 3), u=ug, rtol=0.0, maxit=1, raise_on_noconv=False)
         assert rel_err(o(ug, kind, 0, 16, 3, 2), its[k]) < 1e-12, k
+
+
+def test_mesh_mixed_adjoint_matches_fp64():
+    # L^T lam = g with the FP32 inner cycle and FP64 refinement on a mesh: the FP64 solution to 1e-9
+    case = ("square4", 3, 32, 2, 2)
+    kind, R, N, pt, b = case
+    S64, H = pair(case)
+    Sm, _ = pair(case, precision="mixed")
+    gv = g(rvec(H.fine.dof, b, 41), kind, R, N, pt + 1)
+    lam64, _, _, its64, _ = S64.adjoint(gv, rtol=1e-11, maxit=40, gradients=False)
+    lamm, _, _, itsm, histm = Sm.adjoint(gv, rtol=1e-11, maxit=40, gradients=False)
+    assert max(histm[-1]) <= 1e-11 and itsm <= its64 + 2
+    assert (torch.linalg.vector_norm(lamm - lam64) / torch.linalg.vector_norm(lam64)).item() < 1e-9
