@@ -381,10 +381,21 @@ def main():
     flops = transforms * 2.0 * L0["n"] * nvals
     hbm_bytes = (24 if dom == "pass_inv" else 16) * nvals
     achieved = flops / (avg_ms * 1e-3) / 1e12
-    names = {"pass_fwd": "forward x pass (k_pass_reg<double,4,false>)", "pass_inv": "inverse x pass + update (k_pass_reg<double,4,true>)",
-             "fused": "fused y pass: forward + time solve + inverse (k_fused_pair<double,4,2>: one wave per time component)"}
-    kernel_ids = {"pass_fwd": "k_pass_reg<double, 4, false, 2, true>", "pass_inv": "k_pass_reg<double, 4, true, 2, true>",
-                  "fused": "k_fused_pair<double, 4, 2>"}
+    impl0 = 0 if tuning is None else tuning[0][1]
+    twice = impl0 in (0, 3) and L0["n"] in (63, 127)      # the default FP64 family at n = 63, 127
+    if twice:
+        names = {"pass_fwd": "forward x pass (k_pass_reg2<2,false,true>, twice folded)",
+                 "pass_inv": "inverse x pass + update (k_pass_reg2<2,true,true>, twice folded)",
+                 "fused": "fused y pass: forward + time solve + inverse (k_fused_pair2<2,2>, twice folded, one wave per time component)"}
+        kernel_ids = {"pass_fwd": "k_pass_reg2<2, false, true>", "pass_inv": "k_pass_reg2<2, true, true>",
+                      "fused": "k_fused_pair2<2, 2>"}
+        executed = flops * (L0["n"] + 1) / (4.0 * L0["n"])     # four (h/2)^2 products per column
+    else:
+        names = {"pass_fwd": "forward x pass (k_pass_reg<double,4,false>)", "pass_inv": "inverse x pass + update (k_pass_reg<double,4,true>)",
+                 "fused": "fused y pass: forward + time solve + inverse (k_fused_pair<double,4,2>: one wave per time component)"}
+        kernel_ids = {"pass_fwd": "k_pass_reg<double, 4, false, 2, true>", "pass_inv": "k_pass_reg<double, 4, true, 2, true>",
+                      "fused": "k_fused_pair<double, 4, 2>"}
+        executed = flops * (L0["n"] + 1) / (2.0 * L0["n"])     # two h^2 products per column
     rec = measured_traffic(w["name"], kernel_ids[dom])
     traffic = None if rec is None else rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
     roof = {"kernel": names[dom] + ", fine level", "bound": "mfma", "achieved": achieved,
@@ -392,7 +403,7 @@ def main():
             "traffic_read_write_bytes": None if rec is None else [rec["fetch_bytes_per_launch"],
                                                                   rec["write_bytes_per_launch"]],
             "avg_launch_ms": avg_ms, "launches": cand[dom]["fine_launches"], "flops_per_launch": flops,
-            "executed_mfma_flops_per_launch": flops * (L0["n"] + 1) / (2.0 * L0["n"]),
+            "executed_mfma_flops_per_launch": executed,
             "hbm_bytes_per_launch": hbm_bytes, "hbm_gbs": hbm_bytes / (avg_ms * 1e-3) / 1e9}
     r0 = prof["residual"]
     res_avg = r0["fine_ms_total"] / max(r0["fine_launches"], 1)
@@ -417,7 +428,7 @@ def main():
                    "dof": dof, "levels": S.nlev, "graph": not args.no_graph,
                    "autotuned_levels": None if tuning is None else [
                        {"level": k, "n": S.levels[k]["n"], "N": S.levels[k]["N"], "small_step": bool(t[0]),
-                        "transform": ["auto", "lds", "register"][t[1]], "step_ms": round(t[2], 4)}
+                        "transform": ["default", "lds", "register", "register_twice_folded"][t[1]], "step_ms": round(t[2], 4)}
                        for k, t in enumerate(tuning[:-1])]},
         "time_to_1e-10": {"fp64_s": t64, "fp64_cycles": its64, "mixed_s": tm, "mixed_cycles": itsm,
                           "speedup_mixed_vs_fp64": t64 / tm,

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
 SOURCES = ["stmg_kernels.hip", "stmg_transform.hip", "stmg_smooth_small.hip", "stmg_spatial.hip", "stmg_bf16.hip",
-           "stmg_generic.hip", "stmg_mesh.hip", "stmg_coarse.hip", "stmg_meshgen.cpp", "stmg_host.cpp"]
+           "stmg_generic.hip", "stmg_mesh.hip", "stmg_coarse.hip", "stmg_transform2.hip", "stmg_meshgen.cpp", "stmg_host.cpp"]
 LIB = os.path.join(PKG, "libstmg.so")
 ARCH = os.environ.get("STMG_OFFLOAD_ARCH", "gfx950")
 

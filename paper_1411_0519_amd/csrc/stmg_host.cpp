@@ -111,6 +111,7 @@ struct Level {
   double* G64 = nullptr;  // per-mode inverse blocks [nx][nt][nt]
   float* G32 = nullptr;
   double* Sp64 = nullptr; // plain DST-I (n x n), used by the small-level smoother
+  double* S2_64 = nullptr; // twice-folded fragments (n = 63, 127) [dir][mat][kb][ib][lane]
   float* Sp32 = nullptr;
   int impl = -1;          // transform family chosen for this level (-1: handle default)
   int small = -1;         // small-level smoother on (1) / off (0) for this level (-1: handle default)
@@ -442,6 +443,30 @@ int build_level_tables(st_mg* h, Level& L) {
       Sp[(size_t)k * n + i] = sc * std::sin(PI * (k + 1.0) * (i + 1.0) / (n + 1));
       Sp32[(size_t)k * n + i] = (float)Sp[(size_t)k * n + i];
     }
+  if (twice_folded_ok(n)) {
+    // twice-folded blocks: odd modes O[s][i] = S[2s+1][i+1], even E[s][i] = S[2s+2][i+1] on even i = 2p (mat 0, 2)
+    // and odd i = 2p + 1 (mat 1, 3), rows s < h/2 and contraction p < h/2; the even block has no column
+    // i = h - 1 and its middle row s = h/2 - 1 vanishes on odd i (both stored as exact zeros)
+    const int q = half / 2, KB = q / 16, NC = q / 4;
+    auto M = [&](int mat, int srow, int p) -> double {
+      const int i = mat & 1 ? 2 * p + 1 : 2 * p;
+      const int k = mat < 2 ? 2 * srow + 1 : 2 * srow + 2;
+      if (mat == 3 && (i >= half - 1 || srow == q - 1)) return 0.0;
+      return sc * std::sin(PI * (double)k * (i + 1.0) / (n + 1));
+    };
+    std::vector<double> f2((size_t)2 * 4 * KB * NC * 64);
+    for (int dir = 0; dir < 2; ++dir)
+      for (int mat = 0; mat < 4; ++mat)
+        for (int kb = 0; kb < KB; ++kb)
+          for (int ib = 0; ib < NC; ++ib)
+            for (int lane = 0; lane < 64; ++lane) {
+              const int rr = kb * 16 + (lane & 15), cc = ib * 4 + (lane >> 4);
+              f2[((((size_t)dir * 4 + mat) * KB + kb) * NC + ib) * 64 + lane] =
+                  dir == 0 ? M(mat, rr, cc) : M(mat, cc, rr);
+            }
+    HIPCHK(h, hipMalloc(&L.S2_64, f2.size() * sizeof(double)));
+    HIPCHK(h, hipMemcpy(L.S2_64, f2.data(), f2.size() * sizeof(double), hipMemcpyHostToDevice));
+  }
   HIPCHK(h, hipMalloc(&L.Sp64, Sp.size() * sizeof(double)));
   HIPCHK(h, hipMalloc(&L.Sp32, Sp32.size() * sizeof(float)));
   HIPCHK(h, hipMemcpy(L.Sp64, Sp.data(), Sp.size() * sizeof(double), hipMemcpyHostToDevice));
@@ -700,7 +725,12 @@ int op_block_solve(st_mg* h, int l, bool transpose, const T* src, T* dst, int mo
       HIPCHK(h, launch_pass_bf16(L.hb, inv, (const float*)in, (float*)out, L.S16, n, inner, ncols, (float)om, md, s));
       return ST_OK;
     }
-    HIPCHK(h, launch_dst_pass<T>(L.impl >= 0 ? L.impl : h->impl, L.hb, axis == 0, inv, in, out, Sof<T>(L), n, inner, ncols, om, md, s));
+    const int impl = L.impl >= 0 ? L.impl : h->impl;
+    if (sizeof(T) == 8 && (impl == TRANSFORM_REG2 || impl == TRANSFORM_AUTO) && L.S2_64) {
+      HIPCHK(h, launch_pass_reg2(n, inv, (const double*)in, (double*)out, L.S2_64, inner, ncols, (double)om, md, s));
+      return ST_OK;
+    }
+    HIPCHK(h, launch_dst_pass<T>(impl, L.hb, axis == 0, inv, in, out, Sof<T>(L), n, inner, ncols, om, md, s));
     return ST_OK;
   };
   auto fused = [&](const T* in, T* out, int md, T om) -> int {
@@ -712,7 +742,13 @@ int op_block_solve(st_mg* h, int l, bool transpose, const T* src, T* dst, int mo
                                   slabs, transpose ? 1 : 0, (float)om, md, s));
       return ST_OK;
     }
-    HIPCHK(h, launch_dst_fused<T>(L.impl >= 0 ? L.impl : h->impl, L.hb, nt, in, out, Sof<T>(L), Gof<T>(L), n, inner, slabs,
+    const int impl = L.impl >= 0 ? L.impl : h->impl;
+    if (sizeof(T) == 8 && (impl == TRANSFORM_REG2 || impl == TRANSFORM_AUTO) && L.S2_64) {
+      HIPCHK(h, launch_fused_pair2(n, nt, (const double*)in, (double*)out, L.S2_64, (const double*)Gof<T>(L), inner,
+                                   slabs, transpose ? 1 : 0, (double)om, md, s));
+      return ST_OK;
+    }
+    HIPCHK(h, launch_dst_fused<T>(impl, L.hb, nt, in, out, Sof<T>(L), Gof<T>(L), n, inner, slabs,
                                   transpose ? 1 : 0, om, md, s));
     return ST_OK;
   };
@@ -1404,7 +1440,7 @@ int tune_level(st_mg* h, int l, T* u, T* F, T* r, T* alt, hipStream_t s) {
   cands.push_back({0, TRANSFORM_LDS});
   if (sizeof(T) == 8 && L.hb <= 4) {
     cands.push_back({0, TRANSFORM_AUTO});
-    cands.push_back({0, TRANSFORM_REG});
+    cands.push_back({0, TRANSFORM_REG});   // AUTO is the twice-folded family where it exists
   } else if (sizeof(T) == 4 && L.hb <= 8) {
     cands.push_back({0, TRANSFORM_AUTO});
   }
@@ -1812,7 +1848,7 @@ int setup_impl(const st_mg_params* p, st_mg_t* out, const st_mesh* mesh, int ref
   if (const char* sm = std::getenv("STMG_SMALL")) h->small = std::atoi(sm) != 0;
   if (const char* ti = std::getenv("STMG_TRANSFORM")) {
     const int v = std::atoi(ti);
-    h->impl = (v >= TRANSFORM_AUTO && v <= TRANSFORM_REG) ? v : TRANSFORM_AUTO;
+    h->impl = (v >= TRANSFORM_AUTO && v <= TRANSFORM_REG2) ? v : TRANSFORM_AUTO;
   }
   time_basis(h);
   {
@@ -1948,6 +1984,7 @@ int st_mg_destroy(st_mg_t h) {
     (void)hipFree(L.G32);
     (void)hipFree(L.Sp64);
     (void)hipFree(L.Sp32);
+    (void)hipFree(L.S2_64);
     (void)hipFree(L.D64);
     (void)hipFree(L.D32);
     (void)hipFree(L.C64);

@@ -66,7 +66,7 @@ unsigned residual_blocks_per_slab(int dim, int n, long long nx, int nt);
 int transform_half_blocks(int n);
 // Transform implementation: automatic choice, LDS-staged kernels only, or the
 // FP64 register-resident kernels wherever their state fits.
-enum { TRANSFORM_AUTO = 0, TRANSFORM_LDS = 1, TRANSFORM_REG = 2 };
+enum { TRANSFORM_AUTO = 0, TRANSFORM_LDS = 1, TRANSFORM_REG = 2, TRANSFORM_REG2 = 3 };
 template <typename T>
 hipError_t launch_dst_pass(int impl, int hb, bool xaxis, bool inverse, const T* in, T* out, const T* Sfrag,
                            int n, long long inner, long long ncols, T omega, int mode,
@@ -403,5 +403,19 @@ struct CoarseArgs {
 template <typename T>
 hipError_t launch_coarse_cycle(int dim, int nt, const CoarseArgs<T>* args, size_t lds, const T* F, T* u, int batch,
                                int u_zero, hipStream_t s);
+
+}  // namespace stmg
+
+namespace stmg {
+
+// Twice-folded FP64 register transforms for n = 63 and 127 (stmg_transform2.hip):
+// the x/y passes and the fused slowest-axis solve with half the matrix-core
+// work of the once-folded ones; Sfrag2 is their fragment table.
+bool twice_folded_ok(int n);
+hipError_t launch_pass_reg2(int n, bool inverse, const double* in, double* out, const double* Sfrag2,
+                            long long inner, long long ncols, double omega, int mode, hipStream_t s);
+hipError_t launch_fused_pair2(int n, int nt, const double* in, double* out, const double* Sfrag2, const double* G,
+                              long long inner, long long outer, int transpose, double omega, int mode,
+                              hipStream_t s);
 
 }  // namespace stmg

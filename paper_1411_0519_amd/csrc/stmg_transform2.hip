@@ -1,0 +1,313 @@
+// Twice-folded sine transforms on the FP64 matrix cores (n = 63, 127).
+//
+// The first fold pairs x_i with x_{n-1-i} (odd modes see a_i = x_i + x_{n-1-i},
+// even modes d_i = x_i - x_{n-1-i}).  Each half has a second mirror symmetry:
+// with h = (n+1)/2, the odd-mode rows s and h-1-s of O[s][i] = sin(pi (2s+1)(i+1)
+// / (n+1)) agree on even i and differ in sign on odd i; the even-mode rows s and
+// h-2-s of E[s][i] = sin(pi (2s+2)(i+1)/(n+1)) likewise (the middle row
+// s* = h/2 - 1 vanishes on odd i).  So every half is two (h/2) x (h/2) products
+// on the even- and odd-indexed inputs, P and Q, and the outputs are P + Q (row s)
+// and P - Q (the mirrored row); the inverse transforms first form the sums and
+// differences of mirrored spectral rows.  This halves the matrix-core work of
+// the once-folded kernels.  Spectral order in memory is unchanged (odd mode s at
+// row s, even mode s at row h + s), so the per-mode blocks G are shared.
+//
+// Fragment table [dir][mat][kb][ib][lane], mat = 0: O on even i, 1: O on odd i,
+// 2: E on even i, 3: E on odd i; dir 0 holds A[s][p] (forward), dir 1 A[p][s]
+// (inverse), blocks of 16 rows and chunks of 4 along the contraction.
+#include <hip/hip_runtime.h>
+
+#include "stmg_device.h"
+#include "stmg_internal.h"
+
+namespace stmg {
+
+namespace {
+
+using namespace dev;
+
+typedef v4d acc_t;
+
+__device__ inline acc_t mma(double a, double b, acc_t c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+
+// acc[mat][kb] = sum over chunks ib of A(dir, mat, kb, ib) * B(mat, ib); HB2 = h/32
+// row blocks per product, 2 HB2 * 4 = h/2 contraction indices.  B(mat, ib) is
+// the lane's operand for (mat, chunk ib).
+template <int HB2, int DIR, typename OpFn>
+__device__ inline void mma4(const double* __restrict__ Sfrag, int lane, OpFn op, acc_t (&acc)[4][HB2]) {
+  constexpr int NC = 4 * HB2;   // chunks of 4 along the contraction (h/2 / 4)
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int kb = 0; kb < HB2; ++kb) acc[m][kb] = acc_t{0, 0, 0, 0};
+  const double* s = Sfrag + (size_t)DIR * 4 * HB2 * NC * 64 + lane;
+  double nf[4][HB2];
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int kb = 0; kb < HB2; ++kb) nf[m][kb] = s[((m * HB2 + kb) * NC) * 64];
+#pragma unroll
+  for (int ib = 0; ib < NC; ++ib) {
+    double af[4][HB2];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int kb = 0; kb < HB2; ++kb) af[m][kb] = nf[m][kb];
+    if (ib + 1 < NC) {
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int kb = 0; kb < HB2; ++kb) nf[m][kb] = s[((m * HB2 + kb) * NC + ib + 1) * 64];
+    }
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const double b = op(m, ib);
+#pragma unroll
+      for (int kb = 0; kb < HB2; ++kb) acc[m][kb] = mma(af[m][kb], b, acc[m][kb]);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// Forward operands of chunk ib for contraction index p = 4 ib + g: the
+// physical values x_{2p}, x_{2p+1} and their partners x_{n-1-2p}, x_{n-2-2p}.
+// Returns a_{2p}, a_{2p+1}, d_{2p}, d_{2p+1} (d_{h-1} = 0, a_{h-1} = x_{h-1}).
+template <int HB2>
+__device__ inline void load_twice_folded(const double* __restrict__ src, bool valid, long long inner, int n, int g,
+                                         double (&op)[4][4 * HB2]) {
+  const int h = (n + 1) >> 1;
+#pragma unroll
+  for (int ib = 0; ib < 4 * HB2; ++ib) {
+    const int p = 4 * ib + g;
+    const int i0 = 2 * p, i1 = 2 * p + 1;
+    double x0 = 0, y0 = 0, x1 = 0, y1 = 0;
+    if (valid) {
+      x0 = src[(long long)i0 * inner];
+      y0 = src[(long long)(n - 1 - i0) * inner];
+      x1 = src[(long long)i1 * inner];
+      if (i1 < h - 1) y1 = src[(long long)(n - 1 - i1) * inner];
+    }
+    op[0][ib] = x0 + y0;
+    op[1][ib] = x1 + y1;
+    op[2][ib] = x0 - y0;
+    op[3][ib] = (i1 < h - 1) ? x1 - y1 : 0.0;
+  }
+}
+
+__device__ inline double epi(int mode, double old, double v, double omega) {
+  if (mode == MODE_ADD_SCALED) return old + omega * v;
+  if (mode == MODE_SET_SCALED) return omega * v;
+  return v;
+}
+
+// Physical outputs of an inverse product: row p of the four accumulators holds
+// P_{2p}, P_{2p+1} (odd modes) and Q_{2p}, Q_{2p+1} (even modes); x_i = P_i + Q_i
+// and x_{n-1-i} = P_i - Q_i (i < h-1), x_{h-1} = P_{h-1}.
+template <int HB2>
+__device__ inline void store_twice_unfolded(double* __restrict__ dst, bool valid, long long inner, int n, int g,
+                                            const acc_t (&acc)[4][HB2], int mode, double omega) {
+  if (!valid) return;
+  const int h = (n + 1) >> 1;
+  auto put = [&](int i, double v) {
+    double* q = dst + (long long)i * inner;
+    const double o = (mode == MODE_ADD_SCALED) ? *q : 0.0;
+    *q = epi(mode, o, v, omega);
+  };
+#pragma unroll
+  for (int kb = 0; kb < HB2; ++kb)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int p = kb * 16 + g + 4 * j;
+      const int i0 = 2 * p, i1 = 2 * p + 1;
+      const double P0 = acc[0][kb][j], P1 = acc[1][kb][j], Q0 = acc[2][kb][j], Q1 = acc[3][kb][j];
+      put(i0, P0 + Q0);
+      put(n - 1 - i0, P0 - Q0);
+      if (i1 < h - 1) {
+        put(i1, P1 + Q1);
+        put(n - 1 - i1, P1 - Q1);
+      } else {
+        put(i1, P1);
+      }
+    }
+}
+
+// Inverse operands from the four spectral values of row s: u = y_o[s] +
+// y_o[h-1-s], v = y_o[s] - y_o[h-1-s], ue = y_e[s] + y_e[h-2-s] (y_e[s*] on the
+// middle row), ve = y_e[s] - y_e[h-2-s] (0 on the middle row).
+__device__ inline void inverse_operands(double o, double om, double e, double em, bool middle, double& u, double& v,
+                                        double& ue, double& ve) {
+  u = o + om;
+  v = o - om;
+  ue = middle ? e : e + em;
+  ve = middle ? 0.0 : e - em;
+}
+
+template <int HB2, bool INV, bool UNIT>
+__global__ __launch_bounds__(256) void k_pass_reg2(const double* __restrict__ in, double* __restrict__ out,
+                                                   const double* __restrict__ Sfrag, int n, long long inner_rt,
+                                                   long long ncols, double omega, int mode) {
+  const long long inner = UNIT ? 1 : inner_rt;
+  const int lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
+  const long long wv = xcd_linear(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+  const int h = (n + 1) >> 1;
+  const long long lin = wv * 16 + r;
+  const bool valid = lin < ncols;
+  const long long o = valid ? lin / inner : 0;
+  const long long pos = valid ? lin - o * inner : 0;
+  const long long base = o * (long long)n * inner + pos;
+  double op[4][4 * HB2];
+  if (!INV) {
+    load_twice_folded<HB2>(in + base, valid, inner, n, g, op);
+  } else {
+    // spectral rows s = 4 ib + g (< h/2) and their mirrors
+#pragma unroll
+    for (int ib = 0; ib < 4 * HB2; ++ib) {
+      const int s = 4 * ib + g;
+      const bool middle = s == h / 2 - 1;
+      double yo = 0, yom = 0, ye = 0, yem = 0;
+      if (valid) {
+        yo = in[base + (long long)s * inner];
+        yom = in[base + (long long)(h - 1 - s) * inner];
+        ye = in[base + (long long)(h + s) * inner];
+        if (!middle) yem = in[base + (long long)(h + h - 2 - s) * inner];
+      }
+      inverse_operands(yo, yom, ye, yem, middle, op[0][ib], op[1][ib], op[2][ib], op[3][ib]);
+    }
+  }
+  acc_t acc[4][HB2];
+  mma4<HB2, INV ? 1 : 0>(Sfrag, lane, [&](int m, int ib) { return op[m][ib]; }, acc);
+  if (!INV) {
+    if (valid) {
+#pragma unroll
+      for (int kb = 0; kb < HB2; ++kb)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int s = kb * 16 + g + 4 * j;
+          const double P = acc[0][kb][j], Q = acc[1][kb][j], Pe = acc[2][kb][j], Qe = acc[3][kb][j];
+          out[base + (long long)s * inner] = P + Q;
+          out[base + (long long)(h - 1 - s) * inner] = P - Q;
+          out[base + (long long)(h + s) * inner] = Pe + Qe;
+          if (s != h / 2 - 1) out[base + (long long)(h + h - 2 - s) * inner] = Pe - Qe;
+        }
+    }
+  } else {
+    store_twice_unfolded<HB2>(out + base, valid, inner, n, g, acc, mode, omega);
+  }
+}
+
+// Slowest axis: forward transform, per-mode N_t x N_t solve, inverse transform,
+// one wave per time component (as the once-folded k_fused_pair), the
+// components exchanged through LDS for the solve.
+template <int HB2, int NT>
+__global__ __launch_bounds__(256) void k_fused_pair2(const double* in, double* out, const double* __restrict__ Sfrag,
+                                                     const double* __restrict__ G, int n, long long inner,
+                                                     long long outer, int transpose, double omega, int mode) {
+  constexpr int CG = NT >= 3 ? 1 : 4 / NT;
+  __shared__ double xch[4 * HB2][CG * NT * 64 * 4];
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
+  const int cg = wave / NT, l = wave - (wave / NT) * NT;
+  const long long lin = (xcd_linear(blockIdx.x, gridDim.x) * CG + cg) * 16 + r;
+  const bool valid = lin < outer * inner;
+  const long long o = valid ? lin / inner : 0;
+  const long long pos = valid ? lin - o * inner : 0;
+  const long long cstride = (long long)n * inner;
+  const long long base = o * NT * cstride + (long long)l * cstride + pos;
+  const int h = (n + 1) >> 1;
+  acc_t acc[4][HB2];
+  {
+    double op[4][4 * HB2];
+    load_twice_folded<HB2>(in + base, valid, inner, n, g, op);
+    mma4<HB2, 0>(Sfrag, lane, [&](int m, int ib) { return op[m][ib]; }, acc);
+  }
+  // spectral values (o, om, e, em) of every row to LDS, one barrier
+#pragma unroll
+  for (int kb = 0; kb < HB2; ++kb)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const double P = acc[0][kb][j], Q = acc[1][kb][j], Pe = acc[2][kb][j], Qe = acc[3][kb][j];
+      const int slot = ((cg * NT + l) * 64 + lane) * 4 + j;
+      xch[0 * HB2 + kb][slot] = P + Q;
+      xch[1 * HB2 + kb][slot] = P - Q;
+      xch[2 * HB2 + kb][slot] = Pe + Qe;
+      xch[3 * HB2 + kb][slot] = Pe - Qe;
+    }
+  __syncthreads();
+  // per-mode solve of this wave's component, then the inverse operands
+  double op[4][4 * HB2];
+#pragma unroll
+  for (int kb = 0; kb < HB2; ++kb)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int s = kb * 16 + g + 4 * j;
+      const bool middle = s == h / 2 - 1;
+      const int mode_idx[4] = {s, h - 1 - s, h + s, h + (middle ? s : h - 2 - s)};
+      double y[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        double a = 0.0;
+        if (valid) {
+          const double* gm = G + (pos + inner * (long long)mode_idx[q]) * (NT * NT);
+#pragma unroll
+          for (int m = 0; m < NT; ++m) {
+            const double v = xch[q * HB2 + kb][((cg * NT + m) * 64 + lane) * 4 + j];
+            a += (transpose ? gm[m * NT + l] : gm[l * NT + m]) * v;
+          }
+        }
+        y[q] = a;
+      }
+      // chunk 4 kb + j, contraction row g: the accumulator layout is the operand layout
+      const int ib = 4 * kb + j;
+      inverse_operands(y[0], y[1], y[2], y[3], middle, op[0][ib], op[1][ib], op[2][ib], op[3][ib]);
+    }
+  acc_t out_acc[4][HB2];
+  mma4<HB2, 1>(Sfrag, lane, [&](int m, int ib) { return op[m][ib]; }, out_acc);
+  store_twice_unfolded<HB2>(out + base, valid, inner, n, g, out_acc, mode, omega);
+}
+
+}  // namespace
+
+bool twice_folded_ok(int n) { return n == 63 || n == 127; }
+
+hipError_t launch_pass_reg2(int n, bool inverse, const double* in, double* out, const double* Sfrag2,
+                            long long inner, long long ncols, double omega, int mode, hipStream_t s) {
+  const unsigned grid = (unsigned)((ncols + 63) / 64);
+#define P2(HB2, U)                                                                                        \
+  if (inverse)                                                                                            \
+    hipLaunchKernelGGL((k_pass_reg2<HB2, true, U>), dim3(grid), dim3(256), 0, s, in, out, Sfrag2, n, inner, \
+                       ncols, omega, mode);                                                               \
+  else                                                                                                    \
+    hipLaunchKernelGGL((k_pass_reg2<HB2, false, U>), dim3(grid), dim3(256), 0, s, in, out, Sfrag2, n, inner, \
+                       ncols, omega, mode);                                                               \
+  return hipGetLastError();
+  if (n == 127) {
+    if (inner == 1) { P2(2, true) }
+    P2(2, false)
+  }
+  if (n == 63) {
+    if (inner == 1) { P2(1, true) }
+    P2(1, false)
+  }
+#undef P2
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_fused_pair2(int n, int nt, const double* in, double* out, const double* Sfrag2, const double* G,
+                              long long inner, long long outer, int transpose, double omega, int mode,
+                              hipStream_t s) {
+  const int cg = nt >= 3 ? 1 : 4 / nt;
+  const unsigned grid = (unsigned)((outer * inner + 16 * cg - 1) / (16 * cg));
+  const dim3 block(64 * nt * cg);
+#define F2(HB2, NT)                                                                                          \
+  if (nt == NT) {                                                                                            \
+    hipLaunchKernelGGL((k_fused_pair2<HB2, NT>), dim3(grid), block, 0, s, in, out, Sfrag2, G, n, inner, outer, \
+                       transpose, omega, mode);                                                              \
+    return hipGetLastError();                                                                                \
+  }
+  if (n == 127) { F2(2, 1) F2(2, 2) F2(2, 3) F2(2, 4) }
+  if (n == 63) { F2(1, 1) F2(1, 2) F2(1, 3) F2(1, 4) }
+#undef F2
+  return hipErrorInvalidValue;
+}
+
+}  // namespace stmg
