@@ -117,16 +117,19 @@ __global__ __launch_bounds__(256) void k_residual(const Tin* __restrict__ u,
 // (all x).  It stages the N_t components of u and the coupling combination
 // w = sum_k cb[k] u_{n+dir,k} for rows y0-1 .. y0+TY (zero outside the
 // domain), then applies the separable 9-point mass/stiffness stencils from
-// LDS.  Dynamic LDS: (NT + 1) * (TY + 2) * n elements.
-template <typename Tin, typename Tout, int NT>
+// LDS.  Dynamic LDS: (NT + 1) * (TY + 2) * n elements.  The staged rows and
+// the tile's right-hand side are contiguous ranges of the slab, so thread t
+// handles elements t + 256 i, i < SIT, and the domain test is a range test
+// on the offset; every global load of the workgroup is issued before the
+// first use.  Requires (TY + 2) n <= 256 SIT.
+template <typename Tin, typename Tout, int NT, int SIT>
 __global__ __launch_bounds__(256) void k_residual_tile2d(const Tin* __restrict__ u,
-                                                         const Tin* __restrict__ F,
-                                                         Tout* __restrict__ r, ResidArgs<Tin> a,
-                                                         double* __restrict__ partial, int TY) {
+                                                            const Tin* __restrict__ F,
+                                                            Tout* __restrict__ r, ResidArgs<Tin> a,
+                                                            double* __restrict__ partial, int TY) {
   typedef Tin T;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   T* U = reinterpret_cast<T*>(lds_raw);
-  // logical (slab, row tile) in XCD-contiguous order
   const long long lg = xcd_linear(blockIdx.x + (long long)gridDim.x * slab_index(),
                                   (long long)gridDim.x * gridDim.y * gridDim.z);
   const long long slab = lg / gridDim.x;
@@ -136,69 +139,82 @@ __global__ __launch_bounds__(256) void k_residual_tile2d(const Tin* __restrict__
   const int n = a.n;
   const long long nx = a.nx;
   const int y0 = tile * TY;
-  const int rows = TY + 2;
-  const int plane = rows * n;                 // one component's tile
+  const int plane = (TY + 2) * n;
+  const int ylast = y0 + TY < n ? y0 + TY : n;
+  const int nout = (ylast - y0) * n;
   const int sn = (int)(slab % a.N);
   const bool couple = (sn + a.dir >= 0) && (sn + a.dir < a.N);
   const long long slabsz = (long long)NT * nx;
   const T* un = u + slab * slabsz;
   const T* up = u + (slab + a.dir) * slabsz;
-  const float inv_n = 1.0f / (float)n;
-  // ---- stage
-  for (int e = threadIdx.x; e < plane; e += 256) {
-    const int rr = div_small(e, n, inv_n);
-    const int x = e - rr * n;
-    const int y = y0 - 1 + rr;
-    const bool in = (y >= 0) && (y < n);
-    const long long off = (long long)y * n + x;
-    T w = T(0);
+  const T* Fn = F + slab * slabsz;
+  const long long s0 = (long long)(y0 - 1) * n;   // first staged offset (may be -n)
+  const long long o0 = (long long)y0 * n;         // first output offset
+  T fv[SIT][NT], uv[SIT][NT], pv[SIT][NT];
+#pragma unroll
+  for (int i = 0; i < SIT; ++i) {
+    const int e = threadIdx.x + 256 * i;
+    const long long so = s0 + e;
+    const bool in = e < plane && so >= 0 && so < nx;
 #pragma unroll
     for (int k = 0; k < NT; ++k) {
-      U[k * plane + e] = in ? un[k * nx + off] : T(0);
-      if (couple && in) w += a.cb[k] * up[k * nx + off];
+      uv[i][k] = in ? un[k * nx + so] : T(0);
+      pv[i][k] = (in && couple) ? up[k * nx + so] : T(0);
+      fv[i][k] = e < nout ? Fn[k * nx + o0 + e] : T(0);
     }
-    U[NT * plane + e] = w;
+  }
+#pragma unroll
+  for (int i = 0; i < SIT; ++i) {
+    const int e = threadIdx.x + 256 * i;
+    if (e < plane) {
+      T w = T(0);
+#pragma unroll
+      for (int k = 0; k < NT; ++k) {
+        U[k * plane + e] = uv[i][k];
+        w += a.cb[k] * pv[i][k];
+      }
+      U[NT * plane + e] = w;
+    }
   }
   __syncthreads();
-  // ---- stencils
   double ss = 0.0;
-  const T* Fn = F + slab * slabsz;
   Tout* rn = r + slab * slabsz;
-  const int nout = TY * n;
-  for (int e = threadIdx.x; e < nout; e += 256) {
-    const int yy = div_small(e, n, inv_n);
-    const int x = e - yy * n;
-    const int y = y0 + yy;
-    if (y >= n) continue;
-    const bool hl = x > 0, hr = x < n - 1;
-    T mu[NT + 1], ku[NT];
+  const float inv_n = 1.0f / (float)n;
 #pragma unroll
-    for (int c = 0; c <= NT; ++c) {
-      T m = T(0), kk = T(0);
+  for (int i = 0; i < SIT; ++i) {
+    const int e = threadIdx.x + 256 * i;
+    if (e < nout) {
+      const int yy = div_small(e, n, inv_n);
+      const int x = e - yy * n;
+      const bool hl = x > 0, hr = x < n - 1;
+      T mu[NT + 1], ku[NT];
 #pragma unroll
-      for (int dr = 0; dr < 3; ++dr) {
-        const T* row = U + c * plane + (yy + dr) * n + x;
-        const T l = hl ? row[-1] : T(0);
-        const T m0 = row[0];
-        const T rt = hr ? row[1] : T(0);
-        const T sm = a.wm[0] * l + a.wm[1] * m0 + a.wm[2] * rt;
-        m += a.wm[dr] * sm;
-        if (c < NT) {
-          const T sk = a.wk[0] * l + a.wk[1] * m0 + a.wk[2] * rt;
-          kk += a.wk[dr] * sm + a.wm[dr] * sk;
+      for (int c = 0; c <= NT; ++c) {
+        T m = T(0), kk = T(0);
+#pragma unroll
+        for (int dr = 0; dr < 3; ++dr) {
+          const T* row = U + c * plane + (yy + dr) * n + x;
+          const T l = hl ? row[-1] : T(0);
+          const T m0 = row[0];
+          const T rt = hr ? row[1] : T(0);
+          const T sm = a.wm[0] * l + a.wm[1] * m0 + a.wm[2] * rt;
+          m += a.wm[dr] * sm;
+          if (c < NT) {
+            const T sk = a.wk[0] * l + a.wk[1] * m0 + a.wk[2] * rt;
+            kk += a.wk[dr] * sm + a.wm[dr] * sk;
+          }
         }
+        mu[c] = m;
+        if (c < NT) ku[c] = kk;
       }
-      mu[c] = m;
-      if (c < NT) ku[c] = kk;
-    }
-    const long long off = (long long)y * n + x;
 #pragma unroll
-    for (int l = 0; l < NT; ++l) {
-      T acc = Fn[l * nx + off] + a.ca[l] * mu[NT];
+      for (int l = 0; l < NT; ++l) {
+        T acc = fv[i][l] + a.ca[l] * mu[NT];
 #pragma unroll
-      for (int k = 0; k < NT; ++k) acc -= a.K[l * NT + k] * mu[k] + a.M[l * NT + k] * ku[k];
-      rn[l * nx + off] = (Tout)acc;
-      ss += (double)acc * (double)acc;
+        for (int k = 0; k < NT; ++k) acc -= a.K[l * NT + k] * mu[k] + a.M[l * NT + k] * ku[k];
+        rn[l * nx + o0 + e] = (Tout)acc;
+        ss += (double)acc * (double)acc;
+      }
     }
   }
   if (partial != nullptr) {
@@ -436,12 +452,22 @@ inline unsigned blocks_for(long long total) { return (unsigned)((total + 255) / 
 
 // ================================================================ launchers
 
-int residual_tile_rows(int nt) { return nt <= 2 ? 8 : (nt == 3 ? 6 : 4); }
+// Rows per 2-D residual tile: 8/6/4 for N_t <= 2 / 3 / 4, fewer for wide
+// grids so that the staged rows fit one set of prefetched loads (at most
+// RES_PF_MAX elements; n <= 255 leaves at least 4 rows).
+constexpr int RES_PF_SIT = 6;
+constexpr int RES_PF_MAX = 256 * RES_PF_SIT;
+int residual_tile_rows(int nt, int n) {
+  const int ty = nt <= 2 ? 8 : (nt == 3 ? 6 : 4);
+  if ((ty + 2) * n <= RES_PF_MAX) return ty;
+  const int fit = RES_PF_MAX / n - 2;
+  return fit >= 1 ? fit : 0;
+}
 
 unsigned residual_blocks_per_slab(int dim, int n, long long nx, int nt) {
   if (dim == 2) {
-    const int ty = residual_tile_rows(nt);
-    return (unsigned)((n + ty - 1) / ty);
+    const int ty = residual_tile_rows(nt, n);
+    return ty > 0 ? (unsigned)((n + ty - 1) / ty) : 0u;
   }
   return (unsigned)((nx + 255) / 256);
 }
@@ -452,16 +478,21 @@ hipError_t launch_residual(int dim, int nt, const Tin* u, const Tin* F, Tout* r,
   const unsigned gx = residual_blocks_per_slab(dim, a.n, a.nx, nt);
   const dim3 grid = slab_grid(gx, (long long)a.batch * a.N);
   if (dim == 2) {
-    const int ty = residual_tile_rows(nt);
+    const int ty = residual_tile_rows(nt, a.n);
+    if (ty == 0) return hipErrorInvalidValue;
     const size_t lds = (size_t)(nt + 1) * (ty + 2) * a.n * sizeof(Tin);
-#define RES2_CASE(NT)                                                                        \
-  if (nt == NT) {                                                                            \
-    hipLaunchKernelGGL((k_residual_tile2d<Tin, Tout, NT>), grid, dim3(256), lds, s, u, F, r, a, \
-                       partial, ty);                                                         \
-    return hipGetLastError();                                                                \
+    const int sit = ((ty + 2) * a.n + 255) / 256;
+#define RESPF_CASE(NT, SIT)                                                                     \
+  if (nt == NT && sit == SIT) {                                                                 \
+    hipLaunchKernelGGL((k_residual_tile2d<Tin, Tout, NT, SIT>), grid, dim3(256), lds, s, u, F, r, \
+                       a, partial, ty);                                                         \
+    return hipGetLastError();                                                                   \
   }
-    RES2_CASE(1) RES2_CASE(2) RES2_CASE(3) RES2_CASE(4)
-#undef RES2_CASE
+#define RESPF_NT(NT) RESPF_CASE(NT, 1) RESPF_CASE(NT, 2) RESPF_CASE(NT, 3) RESPF_CASE(NT, 4) \
+                     RESPF_CASE(NT, 5) RESPF_CASE(NT, 6)
+    RESPF_NT(1) RESPF_NT(2) RESPF_NT(3) RESPF_NT(4)
+#undef RESPF_NT
+#undef RESPF_CASE
     return hipErrorInvalidValue;
   }
 #define RES_CASE(D, NT)                                                                \

@@ -58,6 +58,13 @@ def test_residual_parity(case, transpose):
     assert np.allclose(nrm, np.linalg.norm(r_ref, axis=0), rtol=1e-12)
 
 
+# The widest 2-D grid: the residual tile shrinks to 4 rows so that its
+# staged rows fit one set of prefetched loads.
+@pytest.mark.parametrize("case", [(2, 255, 2, 1, 1), (2, 255, 4, 3, 1)], ids=case_id)
+def test_residual_parity_wide(case):
+    test_residual_parity(case, False)
+
+
 @pytest.mark.parametrize("case", OPERATOR_CASES, ids=case_id)
 @pytest.mark.parametrize("transpose", [False, True])
 @pytest.mark.parametrize("impl", ["0", "1", "2"], ids=["auto", "lds", "reg"])
