@@ -111,7 +111,8 @@ struct Level {
   double* G64 = nullptr;  // per-mode inverse blocks [nx][nt][nt]
   float* G32 = nullptr;
   double* Sp64 = nullptr; // plain DST-I (n x n), used by the small-level smoother
-  double* S2_64 = nullptr; // twice-folded fragments (n = 63, 127) [dir][mat][kb][ib][lane]
+  double* S2_64 = nullptr; // twice-folded fragments (FP64: n = 63, 127) [dir][mat][kb][ib][lane]
+  float* S2_32 = nullptr;  // the same for FP32 (n = 63, 127, 255), FP32 contraction order
   float* Sp32 = nullptr;
   int impl = -1;          // transform family chosen for this level (-1: handle default)
   int small = -1;         // small-level smoother on (1) / off (0) for this level (-1: handle default)
@@ -443,7 +444,7 @@ int build_level_tables(st_mg* h, Level& L) {
       Sp[(size_t)k * n + i] = sc * std::sin(PI * (k + 1.0) * (i + 1.0) / (n + 1));
       Sp32[(size_t)k * n + i] = (float)Sp[(size_t)k * n + i];
     }
-  if (twice_folded_ok(n)) {
+  if (twice_folded_ok(n, 4)) {
     // twice-folded blocks: odd modes O[s][i] = S[2s+1][i+1], even E[s][i] = S[2s+2][i+1] on even i = 2p (mat 0, 2)
     // and odd i = 2p + 1 (mat 1, 3), rows s < h/2 and contraction p < h/2; the even block has no column
     // i = h - 1 and its middle row s = h/2 - 1 vanishes on odd i (both stored as exact zeros)
@@ -454,18 +455,27 @@ int build_level_tables(st_mg* h, Level& L) {
       if (mat == 3 && (i >= half - 1 || srow == q - 1)) return 0.0;
       return sc * std::sin(PI * (double)k * (i + 1.0) / (n + 1));
     };
-    std::vector<double> f2((size_t)2 * 4 * KB * NC * 64);
+    const size_t len2 = (size_t)2 * 4 * KB * NC * 64;
+    std::vector<double> f2(len2);
+    std::vector<float> f2_32(len2);
     for (int dir = 0; dir < 2; ++dir)
       for (int mat = 0; mat < 4; ++mat)
         for (int kb = 0; kb < KB; ++kb)
           for (int ib = 0; ib < NC; ++ib)
             for (int lane = 0; lane < 64; ++lane) {
-              const int rr = kb * 16 + (lane & 15), cc = ib * 4 + (lane >> 4);
-              f2[((((size_t)dir * 4 + mat) * KB + kb) * NC + ib) * 64 + lane] =
-                  dir == 0 ? M(mat, rr, cc) : M(mat, cc, rr);
+              const size_t o = ((((size_t)dir * 4 + mat) * KB + kb) * NC + ib) * 64 + lane;
+              // operand lane: row lane % 16 of block kb, contraction index 4 ib + lane / 16
+              const int cc = ib * 4 + (lane >> 4);
+              const int r8 = kb * 16 + twice_fold_row(8, lane & 15), r4 = kb * 16 + twice_fold_row(4, lane & 15);
+              f2[o] = dir == 0 ? M(mat, r8, cc) : M(mat, cc, r8);
+              f2_32[o] = (float)(dir == 0 ? M(mat, r4, cc) : M(mat, cc, r4));
             }
-    HIPCHK(h, hipMalloc(&L.S2_64, f2.size() * sizeof(double)));
-    HIPCHK(h, hipMemcpy(L.S2_64, f2.data(), f2.size() * sizeof(double), hipMemcpyHostToDevice));
+    if (twice_folded_ok(n, 8)) {
+      HIPCHK(h, hipMalloc(&L.S2_64, len2 * sizeof(double)));
+      HIPCHK(h, hipMemcpy(L.S2_64, f2.data(), len2 * sizeof(double), hipMemcpyHostToDevice));
+    }
+    HIPCHK(h, hipMalloc(&L.S2_32, len2 * sizeof(float)));
+    HIPCHK(h, hipMemcpy(L.S2_32, f2_32.data(), len2 * sizeof(float), hipMemcpyHostToDevice));
   }
   HIPCHK(h, hipMalloc(&L.Sp64, Sp.size() * sizeof(double)));
   HIPCHK(h, hipMalloc(&L.Sp32, Sp32.size() * sizeof(float)));
@@ -488,6 +498,9 @@ int build_level_tables(st_mg* h, Level& L) {
 template <typename T> const T* Sof(const Level& L);
 template <> const double* Sof<double>(const Level& L) { return L.S64; }
 template <> const float* Sof<float>(const Level& L) { return L.S32; }
+template <typename T> const T* S2of(const Level& L);
+template <> const double* S2of<double>(const Level& L) { return L.S2_64; }
+template <> const float* S2of<float>(const Level& L) { return L.S2_32; }
 template <typename T> const T* SPof(const Level& L);
 template <> const double* SPof<double>(const Level& L) { return L.Sp64; }
 template <> const float* SPof<float>(const Level& L) { return L.Sp32; }
@@ -726,8 +739,8 @@ int op_block_solve(st_mg* h, int l, bool transpose, const T* src, T* dst, int mo
       return ST_OK;
     }
     const int impl = L.impl >= 0 ? L.impl : h->impl;
-    if (sizeof(T) == 8 && (impl == TRANSFORM_REG2 || impl == TRANSFORM_AUTO) && L.S2_64) {
-      HIPCHK(h, launch_pass_reg2(n, inv, (const double*)in, (double*)out, L.S2_64, inner, ncols, (double)om, md, s));
+    if ((impl == TRANSFORM_REG2 || impl == TRANSFORM_AUTO) && S2of<T>(L)) {
+      HIPCHK(h, launch_pass_reg2<T>(n, inv, in, out, S2of<T>(L), inner, ncols, om, md, s));
       return ST_OK;
     }
     HIPCHK(h, launch_dst_pass<T>(impl, L.hb, axis == 0, inv, in, out, Sof<T>(L), n, inner, ncols, om, md, s));
@@ -743,9 +756,9 @@ int op_block_solve(st_mg* h, int l, bool transpose, const T* src, T* dst, int mo
       return ST_OK;
     }
     const int impl = L.impl >= 0 ? L.impl : h->impl;
-    if (sizeof(T) == 8 && (impl == TRANSFORM_REG2 || impl == TRANSFORM_AUTO) && L.S2_64) {
-      HIPCHK(h, launch_fused_pair2(n, nt, (const double*)in, (double*)out, L.S2_64, (const double*)Gof<T>(L), inner,
-                                   slabs, transpose ? 1 : 0, (double)om, md, s));
+    if ((impl == TRANSFORM_REG2 || impl == TRANSFORM_AUTO) && S2of<T>(L)) {
+      HIPCHK(h, launch_fused_pair2<T>(n, nt, in, out, S2of<T>(L), Gof<T>(L), inner, slabs, transpose ? 1 : 0, om, md,
+                                      s));
       return ST_OK;
     }
     HIPCHK(h, launch_dst_fused<T>(impl, L.hb, nt, in, out, Sof<T>(L), Gof<T>(L), n, inner, slabs,
@@ -1443,6 +1456,7 @@ int tune_level(st_mg* h, int l, T* u, T* F, T* r, T* alt, hipStream_t s) {
     cands.push_back({0, TRANSFORM_REG});   // AUTO is the twice-folded family where it exists
   } else if (sizeof(T) == 4 && L.hb <= 8) {
     cands.push_back({0, TRANSFORM_AUTO});
+    cands.push_back({0, TRANSFORM_REG});
   }
   hipEvent_t e0, e1;
   HIPCHK(h, hipEventCreate(&e0));
@@ -1985,6 +1999,7 @@ int st_mg_destroy(st_mg_t h) {
     (void)hipFree(L.Sp64);
     (void)hipFree(L.Sp32);
     (void)hipFree(L.S2_64);
+    (void)hipFree(L.S2_32);
     (void)hipFree(L.D64);
     (void)hipFree(L.D32);
     (void)hipFree(L.C64);

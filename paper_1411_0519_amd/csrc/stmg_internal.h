@@ -59,6 +59,9 @@ enum { MODE_STORE = 0, MODE_ADD_SCALED = 1, MODE_SET_SCALED = 2 };
 template <typename Tin, typename Tout>
 hipError_t launch_residual(int dim, int nt, const Tin* u, const Tin* F, Tout* r,
                            const ResidArgs<Tin>& a, double* partial, hipStream_t s);
+// Rows per 2-D tile of the residual and spatial smoothing kernels (0: n too
+// wide for one set of prefetched loads).
+int residual_tile_rows(int nt, int n);
 unsigned residual_blocks_per_slab(int dim, int n, long long nx, int nt);
 
 // Folded DST-I transforms (stmg_transform.hip).  hb = transform_half_blocks(n);
@@ -408,14 +411,20 @@ hipError_t launch_coarse_cycle(int dim, int nt, const CoarseArgs<T>* args, size_
 
 namespace stmg {
 
-// Twice-folded FP64 register transforms for n = 63 and 127 (stmg_transform2.hip):
-// the x/y passes and the fused slowest-axis solve with half the matrix-core
-// work of the once-folded ones; Sfrag2 is their fragment table.
-bool twice_folded_ok(int n);
-hipError_t launch_pass_reg2(int n, bool inverse, const double* in, double* out, const double* Sfrag2,
-                            long long inner, long long ncols, double omega, int mode, hipStream_t s);
-hipError_t launch_fused_pair2(int n, int nt, const double* in, double* out, const double* Sfrag2, const double* G,
-                              long long inner, long long outer, int transpose, double omega, int mode,
-                              hipStream_t s);
+// Twice-folded register transforms (stmg_transform2.hip), FP64 for n = 63,
+// 127 and FP32 for n = 63, 127, 255: the x/y passes and the fused slowest-axis
+// solve with half the matrix-core work of the once-folded ones; Sfrag2 is
+// their fragment table.  The f32 instruction's accumulator rows are blocked
+// (row 4 g + j in element j of lane group g) where the f64 one interleaves
+// (g + 4 j), so the FP32 table stores output row twice_fold_row(i) at operand
+// row i and both types share one register order.
+bool twice_folded_ok(int n, int elem_bytes);
+inline int twice_fold_row(int elem_bytes, int i) { return elem_bytes == 8 ? i : (i >> 2) + 4 * (i & 3); }
+template <typename T>
+hipError_t launch_pass_reg2(int n, bool inverse, const T* in, T* out, const T* Sfrag2, long long inner,
+                            long long ncols, T omega, int mode, hipStream_t s);
+template <typename T>
+hipError_t launch_fused_pair2(int n, int nt, const T* in, T* out, const T* Sfrag2, const T* G, long long inner,
+                              long long outer, int transpose, T omega, int mode, hipStream_t s);
 
 }  // namespace stmg

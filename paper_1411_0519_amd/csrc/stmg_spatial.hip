@@ -5,6 +5,7 @@
 // usual [slab][time dof l][z][y][x] layout.
 //
 //   k_spatial          damped block-Jacobi step y = x + omega_x Dinv (f - A x)
+//                      (k_spatial_tile2d: the 2-D form on an LDS tile)
 //                      or the defect y = f - A x, written as y, scale*y or
 //                      base + scale*y (the last step of a cycle writes the
 //                      smoothed iterate u += omega_t x directly)
@@ -67,6 +68,116 @@ __global__ __launch_bounds__(256) void k_spatial(const T* __restrict__ x, const 
     if (a.upd == UPD_ADD) o = base[off + l * nx] + a.scale * y;
     else if (a.upd == UPD_SET) o = a.scale * y;
     out[off + l * nx] = o;
+  }
+}
+
+// The same step in 2-D on an LDS tile: one workgroup owns one slab and TY
+// rows (all x), stages rows y0-1 .. y0+TY of the N_t components of x (zero
+// outside the domain) and applies the separable 9-point stencils from LDS.
+// The staged rows, the tile's f and (for UPD_ADD) its base are contiguous
+// ranges of the slab, so thread t handles elements t + 256 i, i < SIT, and
+// every global load is issued before the first use.  Dynamic LDS:
+// NT * (TY + 2) * n elements; requires (TY + 2) n <= 256 SIT.
+template <typename T, int NT, int SIT>
+__global__ __launch_bounds__(256) void k_spatial_tile2d(const T* __restrict__ x, const T* __restrict__ f,
+                                                        const T* base, T* out, SpatialArgs<T> a, int TY) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  T* U = reinterpret_cast<T*>(lds_raw);
+  const long long lg = xcd_linear(blockIdx.x + (long long)gridDim.x * slab_index(),
+                                  (long long)gridDim.x * gridDim.y * gridDim.z);
+  const long long slab = lg / gridDim.x;
+  const int tile = (int)(lg - slab * gridDim.x);
+  if (slab >= a.slabs) return;
+  const int n = a.n;
+  const long long nx = a.nx;
+  const int y0 = tile * TY;
+  const int plane = (TY + 2) * n;
+  const int ylast = y0 + TY < n ? y0 + TY : n;
+  const int nout = (ylast - y0) * n;
+  const long long sbase = slab * NT * nx;
+  const long long s0 = (long long)(y0 - 1) * n;
+  const long long o0 = (long long)y0 * n;
+  const bool xz = a.x_zero != 0;
+  const bool add = a.upd == UPD_ADD;
+  T fv[SIT][NT], xv[SIT][NT], bv[SIT][NT];
+#pragma unroll
+  for (int i = 0; i < SIT; ++i) {
+    const int e = threadIdx.x + 256 * i;
+    const long long so = s0 + e;
+    const bool in = !xz && e < plane && so >= 0 && so < nx;
+    const bool o = e < nout;
+#pragma unroll
+    for (int k = 0; k < NT; ++k) {
+      xv[i][k] = in ? x[sbase + k * nx + so] : T(0);
+      fv[i][k] = o ? f[sbase + k * nx + o0 + e] : T(0);
+      bv[i][k] = (o && add) ? base[sbase + k * nx + o0 + e] : T(0);
+    }
+  }
+  if (!xz) {
+#pragma unroll
+    for (int i = 0; i < SIT; ++i) {
+      const int e = threadIdx.x + 256 * i;
+      if (e < plane) {
+#pragma unroll
+        for (int k = 0; k < NT; ++k) U[k * plane + e] = xv[i][k];
+      }
+    }
+    __syncthreads();
+  }
+  const float inv_n = 1.0f / (float)n;
+#pragma unroll
+  for (int i = 0; i < SIT; ++i) {
+    const int e = threadIdx.x + 256 * i;
+    if (e >= nout) continue;
+    T mu[NT], ku[NT], xc[NT];
+    if (xz) {
+#pragma unroll
+      for (int c = 0; c < NT; ++c) mu[c] = ku[c] = xc[c] = T(0);
+    } else {
+      const int yy = div_small(e, n, inv_n);
+      const int px = e - yy * n;
+      const bool hl = px > 0, hr = px < n - 1;
+#pragma unroll
+      for (int c = 0; c < NT; ++c) {
+        T m = T(0), kk = T(0);
+#pragma unroll
+        for (int dr = 0; dr < 3; ++dr) {
+          const T* row = U + c * plane + (yy + dr) * n + px;
+          const T l = hl ? row[-1] : T(0);
+          const T m0 = row[0];
+          const T rt = hr ? row[1] : T(0);
+          const T sm = a.wm[0] * l + a.wm[1] * m0 + a.wm[2] * rt;
+          const T sk = a.wk[0] * l + a.wk[1] * m0 + a.wk[2] * rt;
+          m += a.wm[dr] * sm;
+          kk += a.wk[dr] * sm + a.wm[dr] * sk;
+          if (dr == 1) xc[c] = m0;
+        }
+        mu[c] = m;
+        ku[c] = kk;
+      }
+    }
+    T r[NT];
+#pragma unroll
+    for (int l = 0; l < NT; ++l) {
+      T acc = fv[i][l];
+#pragma unroll
+      for (int k = 0; k < NT; ++k) acc -= a.K[l * NT + k] * mu[k] + a.M[l * NT + k] * ku[k];
+      r[l] = acc;
+    }
+#pragma unroll
+    for (int l = 0; l < NT; ++l) {
+      T y = r[l];
+      if (a.op == SP_JACOBI) {
+        T c = T(0);
+#pragma unroll
+        for (int k = 0; k < NT; ++k) c += a.Dinv[l * NT + k] * r[k];
+        y = xc[l] + a.omega * c;
+      }
+      T o = y;
+      if (add) o = bv[i][l] + a.scale * y;
+      else if (a.upd == UPD_SET) o = a.scale * y;
+      out[sbase + l * nx + o0 + e] = o;
+    }
   }
 }
 
@@ -358,6 +469,24 @@ template <typename T>
 hipError_t launch_spatial(int dim, int nt, const T* x, const T* f, const T* base, T* out,
                           const SpatialArgs<T>& a, hipStream_t s) {
   const long long slabs = a.slabs;
+  if (dim == 2) {
+    const int ty = residual_tile_rows(nt, a.n);
+    if (ty == 0) return hipErrorInvalidValue;
+    const size_t lds = (size_t)nt * (ty + 2) * a.n * sizeof(T);
+    const int sit = ((ty + 2) * a.n + 255) / 256;
+    const dim3 grid = slab_grid((unsigned)((a.n + ty - 1) / ty), slabs);
+#define SPT_CASE(NT, SIT)                                                                               \
+  if (nt == NT && sit == SIT) {                                                                         \
+    hipLaunchKernelGGL((k_spatial_tile2d<T, NT, SIT>), grid, dim3(256), lds, s, x, f, base, out, a, ty); \
+    return hipGetLastError();                                                                           \
+  }
+#define SPT_NT(NT) SPT_CASE(NT, 1) SPT_CASE(NT, 2) SPT_CASE(NT, 3) SPT_CASE(NT, 4) SPT_CASE(NT, 5) \
+                   SPT_CASE(NT, 6)
+    SPT_NT(1) SPT_NT(2) SPT_NT(3) SPT_NT(4)
+#undef SPT_NT
+#undef SPT_CASE
+    return hipErrorInvalidValue;
+  }
   SPATIAL_DISPATCH(k_spatial, blocks_for(a.nx), x, f, base, out, a)
 }
 

@@ -1,4 +1,5 @@
-// Twice-folded sine transforms on the FP64 matrix cores (n = 63, 127).
+// Twice-folded sine transforms on the matrix cores: FP64 for n = 63, 127, FP32
+// for n = 63, 127, 255.
 //
 // The first fold pairs x_i with x_{n-1-i} (odd modes see a_i = x_i + x_{n-1-i},
 // even modes d_i = x_i - x_{n-1-i}).  Each half has a second mirror symmetry:
@@ -15,6 +16,15 @@
 // Fragment table [dir][mat][kb][ib][lane], mat = 0: O on even i, 1: O on odd i,
 // 2: E on even i, 3: E on odd i; dir 0 holds A[s][p] (forward), dir 1 A[p][s]
 // (inverse), blocks of 16 rows and chunks of 4 along the contraction.
+//
+// Register order: chunk ib of a product's contraction holds index 4 ib + g in
+// lane group g, and accumulator element j of row block kb holds output row
+// 16 kb + g + 4 j.  That is the f64 instruction's own accumulator layout; the
+// f32 instruction holds row 4 g + j of its A operand there, so the FP32 table
+// stores A row g + 4 j at operand row 4 g + j.  Either way accumulator element
+// j of block kb is, in every lane, the operand of chunk 4 kb + j of the next
+// product (forward product, per-mode solve and inverse product chain in
+// registers), and the four lane groups of a line touch neighbouring elements.
 #include <hip/hip_runtime.h>
 
 #include "stmg_device.h"
@@ -26,29 +36,31 @@ namespace {
 
 using namespace dev;
 
-typedef v4d acc_t;
-
-__device__ inline acc_t mma(double a, double b, acc_t c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+// contraction index of lane group g in chunk ib; output row of element j of block kb
+__device__ inline int cidx(int ib, int g) { return 4 * ib + g; }
+__device__ inline int orow(int kb, int g, int j) { return 16 * kb + g + 4 * j; }
 
 // acc[mat][kb] = sum over chunks ib of A(dir, mat, kb, ib) * B(mat, ib); HB2 = h/32
 // row blocks per product, 2 HB2 * 4 = h/2 contraction indices.  B(mat, ib) is
 // the lane's operand for (mat, chunk ib).
-template <int HB2, int DIR, typename OpFn>
-__device__ inline void mma4(const double* __restrict__ Sfrag, int lane, OpFn op, acc_t (&acc)[4][HB2]) {
+template <typename T, int HB2, int DIR, typename OpFn>
+__device__ inline void mma4(const T* __restrict__ Sfrag, int lane, OpFn op,
+                            typename Mfma<T>::acc_t (&acc)[4][HB2]) {
+  typedef typename Mfma<T>::acc_t acc_t;
   constexpr int NC = 4 * HB2;   // chunks of 4 along the contraction (h/2 / 4)
 #pragma unroll
   for (int m = 0; m < 4; ++m)
 #pragma unroll
     for (int kb = 0; kb < HB2; ++kb) acc[m][kb] = acc_t{0, 0, 0, 0};
-  const double* s = Sfrag + (size_t)DIR * 4 * HB2 * NC * 64 + lane;
-  double nf[4][HB2];
+  const T* s = Sfrag + (size_t)DIR * 4 * HB2 * NC * 64 + lane;
+  T nf[4][HB2];
 #pragma unroll
   for (int m = 0; m < 4; ++m)
 #pragma unroll
     for (int kb = 0; kb < HB2; ++kb) nf[m][kb] = s[((m * HB2 + kb) * NC) * 64];
 #pragma unroll
   for (int ib = 0; ib < NC; ++ib) {
-    double af[4][HB2];
+    T af[4][HB2];
 #pragma unroll
     for (int m = 0; m < 4; ++m)
 #pragma unroll
@@ -61,26 +73,26 @@ __device__ inline void mma4(const double* __restrict__ Sfrag, int lane, OpFn op,
     }
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-      const double b = op(m, ib);
+      const T b = op(m, ib);
 #pragma unroll
-      for (int kb = 0; kb < HB2; ++kb) acc[m][kb] = mma(af[m][kb], b, acc[m][kb]);
+      for (int kb = 0; kb < HB2; ++kb) acc[m][kb] = Mfma<T>::op(af[m][kb], b, acc[m][kb]);
     }
     __builtin_amdgcn_sched_barrier(0);
   }
 }
 
-// Forward operands of chunk ib for contraction index p = 4 ib + g: the
+// Forward operands of chunk ib for contraction index p = cidx(ib, g): the
 // physical values x_{2p}, x_{2p+1} and their partners x_{n-1-2p}, x_{n-2-2p}.
 // Returns a_{2p}, a_{2p+1}, d_{2p}, d_{2p+1} (d_{h-1} = 0, a_{h-1} = x_{h-1}).
-template <int HB2>
-__device__ inline void load_twice_folded(const double* __restrict__ src, bool valid, long long inner, int n, int g,
-                                         double (&op)[4][4 * HB2]) {
+template <typename T, int HB2>
+__device__ inline void load_twice_folded(const T* __restrict__ src, bool valid, long long inner, int n, int g,
+                                         T (&op)[4][4 * HB2]) {
   const int h = (n + 1) >> 1;
 #pragma unroll
   for (int ib = 0; ib < 4 * HB2; ++ib) {
-    const int p = 4 * ib + g;
+    const int p = cidx(ib, g);
     const int i0 = 2 * p, i1 = 2 * p + 1;
-    double x0 = 0, y0 = 0, x1 = 0, y1 = 0;
+    T x0 = 0, y0 = 0, x1 = 0, y1 = 0;
     if (valid) {
       x0 = src[(long long)i0 * inner];
       y0 = src[(long long)(n - 1 - i0) * inner];
@@ -90,11 +102,12 @@ __device__ inline void load_twice_folded(const double* __restrict__ src, bool va
     op[0][ib] = x0 + y0;
     op[1][ib] = x1 + y1;
     op[2][ib] = x0 - y0;
-    op[3][ib] = (i1 < h - 1) ? x1 - y1 : 0.0;
+    op[3][ib] = (i1 < h - 1) ? x1 - y1 : T(0);
   }
 }
 
-__device__ inline double epi(int mode, double old, double v, double omega) {
+template <typename T>
+__device__ inline T epi(int mode, T old, T v, T omega) {
   if (mode == MODE_ADD_SCALED) return old + omega * v;
   if (mode == MODE_SET_SCALED) return omega * v;
   return v;
@@ -102,31 +115,67 @@ __device__ inline double epi(int mode, double old, double v, double omega) {
 
 // Physical outputs of an inverse product: row p of the four accumulators holds
 // P_{2p}, P_{2p+1} (odd modes) and Q_{2p}, Q_{2p+1} (even modes); x_i = P_i + Q_i
-// and x_{n-1-i} = P_i - Q_i (i < h-1), x_{h-1} = P_{h-1}.
-template <int HB2>
-__device__ inline void store_twice_unfolded(double* __restrict__ dst, bool valid, long long inner, int n, int g,
-                                            const acc_t (&acc)[4][HB2], int mode, double omega) {
-  if (!valid) return;
+// and x_{n-1-i} = P_i - Q_i (i < h-1), x_{h-1} = P_{h-1}.  The four positions of
+// element j of block kb are put_pos(); with MODE_ADD_SCALED the old values are
+// loaded by load_old() before the products (PRE), so that those loads overlap
+// them, or at the store.
+__device__ inline void put_pos(int n, int kb, int g, int j, int (&pos)[4], bool& tail) {
   const int h = (n + 1) >> 1;
-  auto put = [&](int i, double v) {
-    double* q = dst + (long long)i * inner;
-    const double o = (mode == MODE_ADD_SCALED) ? *q : 0.0;
-    *q = epi(mode, o, v, omega);
-  };
+  const int p = orow(kb, g, j);
+  const int i0 = 2 * p, i1 = 2 * p + 1;
+  tail = i1 >= h - 1;
+  pos[0] = i0;
+  pos[1] = n - 1 - i0;
+  pos[2] = i1;
+  pos[3] = n - 1 - i1;
+}
+
+template <typename T, int HB2>
+__device__ inline void load_old(const T* __restrict__ dst, bool valid, long long inner, int n, int g,
+                                T (&old)[HB2][4][4]) {
 #pragma unroll
   for (int kb = 0; kb < HB2; ++kb)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int p = kb * 16 + g + 4 * j;
-      const int i0 = 2 * p, i1 = 2 * p + 1;
-      const double P0 = acc[0][kb][j], P1 = acc[1][kb][j], Q0 = acc[2][kb][j], Q1 = acc[3][kb][j];
-      put(i0, P0 + Q0);
-      put(n - 1 - i0, P0 - Q0);
-      if (i1 < h - 1) {
-        put(i1, P1 + Q1);
-        put(n - 1 - i1, P1 - Q1);
-      } else {
-        put(i1, P1);
+      int pos[4];
+      bool tail;
+      put_pos(n, kb, g, j, pos, tail);
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        old[kb][j][c] = (valid && (c < 3 || !tail)) ? dst[(long long)pos[c] * inner] : T(0);
+    }
+}
+
+template <typename T, int HB2>
+__device__ inline void zero_old(T (&old)[HB2][4][4]) {
+#pragma unroll
+  for (int kb = 0; kb < HB2; ++kb)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) old[kb][j][c] = T(0);
+}
+
+template <typename T, int HB2, bool PRE>
+__device__ inline void store_twice_unfolded(T* __restrict__ dst, bool valid, long long inner, int n, int g,
+                                            const typename Mfma<T>::acc_t (&acc)[4][HB2], int mode, T omega,
+                                            const T (&old)[HB2][4][4]) {
+  if (!valid) return;
+#pragma unroll
+  for (int kb = 0; kb < HB2; ++kb)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      int pos[4];
+      bool tail;
+      put_pos(n, kb, g, j, pos, tail);
+      const T P0 = acc[0][kb][j], P1 = acc[1][kb][j], Q0 = acc[2][kb][j], Q1 = acc[3][kb][j];
+      T v[4] = {P0 + Q0, P0 - Q0, tail ? P1 : P1 + Q1, P1 - Q1};
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        if (c == 3 && tail) continue;
+        T* q = dst + (long long)pos[c] * inner;
+        const T o = PRE ? old[kb][j][c] : (mode == MODE_ADD_SCALED ? *q : T(0));
+        *q = epi<T>(mode, o, v[c], omega);
       }
     }
 }
@@ -134,18 +183,19 @@ __device__ inline void store_twice_unfolded(double* __restrict__ dst, bool valid
 // Inverse operands from the four spectral values of row s: u = y_o[s] +
 // y_o[h-1-s], v = y_o[s] - y_o[h-1-s], ue = y_e[s] + y_e[h-2-s] (y_e[s*] on the
 // middle row), ve = y_e[s] - y_e[h-2-s] (0 on the middle row).
-__device__ inline void inverse_operands(double o, double om, double e, double em, bool middle, double& u, double& v,
-                                        double& ue, double& ve) {
+template <typename T>
+__device__ inline void inverse_operands(T o, T om, T e, T em, bool middle, T& u, T& v, T& ue, T& ve) {
   u = o + om;
   v = o - om;
   ue = middle ? e : e + em;
-  ve = middle ? 0.0 : e - em;
+  ve = middle ? T(0) : e - em;
 }
 
-template <int HB2, bool INV, bool UNIT>
-__global__ __launch_bounds__(256) void k_pass_reg2(const double* __restrict__ in, double* __restrict__ out,
-                                                   const double* __restrict__ Sfrag, int n, long long inner_rt,
-                                                   long long ncols, double omega, int mode) {
+template <typename T, int HB2, bool INV, bool UNIT>
+__global__ __launch_bounds__(256) void k_pass_reg2(const T* __restrict__ in, T* __restrict__ out,
+                                                   const T* __restrict__ Sfrag, int n, long long inner_rt,
+                                                   long long ncols, T omega, int mode) {
+  typedef typename Mfma<T>::acc_t acc_t;
   const long long inner = UNIT ? 1 : inner_rt;
   const int lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
   const long long wv = xcd_linear(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
@@ -155,35 +205,38 @@ __global__ __launch_bounds__(256) void k_pass_reg2(const double* __restrict__ in
   const long long o = valid ? lin / inner : 0;
   const long long pos = valid ? lin - o * inner : 0;
   const long long base = o * (long long)n * inner + pos;
-  double op[4][4 * HB2];
+  T op[4][4 * HB2];
   if (!INV) {
-    load_twice_folded<HB2>(in + base, valid, inner, n, g, op);
+    load_twice_folded<T, HB2>(in + base, valid, inner, n, g, op);
   } else {
-    // spectral rows s = 4 ib + g (< h/2) and their mirrors
+    // spectral rows s = cidx(ib, g) (< h/2) and their mirrors
 #pragma unroll
     for (int ib = 0; ib < 4 * HB2; ++ib) {
-      const int s = 4 * ib + g;
+      const int s = cidx(ib, g);
       const bool middle = s == h / 2 - 1;
-      double yo = 0, yom = 0, ye = 0, yem = 0;
+      T yo = 0, yom = 0, ye = 0, yem = 0;
       if (valid) {
         yo = in[base + (long long)s * inner];
         yom = in[base + (long long)(h - 1 - s) * inner];
         ye = in[base + (long long)(h + s) * inner];
         if (!middle) yem = in[base + (long long)(h + h - 2 - s) * inner];
       }
-      inverse_operands(yo, yom, ye, yem, middle, op[0][ib], op[1][ib], op[2][ib], op[3][ib]);
+      inverse_operands<T>(yo, yom, ye, yem, middle, op[0][ib], op[1][ib], op[2][ib], op[3][ib]);
     }
   }
+  T old[HB2][4][4];
+  if (INV && mode == MODE_ADD_SCALED) load_old<T, HB2>(out + base, valid, inner, n, g, old);
+  else zero_old<T, HB2>(old);
   acc_t acc[4][HB2];
-  mma4<HB2, INV ? 1 : 0>(Sfrag, lane, [&](int m, int ib) { return op[m][ib]; }, acc);
+  mma4<T, HB2, INV ? 1 : 0>(Sfrag, lane, [&](int m, int ib) { return op[m][ib]; }, acc);
   if (!INV) {
     if (valid) {
 #pragma unroll
       for (int kb = 0; kb < HB2; ++kb)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const int s = kb * 16 + g + 4 * j;
-          const double P = acc[0][kb][j], Q = acc[1][kb][j], Pe = acc[2][kb][j], Qe = acc[3][kb][j];
+          const int s = orow(kb, g, j);
+          const T P = acc[0][kb][j], Q = acc[1][kb][j], Pe = acc[2][kb][j], Qe = acc[3][kb][j];
           out[base + (long long)s * inner] = P + Q;
           out[base + (long long)(h - 1 - s) * inner] = P - Q;
           out[base + (long long)(h + s) * inner] = Pe + Qe;
@@ -191,19 +244,20 @@ __global__ __launch_bounds__(256) void k_pass_reg2(const double* __restrict__ in
         }
     }
   } else {
-    store_twice_unfolded<HB2>(out + base, valid, inner, n, g, acc, mode, omega);
+    store_twice_unfolded<T, HB2, true>(out + base, valid, inner, n, g, acc, mode, omega, old);
   }
 }
 
 // Slowest axis: forward transform, per-mode N_t x N_t solve, inverse transform,
 // one wave per time component (as the once-folded k_fused_pair), the
 // components exchanged through LDS for the solve.
-template <int HB2, int NT>
-__global__ __launch_bounds__(256) void k_fused_pair2(const double* in, double* out, const double* __restrict__ Sfrag,
-                                                     const double* __restrict__ G, int n, long long inner,
-                                                     long long outer, int transpose, double omega, int mode) {
+template <typename T, int HB2, int NT>
+__global__ __launch_bounds__(256) void k_fused_pair2(const T* in, T* out, const T* __restrict__ Sfrag,
+                                                     const T* __restrict__ G, int n, long long inner,
+                                                     long long outer, int transpose, T omega, int mode) {
+  typedef typename Mfma<T>::acc_t acc_t;
   constexpr int CG = NT >= 3 ? 1 : 4 / NT;
-  __shared__ double xch[4 * HB2][CG * NT * 64 * 4];
+  __shared__ T xch[4 * HB2][CG * NT * 64 * 4];
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
   const int cg = wave / NT, l = wave - (wave / NT) * NT;
@@ -216,16 +270,16 @@ __global__ __launch_bounds__(256) void k_fused_pair2(const double* in, double* o
   const int h = (n + 1) >> 1;
   acc_t acc[4][HB2];
   {
-    double op[4][4 * HB2];
-    load_twice_folded<HB2>(in + base, valid, inner, n, g, op);
-    mma4<HB2, 0>(Sfrag, lane, [&](int m, int ib) { return op[m][ib]; }, acc);
+    T op[4][4 * HB2];
+    load_twice_folded<T, HB2>(in + base, valid, inner, n, g, op);
+    mma4<T, HB2, 0>(Sfrag, lane, [&](int m, int ib) { return op[m][ib]; }, acc);
   }
   // spectral values (o, om, e, em) of every row to LDS, one barrier
 #pragma unroll
   for (int kb = 0; kb < HB2; ++kb)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const double P = acc[0][kb][j], Q = acc[1][kb][j], Pe = acc[2][kb][j], Qe = acc[3][kb][j];
+      const T P = acc[0][kb][j], Q = acc[1][kb][j], Pe = acc[2][kb][j], Qe = acc[3][kb][j];
       const int slot = ((cg * NT + l) * 64 + lane) * 4 + j;
       xch[0 * HB2 + kb][slot] = P + Q;
       xch[1 * HB2 + kb][slot] = P - Q;
@@ -234,23 +288,23 @@ __global__ __launch_bounds__(256) void k_fused_pair2(const double* in, double* o
     }
   __syncthreads();
   // per-mode solve of this wave's component, then the inverse operands
-  double op[4][4 * HB2];
+  T op[4][4 * HB2];
 #pragma unroll
   for (int kb = 0; kb < HB2; ++kb)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int s = kb * 16 + g + 4 * j;
+      const int s = orow(kb, g, j);
       const bool middle = s == h / 2 - 1;
       const int mode_idx[4] = {s, h - 1 - s, h + s, h + (middle ? s : h - 2 - s)};
-      double y[4];
+      T y[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        double a = 0.0;
+        T a = T(0);
         if (valid) {
-          const double* gm = G + (pos + inner * (long long)mode_idx[q]) * (NT * NT);
+          const T* gm = G + (pos + inner * (long long)mode_idx[q]) * (NT * NT);
 #pragma unroll
           for (int m = 0; m < NT; ++m) {
-            const double v = xch[q * HB2 + kb][((cg * NT + m) * 64 + lane) * 4 + j];
+            const T v = xch[q * HB2 + kb][((cg * NT + m) * 64 + lane) * 4 + j];
             a += (transpose ? gm[m * NT + l] : gm[l * NT + m]) * v;
           }
         }
@@ -258,28 +312,41 @@ __global__ __launch_bounds__(256) void k_fused_pair2(const double* in, double* o
       }
       // chunk 4 kb + j, contraction row g: the accumulator layout is the operand layout
       const int ib = 4 * kb + j;
-      inverse_operands(y[0], y[1], y[2], y[3], middle, op[0][ib], op[1][ib], op[2][ib], op[3][ib]);
+      inverse_operands<T>(y[0], y[1], y[2], y[3], middle, op[0][ib], op[1][ib], op[2][ib], op[3][ib]);
     }
   acc_t out_acc[4][HB2];
-  mma4<HB2, 1>(Sfrag, lane, [&](int m, int ib) { return op[m][ib]; }, out_acc);
-  store_twice_unfolded<HB2>(out + base, valid, inner, n, g, out_acc, mode, omega);
+  mma4<T, HB2, 1>(Sfrag, lane, [&](int m, int ib) { return op[m][ib]; }, out_acc);
+  T none[HB2][4][4];
+  zero_old<T, HB2>(none);
+  store_twice_unfolded<T, HB2, false>(out + base, valid, inner, n, g, out_acc, mode, omega, none);
 }
 
 }  // namespace
 
-bool twice_folded_ok(int n) { return n == 63 || n == 127; }
+bool twice_folded_ok(int n, int elem_bytes) {
+  if (n == 63 || n == 127) return true;
+  return elem_bytes == 4 && n == 255;    // FP64 at h/2 = 64 would not fit in registers
+}
 
-hipError_t launch_pass_reg2(int n, bool inverse, const double* in, double* out, const double* Sfrag2,
-                            long long inner, long long ncols, double omega, int mode, hipStream_t s) {
+template <typename T>
+hipError_t launch_pass_reg2(int n, bool inverse, const T* in, T* out, const T* Sfrag2, long long inner,
+                            long long ncols, T omega, int mode, hipStream_t s) {
   const unsigned grid = (unsigned)((ncols + 63) / 64);
-#define P2(HB2, U)                                                                                        \
-  if (inverse)                                                                                            \
-    hipLaunchKernelGGL((k_pass_reg2<HB2, true, U>), dim3(grid), dim3(256), 0, s, in, out, Sfrag2, n, inner, \
-                       ncols, omega, mode);                                                               \
-  else                                                                                                    \
-    hipLaunchKernelGGL((k_pass_reg2<HB2, false, U>), dim3(grid), dim3(256), 0, s, in, out, Sfrag2, n, inner, \
-                       ncols, omega, mode);                                                               \
+#define P2(HB2, U)                                                                                          \
+  if (inverse)                                                                                              \
+    hipLaunchKernelGGL((k_pass_reg2<T, HB2, true, U>), dim3(grid), dim3(256), 0, s, in, out, Sfrag2, n, inner, \
+                       ncols, omega, mode);                                                                 \
+  else                                                                                                      \
+    hipLaunchKernelGGL((k_pass_reg2<T, HB2, false, U>), dim3(grid), dim3(256), 0, s, in, out, Sfrag2, n,       \
+                       inner, ncols, omega, mode);                                                          \
   return hipGetLastError();
+  if (!twice_folded_ok(n, (int)sizeof(T))) return hipErrorInvalidValue;
+  if constexpr (sizeof(T) == 4) {
+    if (n == 255) {
+      if (inner == 1) { P2(4, true) }
+      P2(4, false)
+    }
+  }
   if (n == 127) {
     if (inner == 1) { P2(2, true) }
     P2(2, false)
@@ -292,22 +359,35 @@ hipError_t launch_pass_reg2(int n, bool inverse, const double* in, double* out, 
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_fused_pair2(int n, int nt, const double* in, double* out, const double* Sfrag2, const double* G,
-                              long long inner, long long outer, int transpose, double omega, int mode,
-                              hipStream_t s) {
+template <typename T>
+hipError_t launch_fused_pair2(int n, int nt, const T* in, T* out, const T* Sfrag2, const T* G, long long inner,
+                              long long outer, int transpose, T omega, int mode, hipStream_t s) {
   const int cg = nt >= 3 ? 1 : 4 / nt;
   const unsigned grid = (unsigned)((outer * inner + 16 * cg - 1) / (16 * cg));
   const dim3 block(64 * nt * cg);
-#define F2(HB2, NT)                                                                                          \
-  if (nt == NT) {                                                                                            \
-    hipLaunchKernelGGL((k_fused_pair2<HB2, NT>), dim3(grid), block, 0, s, in, out, Sfrag2, G, n, inner, outer, \
-                       transpose, omega, mode);                                                              \
-    return hipGetLastError();                                                                                \
+#define F2(HB2, NT)                                                                                             \
+  if (nt == NT) {                                                                                               \
+    hipLaunchKernelGGL((k_fused_pair2<T, HB2, NT>), dim3(grid), block, 0, s, in, out, Sfrag2, G, n, inner, outer, \
+                       transpose, omega, mode);                                                                 \
+    return hipGetLastError();                                                                                   \
+  }
+  if (!twice_folded_ok(n, (int)sizeof(T))) return hipErrorInvalidValue;
+  if constexpr (sizeof(T) == 4) {
+    if (n == 255) { F2(4, 1) F2(4, 2) F2(4, 3) F2(4, 4) }
   }
   if (n == 127) { F2(2, 1) F2(2, 2) F2(2, 3) F2(2, 4) }
   if (n == 63) { F2(1, 1) F2(1, 2) F2(1, 3) F2(1, 4) }
 #undef F2
   return hipErrorInvalidValue;
 }
+
+template hipError_t launch_pass_reg2<double>(int, bool, const double*, double*, const double*, long long, long long,
+                                             double, int, hipStream_t);
+template hipError_t launch_pass_reg2<float>(int, bool, const float*, float*, const float*, long long, long long,
+                                            float, int, hipStream_t);
+template hipError_t launch_fused_pair2<double>(int, int, const double*, double*, const double*, const double*,
+                                               long long, long long, int, double, int, hipStream_t);
+template hipError_t launch_fused_pair2<float>(int, int, const float*, float*, const float*, const float*, long long,
+                                              long long, int, float, int, hipStream_t);
 
 }  // namespace stmg

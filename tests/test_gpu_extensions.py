@@ -46,11 +46,12 @@ FP32_SOLVE_CASES = [(1, 255, 8, 1, 2), (1, 63, 4, 3, 1), (2, 255, 2, 1, 1), (2, 
 
 @pytest.mark.parametrize("case", FP32_SOLVE_CASES, ids=lambda c: "d{}n{}N{}p{}b{}".format(*c))
 @pytest.mark.parametrize("transpose", [False, True])
-@pytest.mark.parametrize("impl", ["0", "1", "2"], ids=["auto", "lds", "reg"])
+@pytest.mark.parametrize("impl", ["0", "1", "2", "3"], ids=["auto", "lds", "reg", "reg2"])
 def test_fp32_block_solve_families(case, transpose, impl, monkeypatch):
     # Every FP32 transform family (LDS-staged, register-resident with the LDS
-    # re-layout between the time solve and the inverse product) against the
-    # oracle's sparse LU, with the FP32 backward-error bound 8 d n u32 per slab.
+    # re-layout between the time solve and the inverse product, twice folded
+    # where n = 63, 127, 255) against the slab matrix, with the FP32
+    # backward-error bound 8 d n u32 per slab.
     d, n, N, pt, b = case
     print(f"fp32 block solve {case} transpose={transpose} impl={impl}", flush=True)
     monkeypatch.setenv("STMG_TRANSFORM", impl)

@@ -1,12 +1,12 @@
-"""GPU parity of the twice-folded FP64 transforms (n = 63, 127; forced with
-STMG_TRANSFORM=3) against the oracle's exact slab solves and the once-folded
-kernels, through the C ABI."""
+"""GPU parity of the twice-folded transforms (FP64: n = 63, 127; FP32: n = 63,
+127, 255; forced with STMG_TRANSFORM=3) against the oracle's exact slab solves
+and the once-folded kernels, through the C ABI."""
 import numpy as np
 import pytest
 import torch
 
 from gpu_util import DEV, rel_err, to_gpu, to_oracle
-from oracle import multigrid
+from oracle import multigrid, spacetime
 
 pytestmark = pytest.mark.gpu
 
@@ -69,3 +69,47 @@ def test_twice_folded_smoothing_update_modes(monkeypatch):
     S2.smooth(u2, F)
     S1.smooth(u1, F)
     assert ((u2 - u1).abs().max() / u1.abs().max()).item() < 1e-13
+
+
+FP32_CASES = [(1, 63, 8, 1, 2), (1, 255, 4, 1, 1), (2, 63, 4, 1, 1), (2, 127, 4, 1, 2), (2, 255, 2, 2, 1),
+              (2, 127, 2, 3, 1), (2, 63, 2, 0, 1)]
+
+
+@pytest.mark.parametrize("case", FP32_CASES, ids=cid)
+@pytest.mark.parametrize("transpose", [False, True])
+def test_twice_folded_fp32_block_solve(case, transpose, monkeypatch):
+    # FP32 twice-folded slab solves: backward error against the slab matrix
+    # within 8 d n u32 per slab, and agreement with the once-folded FP32
+    # register kernels to the same order
+    print(f"twice folded fp32 block solve {case} transpose={transpose}", flush=True)
+    d, n, N, pt, b = case
+    S2, S1 = solvers(case, monkeypatch, precision="fp32")
+    lev = spacetime.SpaceTimeLevel(d, n, N, pt, 1.0 / N)
+    r = np.random.default_rng(3).uniform(-1, 1, (lev.dof, b)).astype(np.float32).astype(np.float64)
+    x2 = to_oracle(S2.block_solve(to_gpu(r, torch.float32), transpose=transpose), b)
+    x1 = to_oracle(S1.block_solve(to_gpu(r, torch.float32), transpose=transpose), b)
+    A = (lev.A.T if transpose else lev.A).tocsr()
+    normA = abs(A).sum(axis=1).max()
+    xs = x2.reshape(N, lev.slab, b).transpose(1, 0, 2).reshape(lev.slab, -1)
+    rs = r.reshape(N, lev.slab, b).transpose(1, 0, 2).reshape(lev.slab, -1)
+    be = np.abs(A @ xs - rs).max(axis=0) / (normA * np.abs(xs).max(axis=0))
+    assert np.all(be < 8 * d * n * 2.0 ** -24), be.max()
+    assert rel_err(x2, x1) < 64 * d * n * 2.0 ** -24
+
+
+def test_twice_folded_fp32_3d_and_update_modes(monkeypatch):
+    # 3-D FP32 (two x/y passes, fused z pass) and the smoothing update u += omega x,
+    # against the once-folded FP32 register kernels
+    case = (3, 63, 2, 1, 1)
+    S2, S1 = solvers(case, monkeypatch, precision="fp32")
+    rng = np.random.default_rng(7)
+    dof = S2.level_dof(0)
+    u = to_gpu(rng.uniform(-1, 1, (dof, 1)), torch.float32)
+    F = to_gpu(rng.uniform(-1, 1, (dof, 1)), torch.float32)
+    x2 = S2.block_solve(F)
+    x1 = S1.block_solve(F)
+    assert ((x2 - x1).abs().max() / x1.abs().max()).item() < 64 * 3 * 63 * 2.0 ** -24
+    u2, u1 = u.clone(), u.clone()
+    S2.smooth(u2, F)
+    S1.smooth(u1, F)
+    assert ((u2 - u1).abs().max() / u1.abs().max()).item() < 64 * 3 * 63 * 2.0 ** -24
