@@ -201,6 +201,18 @@ def cpu_baseline(budget_s=20.0):
             "host_cpus_available": len(os.sched_getaffinity(0))}
 
 
+TRANSFORM_NAMES = ["default", "lds", "register", "register_twice_folded", "slab_resident"]
+
+
+def tuned_levels(S, tuning):
+    """Per-level kernel families the autotuner picked (all but the coarsest level)."""
+    if tuning is None:
+        return None
+    return [{"level": k, "n": S.levels[k]["n"], "N": S.levels[k]["N"], "small_step": bool(t[0]),
+             "transform": TRANSFORM_NAMES[t[1]], "step_ms": round(t[2], 4)}
+            for k, t in enumerate(tuning[:-1])]
+
+
 def measured_traffic(workload_name, kernel):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     record (FETCH_SIZE / WRITE_SIZE runs, scaled by a device copy of known
@@ -426,11 +438,9 @@ def main():
         "config": {"workload": f"{w['name']}: {d}-D Q1 {n}^{d} interior, N={N} slabs, DG p_t={pt}, "
                                f"batch {b}, FP64, omega=1/2, nu1=nu2=2, schedule {S.schedule}",
                    "dof": dof, "levels": S.nlev, "graph": not args.no_graph,
-                   "autotuned_levels": None if tuning is None else [
-                       {"level": k, "n": S.levels[k]["n"], "N": S.levels[k]["N"], "small_step": bool(t[0]),
-                        "transform": ["default", "lds", "register", "register_twice_folded"][t[1]], "step_ms": round(t[2], 4)}
-                       for k, t in enumerate(tuning[:-1])]},
+                   "autotuned_levels": tuned_levels(S, tuning)},
         "time_to_1e-10": {"fp64_s": t64, "fp64_cycles": its64, "mixed_s": tm, "mixed_cycles": itsm,
+                          "mixed_inner_levels": tuned_levels(S, tuning_mixed),
                           "speedup_mixed_vs_fp64": t64 / tm,
                           "mixed_rel_error_vs_fp64": err_mixed,
                           "fp64_final_relres": hist64[-1][0], "mixed_final_relres": histm[-1][0],

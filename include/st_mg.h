@@ -249,15 +249,18 @@ int st_mg_set_graph(st_mg_t h, int enable);
 /* Autotuner: per level, time one smoothing step with every applicable kernel
  * family (one-kernel small-level step with the slab in LDS; LDS-staged
  * transforms; register-resident transforms, once folded; the default family,
- * which for FP64 at n = 63 and 127 is the twice-folded register transform
- * with half the matrix-core work) and keep the fastest.  With the
- * spatial-cycle smoother the transforms serve only the coarsest level and
- * nothing is tuned.
+ * which at n = 63 and 127 (FP32 also 255) is the twice-folded register
+ * transform with half the matrix-core work; in 2-D with N_t <= 2 at FP64
+ * n = 63 and FP32 n = 63, 127, the slab-resident block solve, one workgroup
+ * per slab running all twice-folded passes from LDS) and keep the fastest.
+ * With the spatial-cycle smoother the transforms serve only the coarsest
+ * level and nothing is tuned.
  * u_scratch, F_scratch: two fine-level device vectors of the handle's vector
  * type whose contents are overwritten (may be NULL for ST_MIXED).  Needs a
  * bound workspace; synchronises the stream. */
 int st_mg_autotune(st_mg_t h, void* u_scratch, void* F_scratch, void* stream);
-/* Choice for one level: small (1/0), transform family (0 default, 1 LDS, 2 register once folded), tuned step ms. */
+/* Choice for one level: small (1/0), transform family (0 default, 1 LDS, 2 register once folded, 3 twice folded,
+ * 4 slab-resident), tuned step ms. */
 int st_mg_level_tuning(st_mg_t h, int level, int* small, int* impl, float* ms);
 
 /* Per-kernel timing with HIP events recorded around every launch on the

@@ -716,6 +716,19 @@ bool bf16_level(const st_mg* h, const Level& L) {
   return sizeof(T) == 4 && h->p.precision == ST_MIXED_BF16 && L.hb <= 8;
 }
 
+// The slab-resident kernel applies to this level (2-D, twice-folded sizes, N_t <= 2, not a BF16 level)
+// and is its chosen family.
+template <typename T>
+bool slab_capable(const st_mg* h, const Level& L) {
+  return !high_order(h) && !bf16_level<T>(h, L) && S2of<T>(L) != nullptr &&
+         slab_solve2_lds(h->p.dim, L.n, h->nt, (int)sizeof(T)) > 0;
+}
+template <typename T>
+bool slab_level(const st_mg* h, const Level& L) {
+  const int impl = L.impl >= 0 ? L.impl : h->impl;
+  return impl == TRANSFORM_SLAB && slab_capable<T>(h, L);
+}
+
 // x = D^{-1} src written into dst with `mode` (store / += omega x / = omega x):
 // folded DST passes along the leading axes, the fused forward/time-solve/inverse
 // pass along the slowest axis, then the inverse passes.  Intermediate data
@@ -738,7 +751,8 @@ int op_block_solve(st_mg* h, int l, bool transpose, const T* src, T* dst, int mo
       HIPCHK(h, launch_pass_bf16(L.hb, inv, (const float*)in, (float*)out, L.S16, n, inner, ncols, (float)om, md, s));
       return ST_OK;
     }
-    const int impl = L.impl >= 0 ? L.impl : h->impl;
+    int impl = L.impl >= 0 ? L.impl : h->impl;
+    if (impl == TRANSFORM_SLAB) impl = TRANSFORM_AUTO;   // levels the slab kernel does not take
     if ((impl == TRANSFORM_REG2 || impl == TRANSFORM_AUTO) && S2of<T>(L)) {
       HIPCHK(h, launch_pass_reg2<T>(n, inv, in, out, S2of<T>(L), inner, ncols, om, md, s));
       return ST_OK;
@@ -755,7 +769,8 @@ int op_block_solve(st_mg* h, int l, bool transpose, const T* src, T* dst, int mo
                                   slabs, transpose ? 1 : 0, (float)om, md, s));
       return ST_OK;
     }
-    const int impl = L.impl >= 0 ? L.impl : h->impl;
+    int impl = L.impl >= 0 ? L.impl : h->impl;
+    if (impl == TRANSFORM_SLAB) impl = TRANSFORM_AUTO;
     if ((impl == TRANSFORM_REG2 || impl == TRANSFORM_AUTO) && S2of<T>(L)) {
       HIPCHK(h, launch_fused_pair2<T>(n, nt, in, out, S2of<T>(L), Gof<T>(L), inner, slabs, transpose ? 1 : 0, om, md,
                                       s));
@@ -765,6 +780,12 @@ int op_block_solve(st_mg* h, int l, bool transpose, const T* src, T* dst, int mo
                                   transpose ? 1 : 0, om, md, s));
     return ST_OK;
   };
+  if (slab_level<T>(h, L)) {
+    ProfScope ps(h, ST_PROF_FUSED, l, s);
+    HIPCHK(h, launch_slab_solve2<T>(n, nt, src, dst, S2of<T>(L), Gof<T>(L), slabs, transpose ? 1 : 0, omega, mode,
+                                    s));
+    return ST_OK;
+  }
   if (high_order(h)) {
     // N_t > NT_MAX: transform every axis, per-mode time solve, inverse transforms
     const T* cur = src;
@@ -1458,6 +1479,7 @@ int tune_level(st_mg* h, int l, T* u, T* F, T* r, T* alt, hipStream_t s) {
     cands.push_back({0, TRANSFORM_AUTO});
     cands.push_back({0, TRANSFORM_REG});
   }
+  if (slab_capable<T>(h, L)) cands.push_back({0, TRANSFORM_SLAB});
   hipEvent_t e0, e1;
   HIPCHK(h, hipEventCreate(&e0));
   HIPCHK(h, hipEventCreate(&e1));
@@ -1862,7 +1884,7 @@ int setup_impl(const st_mg_params* p, st_mg_t* out, const st_mesh* mesh, int ref
   if (const char* sm = std::getenv("STMG_SMALL")) h->small = std::atoi(sm) != 0;
   if (const char* ti = std::getenv("STMG_TRANSFORM")) {
     const int v = std::atoi(ti);
-    h->impl = (v >= TRANSFORM_AUTO && v <= TRANSFORM_REG2) ? v : TRANSFORM_AUTO;
+    h->impl = (v >= TRANSFORM_AUTO && v <= TRANSFORM_SLAB) ? v : TRANSFORM_AUTO;
   }
   time_basis(h);
   {

@@ -69,7 +69,7 @@ unsigned residual_blocks_per_slab(int dim, int n, long long nx, int nt);
 int transform_half_blocks(int n);
 // Transform implementation: automatic choice, LDS-staged kernels only, or the
 // FP64 register-resident kernels wherever their state fits.
-enum { TRANSFORM_AUTO = 0, TRANSFORM_LDS = 1, TRANSFORM_REG = 2, TRANSFORM_REG2 = 3 };
+enum { TRANSFORM_AUTO = 0, TRANSFORM_LDS = 1, TRANSFORM_REG = 2, TRANSFORM_REG2 = 3, TRANSFORM_SLAB = 4 };
 template <typename T>
 hipError_t launch_dst_pass(int impl, int hb, bool xaxis, bool inverse, const T* in, T* out, const T* Sfrag,
                            int n, long long inner, long long ncols, T omega, int mode,
@@ -423,6 +423,13 @@ inline int twice_fold_row(int elem_bytes, int i) { return elem_bytes == 8 ? i : 
 template <typename T>
 hipError_t launch_pass_reg2(int n, bool inverse, const T* in, T* out, const T* Sfrag2, long long inner,
                             long long ncols, T omega, int mode, hipStream_t s);
+// 2-D slab-resident block solve with the twice-folded passes (one workgroup
+// per slab, slab in LDS; FP64 n = 63, FP32 n = 63, 127; N_t <= 2): LDS bytes,
+// 0 when the level does not qualify.
+size_t slab_solve2_lds(int dim, int n, int nt, int elem_bytes);
+template <typename T>
+hipError_t launch_slab_solve2(int n, int nt, const T* src, T* dst, const T* Sfrag2, const T* G, long long slabs,
+                              int transpose, T omega, int mode, hipStream_t s);
 template <typename T>
 hipError_t launch_fused_pair2(int n, int nt, const T* in, T* out, const T* Sfrag2, const T* G, long long inner,
                               long long outer, int transpose, T omega, int mode, hipStream_t s);

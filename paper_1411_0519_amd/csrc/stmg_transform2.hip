@@ -84,8 +84,8 @@ __device__ inline void mma4(const T* __restrict__ Sfrag, int lane, OpFn op,
 // Forward operands of chunk ib for contraction index p = cidx(ib, g): the
 // physical values x_{2p}, x_{2p+1} and their partners x_{n-1-2p}, x_{n-2-2p}.
 // Returns a_{2p}, a_{2p+1}, d_{2p}, d_{2p+1} (d_{h-1} = 0, a_{h-1} = x_{h-1}).
-template <typename T, int HB2>
-__device__ inline void load_twice_folded(const T* __restrict__ src, bool valid, long long inner, int n, int g,
+template <typename T, int HB2, typename I = long long>
+__device__ inline void load_twice_folded(const T* __restrict__ src, bool valid, I inner, int n, int g,
                                          T (&op)[4][4 * HB2]) {
   const int h = (n + 1) >> 1;
 #pragma unroll
@@ -94,10 +94,10 @@ __device__ inline void load_twice_folded(const T* __restrict__ src, bool valid, 
     const int i0 = 2 * p, i1 = 2 * p + 1;
     T x0 = 0, y0 = 0, x1 = 0, y1 = 0;
     if (valid) {
-      x0 = src[(long long)i0 * inner];
-      y0 = src[(long long)(n - 1 - i0) * inner];
-      x1 = src[(long long)i1 * inner];
-      if (i1 < h - 1) y1 = src[(long long)(n - 1 - i1) * inner];
+      x0 = src[(I)i0 * inner];
+      y0 = src[(I)(n - 1 - i0) * inner];
+      x1 = src[(I)i1 * inner];
+      if (i1 < h - 1) y1 = src[(I)(n - 1 - i1) * inner];
     }
     op[0][ib] = x0 + y0;
     op[1][ib] = x1 + y1;
@@ -156,8 +156,8 @@ __device__ inline void zero_old(T (&old)[HB2][4][4]) {
       for (int c = 0; c < 4; ++c) old[kb][j][c] = T(0);
 }
 
-template <typename T, int HB2, bool PRE>
-__device__ inline void store_twice_unfolded(T* __restrict__ dst, bool valid, long long inner, int n, int g,
+template <typename T, int HB2, bool PRE, typename I = long long>
+__device__ inline void store_twice_unfolded(T* __restrict__ dst, bool valid, I inner, int n, int g,
                                             const typename Mfma<T>::acc_t (&acc)[4][HB2], int mode, T omega,
                                             const T (&old)[HB2][4][4]) {
   if (!valid) return;
@@ -173,7 +173,7 @@ __device__ inline void store_twice_unfolded(T* __restrict__ dst, bool valid, lon
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         if (c == 3 && tail) continue;
-        T* q = dst + (long long)pos[c] * inner;
+        T* q = dst + (I)pos[c] * inner;
         const T o = PRE ? old[kb][j][c] : (mode == MODE_ADD_SCALED ? *q : T(0));
         *q = epi<T>(mode, o, v[c], omega);
       }
@@ -321,6 +321,189 @@ __global__ __launch_bounds__(256) void k_fused_pair2(const T* in, T* out, const 
   store_twice_unfolded<T, HB2, false>(out + base, valid, inner, n, g, out_acc, mode, omega, none);
 }
 
+// 2-D slab-resident block solve: one workgroup of 512 threads per slab holds
+// the slab's N_t x n x n values in LDS and runs the forward x pass, the fused
+// y pass with the per-mode solve, and the inverse x pass there, each wave
+// taking groups of 16 lines (x passes) or 16 columns with all N_t components
+// (y pass), so no component exchange is needed; barriers separate the
+// passes.  The slab is read once and written once:
+// dst = epi(mode, dst, D^{-1} src).  src and dst may alias (a workgroup reads
+// its whole slab before it writes).  Dynamic LDS: N_t n^2 elements.
+template <typename T, int HB2, int NT>
+__global__ __launch_bounds__(512) void k_slab_solve2(const T* src, T* dst, const T* __restrict__ Sfrag,
+                                                     const T* __restrict__ G, int n, long long slabs, int transpose,
+                                                     T omega, int mode) {
+  typedef typename Mfma<T>::acc_t acc_t;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  T* R = reinterpret_cast<T*>(lds_raw);
+  const long long slab = slab_index();
+  if (slab >= slabs) return;
+  const int nn = n * n;
+  const int total = NT * nn;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
+  const int h = (n + 1) >> 1;
+  const T* sp = src + slab * (long long)total;
+  T* dp = dst + slab * (long long)total;
+  // ---- slab to LDS, eight loads in flight per thread
+#pragma unroll 1
+  for (int e0 = threadIdx.x; e0 < total; e0 += 512 * 8) {
+    T v[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int e = e0 + 512 * i;
+      v[i] = e < total ? sp[e] : T(0);
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int e = e0 + 512 * i;
+      if (e < total) R[e] = v[i];
+    }
+  }
+  __syncthreads();
+  // ---- forward x pass: line = component * n + y, in place in spectral order
+  const int xgroups = (NT * n + 15) >> 4;
+#pragma unroll 1
+  for (int gi = wave; gi < xgroups; gi += 8) {
+    // an opaque copy of the table pointer: its loads are not hoisted out of the loop and kept live
+    const T* Sf = Sfrag;
+    asm volatile("" : "+s"(Sf));
+    const int line = gi * 16 + r;
+    const bool valid = line < NT * n;
+    T* lp = R + (valid ? line : 0) * n;
+    T op[4][4 * HB2];
+    load_twice_folded<T, HB2, int>(lp, valid, 1, n, g, op);
+    acc_t acc[4][HB2];
+    mma4<T, HB2, 0>(Sf, lane, [&](int m, int ib) { return op[m][ib]; }, acc);
+    if (valid) {
+#pragma unroll
+      for (int kb = 0; kb < HB2; ++kb)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int s = orow(kb, g, j);
+          const T P = acc[0][kb][j], Q = acc[1][kb][j], Pe = acc[2][kb][j], Qe = acc[3][kb][j];
+          lp[s] = P + Q;
+          lp[h - 1 - s] = P - Q;
+          lp[h + s] = Pe + Qe;
+          if (s != h / 2 - 1) lp[h + h - 2 - s] = Pe - Qe;
+        }
+    }
+  }
+  __syncthreads();
+  // ---- y pass: column c (spectral x index) of every component, forward,
+  // per-mode N_t x N_t solve, inverse, in place
+  const int ygroups = (n + 15) >> 4;
+#pragma unroll 1
+  for (int gi = wave; gi < ygroups; gi += 8) {
+    const T* Sf = Sfrag;
+    asm volatile("" : "+s"(Sf));
+    const int col = gi * 16 + r;
+    const bool valid = col < n;
+    const int cc = valid ? col : 0;
+    acc_t acc[NT][4][HB2];
+#pragma unroll
+    for (int l = 0; l < NT; ++l) {
+      T op[4][4 * HB2];
+      load_twice_folded<T, HB2, int>(R + l * nn + cc, valid, n, n, g, op);
+      mma4<T, HB2, 0>(Sf, lane, [&](int m, int ib) { return op[m][ib]; }, acc[l]);
+      __builtin_amdgcn_sched_barrier(0);   // one component's operands live at a time
+    }
+    // per (kb, j): the four modes s, h-1-s, h+s, h+(h-2-s) of every component
+#pragma unroll
+    for (int kb = 0; kb < HB2; ++kb)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int s = orow(kb, g, j);
+        const bool middle = s == h / 2 - 1;
+        const int mode_idx[4] = {s, h - 1 - s, h + s, h + (middle ? s : h - 2 - s)};
+        T v[NT][4];
+#pragma unroll
+        for (int l = 0; l < NT; ++l) {
+          const T P = acc[l][0][kb][j], Q = acc[l][1][kb][j], Pe = acc[l][2][kb][j], Qe = acc[l][3][kb][j];
+          v[l][0] = P + Q;
+          v[l][1] = P - Q;
+          v[l][2] = Pe + Qe;
+          v[l][3] = Pe - Qe;
+        }
+#pragma unroll
+        for (int l = 0; l < NT; ++l) {
+          T y[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            T a = T(0);
+            if (valid) {
+              const T* gm = G + (cc + n * mode_idx[q]) * (NT * NT);
+#pragma unroll
+              for (int m = 0; m < NT; ++m) a += (transpose ? gm[m * NT + l] : gm[l * NT + m]) * v[m][q];
+            }
+            y[q] = a;
+          }
+          T u0, u1, u2, u3;
+          inverse_operands<T>(y[0], y[1], y[2], y[3], middle, u0, u1, u2, u3);
+          acc[l][0][kb][j] = u0;   // the operand of chunk 4 kb + j, kept in place
+          acc[l][1][kb][j] = u1;
+          acc[l][2][kb][j] = u2;
+          acc[l][3][kb][j] = u3;
+        }
+        // keeps the compiler from hoisting every row's block loads (register spills)
+        __builtin_amdgcn_sched_barrier(0);
+      }
+#pragma unroll
+    for (int l = 0; l < NT; ++l) {
+      acc_t out_acc[4][HB2];
+      mma4<T, HB2, 1>(Sf, lane, [&](int m, int ib) { return (T)acc[l][m][ib >> 2][ib & 3]; }, out_acc);
+      T none[HB2][4][4];
+      zero_old<T, HB2>(none);
+      store_twice_unfolded<T, HB2, false, int>(R + l * nn + cc, valid, n, n, g, out_acc, MODE_STORE, T(1), none);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  __syncthreads();
+  // ---- inverse x pass, in place in physical order
+#pragma unroll 1
+  for (int gi = wave; gi < xgroups; gi += 8) {
+    const T* Sf = Sfrag;
+    asm volatile("" : "+s"(Sf));
+    const int line = gi * 16 + r;
+    const bool valid = line < NT * n;
+    T* lp = R + (valid ? line : 0) * n;
+    T op[4][4 * HB2];
+#pragma unroll
+    for (int ib = 0; ib < 4 * HB2; ++ib) {
+      const int s = cidx(ib, g);
+      const bool middle = s == h / 2 - 1;
+      T yo = 0, yom = 0, ye = 0, yem = 0;
+      if (valid) {
+        yo = lp[s];
+        yom = lp[h - 1 - s];
+        ye = lp[h + s];
+        if (!middle) yem = lp[h + h - 2 - s];
+      }
+      inverse_operands<T>(yo, yom, ye, yem, middle, op[0][ib], op[1][ib], op[2][ib], op[3][ib]);
+    }
+    acc_t acc[4][HB2];
+    mma4<T, HB2, 1>(Sf, lane, [&](int m, int ib) { return op[m][ib]; }, acc);
+    T none[HB2][4][4];
+    zero_old<T, HB2>(none);
+    store_twice_unfolded<T, HB2, false, int>(lp, valid, 1, n, g, acc, MODE_STORE, T(1), none);
+  }
+  __syncthreads();
+  // ---- result to dst
+#pragma unroll 1
+  for (int e0 = threadIdx.x; e0 < total; e0 += 512 * 8) {
+    T old[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int e = e0 + 512 * i;
+      old[i] = (e < total && mode == MODE_ADD_SCALED) ? dp[e] : T(0);
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int e = e0 + 512 * i;
+      if (e < total) dp[e] = epi<T>(mode, old[i], R[e], omega);
+    }
+  }
+}
+
 }  // namespace
 
 bool twice_folded_ok(int n, int elem_bytes) {
@@ -381,6 +564,39 @@ hipError_t launch_fused_pair2(int n, int nt, const T* in, T* out, const T* Sfrag
   return hipErrorInvalidValue;
 }
 
+size_t slab_solve2_lds(int dim, int n, int nt, int elem_bytes) {
+  if (dim != 2 || nt < 1 || nt > 2 || !twice_folded_ok(n, elem_bytes) || n > 127) return 0;
+  const size_t bytes = (size_t)nt * n * n * elem_bytes;
+  return bytes <= 160 * 1024 ? bytes : 0;
+}
+
+template <typename T>
+hipError_t launch_slab_solve2(int n, int nt, const T* src, T* dst, const T* Sfrag2, const T* G, long long slabs,
+                              int transpose, T omega, int mode, hipStream_t s) {
+  const size_t lds = slab_solve2_lds(2, n, nt, (int)sizeof(T));
+  if (lds == 0) return hipErrorInvalidValue;
+  const dim3 grid = slab_grid(1, slabs);
+#define SL2(HB2, NT)                                                                                         \
+  if (nt == NT) {                                                                                            \
+    const void* fn = reinterpret_cast<const void*>(&k_slab_solve2<T, HB2, NT>);                              \
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);            \
+    if (e != hipSuccess) return e;                                                                           \
+    hipLaunchKernelGGL((k_slab_solve2<T, HB2, NT>), grid, dim3(512), lds, s, src, dst, Sfrag2, G, n, slabs,    \
+                       transpose, omega, mode);                                                              \
+    return hipGetLastError();                                                                                \
+  }
+  if (n == 63) { SL2(1, 1) SL2(1, 2) }
+  if constexpr (sizeof(T) == 4) {
+    if (n == 127) { SL2(2, 1) SL2(2, 2) }
+  }
+#undef SL2
+  return hipErrorInvalidValue;
+}
+
+template hipError_t launch_slab_solve2<double>(int, int, const double*, double*, const double*, const double*,
+                                               long long, int, double, int, hipStream_t);
+template hipError_t launch_slab_solve2<float>(int, int, const float*, float*, const float*, const float*, long long,
+                                              int, float, int, hipStream_t);
 template hipError_t launch_pass_reg2<double>(int, bool, const double*, double*, const double*, long long, long long,
                                              double, int, hipStream_t);
 template hipError_t launch_pass_reg2<float>(int, bool, const float*, float*, const float*, long long, long long,

@@ -113,3 +113,87 @@ def test_twice_folded_fp32_3d_and_update_modes(monkeypatch):
     S2.smooth(u2, F)
     S1.smooth(u1, F)
     assert ((u2 - u1).abs().max() / u1.abs().max()).item() < 64 * 3 * 63 * 2.0 ** -24
+
+
+# Slab-resident block solve (STMG_TRANSFORM=4): 2-D, FP64 n = 63, FP32 n = 63, 127, N_t <= 2
+SLAB_CASES = [(2, 63, 4, 1, 1), (2, 63, 2, 0, 2), (2, 127, 2, 1, 1), (2, 127, 4, 0, 1), (2, 63, 8, 1, 2)]
+
+
+def slab_solvers(case, monkeypatch, **kw):
+    d, n, N, pt, b = case
+    monkeypatch.setenv("STMG_TRANSFORM", "4")
+    S4 = stmg.Solver(d, n, N, pt=pt, batch=b, device=DEV, **kw)
+    monkeypatch.setenv("STMG_TRANSFORM", "2")
+    S1 = stmg.Solver(d, n, N, pt=pt, batch=b, device=DEV, **kw)
+    monkeypatch.delenv("STMG_TRANSFORM")
+    return S4, S1
+
+
+@pytest.mark.parametrize("case", [c for c in SLAB_CASES if c[1] == 63], ids=cid)
+@pytest.mark.parametrize("transpose", [False, True])
+def test_slab_block_solve_fp64(case, transpose, monkeypatch):
+    print(f"slab block solve fp64 {case} transpose={transpose}", flush=True)
+    d, n, N, pt, b = case
+    S4, S1 = slab_solvers(case, monkeypatch)
+    r = np.random.default_rng(11).uniform(-1, 1, (S4.level_dof(0) // b, b))
+    x4 = S4.block_solve(to_gpu(r), transpose=transpose)
+    x1 = S1.block_solve(to_gpu(r), transpose=transpose)
+    assert rel_err(to_oracle(x4, b), to_oracle(x1, b)) < 1e-13
+    H = multigrid.Hierarchy(d, n, N, pt, transpose=transpose)
+    assert rel_err(to_oracle(x4, b), H.block_solve(len(H.levels) - 1, r)) < 1e-12
+
+
+@pytest.mark.parametrize("case", SLAB_CASES, ids=cid)
+@pytest.mark.parametrize("transpose", [False, True])
+def test_slab_block_solve_fp32(case, transpose, monkeypatch):
+    print(f"slab block solve fp32 {case} transpose={transpose}", flush=True)
+    d, n, N, pt, b = case
+    S4, S1 = slab_solvers(case, monkeypatch, precision="fp32")
+    lev = spacetime.SpaceTimeLevel(d, n, N, pt, 1.0 / N)
+    r = np.random.default_rng(13).uniform(-1, 1, (lev.dof, b)).astype(np.float32).astype(np.float64)
+    x4 = to_oracle(S4.block_solve(to_gpu(r, torch.float32), transpose=transpose), b)
+    x1 = to_oracle(S1.block_solve(to_gpu(r, torch.float32), transpose=transpose), b)
+    A = (lev.A.T if transpose else lev.A).tocsr()
+    normA = abs(A).sum(axis=1).max()
+    xs = x4.reshape(N, lev.slab, b).transpose(1, 0, 2).reshape(lev.slab, -1)
+    rs = r.reshape(N, lev.slab, b).transpose(1, 0, 2).reshape(lev.slab, -1)
+    be = np.abs(A @ xs - rs).max(axis=0) / (normA * np.abs(xs).max(axis=0))
+    assert np.all(be < 8 * d * n * 2.0 ** -24), be.max()
+    assert rel_err(x4, x1) < 64 * d * n * 2.0 ** -24
+
+
+def test_slab_smoothing_and_iterates(monkeypatch):
+    # the slab kernel inside smoothing steps (u += omega D^{-1} r) and in whole V-cycles on
+    # 63^2 x 16 (level 0 slab-resident, coarser levels the default family): oracle iterates to 1e-12
+    case = (2, 63, 16, 1, 1)
+    d, n, N, pt, b = case
+    S4, S1 = slab_solvers(case, monkeypatch)
+    rng = np.random.default_rng(17)
+    u = to_gpu(rng.uniform(-1, 1, (S4.level_dof(0), 1)))
+    F = to_gpu(rng.uniform(-1, 1, (S4.level_dof(0), 1)))
+    u4, u1 = u.clone(), u.clone()
+    S4.smooth(u4, F)
+    S1.smooth(u1, F)
+    assert ((u4 - u1).abs().max() / u1.abs().max()).item() < 1e-13
+    H = multigrid.Hierarchy(d, n, N, pt)
+    Fo = np.random.default_rng(5).uniform(-1, 1, (H.fine.dof, b))
+    _, _, its = H.solve(Fo, rtol=0.0, maxit=3, keep_iterates=True)
+    uu = torch.zeros(S4.level_dof(0), dtype=torch.float64, device=DEV)
+    for k in range(1, 4):
+        S4.solve(to_gpu(Fo), u=uu, rtol=0.0, maxit=1, raise_on_noconv=False)
+        assert rel_err(to_oracle(uu, b), its[k]) < 1e-12, k
+
+
+def test_slab_mixed_reaches_fp64_tolerance(monkeypatch):
+    # mixed precision with every qualifying FP32 level slab-resident: same 1e-10 as FP64
+    d, n, N, pt = 2, 127, 16, 1
+    monkeypatch.setenv("STMG_TRANSFORM", "4")
+    M = stmg.Solver(d, n, N, pt=pt, device=DEV, precision="mixed")
+    monkeypatch.delenv("STMG_TRANSFORM")
+    S = stmg.Solver(d, n, N, pt=pt, device=DEV)
+    F = to_gpu(np.random.default_rng(19).uniform(-1, 1, (S.level_dof(0), 1)))
+    u64, it64, _ = S.solve(F, rtol=1e-10, maxit=60)
+    um, itm, hist = M.solve(F, rtol=1e-10, maxit=60)
+    assert hist[-1][0] < 1e-10
+    assert abs(itm - it64) <= 2
+    assert (torch.linalg.vector_norm(um - u64) / torch.linalg.vector_norm(u64)).item() < 1e-8
