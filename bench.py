@@ -201,7 +201,8 @@ def cpu_baseline(budget_s=20.0):
             "host_cpus_available": len(os.sched_getaffinity(0))}
 
 
-TRANSFORM_NAMES = ["default", "lds", "register", "register_twice_folded", "slab_resident"]
+TRANSFORM_NAMES = ["default", "lds", "register", "register_twice_folded", "slab_resident",
+                   "twice_folded_residual_fused"]
 
 
 def tuned_levels(S, tuning):
@@ -330,7 +331,7 @@ def main():
         S.profile_start()
         S.solve(F, u=u2, rtol=0.0, maxit=args.steps, raise_on_noconv=False)
         torch.cuda.synchronize()
-        kinds = ["residual", "pass_fwd", "pass_inv", "fused", "small", "restrict", "prolong", "other"]
+        kinds = ["residual", "resid_x", "pass_fwd", "pass_inv", "fused", "small", "restrict", "prolong", "other"]
         prof = {}
         for k in kinds:
             tot, cnt = S.profile_read(k, level=-1)
@@ -421,6 +422,8 @@ def main():
     res_avg = r0["fine_ms_total"] / max(r0["fine_launches"], 1)
     res_bytes = 3 * 8 * nvals                           # read u, F; write r
     res_gbs = res_bytes / (res_avg * 1e-3) / 1e9
+    rx0 = prof["resid_x"]                               # read u, F; write the x-transformed residual
+    rx_avg = rx0["fine_ms_total"] / rx0["fine_launches"] if rx0["fine_launches"] > 0 else None
     total_prof = sum(v["ms_total"] for v in prof.values())
     out = {
         "metric": "space-time DoF*V-cycles/s (+ time-to-1e-10, mixed vs FP64)",
@@ -447,9 +450,15 @@ def main():
                           "mixed_bf16_s": tb, "mixed_bf16_cycles": itsb, "speedup_mixed_bf16_vs_fp64": t64 / tb,
                           "mixed_bf16_rel_error_vs_fp64": err_bf16, "mixed_bf16_final_relres": histb[-1][0]},
         "roofline": roof,
-        "residual_kernel": {"bound": "hbm", "achieved": res_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "residual_kernel": {"kernel": "k_residual_tile2d (fine level: residual norms and restriction)",
+                            "bound": "hbm", "achieved": res_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                             "frac": res_gbs / HBM_PEAK_GBS, "avg_launch_ms": res_avg,
-                            "bytes_per_launch": res_bytes},
+                            "launches": r0["fine_launches"], "bytes_per_launch": res_bytes},
+        "residual_xfwd_kernel": None if rx_avg is None else {
+            "kernel": "k_resid_xfwd (fine level: residual fused with the forward x pass, smoothing steps)",
+            "bound": "hbm", "achieved": res_bytes / (rx_avg * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": res_bytes / (rx_avg * 1e-3) / 1e9 / HBM_PEAK_GBS, "avg_launch_ms": rx_avg,
+            "launches": prof["resid_x"]["fine_launches"], "bytes_per_launch": res_bytes},
         "kernel_breakdown_ms_per_step": {k: v["ms_total"] / args.steps for k, v in prof.items()},
         "profiled_ms_per_step": total_prof / args.steps,
     }

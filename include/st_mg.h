@@ -252,7 +252,8 @@ int st_mg_set_graph(st_mg_t h, int enable);
  * which at n = 63 and 127 (FP32 also 255) is the twice-folded register
  * transform with half the matrix-core work; in 2-D with N_t <= 2 at FP64
  * n = 63 and FP32 n = 63, 127, the slab-resident block solve, one workgroup
- * per slab running all twice-folded passes from LDS) and keep the fastest.
+ * per slab running all twice-folded passes from LDS; in 2-D with N_t = 2 at n = 63, 127, the residual fused
+ * with the forward twice-folded x pass) and keep the fastest.
  * With the spatial-cycle smoother the transforms serve only the coarsest
  * level and nothing is tuned.
  * u_scratch, F_scratch: two fine-level device vectors of the handle's vector
@@ -260,7 +261,7 @@ int st_mg_set_graph(st_mg_t h, int enable);
  * bound workspace; synchronises the stream. */
 int st_mg_autotune(st_mg_t h, void* u_scratch, void* F_scratch, void* stream);
 /* Choice for one level: small (1/0), transform family (0 default, 1 LDS, 2 register once folded, 3 twice folded,
- * 4 slab-resident), tuned step ms. */
+ * 4 slab-resident, 5 twice folded with the residual fused into the forward x pass), tuned step ms. */
 int st_mg_level_tuning(st_mg_t h, int level, int* small, int* impl, float* ms);
 
 /* Per-kernel timing with HIP events recorded around every launch on the
@@ -277,7 +278,8 @@ enum {
   ST_PROF_RESTRICT = 5, ST_PROF_PROLONG = 6, ST_PROF_OTHER = 7,
   ST_PROF_JACOBI = 8,     /* spatial cycle: block-Jacobi steps and defects        */
   ST_PROF_XFER_X = 9,     /* spatial cycle: restriction / prolongation in space   */
-  ST_PROF_KINDS = 10
+  ST_PROF_RESID_X = 10,   /* residual fused with the forward x pass               */
+  ST_PROF_KINDS = 11
 };
 int st_mg_profile_start(st_mg_t h);
 int st_mg_profile_stop(st_mg_t h);

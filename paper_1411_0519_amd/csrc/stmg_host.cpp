@@ -116,6 +116,7 @@ struct Level {
   float* Sp32 = nullptr;
   int impl = -1;          // transform family chosen for this level (-1: handle default)
   int small = -1;         // small-level smoother on (1) / off (0) for this level (-1: handle default)
+  int rx = -1;            // residual fused with the forward x pass (1) / separate (0) (-1: handle default)
   float tuned_ms = 0.f;   // autotuned smoothing-step time
   void* u = nullptr;      // workspace vectors (inner precision), coarse levels only
   void* u2 = nullptr;     // second iterate buffer for the small-level smoother
@@ -211,6 +212,7 @@ struct st_mg {
   int graph = 0;
   int impl = TRANSFORM_AUTO;
   bool small = true;      // one-kernel smoothing steps on levels whose slabs fit in LDS
+  bool rx = false;        // residual fused with the forward x pass where it applies (autotuned per level)
   // coarse end of every cycle in one workgroup from level `tail` down (-1: off);
   // argument blocks in device memory for the forward and the adjoint cycle
   int tail = -1;
@@ -735,7 +737,7 @@ bool slab_level(const st_mg* h, const Level& L) {
 // alternate between the buffers A and B; src is only read.
 template <typename T>
 int op_block_solve(st_mg* h, int l, bool transpose, const T* src, T* dst, int mode, T omega, T* A,
-                   T* B, hipStream_t s) {
+                   T* B, hipStream_t s, bool x_done = false) {
   const Level& L = h->lv[l];
   const int d = h->p.dim, n = L.n, nt = h->nt;
   const long long slabs = (long long)h->p.batch * L.N;
@@ -811,7 +813,8 @@ int op_block_solve(st_mg* h, int l, bool transpose, const T* src, T* dst, int mo
   }
   if (d == 1) return fused(src, dst, mode, omega);
   if (d == 2) {
-    CHK(pass(0, false, src, A, MODE_STORE, T(1)));
+    // x_done: src already holds the forward x pass of the right-hand side, in A
+    if (!x_done) CHK(pass(0, false, src, A, MODE_STORE, T(1)));
     CHK(fused(A, A, MODE_STORE, T(1)));
     return pass(0, true, A, dst, mode, omega);
   }
@@ -1198,6 +1201,35 @@ int coarsest_solve<float>(st_mg* h, bool transpose, float* u, const float* F, hi
 template <typename T>
 int vcycle(st_mg* h, int l, bool transpose, T* u, const T* F, bool u_zero, bool r_ready, hipStream_t s);
 
+// The residual of this level is fused with the forward x pass of the block solve: 2-D, N_t = 2, the twice-folded
+// family (n = 63, 127), exact smoother, and chosen for the level.
+template <typename T>
+bool rx_level(const st_mg* h, int l) {
+  const Level& L = h->lv[l];
+  if (h->mesh || inexact_level(h, l) || high_order(h) || bf16_level<T>(h, L) || slab_level<T>(h, L)) return false;
+  const int impl = L.impl >= 0 ? L.impl : h->impl;
+  if (impl != TRANSFORM_AUTO && impl != TRANSFORM_REG2) return false;
+  const bool on = L.rx >= 0 ? L.rx != 0 : h->rx;
+  return on && S2of<T>(L) != nullptr && resid_xfwd_ok(h->p.dim, L.n, h->nt, (int)sizeof(T));
+}
+
+// One damped block-Jacobi step u += omega D^{-1}(F - L u) on level l (r and A are scratch).
+template <typename T>
+int smooth_step(st_mg* h, int l, bool transpose, T* u, const T* F, T* r, T* A, hipStream_t s) {
+  const T om = (T)h->p.omega;
+  if (rx_level<T>(h, l)) {
+    const Level& L = h->lv[l];
+    const ResidArgs<T> a = resid_args<T>(h, L, transpose);
+    {
+      ProfScope ps(h, ST_PROF_RESID_X, l, s);
+      HIPCHK(h, launch_resid_xfwd<T>(L.n, u, F, A, a, S2of<T>(L), s));
+    }
+    return op_block_solve<T>(h, l, transpose, A, u, MODE_ADD_SCALED, om, A, r, s, true);
+  }
+  CHK((op_residual<T, T>(h, l, transpose, u, F, r, false, s)));
+  return op_smoother_solve<T>(h, l, transpose, r, u, MODE_ADD_SCALED, om, A, r, s);
+}
+
 // V-cycle on a small level: each smoothing step is one kernel that reads one
 // iterate buffer and writes the other (level 0 borrows the transform buffer);
 // the result is copied back when the step count leaves it in the other buffer.
@@ -1255,9 +1287,10 @@ int vcycle(st_mg* h, int l, bool transpose, T* u, const T* F, bool u_zero, bool 
   for (int i = 0; i < h->p.nu1; ++i) {
     if (i == 0 && u_zero) {
       CHK(op_smoother_solve<T>(h, l, transpose, F, u, MODE_SET_SCALED, om, A, r, s));
-    } else {
-      if (!(i == 0 && r_ready)) CHK((op_residual<T, T>(h, l, transpose, u, F, r, false, s)));
+    } else if (i == 0 && r_ready) {
       CHK(op_smoother_solve<T>(h, l, transpose, r, u, MODE_ADD_SCALED, om, A, r, s));
+    } else {
+      CHK(smooth_step<T>(h, l, transpose, u, F, r, A, s));
     }
   }
   const Level& C = h->lv[l + 1];
@@ -1277,10 +1310,7 @@ int vcycle(st_mg* h, int l, bool transpose, T* u, const T* F, bool u_zero, bool 
     HIPCHK(h, launch_fill<T>(u, len, s));
   }
   CHK(op_prolong<T>(h, l, uc, u, s));
-  for (int i = 0; i < h->p.nu2; ++i) {
-    CHK((op_residual<T, T>(h, l, transpose, u, F, r, false, s)));
-    CHK(op_smoother_solve<T>(h, l, transpose, r, u, MODE_ADD_SCALED, om, A, r, s));
-  }
+  for (int i = 0; i < h->p.nu2; ++i) CHK(smooth_step<T>(h, l, transpose, u, F, r, A, s));
   return ST_OK;
 }
 
@@ -1467,19 +1497,21 @@ int tune_level(st_mg* h, int l, T* u, T* F, T* r, T* alt, hipStream_t s) {
   const long long len = L.dof(h->nt, h->p.batch);
   HIPCHK(h, launch_fill<T>(u, len, s));
   HIPCHK(h, launch_fill<T>(F, len, s));
-  struct Cand { int small, impl; };
+  struct Cand { int small, impl, rx; };
   std::vector<Cand> cands;
   const bool can_small = !high_order(h) && smooth_small_lds(h->p.dim, L.n, L.nx, h->nt, sizeof(T)) > 0;
-  if (can_small) cands.push_back({1, TRANSFORM_AUTO});
-  cands.push_back({0, TRANSFORM_LDS});
+  if (can_small) cands.push_back({1, TRANSFORM_AUTO, 0});
+  cands.push_back({0, TRANSFORM_LDS, 0});
   if (sizeof(T) == 8 && L.hb <= 4) {
-    cands.push_back({0, TRANSFORM_AUTO});
-    cands.push_back({0, TRANSFORM_REG});   // AUTO is the twice-folded family where it exists
+    cands.push_back({0, TRANSFORM_AUTO, 0});
+    cands.push_back({0, TRANSFORM_REG, 0});   // AUTO is the twice-folded family where it exists
   } else if (sizeof(T) == 4 && L.hb <= 8) {
-    cands.push_back({0, TRANSFORM_AUTO});
-    cands.push_back({0, TRANSFORM_REG});
+    cands.push_back({0, TRANSFORM_AUTO, 0});
+    cands.push_back({0, TRANSFORM_REG, 0});
   }
-  if (slab_capable<T>(h, L)) cands.push_back({0, TRANSFORM_SLAB});
+  if (slab_capable<T>(h, L)) cands.push_back({0, TRANSFORM_SLAB, 0});
+  if (!high_order(h) && !bf16_level<T>(h, L) && S2of<T>(L) && resid_xfwd_ok(h->p.dim, L.n, h->nt, (int)sizeof(T)))
+    cands.push_back({0, TRANSFORM_AUTO, 1});
   hipEvent_t e0, e1;
   HIPCHK(h, hipEventCreate(&e0));
   HIPCHK(h, hipEventCreate(&e1));
@@ -1490,10 +1522,10 @@ int tune_level(st_mg* h, int l, T* u, T* F, T* r, T* alt, hipStream_t s) {
   for (const Cand& c : cands) {
     L.small = c.small;
     L.impl = c.impl;
+    L.rx = c.rx;
     auto step = [&]() -> int {
       if (c.small) return op_smooth_small<T>(h, l, false, u, alt, F, false, s);
-      CHK((op_residual<T, T>(h, l, false, u, F, r, false, s)));
-      return op_block_solve<T>(h, l, false, r, u, MODE_ADD_SCALED, (T)h->p.omega, (T*)h->tmp, r, s);
+      return smooth_step<T>(h, l, false, u, F, r, (T*)h->tmp, s);
     };
     int rc = step();
     float ms = 1e30f;
@@ -1523,6 +1555,7 @@ int tune_level(st_mg* h, int l, T* u, T* F, T* r, T* alt, hipStream_t s) {
   (void)hipEventDestroy(e1);
   L.small = pick.small;
   L.impl = pick.impl;
+  L.rx = pick.rx;
   L.tuned_ms = best;
   return ST_OK;
 }
@@ -1882,6 +1915,7 @@ int setup_impl(const st_mg_params* p, st_mg_t* out, const st_mesh* mesh, int ref
   // tuning knob: STMG_TRANSFORM=1 forces the LDS-staged transforms, =2 the register ones
   // tuning knob: STMG_SMALL=0 turns the one-kernel small-level smoother off
   if (const char* sm = std::getenv("STMG_SMALL")) h->small = std::atoi(sm) != 0;
+  if (const char* rx = std::getenv("STMG_RX")) h->rx = std::atoi(rx) != 0;
   if (const char* ti = std::getenv("STMG_TRANSFORM")) {
     const int v = std::atoi(ti);
     h->impl = (v >= TRANSFORM_AUTO && v <= TRANSFORM_SLAB) ? v : TRANSFORM_AUTO;
@@ -2238,16 +2272,11 @@ int st_mg_smooth(st_mg_t h, int level, int prec, int transpose, void* u, const v
   CHK(check_level(h, level, prec, false));
   if (!u || !F) return fail(h, ST_EINVAL, "null vector");
   hipStream_t s = (hipStream_t)stream;
-  if (prec == ST_FP64) {
-    double* r = level_r<double>(h, level);
-    CHK((op_residual<double, double>(h, level, transpose != 0, (const double*)u, (const double*)F, r, false, s)));
-    return op_smoother_solve<double>(h, level, transpose != 0, r, (double*)u, MODE_ADD_SCALED, h->p.omega,
-                                     (double*)h->tmp, r, s);
-  }
-  float* r = level_r<float>(h, level);
-  CHK((op_residual<float, float>(h, level, transpose != 0, (const float*)u, (const float*)F, r, false, s)));
-  return op_smoother_solve<float>(h, level, transpose != 0, r, (float*)u, MODE_ADD_SCALED, (float)h->p.omega,
-                                  (float*)h->tmp, r, s);
+  if (prec == ST_FP64)
+    return smooth_step<double>(h, level, transpose != 0, (double*)u, (const double*)F, level_r<double>(h, level),
+                               (double*)h->tmp, s);
+  return smooth_step<float>(h, level, transpose != 0, (float*)u, (const float*)F, level_r<float>(h, level),
+                            (float*)h->tmp, s);
 }
 
 int st_mg_restrict(st_mg_t h, int level, int prec, const void* r_fine, void* F_coarse, void* stream) {
@@ -2332,7 +2361,7 @@ int st_mg_level_tuning(st_mg_t h, int level, int* small, int* impl, float* ms) {
   if (!h || level < 0 || level >= (int)h->lv.size()) return ST_EINVAL;
   const Level& L = h->lv[level];
   if (small) *small = L.small >= 0 ? L.small : (h->small ? 1 : 0);
-  if (impl) *impl = L.impl >= 0 ? L.impl : h->impl;
+  if (impl) *impl = L.rx == 1 ? 5 : (L.impl >= 0 ? L.impl : h->impl);   // 5: twice folded, residual fused in
   if (ms) *ms = L.tuned_ms;
   return ST_OK;
 }

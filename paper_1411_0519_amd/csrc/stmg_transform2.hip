@@ -27,6 +27,8 @@
 // registers), and the four lane groups of a line touch neighbouring elements.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "stmg_device.h"
 #include "stmg_internal.h"
 
@@ -78,6 +80,24 @@ __device__ inline void mma4(const T* __restrict__ Sfrag, int lane, OpFn op,
       for (int kb = 0; kb < HB2; ++kb) acc[m][kb] = Mfma<T>::op(af[m][kb], b, acc[m][kb]);
     }
     __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// acc[kb] = sum over chunks ib of A(dir, mat, kb, ib) * B(ib): one of the four
+// products of mma4.
+template <typename T, int HB2, int DIR, typename OpFn>
+__device__ inline void mma1(const T* __restrict__ Sfrag, int lane, int mat, OpFn op,
+                            typename Mfma<T>::acc_t (&acc)[HB2]) {
+  typedef typename Mfma<T>::acc_t acc_t;
+  constexpr int NC = 4 * HB2;
+#pragma unroll
+  for (int kb = 0; kb < HB2; ++kb) acc[kb] = acc_t{0, 0, 0, 0};
+  const T* s = Sfrag + (size_t)DIR * 4 * HB2 * NC * 64 + (size_t)mat * HB2 * NC * 64 + lane;
+#pragma unroll
+  for (int ib = 0; ib < NC; ++ib) {
+    const T b = op(ib);
+#pragma unroll
+    for (int kb = 0; kb < HB2; ++kb) acc[kb] = Mfma<T>::op(s[(kb * NC + ib) * 64], b, acc[kb]);
   }
 }
 
@@ -504,6 +524,168 @@ __global__ __launch_bounds__(512) void k_slab_solve2(const T* src, T* dst, const
   }
 }
 
+// 2-D residual fused with the forward x pass (N_t = 2): a workgroup owns one
+// slab and 8 rows, stages rows y0-1 .. y0+8 of u and of the coupling
+// combination of the neighbouring slab in LDS (every global load issued
+// first), forms r = F - L u in registers, puts its 16 lines (2 components x 8
+// rows) back into LDS, and the four waves each run one of the four twice-
+// folded products (O and E on even and odd inputs) on those 16 lines; the
+// sums and differences of their results are the spectral x lines, stored to
+// xhat in the layout of r.  The residual itself never reaches HBM.
+// Dynamic LDS: max(3 (TY + 2) n, 2 TY n + 4 * 16 * 16 HB2) elements.
+template <typename T, int HB2, int SIT>
+__global__ __launch_bounds__(256) void k_resid_xfwd(const T* __restrict__ u, const T* __restrict__ F,
+                                                    T* __restrict__ xhat, ResidArgs<T> a,
+                                                    const T* __restrict__ Sfrag) {
+  constexpr int NT = 2, TY = 8;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  T* U = reinterpret_cast<T*>(lds_raw);
+  const long long lg = xcd_linear(blockIdx.x + (long long)gridDim.x * slab_index(),
+                                  (long long)gridDim.x * gridDim.y * gridDim.z);
+  const long long slab = lg / gridDim.x;
+  const int tile = (int)(lg - slab * gridDim.x);
+  const long long nslab = (long long)a.batch * a.N;
+  if (slab >= nslab) return;
+  const int n = a.n;
+  const long long nx = a.nx;
+  const int h = (n + 1) >> 1;
+  const int y0 = tile * TY;
+  const int plane = (TY + 2) * n;
+  const int rows = (y0 + TY < n ? y0 + TY : n) - y0;
+  const int nout = rows * n;
+  const int sn = (int)(slab % a.N);
+  const bool couple = (sn + a.dir >= 0) && (sn + a.dir < a.N);
+  const long long slabsz = (long long)NT * nx;
+  const T* un = u + slab * slabsz;
+  const T* up = u + (slab + a.dir) * slabsz;
+  const T* Fn = F + slab * slabsz;
+  const long long s0 = (long long)(y0 - 1) * n;
+  const long long o0 = (long long)y0 * n;
+  T fv[SIT][NT], uv[SIT][NT], pv[SIT][NT];
+#pragma unroll
+  for (int i = 0; i < SIT; ++i) {
+    const int e = threadIdx.x + 256 * i;
+    const long long so = s0 + e;
+    const bool in = e < plane && so >= 0 && so < nx;
+#pragma unroll
+    for (int k = 0; k < NT; ++k) {
+      uv[i][k] = in ? un[k * nx + so] : T(0);
+      pv[i][k] = (in && couple) ? up[k * nx + so] : T(0);
+      fv[i][k] = e < nout ? Fn[k * nx + o0 + e] : T(0);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < SIT; ++i) {
+    const int e = threadIdx.x + 256 * i;
+    if (e < plane) {
+      T w = T(0);
+#pragma unroll
+      for (int k = 0; k < NT; ++k) {
+        U[k * plane + e] = uv[i][k];
+        w += a.cb[k] * pv[i][k];
+      }
+      U[NT * plane + e] = w;
+    }
+  }
+  __syncthreads();
+  const float inv_n = 1.0f / (float)n;
+  T rv[SIT][NT];
+#pragma unroll
+  for (int i = 0; i < SIT; ++i) {
+    const int e = threadIdx.x + 256 * i;
+#pragma unroll
+    for (int l = 0; l < NT; ++l) rv[i][l] = T(0);
+    if (e < nout) {
+      const int yy = div_small(e, n, inv_n);
+      const int x = e - yy * n;
+      const bool hl = x > 0, hr = x < n - 1;
+      T mu[NT + 1], ku[NT];
+#pragma unroll
+      for (int c = 0; c <= NT; ++c) {
+        T m = T(0), kk = T(0);
+#pragma unroll
+        for (int dr = 0; dr < 3; ++dr) {
+          const T* row = U + c * plane + (yy + dr) * n + x;
+          const T l = hl ? row[-1] : T(0);
+          const T m0 = row[0];
+          const T rt = hr ? row[1] : T(0);
+          const T sm = a.wm[0] * l + a.wm[1] * m0 + a.wm[2] * rt;
+          m += a.wm[dr] * sm;
+          if (c < NT) {
+            const T sk = a.wk[0] * l + a.wk[1] * m0 + a.wk[2] * rt;
+            kk += a.wk[dr] * sm + a.wm[dr] * sk;
+          }
+        }
+        mu[c] = m;
+        if (c < NT) ku[c] = kk;
+      }
+#pragma unroll
+      for (int l = 0; l < NT; ++l) {
+        T acc = fv[i][l] + a.ca[l] * mu[NT];
+#pragma unroll
+        for (int k = 0; k < NT; ++k) acc -= a.K[l * NT + k] * mu[k] + a.M[l * NT + k] * ku[k];
+        rv[i][l] = acc;
+      }
+    }
+  }
+  __syncthreads();   // every stencil read of U is done
+  // r lines into LDS: line l * TY + yy, element x
+  T* Rl = U;
+#pragma unroll
+  for (int i = 0; i < SIT; ++i) {
+    const int e = threadIdx.x + 256 * i;
+    if (e < nout) {
+#pragma unroll
+      for (int l = 0; l < NT; ++l) Rl[l * TY * n + e] = rv[i][l];
+    }
+  }
+  __syncthreads();
+  // wave m: product m of the 16 lines; results to Pb[m][line][row]
+  constexpr int PR = 16 * HB2;   // rows of one product (h / 2)
+  T* Pb = U + NT * TY * n;
+  {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
+    const int yy = r & (TY - 1);
+    const bool valid = yy < rows;
+    const T* lp = Rl + r * n;   // line r = component r / TY, row r % TY
+    T op[4 * HB2];
+#pragma unroll
+    for (int ib = 0; ib < 4 * HB2; ++ib) {
+      const int p = cidx(ib, g);
+      const int i0 = 2 * p, i1 = 2 * p + 1;
+      T v = T(0);
+      if (valid) {
+        if (wave == 0) v = lp[i0] + lp[n - 1 - i0];
+        else if (wave == 1) v = i1 < h - 1 ? lp[i1] + lp[n - 1 - i1] : lp[i1];
+        else if (wave == 2) v = lp[i0] - lp[n - 1 - i0];
+        else v = i1 < h - 1 ? lp[i1] - lp[n - 1 - i1] : T(0);
+      }
+      op[ib] = v;
+    }
+    typename Mfma<T>::acc_t acc[HB2];
+    mma1<T, HB2, 0>(Sfrag, lane, wave, [&](int ib) { return op[ib]; }, acc);
+#pragma unroll
+    for (int kb = 0; kb < HB2; ++kb)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) Pb[(wave * 16 + r) * PR + orow(kb, g, j)] = acc[kb][j];
+  }
+  __syncthreads();
+  // spectral lines: row s of line L gives positions s, h-1-s, h+s, h+h-2-s
+  T* xo = xhat + slab * slabsz;
+  for (int it = threadIdx.x; it < 16 * PR; it += 256) {
+    const int line = it / PR, sr = it - line * PR;
+    const int l = line / TY, yy = line - l * TY;
+    if (yy >= rows) continue;
+    const T P = Pb[(0 * 16 + line) * PR + sr], Q = Pb[(1 * 16 + line) * PR + sr];
+    const T Pe = Pb[(2 * 16 + line) * PR + sr], Qe = Pb[(3 * 16 + line) * PR + sr];
+    T* dst = xo + l * nx + (long long)(y0 + yy) * n;
+    dst[sr] = P + Q;
+    dst[h - 1 - sr] = P - Q;
+    dst[h + sr] = Pe + Qe;
+    if (sr != h / 2 - 1) dst[h + h - 2 - sr] = Pe - Qe;
+  }
+}
+
 }  // namespace
 
 bool twice_folded_ok(int n, int elem_bytes) {
@@ -597,6 +779,31 @@ template hipError_t launch_slab_solve2<double>(int, int, const double*, double*,
                                                long long, int, double, int, hipStream_t);
 template hipError_t launch_slab_solve2<float>(int, int, const float*, float*, const float*, const float*, long long,
                                               int, float, int, hipStream_t);
+bool resid_xfwd_ok(int dim, int n, int nt, int elem_bytes) {
+  return dim == 2 && nt == 2 && (n == 63 || n == 127) && twice_folded_ok(n, elem_bytes);
+}
+
+unsigned resid_xfwd_blocks_per_slab(int n) { return (unsigned)((n + 7) / 8); }
+
+template <typename T>
+hipError_t launch_resid_xfwd(int n, const T* u, const T* F, T* xhat, const ResidArgs<T>& a, const T* Sfrag2,
+                             hipStream_t s) {
+  if (!resid_xfwd_ok(2, n, 2, (int)sizeof(T)) || a.n != n) return hipErrorInvalidValue;
+  const int HB2 = n == 127 ? 2 : 1;
+  const size_t elems = std::max<size_t>((size_t)3 * 10 * n, (size_t)2 * 8 * n + (size_t)4 * 16 * 16 * HB2);
+  const size_t lds = elems * sizeof(T);
+  const dim3 grid = slab_grid(resid_xfwd_blocks_per_slab(n), (long long)a.batch * a.N);
+  if (n == 127)
+    hipLaunchKernelGGL((k_resid_xfwd<T, 2, 5>), grid, dim3(256), lds, s, u, F, xhat, a, Sfrag2);
+  else
+    hipLaunchKernelGGL((k_resid_xfwd<T, 1, 3>), grid, dim3(256), lds, s, u, F, xhat, a, Sfrag2);
+  return hipGetLastError();
+}
+
+template hipError_t launch_resid_xfwd<double>(int, const double*, const double*, double*, const ResidArgs<double>&,
+                                              const double*, hipStream_t);
+template hipError_t launch_resid_xfwd<float>(int, const float*, const float*, float*, const ResidArgs<float>&,
+                                             const float*, hipStream_t);
 template hipError_t launch_pass_reg2<double>(int, bool, const double*, double*, const double*, long long, long long,
                                              double, int, hipStream_t);
 template hipError_t launch_pass_reg2<float>(int, bool, const float*, float*, const float*, long long, long long,

@@ -197,3 +197,51 @@ def test_slab_mixed_reaches_fp64_tolerance(monkeypatch):
     assert hist[-1][0] < 1e-10
     assert abs(itm - it64) <= 2
     assert (torch.linalg.vector_norm(um - u64) / torch.linalg.vector_norm(u64)).item() < 1e-8
+
+
+# Residual fused with the forward x pass (STMG_RX=1): 2-D, N_t = 2, n = 63, 127
+RX_CASES = [(2, 63, 4, 1, 1), (2, 127, 2, 1, 2), (2, 63, 8, 1, 2)]
+
+
+def rx_solvers(case, monkeypatch, **kw):
+    d, n, N, pt, b = case
+    monkeypatch.setenv("STMG_RX", "1")
+    Sx = stmg.Solver(d, n, N, pt=pt, batch=b, device=DEV, **kw)
+    monkeypatch.setenv("STMG_RX", "0")
+    S0 = stmg.Solver(d, n, N, pt=pt, batch=b, device=DEV, **kw)
+    monkeypatch.delenv("STMG_RX")
+    return Sx, S0
+
+
+@pytest.mark.parametrize("case", RX_CASES, ids=cid)
+@pytest.mark.parametrize("transpose", [False, True])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_fused_residual_smoothing_step(case, transpose, precision, monkeypatch):
+    # one smoothing step u += omega D^{-1}(F - L u) with and without the fused residual
+    print(f"fused residual step {case} transpose={transpose} {precision}", flush=True)
+    d, n, N, pt, b = case
+    Sx, S0 = rx_solvers(case, monkeypatch, precision=precision)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    rng = np.random.default_rng(23)
+    dof = Sx.level_dof(0) // b
+    u = to_gpu(rng.uniform(-1, 1, (dof, b)), dt)
+    F = to_gpu(rng.uniform(-1, 1, (dof, b)), dt)
+    ux, u0 = u.clone(), u.clone()
+    Sx.smooth(ux, F, transpose=transpose)
+    S0.smooth(u0, F, transpose=transpose)
+    tol = 1e-13 if precision == "fp64" else 64 * d * n * 2.0 ** -24
+    assert ((ux - u0).abs().max() / u0.abs().max()).item() < tol
+
+
+def test_fused_residual_iterates_match_oracle(monkeypatch):
+    # whole V-cycles with the fused residual on every qualifying level: oracle iterates to 1e-12
+    case = (2, 127, 8, 1, 1)
+    d, n, N, pt, b = case
+    Sx, _ = rx_solvers(case, monkeypatch)
+    H = multigrid.Hierarchy(d, n, N, pt)
+    F = np.random.default_rng(29).uniform(-1, 1, (H.fine.dof, b))
+    _, _, its = H.solve(F, rtol=0.0, maxit=3, keep_iterates=True)
+    u = torch.zeros(Sx.level_dof(0), dtype=torch.float64, device=DEV)
+    for k in range(1, 4):
+        Sx.solve(to_gpu(F), u=u, rtol=0.0, maxit=1, raise_on_noconv=False)
+        assert rel_err(to_oracle(u, b), its[k]) < 1e-12, k
