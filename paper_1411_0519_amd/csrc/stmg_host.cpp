@@ -1206,11 +1206,20 @@ int vcycle(st_mg* h, int l, bool transpose, T* u, const T* F, bool u_zero, bool 
 template <typename T>
 bool rx_level(const st_mg* h, int l) {
   const Level& L = h->lv[l];
-  if (h->mesh || inexact_level(h, l) || high_order(h) || bf16_level<T>(h, L) || slab_level<T>(h, L)) return false;
+  if (h->mesh || inexact_level(h, l) || high_order(h) || bf16_level<T>(h, L) || slab_level<T>(h, L) ||
+      small_level<T>(h, l))
+    return false;
   const int impl = L.impl >= 0 ? L.impl : h->impl;
   if (impl != TRANSFORM_AUTO && impl != TRANSFORM_REG2) return false;
   const bool on = L.rx >= 0 ? L.rx != 0 : h->rx;
   return on && S2of<T>(L) != nullptr && resid_xfwd_ok(h->p.dim, L.n, h->nt, (int)sizeof(T));
+}
+
+// The fine-level residual norm kernel also applies the forward x pass and leaves the result in the transform
+// buffer, where the first pre-smoothing step of the next cycle takes it (FP64/FP32 handles, nu1 >= 1).
+template <typename T>
+bool norm_xhat(const st_mg* h) {
+  return !is_mixed(h) && h->p.nu1 >= 1 && rx_level<T>(h, 0);
 }
 
 // One damped block-Jacobi step u += omega D^{-1}(F - L u) on level l (r and A are scratch).
@@ -1222,7 +1231,7 @@ int smooth_step(st_mg* h, int l, bool transpose, T* u, const T* F, T* r, T* A, h
     const ResidArgs<T> a = resid_args<T>(h, L, transpose);
     {
       ProfScope ps(h, ST_PROF_RESID_X, l, s);
-      HIPCHK(h, launch_resid_xfwd<T>(L.n, u, F, A, a, S2of<T>(L), s));
+      HIPCHK(h, launch_resid_xfwd<T>(L.n, u, F, A, a, S2of<T>(L), nullptr, s));
     }
     return op_block_solve<T>(h, l, transpose, A, u, MODE_ADD_SCALED, om, A, r, s, true);
   }
@@ -1288,7 +1297,10 @@ int vcycle(st_mg* h, int l, bool transpose, T* u, const T* F, bool u_zero, bool 
     if (i == 0 && u_zero) {
       CHK(op_smoother_solve<T>(h, l, transpose, F, u, MODE_SET_SCALED, om, A, r, s));
     } else if (i == 0 && r_ready) {
-      CHK(op_smoother_solve<T>(h, l, transpose, r, u, MODE_ADD_SCALED, om, A, r, s));
+      if (l == 0 && norm_xhat<T>(h))   // the norm kernel left the x-transformed residual in A
+        CHK(op_block_solve<T>(h, l, transpose, A, u, MODE_ADD_SCALED, om, A, r, s, true));
+      else
+        CHK(op_smoother_solve<T>(h, l, transpose, r, u, MODE_ADD_SCALED, om, A, r, s));
     } else {
       CHK(smooth_step<T>(h, l, transpose, u, F, r, A, s));
     }
@@ -1328,6 +1340,18 @@ int fine_residual_norm(st_mg* h, bool transpose, const void* u, const void* F, h
   if (is_mixed(h))
     return op_residual<double, float>(h, 0, transpose, (const double*)u, (const double*)F,
                                       (float*)h->F32, true, s);
+  if (norm_xhat<T>(h)) {
+    const Level& L = h->lv[0];
+    {
+      ProfScope ps(h, ST_PROF_RESID_X, 0, s);
+      HIPCHK(h, launch_resid_xfwd<T>(L.n, (const T*)u, (const T*)F, (T*)h->tmp, resid_args<T>(h, L, transpose),
+                                     S2of<T>(L), h->partial, s));
+    }
+    ProfScope ps(h, ST_PROF_OTHER, 0, s);
+    const long long per = (long long)resid_blocks(h, L) * L.N;
+    HIPCHK(h, launch_norm_final(h->partial, per, h->p.batch, h->norm_dev, s));
+    return ST_OK;
+  }
   return op_residual<T, T>(h, 0, transpose, (const T*)u, (const T*)F, level_r<T>(h, 0), true, s);
 }
 

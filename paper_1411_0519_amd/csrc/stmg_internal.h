@@ -431,11 +431,12 @@ template <typename T>
 hipError_t launch_slab_solve2(int n, int nt, const T* src, T* dst, const T* Sfrag2, const T* G, long long slabs,
                               int transpose, T omega, int mode, hipStream_t s);
 // 2-D residual fused with the forward twice-folded x pass (N_t = 2, n = 63,
-// 127): xhat = (S_x (x) I) (F - L u) in the layout of r, no norm partials.
+// 127): xhat = (S_x (x) I) (F - L u) in the layout of r; with `partial` the
+// per-tile sums of r^2 in the residual kernel's layout.
 bool resid_xfwd_ok(int dim, int n, int nt, int elem_bytes);
 template <typename T>
 hipError_t launch_resid_xfwd(int n, const T* u, const T* F, T* xhat, const ResidArgs<T>& a, const T* Sfrag2,
-                             hipStream_t s);
+                             double* partial, hipStream_t s);
 template <typename T>
 hipError_t launch_fused_pair2(int n, int nt, const T* in, T* out, const T* Sfrag2, const T* G, long long inner,
                               long long outer, int transpose, T omega, int mode, hipStream_t s);

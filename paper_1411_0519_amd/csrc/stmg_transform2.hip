@@ -531,12 +531,13 @@ __global__ __launch_bounds__(512) void k_slab_solve2(const T* src, T* dst, const
 // rows) back into LDS, and the four waves each run one of the four twice-
 // folded products (O and E on even and odd inputs) on those 16 lines; the
 // sums and differences of their results are the spectral x lines, stored to
-// xhat in the layout of r.  The residual itself never reaches HBM.
+// xhat in the layout of r.  The residual itself never reaches HBM; with
+// `partial` the workgroup's sum of r^2 is written as the residual kernel does.
 // Dynamic LDS: max(3 (TY + 2) n, 2 TY n + 4 * 16 * 16 HB2) elements.
 template <typename T, int HB2, int SIT>
 __global__ __launch_bounds__(256) void k_resid_xfwd(const T* __restrict__ u, const T* __restrict__ F,
                                                     T* __restrict__ xhat, ResidArgs<T> a,
-                                                    const T* __restrict__ Sfrag) {
+                                                    const T* __restrict__ Sfrag, double* __restrict__ partial) {
   constexpr int NT = 2, TY = 8;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   T* U = reinterpret_cast<T*>(lds_raw);
@@ -627,6 +628,18 @@ __global__ __launch_bounds__(256) void k_resid_xfwd(const T* __restrict__ u, con
         rv[i][l] = acc;
       }
     }
+  }
+  if (partial != nullptr) {
+    double ss = 0.0;
+#pragma unroll
+    for (int i = 0; i < SIT; ++i)
+#pragma unroll
+      for (int l = 0; l < NT; ++l) ss += (double)rv[i][l] * (double)rv[i][l];
+    __shared__ double red[4];
+    for (int off = 32; off > 0; off >>= 1) ss += __shfl_down(ss, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = ss;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[slab * gridDim.x + tile] = red[0] + red[1] + red[2] + red[3];
   }
   __syncthreads();   // every stencil read of U is done
   // r lines into LDS: line l * TY + yy, element x
@@ -787,23 +800,23 @@ unsigned resid_xfwd_blocks_per_slab(int n) { return (unsigned)((n + 7) / 8); }
 
 template <typename T>
 hipError_t launch_resid_xfwd(int n, const T* u, const T* F, T* xhat, const ResidArgs<T>& a, const T* Sfrag2,
-                             hipStream_t s) {
+                             double* partial, hipStream_t s) {
   if (!resid_xfwd_ok(2, n, 2, (int)sizeof(T)) || a.n != n) return hipErrorInvalidValue;
   const int HB2 = n == 127 ? 2 : 1;
   const size_t elems = std::max<size_t>((size_t)3 * 10 * n, (size_t)2 * 8 * n + (size_t)4 * 16 * 16 * HB2);
   const size_t lds = elems * sizeof(T);
   const dim3 grid = slab_grid(resid_xfwd_blocks_per_slab(n), (long long)a.batch * a.N);
   if (n == 127)
-    hipLaunchKernelGGL((k_resid_xfwd<T, 2, 5>), grid, dim3(256), lds, s, u, F, xhat, a, Sfrag2);
+    hipLaunchKernelGGL((k_resid_xfwd<T, 2, 5>), grid, dim3(256), lds, s, u, F, xhat, a, Sfrag2, partial);
   else
-    hipLaunchKernelGGL((k_resid_xfwd<T, 1, 3>), grid, dim3(256), lds, s, u, F, xhat, a, Sfrag2);
+    hipLaunchKernelGGL((k_resid_xfwd<T, 1, 3>), grid, dim3(256), lds, s, u, F, xhat, a, Sfrag2, partial);
   return hipGetLastError();
 }
 
 template hipError_t launch_resid_xfwd<double>(int, const double*, const double*, double*, const ResidArgs<double>&,
-                                              const double*, hipStream_t);
+                                              const double*, double*, hipStream_t);
 template hipError_t launch_resid_xfwd<float>(int, const float*, const float*, float*, const ResidArgs<float>&,
-                                             const float*, hipStream_t);
+                                             const float*, double*, hipStream_t);
 template hipError_t launch_pass_reg2<double>(int, bool, const double*, double*, const double*, long long, long long,
                                              double, int, hipStream_t);
 template hipError_t launch_pass_reg2<float>(int, bool, const float*, float*, const float*, long long, long long,

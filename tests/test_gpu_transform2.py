@@ -245,3 +245,21 @@ def test_fused_residual_iterates_match_oracle(monkeypatch):
     for k in range(1, 4):
         Sx.solve(to_gpu(F), u=u, rtol=0.0, maxit=1, raise_on_noconv=False)
         assert rel_err(to_oracle(u, b), its[k]) < 1e-12, k
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_fused_residual_norms_and_solve(precision, monkeypatch):
+    # the fine residual norm kernel leaves the x-transformed residual for the next cycle's first
+    # smoothing step: residual histories and solutions with and without the fused path agree
+    case = (2, 63, 16, 1, 2)
+    d, n, N, pt, b = case
+    Sx, S0 = rx_solvers(case, monkeypatch, precision=precision)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    F = to_gpu(np.random.default_rng(31).uniform(-1, 1, (Sx.level_dof(0) // b, b)), dt)
+    rtol = 1e-10 if precision == "fp64" else 1e-5
+    ux, itx, hx = Sx.solve(F, rtol=rtol, maxit=40)
+    u0, it0, h0 = S0.solve(F, rtol=rtol, maxit=40)
+    assert itx == it0
+    tol = 1e-12 if precision == "fp64" else 1e-4
+    assert np.allclose(np.asarray(hx), np.asarray(h0), rtol=tol, atol=0)
+    assert ((ux - u0).abs().max() / u0.abs().max()).item() < (1e-12 if precision == "fp64" else 1e-5)
