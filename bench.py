@@ -395,7 +395,8 @@ def main():
     hbm_bytes = (24 if dom == "pass_inv" else 16) * nvals
     achieved = flops / (avg_ms * 1e-3) / 1e12
     impl0 = 0 if tuning is None else tuning[0][1]
-    twice = impl0 in (0, 3) and L0["n"] in (63, 127)      # the default FP64 family at n = 63, 127
+    # the default FP64 family at n = 63, 127 is twice folded (5: the same with the residual fused in)
+    twice = impl0 in (0, 3, 5) and L0["n"] in (63, 127)
     if twice:
         names = {"pass_fwd": "forward x pass (k_pass_reg2<double,2,false,true>, twice folded)",
                  "pass_inv": "inverse x pass + update (k_pass_reg2<double,2,true,true>, twice folded)",
