@@ -113,6 +113,7 @@ struct Level {
   double* Sp64 = nullptr; // plain DST-I (n x n), used by the small-level smoother
   double* S2_64 = nullptr; // twice-folded fragments (FP64: n = 63, 127) [dir][mat][kb][ib][lane]
   float* S2_32 = nullptr;  // the same for FP32 (n = 63, 127, 255), FP32 contraction order
+  void* S2_16 = nullptr;   // the same in bf16 for the BF16 inner cycle: [dir][mat][kb][c][lane][4]
   float* Sp32 = nullptr;
   int impl = -1;          // transform family chosen for this level (-1: handle default)
   int small = -1;         // small-level smoother on (1) / off (0) for this level (-1: handle default)
@@ -478,6 +479,22 @@ int build_level_tables(st_mg* h, Level& L) {
     }
     HIPCHK(h, hipMalloc(&L.S2_32, len2 * sizeof(float)));
     HIPCHK(h, hipMemcpy(L.S2_32, f2_32.data(), len2 * sizeof(float), hipMemcpyHostToDevice));
+    // bf16 operands of v_mfma_f32_16x16x16_bf16: lane supplies operand row lane % 16 (logical row
+    // twice_fold_row) and the four contraction indices 4 (4 c + e) + lane / 16, e < 4, of chunk c
+    std::vector<uint16_t> f2_16((size_t)2 * 4 * KB * KB * 64 * 4);
+    for (int dir = 0; dir < 2; ++dir)
+      for (int mat = 0; mat < 4; ++mat)
+        for (int kb = 0; kb < KB; ++kb)
+          for (int c = 0; c < KB; ++c)
+            for (int lane = 0; lane < 64; ++lane)
+              for (int e = 0; e < 4; ++e) {
+                const size_t o = (((((size_t)dir * 4 + mat) * KB + kb) * KB + c) * 64 + lane) * 4 + e;
+                const int rr = kb * 16 + twice_fold_row(4, lane & 15);
+                const int cc = 4 * (4 * c + e) + (lane >> 4);
+                f2_16[o] = bf16_round(dir == 0 ? M(mat, rr, cc) : M(mat, cc, rr));
+              }
+    HIPCHK(h, hipMalloc(&L.S2_16, f2_16.size() * sizeof(uint16_t)));
+    HIPCHK(h, hipMemcpy(L.S2_16, f2_16.data(), f2_16.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
   }
   HIPCHK(h, hipMalloc(&L.Sp64, Sp.size() * sizeof(double)));
   HIPCHK(h, hipMalloc(&L.Sp32, Sp32.size() * sizeof(float)));
@@ -749,6 +766,11 @@ int op_block_solve(st_mg* h, int l, bool transpose, const T* src, T* dst, int mo
     for (int i = axis + 1; i < d; ++i) rest *= nn;
     const long long ncols = slabs * nt * rest * inner;
     ProfScope ps(h, inv ? ST_PROF_PASS_INV : ST_PROF_PASS_FWD, l, s);
+    if (bf16_level<T>(h, L) && L.S2_16) {
+      HIPCHK(h, launch_pass_reg2<float>(n, inv, (const float*)in, (float*)out, (const float*)L.S2_16, inner, ncols,
+                                        (float)om, md, s, true));
+      return ST_OK;
+    }
     if (bf16_level<T>(h, L)) {
       HIPCHK(h, launch_pass_bf16(L.hb, inv, (const float*)in, (float*)out, L.S16, n, inner, ncols, (float)om, md, s));
       return ST_OK;
@@ -766,6 +788,12 @@ int op_block_solve(st_mg* h, int l, bool transpose, const T* src, T* dst, int mo
     long long inner = 1;
     for (int i = 0; i < d - 1; ++i) inner *= nn;
     ProfScope ps(h, ST_PROF_FUSED, l, s);
+    if (bf16_level<T>(h, L) && L.S2_16) {
+      HIPCHK(h, launch_fused_pair2<float>(n, nt, (const float*)in, (float*)out, (const float*)L.S2_16,
+                                          (const float*)Gof<T>(L), inner, slabs, transpose ? 1 : 0, (float)om, md, s,
+                                          true));
+      return ST_OK;
+    }
     if (bf16_level<T>(h, L)) {
       HIPCHK(h, launch_fused_bf16(L.hb, nt, (const float*)in, (float*)out, L.S16, (const float*)Gof<T>(L), n, inner,
                                   slabs, transpose ? 1 : 0, (float)om, md, s));
@@ -2080,6 +2108,7 @@ int st_mg_destroy(st_mg_t h) {
     (void)hipFree(L.Sp32);
     (void)hipFree(L.S2_64);
     (void)hipFree(L.S2_32);
+    (void)hipFree(L.S2_16);
     (void)hipFree(L.D64);
     (void)hipFree(L.D32);
     (void)hipFree(L.C64);

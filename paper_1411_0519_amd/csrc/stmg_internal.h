@@ -418,11 +418,13 @@ namespace stmg {
 // (row 4 g + j in element j of lane group g) where the f64 one interleaves
 // (g + 4 j), so the FP32 table stores output row twice_fold_row(i) at operand
 // row i and both types share one register order.
+// With bf16 (FP32 data only) Sfrag2 is the bf16 table of packed quadruples
+// (v_mfma_f32_16x16x16_bf16 operands, rows permuted the same way).
 bool twice_folded_ok(int n, int elem_bytes);
 inline int twice_fold_row(int elem_bytes, int i) { return elem_bytes == 8 ? i : (i >> 2) + 4 * (i & 3); }
 template <typename T>
 hipError_t launch_pass_reg2(int n, bool inverse, const T* in, T* out, const T* Sfrag2, long long inner,
-                            long long ncols, T omega, int mode, hipStream_t s);
+                            long long ncols, T omega, int mode, hipStream_t s, bool bf16 = false);
 // 2-D slab-resident block solve with the twice-folded passes (one workgroup
 // per slab, slab in LDS; FP64 n = 63, FP32 n = 63, 127; N_t <= 2): LDS bytes,
 // 0 when the level does not qualify.
@@ -439,6 +441,6 @@ hipError_t launch_resid_xfwd(int n, const T* u, const T* F, T* xhat, const Resid
                              double* partial, hipStream_t s);
 template <typename T>
 hipError_t launch_fused_pair2(int n, int nt, const T* in, T* out, const T* Sfrag2, const T* G, long long inner,
-                              long long outer, int transpose, T omega, int mode, hipStream_t s);
+                              long long outer, int transpose, T omega, int mode, hipStream_t s, bool bf16 = false);
 
 }  // namespace stmg

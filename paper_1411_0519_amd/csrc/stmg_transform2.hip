@@ -1,5 +1,6 @@
 // Twice-folded sine transforms on the matrix cores: FP64 for n = 63, 127, FP32
-// for n = 63, 127, 255.
+// for n = 63, 127, 255, and FP32 data with bf16 operands (BF = true:
+// v_mfma_f32_16x16x16_bf16, FP32 accumulation) for the same n.
 //
 // The first fold pairs x_i with x_{n-1-i} (odd modes see a_i = x_i + x_{n-1-i},
 // even modes d_i = x_i - x_{n-1-i}).  Each half has a second mirror symmetry:
@@ -45,9 +46,41 @@ __device__ inline int orow(int kb, int g, int j) { return 16 * kb + g + 4 * j; }
 // acc[mat][kb] = sum over chunks ib of A(dir, mat, kb, ib) * B(mat, ib); HB2 = h/32
 // row blocks per product, 2 HB2 * 4 = h/2 contraction indices.  B(mat, ib) is
 // the lane's operand for (mat, chunk ib).
-template <typename T, int HB2, int DIR, typename OpFn>
+typedef short v4s __attribute__((ext_vector_type(4)));
+
+__device__ inline short bf16_bits(float x) { return __builtin_bit_cast(short, (__bf16)x); }
+
+// BF16 products: chunk c of 16 contraction indices holds values 4c + q (q < 4)
+// of a lane, packed; the table is [dir][mat][kb][c][lane] of four bf16.
+template <int HB2, int DIR, typename OpFn>
+__device__ inline void mma4_bf16(const v4s* __restrict__ F, int lane, OpFn op, v4f (&acc)[4][HB2]) {
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int kb = 0; kb < HB2; ++kb) acc[m][kb] = v4f{0.f, 0.f, 0.f, 0.f};
+  const v4s* f = F + (size_t)DIR * 4 * HB2 * HB2 * 64 + lane;
+#pragma unroll
+  for (int c = 0; c < HB2; ++c) {
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      v4s b;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) b[q] = bf16_bits(op(m, 4 * c + q));
+#pragma unroll
+      for (int kb = 0; kb < HB2; ++kb)
+        acc[m][kb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(f[((m * HB2 + kb) * HB2 + c) * 64], b, acc[m][kb], 0,
+                                                               0, 0);
+    }
+  }
+}
+
+template <typename T, int HB2, int DIR, bool BF = false, typename OpFn>
 __device__ inline void mma4(const T* __restrict__ Sfrag, int lane, OpFn op,
                             typename Mfma<T>::acc_t (&acc)[4][HB2]) {
+  if constexpr (BF) {
+    mma4_bf16<HB2, DIR>(reinterpret_cast<const v4s*>(Sfrag), lane, op, acc);
+    return;
+  }
   typedef typename Mfma<T>::acc_t acc_t;
   constexpr int NC = 4 * HB2;   // chunks of 4 along the contraction (h/2 / 4)
 #pragma unroll
@@ -211,7 +244,7 @@ __device__ inline void inverse_operands(T o, T om, T e, T em, bool middle, T& u,
   ve = middle ? T(0) : e - em;
 }
 
-template <typename T, int HB2, bool INV, bool UNIT>
+template <typename T, int HB2, bool INV, bool UNIT, bool BF>
 __global__ __launch_bounds__(256) void k_pass_reg2(const T* __restrict__ in, T* __restrict__ out,
                                                    const T* __restrict__ Sfrag, int n, long long inner_rt,
                                                    long long ncols, T omega, int mode) {
@@ -248,7 +281,7 @@ __global__ __launch_bounds__(256) void k_pass_reg2(const T* __restrict__ in, T* 
   if (INV && mode == MODE_ADD_SCALED) load_old<T, HB2>(out + base, valid, inner, n, g, old);
   else zero_old<T, HB2>(old);
   acc_t acc[4][HB2];
-  mma4<T, HB2, INV ? 1 : 0>(Sfrag, lane, [&](int m, int ib) { return op[m][ib]; }, acc);
+  mma4<T, HB2, INV ? 1 : 0, BF>(Sfrag, lane, [&](int m, int ib) { return op[m][ib]; }, acc);
   if (!INV) {
     if (valid) {
 #pragma unroll
@@ -271,7 +304,7 @@ __global__ __launch_bounds__(256) void k_pass_reg2(const T* __restrict__ in, T* 
 // Slowest axis: forward transform, per-mode N_t x N_t solve, inverse transform,
 // one wave per time component (as the once-folded k_fused_pair), the
 // components exchanged through LDS for the solve.
-template <typename T, int HB2, int NT>
+template <typename T, int HB2, int NT, bool BF>
 __global__ __launch_bounds__(256) void k_fused_pair2(const T* in, T* out, const T* __restrict__ Sfrag,
                                                      const T* __restrict__ G, int n, long long inner,
                                                      long long outer, int transpose, T omega, int mode) {
@@ -292,7 +325,7 @@ __global__ __launch_bounds__(256) void k_fused_pair2(const T* in, T* out, const 
   {
     T op[4][4 * HB2];
     load_twice_folded<T, HB2>(in + base, valid, inner, n, g, op);
-    mma4<T, HB2, 0>(Sfrag, lane, [&](int m, int ib) { return op[m][ib]; }, acc);
+    mma4<T, HB2, 0, BF>(Sfrag, lane, [&](int m, int ib) { return op[m][ib]; }, acc);
   }
   // spectral values (o, om, e, em) of every row to LDS, one barrier
 #pragma unroll
@@ -335,7 +368,7 @@ __global__ __launch_bounds__(256) void k_fused_pair2(const T* in, T* out, const 
       inverse_operands<T>(y[0], y[1], y[2], y[3], middle, op[0][ib], op[1][ib], op[2][ib], op[3][ib]);
     }
   acc_t out_acc[4][HB2];
-  mma4<T, HB2, 1>(Sfrag, lane, [&](int m, int ib) { return op[m][ib]; }, out_acc);
+  mma4<T, HB2, 1, BF>(Sfrag, lane, [&](int m, int ib) { return op[m][ib]; }, out_acc);
   T none[HB2][4][4];
   zero_old<T, HB2>(none);
   store_twice_unfolded<T, HB2, false>(out + base, valid, inner, n, g, out_acc, mode, omega, none);
@@ -708,17 +741,22 @@ bool twice_folded_ok(int n, int elem_bytes) {
 
 template <typename T>
 hipError_t launch_pass_reg2(int n, bool inverse, const T* in, T* out, const T* Sfrag2, long long inner,
-                            long long ncols, T omega, int mode, hipStream_t s) {
+                            long long ncols, T omega, int mode, hipStream_t s, bool bf16) {
   const unsigned grid = (unsigned)((ncols + 63) / 64);
-#define P2(HB2, U)                                                                                          \
-  if (inverse)                                                                                              \
-    hipLaunchKernelGGL((k_pass_reg2<T, HB2, true, U>), dim3(grid), dim3(256), 0, s, in, out, Sfrag2, n, inner, \
-                       ncols, omega, mode);                                                                 \
-  else                                                                                                      \
-    hipLaunchKernelGGL((k_pass_reg2<T, HB2, false, U>), dim3(grid), dim3(256), 0, s, in, out, Sfrag2, n,       \
-                       inner, ncols, omega, mode);                                                          \
+#define P2B(HB2, U, B)                                                                                         \
+  if (inverse)                                                                                                 \
+    hipLaunchKernelGGL((k_pass_reg2<T, HB2, true, U, B>), dim3(grid), dim3(256), 0, s, in, out, Sfrag2, n, inner, \
+                       ncols, omega, mode);                                                                    \
+  else                                                                                                         \
+    hipLaunchKernelGGL((k_pass_reg2<T, HB2, false, U, B>), dim3(grid), dim3(256), 0, s, in, out, Sfrag2, n,       \
+                       inner, ncols, omega, mode);                                                             \
   return hipGetLastError();
-  if (!twice_folded_ok(n, (int)sizeof(T))) return hipErrorInvalidValue;
+#define P2(HB2, U)                      \
+  if constexpr (sizeof(T) == 4) {       \
+    if (bf16) { P2B(HB2, U, true) }     \
+  }                                     \
+  P2B(HB2, U, false)
+  if (!twice_folded_ok(n, (int)sizeof(T)) || (bf16 && sizeof(T) != 4)) return hipErrorInvalidValue;
   if constexpr (sizeof(T) == 4) {
     if (n == 255) {
       if (inner == 1) { P2(4, true) }
@@ -734,28 +772,35 @@ hipError_t launch_pass_reg2(int n, bool inverse, const T* in, T* out, const T* S
     P2(1, false)
   }
 #undef P2
+#undef P2B
   return hipErrorInvalidValue;
 }
 
 template <typename T>
 hipError_t launch_fused_pair2(int n, int nt, const T* in, T* out, const T* Sfrag2, const T* G, long long inner,
-                              long long outer, int transpose, T omega, int mode, hipStream_t s) {
+                              long long outer, int transpose, T omega, int mode, hipStream_t s, bool bf16) {
   const int cg = nt >= 3 ? 1 : 4 / nt;
   const unsigned grid = (unsigned)((outer * inner + 16 * cg - 1) / (16 * cg));
   const dim3 block(64 * nt * cg);
-#define F2(HB2, NT)                                                                                             \
-  if (nt == NT) {                                                                                               \
-    hipLaunchKernelGGL((k_fused_pair2<T, HB2, NT>), dim3(grid), block, 0, s, in, out, Sfrag2, G, n, inner, outer, \
-                       transpose, omega, mode);                                                                 \
-    return hipGetLastError();                                                                                   \
+#define F2B(HB2, NT, B)                                                                                          \
+  if (nt == NT) {                                                                                                \
+    hipLaunchKernelGGL((k_fused_pair2<T, HB2, NT, B>), dim3(grid), block, 0, s, in, out, Sfrag2, G, n, inner,      \
+                       outer, transpose, omega, mode);                                                           \
+    return hipGetLastError();                                                                                    \
   }
-  if (!twice_folded_ok(n, (int)sizeof(T))) return hipErrorInvalidValue;
+#define F2(HB2, NT)                                  \
+  if constexpr (sizeof(T) == 4) {                    \
+    if (bf16) { F2B(HB2, NT, true) }                 \
+  }                                                  \
+  F2B(HB2, NT, false)
+  if (!twice_folded_ok(n, (int)sizeof(T)) || (bf16 && sizeof(T) != 4)) return hipErrorInvalidValue;
   if constexpr (sizeof(T) == 4) {
     if (n == 255) { F2(4, 1) F2(4, 2) F2(4, 3) F2(4, 4) }
   }
   if (n == 127) { F2(2, 1) F2(2, 2) F2(2, 3) F2(2, 4) }
   if (n == 63) { F2(1, 1) F2(1, 2) F2(1, 3) F2(1, 4) }
 #undef F2
+#undef F2B
   return hipErrorInvalidValue;
 }
 
@@ -818,12 +863,12 @@ template hipError_t launch_resid_xfwd<double>(int, const double*, const double*,
 template hipError_t launch_resid_xfwd<float>(int, const float*, const float*, float*, const ResidArgs<float>&,
                                              const float*, double*, hipStream_t);
 template hipError_t launch_pass_reg2<double>(int, bool, const double*, double*, const double*, long long, long long,
-                                             double, int, hipStream_t);
+                                             double, int, hipStream_t, bool);
 template hipError_t launch_pass_reg2<float>(int, bool, const float*, float*, const float*, long long, long long,
-                                            float, int, hipStream_t);
+                                            float, int, hipStream_t, bool);
 template hipError_t launch_fused_pair2<double>(int, int, const double*, double*, const double*, const double*,
-                                               long long, long long, int, double, int, hipStream_t);
+                                               long long, long long, int, double, int, hipStream_t, bool);
 template hipError_t launch_fused_pair2<float>(int, int, const float*, float*, const float*, const float*, long long,
-                                              long long, int, float, int, hipStream_t);
+                                              long long, int, float, int, hipStream_t, bool);
 
 }  // namespace stmg
