@@ -398,11 +398,11 @@ def main():
     # the default FP64 family at n = 63, 127 is twice folded (5: the same with the residual fused in)
     twice = impl0 in (0, 3, 5) and L0["n"] in (63, 127)
     if twice:
-        names = {"pass_fwd": "forward x pass (k_pass_reg2<double,2,false,true>, twice folded)",
-                 "pass_inv": "inverse x pass + update (k_pass_reg2<double,2,true,true>, twice folded)",
-                 "fused": "fused y pass: forward + time solve + inverse (k_fused_pair2<double,2,2>, twice folded, one wave per time component)"}
-        kernel_ids = {"pass_fwd": "k_pass_reg2<double, 2, false, true>", "pass_inv": "k_pass_reg2<double, 2, true, true>",
-                      "fused": "k_fused_pair2<double, 2, 2>"}
+        names = {"pass_fwd": "forward x pass (k_pass_reg2<double,2,false,true,false>, twice folded)",
+                 "pass_inv": "inverse x pass + update (k_pass_reg2<double,2,true,true,false>, twice folded)",
+                 "fused": "fused y pass: forward + time solve + inverse (k_fused_pair2<double,2,2,false>, twice folded, one wave per time component)"}
+        kernel_ids = {"pass_fwd": "k_pass_reg2<double, 2, false, true, false>",
+                      "pass_inv": "k_pass_reg2<double, 2, true, true, false>", "fused": "k_fused_pair2<double, 2, 2, false>"}
         executed = flops * (L0["n"] + 1) / (4.0 * L0["n"])     # four (h/2)^2 products per column
     else:
         names = {"pass_fwd": "forward x pass (k_pass_reg<double,4,false>)", "pass_inv": "inverse x pass + update (k_pass_reg<double,4,true>)",
