@@ -114,6 +114,8 @@ struct Level {
   double* S2_64 = nullptr; // twice-folded fragments (FP64: n = 63, 127) [dir][mat][kb][ib][lane]
   float* S2_32 = nullptr;  // the same for FP32 (n = 63, 127, 255), FP32 contraction order
   void* S2_16 = nullptr;   // the same in bf16 for the BF16 inner cycle: [dir][mat][kb][c][lane][4]
+  double* eig64 = nullptr; // 1-D eigenvalues m_s then kappa_s in spectral order (2n)
+  float* eig32 = nullptr;
   float* Sp32 = nullptr;
   int impl = -1;          // transform family chosen for this level (-1: handle default)
   int small = -1;         // small-level smoother on (1) / off (0) for this level (-1: handle default)
@@ -418,6 +420,20 @@ int build_level_tables(st_mg* h, Level& L) {
     m1[s] = hh / 3.0 * (2.0 + c);
     k1[s] = 2.0 / hh * (1.0 - c);
   }
+  {
+    std::vector<double> e64(2 * (size_t)n);
+    std::vector<float> e32(2 * (size_t)n);
+    for (int i = 0; i < n; ++i) {
+      e64[i] = m1[i];
+      e64[n + i] = k1[i];
+      e32[i] = (float)m1[i];
+      e32[n + i] = (float)k1[i];
+    }
+    HIPCHK(h, hipMalloc(&L.eig64, e64.size() * sizeof(double)));
+    HIPCHK(h, hipMalloc(&L.eig32, e32.size() * sizeof(float)));
+    HIPCHK(h, hipMemcpy(L.eig64, e64.data(), e64.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(h, hipMemcpy(L.eig32, e32.data(), e32.size() * sizeof(float), hipMemcpyHostToDevice));
+  }
   const long long nx = L.nx;
   std::vector<double> G((size_t)nx * nt * nt);
   std::vector<float> G32((size_t)nx * nt * nt);
@@ -517,6 +533,9 @@ int build_level_tables(st_mg* h, Level& L) {
 template <typename T> const T* Sof(const Level& L);
 template <> const double* Sof<double>(const Level& L) { return L.S64; }
 template <> const float* Sof<float>(const Level& L) { return L.S32; }
+template <typename T> const T* Eigof(const Level& L);
+template <> const double* Eigof<double>(const Level& L) { return L.eig64; }
+template <> const float* Eigof<float>(const Level& L) { return L.eig32; }
 template <typename T> const T* S2of(const Level& L);
 template <> const double* S2of<double>(const Level& L) { return L.S2_64; }
 template <> const float* S2of<float>(const Level& L) { return L.S2_32; }
@@ -784,6 +803,17 @@ int op_block_solve(st_mg* h, int l, bool transpose, const T* src, T* dst, int mo
     HIPCHK(h, launch_dst_pass<T>(impl, L.hb, axis == 0, inv, in, out, Sof<T>(L), n, inner, ncols, om, md, s));
     return ST_OK;
   };
+  // per-mode blocks from the eigenvalues for the twice-folded fused pass (N_t <= 2)
+  ModeEig<T> me{};
+  const ModeEig<T>* mep = nullptr;
+  if (nt <= 2) {
+    me.eig = Eigof<T>(L);
+    for (int i = 0; i < nt * nt; ++i) {
+      me.K[i] = (T)h->Kt[i];
+      me.M[i] = (T)(L.tau * h->Mh[i]);
+    }
+    mep = &me;
+  }
   auto fused = [&](const T* in, T* out, int md, T om) -> int {
     long long inner = 1;
     for (int i = 0; i < d - 1; ++i) inner *= nn;
@@ -791,7 +821,7 @@ int op_block_solve(st_mg* h, int l, bool transpose, const T* src, T* dst, int mo
     if (bf16_level<T>(h, L) && L.S2_16) {
       HIPCHK(h, launch_fused_pair2<float>(n, nt, (const float*)in, (float*)out, (const float*)L.S2_16,
                                           (const float*)Gof<T>(L), inner, slabs, transpose ? 1 : 0, (float)om, md, s,
-                                          true));
+                                          true, (const ModeEig<float>*)mep));
       return ST_OK;
     }
     if (bf16_level<T>(h, L)) {
@@ -803,7 +833,7 @@ int op_block_solve(st_mg* h, int l, bool transpose, const T* src, T* dst, int mo
     if (impl == TRANSFORM_SLAB) impl = TRANSFORM_AUTO;
     if ((impl == TRANSFORM_REG2 || impl == TRANSFORM_AUTO) && S2of<T>(L)) {
       HIPCHK(h, launch_fused_pair2<T>(n, nt, in, out, S2of<T>(L), Gof<T>(L), inner, slabs, transpose ? 1 : 0, om, md,
-                                      s));
+                                      s, false, mep));
       return ST_OK;
     }
     HIPCHK(h, launch_dst_fused<T>(impl, L.hb, nt, in, out, Sof<T>(L), Gof<T>(L), n, inner, slabs,
@@ -2109,6 +2139,8 @@ int st_mg_destroy(st_mg_t h) {
     (void)hipFree(L.S2_64);
     (void)hipFree(L.S2_32);
     (void)hipFree(L.S2_16);
+    (void)hipFree(L.eig64);
+    (void)hipFree(L.eig32);
     (void)hipFree(L.D64);
     (void)hipFree(L.D32);
     (void)hipFree(L.C64);

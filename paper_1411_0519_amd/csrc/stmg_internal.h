@@ -418,6 +418,16 @@ namespace stmg {
 // (row 4 g + j in element j of lane group g) where the f64 one interleaves
 // (g + 4 j), so the FP32 table stores output row twice_fold_row(i) at operand
 // row i and both types share one register order.
+// Per-mode time blocks from the 1-D eigenvalues (N_t <= 2): eig holds m_s then
+// kappa_s of one axis in spectral order (2n values), K = K_tau, M = M_tau;
+// the block of mode (s_1, .., s_d) is (mu K + nu M)^{-1} with mu = prod m and
+// nu = sum_a kappa_a prod_{b != a} m_b.  eig == nullptr: read the table G.
+template <typename T>
+struct ModeEig {
+  const T* eig;
+  T K[4];
+  T M[4];
+};
 // With bf16 (FP32 data only) Sfrag2 is the bf16 table of packed quadruples
 // (v_mfma_f32_16x16x16_bf16 operands, rows permuted the same way).
 bool twice_folded_ok(int n, int elem_bytes);
@@ -441,6 +451,7 @@ hipError_t launch_resid_xfwd(int n, const T* u, const T* F, T* xhat, const Resid
                              double* partial, hipStream_t s);
 template <typename T>
 hipError_t launch_fused_pair2(int n, int nt, const T* in, T* out, const T* Sfrag2, const T* G, long long inner,
-                              long long outer, int transpose, T omega, int mode, hipStream_t s, bool bf16 = false);
+                              long long outer, int transpose, T omega, int mode, hipStream_t s, bool bf16 = false,
+                              const ModeEig<T>* me = nullptr);
 
 }  // namespace stmg

@@ -244,6 +244,59 @@ __device__ inline void inverse_operands(T o, T om, T e, T em, bool middle, T& u,
   ve = middle ? T(0) : e - em;
 }
 
+// Row l of the per-mode time block G (of G^T with transpose) for N_t <= 2 from
+// the eigenvalues: mode s along the pass axis, (P, Q) = (prod m, sum kappa prod
+// m) over the other axes of the lane's position.
+template <typename T, int NT>
+__device__ inline void mode_row(const ModeEig<T>& me, int n, T P, T Q, int s, int l, int transpose, T (&g)[NT]) {
+  const T ms = me.eig[s], ks = me.eig[n + s];
+  const T mu = P * ms, nu = Q * ms + P * ks;
+  if constexpr (NT == 1) {
+    g[0] = T(1) / (mu * me.K[0] + nu * me.M[0]);
+  } else {
+    const T d00 = mu * me.K[0] + nu * me.M[0], d01 = mu * me.K[1] + nu * me.M[1];
+    const T d10 = mu * me.K[2] + nu * me.M[2], d11 = mu * me.K[3] + nu * me.M[3];
+    const T det = d00 * d11 - d01 * d10;
+    T inv;
+    if constexpr (sizeof(T) == 8) {
+      // hardware reciprocal refined by two Newton steps r <- r + r (1 - det r): about one ulp, far
+      // cheaper than the IEEE division sequence (det > 0: the block is positive definite)
+      double r = __builtin_amdgcn_rcp(det);
+      r = __builtin_fma(r, __builtin_fma(-det, r, 1.0), r);
+      r = __builtin_fma(r, __builtin_fma(-det, r, 1.0), r);
+      inv = r;
+    } else {
+      inv = T(1) / det;
+    }
+    // G = inv [[d11, -d01], [-d10, d00]]
+    const T g00 = d11 * inv, g01 = -d01 * inv, g10 = -d10 * inv, g11 = d00 * inv;
+    if (l == 0) {
+      g[0] = g00;
+      g[1] = transpose ? g10 : g01;
+    } else {
+      g[0] = transpose ? g01 : g10;
+      g[1] = g11;
+    }
+  }
+}
+
+// (P, Q) of a position `pos` of the axes before the pass axis (spectral order).
+template <typename T>
+__device__ inline void mode_pq(const ModeEig<T>& me, int n, long long inner, long long pos, T& P, T& Q) {
+  if (inner == 1) {
+    P = T(1);
+    Q = T(0);
+  } else if (inner == n) {
+    P = me.eig[pos];
+    Q = me.eig[n + pos];
+  } else {
+    const int xs = (int)(pos % n), ys = (int)(pos / n);
+    const T mx = me.eig[xs], kx = me.eig[n + xs], my = me.eig[ys], ky = me.eig[n + ys];
+    P = mx * my;
+    Q = kx * my + mx * ky;
+  }
+}
+
 template <typename T, int HB2, bool INV, bool UNIT, bool BF>
 __global__ __launch_bounds__(256) void k_pass_reg2(const T* __restrict__ in, T* __restrict__ out,
                                                    const T* __restrict__ Sfrag, int n, long long inner_rt,
@@ -307,7 +360,8 @@ __global__ __launch_bounds__(256) void k_pass_reg2(const T* __restrict__ in, T* 
 template <typename T, int HB2, int NT, bool BF>
 __global__ __launch_bounds__(256) void k_fused_pair2(const T* in, T* out, const T* __restrict__ Sfrag,
                                                      const T* __restrict__ G, int n, long long inner,
-                                                     long long outer, int transpose, T omega, int mode) {
+                                                     long long outer, int transpose, T omega, int mode,
+                                                     ModeEig<T> me) {
   typedef typename Mfma<T>::acc_t acc_t;
   constexpr int CG = NT >= 3 ? 1 : 4 / NT;
   __shared__ T xch[4 * HB2][CG * NT * 64 * 4];
@@ -340,6 +394,8 @@ __global__ __launch_bounds__(256) void k_fused_pair2(const T* in, T* out, const 
       xch[3 * HB2 + kb][slot] = Pe - Qe;
     }
   __syncthreads();
+  T P0 = T(0), Q0 = T(0);
+  if (NT <= 2 && me.eig != nullptr && valid) mode_pq<T>(me, n, inner, pos, P0, Q0);
   // per-mode solve of this wave's component, then the inverse operands
   T op[4][4 * HB2];
 #pragma unroll
@@ -354,11 +410,23 @@ __global__ __launch_bounds__(256) void k_fused_pair2(const T* in, T* out, const 
       for (int q = 0; q < 4; ++q) {
         T a = T(0);
         if (valid) {
-          const T* gm = G + (pos + inner * (long long)mode_idx[q]) * (NT * NT);
+          bool done = false;
+          if constexpr (NT <= 2) {
+            if (me.eig != nullptr) {
+              T gr[NT];
+              mode_row<T, NT>(me, n, P0, Q0, mode_idx[q], l, transpose, gr);
 #pragma unroll
-          for (int m = 0; m < NT; ++m) {
-            const T v = xch[q * HB2 + kb][((cg * NT + m) * 64 + lane) * 4 + j];
-            a += (transpose ? gm[m * NT + l] : gm[l * NT + m]) * v;
+              for (int m = 0; m < NT; ++m) a += gr[m] * xch[q * HB2 + kb][((cg * NT + m) * 64 + lane) * 4 + j];
+              done = true;
+            }
+          }
+          if (!done) {
+            const T* gm = G + (pos + inner * (long long)mode_idx[q]) * (NT * NT);
+#pragma unroll
+            for (int m = 0; m < NT; ++m) {
+              const T v = xch[q * HB2 + kb][((cg * NT + m) * 64 + lane) * 4 + j];
+              a += (transpose ? gm[m * NT + l] : gm[l * NT + m]) * v;
+            }
           }
         }
         y[q] = a;
@@ -778,14 +846,17 @@ hipError_t launch_pass_reg2(int n, bool inverse, const T* in, T* out, const T* S
 
 template <typename T>
 hipError_t launch_fused_pair2(int n, int nt, const T* in, T* out, const T* Sfrag2, const T* G, long long inner,
-                              long long outer, int transpose, T omega, int mode, hipStream_t s, bool bf16) {
+                              long long outer, int transpose, T omega, int mode, hipStream_t s, bool bf16,
+                              const ModeEig<T>* me) {
+  ModeEig<T> mev{};
+  if (me != nullptr && nt <= 2) mev = *me;
   const int cg = nt >= 3 ? 1 : 4 / nt;
   const unsigned grid = (unsigned)((outer * inner + 16 * cg - 1) / (16 * cg));
   const dim3 block(64 * nt * cg);
 #define F2B(HB2, NT, B)                                                                                          \
   if (nt == NT) {                                                                                                \
     hipLaunchKernelGGL((k_fused_pair2<T, HB2, NT, B>), dim3(grid), block, 0, s, in, out, Sfrag2, G, n, inner,      \
-                       outer, transpose, omega, mode);                                                           \
+                       outer, transpose, omega, mode, mev);                                                      \
     return hipGetLastError();                                                                                    \
   }
 #define F2(HB2, NT)                                  \
@@ -867,8 +938,9 @@ template hipError_t launch_pass_reg2<double>(int, bool, const double*, double*, 
 template hipError_t launch_pass_reg2<float>(int, bool, const float*, float*, const float*, long long, long long,
                                             float, int, hipStream_t, bool);
 template hipError_t launch_fused_pair2<double>(int, int, const double*, double*, const double*, const double*,
-                                               long long, long long, int, double, int, hipStream_t, bool);
+                                               long long, long long, int, double, int, hipStream_t, bool,
+                                               const ModeEig<double>*);
 template hipError_t launch_fused_pair2<float>(int, int, const float*, float*, const float*, const float*, long long,
-                                              long long, int, float, int, hipStream_t, bool);
+                                              long long, int, float, int, hipStream_t, bool, const ModeEig<float>*);
 
 }  // namespace stmg
