@@ -230,6 +230,7 @@ struct SmallArgs {
   T omega;
   int transpose;    // apply G^T in the per-mode solve
   int u_zero;       // u_in is treated as zero (u_in may be null)
+  int s_lds;        // set by the launcher: the sine matrix is staged in LDS
 };
 // LDS bytes the small-level kernel needs (0 if the level does not qualify).
 size_t smooth_small_lds(int dim, int n, long long nx, int nt, size_t elem);

@@ -31,6 +31,7 @@ __device__ inline void coords(int j, int n, int& x, int& y, int& z) {
 }
 
 // one DST-I pass along `axis` over the NT components: out = S * in along the axis
+// (four independent partial sums per output, so that the loads of a row overlap)
 template <typename T, int D, int NT>
 __device__ inline void dst_axis(const T* __restrict__ S, const T* in, T* out, int n, int nx, int axis) {
   const int stride = axis == 0 ? 1 : (axis == 1 ? n : n * n);
@@ -39,15 +40,22 @@ __device__ inline void dst_axis(const T* __restrict__ S, const T* in, T* out, in
     const int k = (j / stride) % n;
     const int base = l * nx + j - k * stride;
     const T* srow = S + k * n;
-    T acc = T(0);
-    for (int i = 0; i < n; ++i) acc += srow[i] * in[base + i * stride];
-    out[e] = acc;
+    T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
+    int i = 0;
+    for (; i + 4 <= n; i += 4) {
+      a0 += srow[i] * in[base + i * stride];
+      a1 += srow[i + 1] * in[base + (i + 1) * stride];
+      a2 += srow[i + 2] * in[base + (i + 2) * stride];
+      a3 += srow[i + 3] * in[base + (i + 3) * stride];
+    }
+    for (; i < n; ++i) a0 += srow[i] * in[base + i * stride];
+    out[e] = (a0 + a1) + (a2 + a3);
   }
 }
 
 template <typename T, int D, int NT>
-__global__ __launch_bounds__(256) void k_smooth_small(const T* __restrict__ u_in, T* __restrict__ u_out,
-                                                      const T* __restrict__ F, const T* __restrict__ S,
+__global__ __launch_bounds__(512) void k_smooth_small(const T* __restrict__ u_in, T* __restrict__ u_out,
+                                                      const T* __restrict__ F, const T* __restrict__ Sg,
                                                       const T* __restrict__ G, SmallArgs<T> a) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   const ResidArgs<T>& ra = a.r;
@@ -57,12 +65,16 @@ __global__ __launch_bounds__(256) void k_smooth_small(const T* __restrict__ u_in
   T* W = U + NT * nx;                     // nx   (coupling combination of the neighbour slab)
   T* R = W + nx;                          // NT * nx
   T* Q = R + NT * nx;                     // NT * nx
+  T* Sl = Q + NT * nx;                    // n * n (the sine matrix, when a.s_lds)
   const long long slab = slab_index();
   if (slab >= (long long)ra.batch * ra.N) return;
   const int sn = (int)(slab % ra.N);
   const long long slabsz = (long long)NT * nx;
   const bool couple = !a.u_zero && sn + ra.dir >= 0 && sn + ra.dir < ra.N;
   for (int e = threadIdx.x; e < NT * nx; e += blockDim.x) U[e] = a.u_zero ? T(0) : u_in[slab * slabsz + e];
+  if (a.s_lds)
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) Sl[e] = Sg[e];
+  const T* S = a.s_lds ? Sl : Sg;
   for (int j = threadIdx.x; j < nx; j += blockDim.x) {
     T w = T(0);
     if (couple) {
@@ -171,10 +183,11 @@ __global__ __launch_bounds__(256) void k_copy(const T* __restrict__ in, T* __res
 }  // namespace
 
 size_t smooth_small_lds(int dim, int n, long long nx, int nt, size_t elem) {
-  (void)n;
   if (dim < 1 || dim > 3 || nt < 1 || nt > NT_MAX) return 0;
   const size_t bytes = (size_t)(3 * nt + 1) * (size_t)nx * elem;
-  return bytes <= 64 * 1024 ? bytes : 0;
+  if (bytes > 64 * 1024) return 0;
+  const size_t with_s = bytes + (size_t)n * n * elem;   // the sine matrix too, where it fits
+  return with_s <= 64 * 1024 ? with_s : bytes;
 }
 
 template <typename T>
@@ -182,10 +195,12 @@ hipError_t launch_smooth_small(int dim, int nt, const T* u_in, T* u_out, const T
                                const T* G, const SmallArgs<T>& a, hipStream_t s) {
   const size_t lds = smooth_small_lds(dim, a.r.n, a.r.nx, nt, sizeof(T));
   if (lds == 0) return hipErrorInvalidValue;
+  SmallArgs<T> b = a;
+  b.s_lds = lds > (size_t)(3 * nt + 1) * (size_t)a.r.nx * sizeof(T) ? 1 : 0;
   const dim3 grid = slab_grid(1, (long long)a.r.batch * a.r.N);
 #define SMALL_CASE(D, NT)                                                                     \
   if (dim == D && nt == NT) {                                                                 \
-    hipLaunchKernelGGL((k_smooth_small<T, D, NT>), grid, dim3(256), lds, s, u_in, u_out, F, Splain, G, a); \
+    hipLaunchKernelGGL((k_smooth_small<T, D, NT>), grid, dim3(512), lds, s, u_in, u_out, F, Splain, G, b); \
     return hipGetLastError();                                                                 \
   }
   SMALL_CASE(1, 1) SMALL_CASE(1, 2) SMALL_CASE(1, 3) SMALL_CASE(1, 4)
