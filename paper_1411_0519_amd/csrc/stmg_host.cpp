@@ -661,7 +661,7 @@ GenTransfer<T> gen_transfer(const st_mg* h, int lf) {
 
 unsigned resid_blocks(const st_mg* h, const Level& L) {
   if (h->mesh) return mesh_blocks_per_slab(L.nx);
-  return high_order(h) ? residual_gen_blocks_per_slab(L.nx) : residual_blocks_per_slab(h->p.dim, L.n, L.nx, h->nt);
+  return high_order(h) ? residual_gen_blocks_per_slab(L.nx) : residual_blocks_per_slab(h->p.dim, L.n, L.nx, h->nt, (long long)h->p.batch * L.N);
 }
 
 // ------------------------------------------------------------ P1 mesh data

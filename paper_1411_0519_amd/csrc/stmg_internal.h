@@ -62,7 +62,7 @@ hipError_t launch_residual(int dim, int nt, const Tin* u, const Tin* F, Tout* r,
 // Rows per 2-D tile of the residual and spatial smoothing kernels (0: n too
 // wide for one set of prefetched loads).
 int residual_tile_rows(int nt, int n);
-unsigned residual_blocks_per_slab(int dim, int n, long long nx, int nt);
+unsigned residual_blocks_per_slab(int dim, int n, long long nx, int nt, long long slabs);
 
 // Folded DST-I transforms (stmg_transform.hip).  hb = transform_half_blocks(n);
 // Sfrag = [dir fwd/inv][half odd/even][kb < hb][ib < 4 hb][64 lanes] fragments.

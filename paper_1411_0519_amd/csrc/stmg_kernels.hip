@@ -14,6 +14,8 @@
 //               (bi/tri)linear interpolation in space.
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
+
 #include "stmg_device.h"
 #include "stmg_internal.h"
 
@@ -214,6 +216,205 @@ __global__ __launch_bounds__(256) void k_residual_tile2d(const Tin* __restrict__
         for (int k = 0; k < NT; ++k) acc -= a.K[l * NT + k] * mu[k] + a.M[l * NT + k] * ku[k];
         rn[l * nx + o0 + e] = (Tout)acc;
         ss += (double)acc * (double)acc;
+      }
+    }
+  }
+  if (partial != nullptr) {
+    const double s2 = block_sum(ss);
+    if (threadIdx.x == 0) partial[slab * gridDim.x + tile] = s2;
+  }
+}
+
+// 3-D residual, marching in z.  One workgroup owns one slab, TY rows of y
+// (all x) and the z-planes z0 .. z1-1.  The separable 27-point stencils split
+// into planar parts: per plane p and component c, A_c(p) = (m (x) m) u_c(p) and
+// B_c(p) = (k (x) m + m (x) k) u_c(p) (y (x) x), and A_w(p) for the coupling
+// combination w = sum_k cb[k] u_{n+dir,k}.  Then
+//   (M_h u_c)(z) = sum_dz m[dz] A_c(z+dz),
+//   (K_h u_c)(z) = sum_dz k[dz] A_c(z+dz) + m[dz] B_c(z+dz),
+// so a thread keeps the planar values of three consecutive planes in
+// registers and every plane of u (and of the neighbour slab) is staged in LDS
+// once: rows y0-1 .. y0+TY (zero outside the domain), (NT + 1) (TY + 2) n
+// elements.  The next plane's loads and the next output plane's right-hand
+// side are issued before the current plane's stencils.  Planes -1 and n are
+// the Dirichlet boundary (zero).  Thread t of the BS threads owns output
+// positions t + BS i, i < OIT (TY n <= BS OIT), and staged positions
+// t + BS i, i < SIT ((TY + 2) n <= BS SIT).
+template <typename Tin, typename Tout, int NT, int BS, int OIT, int SIT>
+__global__ __launch_bounds__(BS) void k_residual_tile3d(const Tin* __restrict__ u,
+                                                            const Tin* __restrict__ F,
+                                                            Tout* __restrict__ r, ResidArgs<Tin> a,
+                                                            double* __restrict__ partial, int TY, int ZC) {
+  typedef Tin T;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  T* U = reinterpret_cast<T*>(lds_raw);
+  const long long lg = xcd_linear(blockIdx.x + (long long)gridDim.x * slab_index(),
+                                  (long long)gridDim.x * gridDim.y * gridDim.z);
+  const long long slab = lg / gridDim.x;
+  const int tile = (int)(lg - slab * gridDim.x);
+  const long long nslab = (long long)a.batch * a.N;
+  if (slab >= nslab) return;
+  const int n = a.n;
+  const long long nx = a.nx;
+  const long long nn = (long long)n * n;
+  const int nyt = (n + TY - 1) / TY;
+  const int yt = tile % nyt;
+  const int z0 = (tile / nyt) * ZC;
+  const int z1 = z0 + ZC < n ? z0 + ZC : n;
+  const int y0 = yt * TY;
+  const int ylast = y0 + TY < n ? y0 + TY : n;
+  const int plane = (TY + 2) * n;
+  const int nout = (ylast - y0) * n;
+  const int sn = (int)(slab % a.N);
+  const bool couple = (sn + a.dir >= 0) && (sn + a.dir < a.N);
+  const long long slabsz = (long long)NT * nx;
+  const T* un = u + slab * slabsz;
+  const T* up = u + (slab + a.dir) * slabsz;
+  const T* Fn = F + slab * slabsz;
+  Tout* rn = r + slab * slabsz;
+  const long long s0 = (long long)(y0 - 1) * n;   // first staged offset within a plane (may be -n)
+  const long long o0 = (long long)y0 * n;         // first output offset within a plane
+
+  // output positions of this thread
+  const float inv_n = 1.0f / (float)n;
+  int oy[OIT], ox[OIT];
+#pragma unroll
+  for (int i = 0; i < OIT; ++i) {
+    const int e = threadIdx.x + BS * i;
+    oy[i] = div_small(e, n, inv_n);
+    ox[i] = e - oy[i] * n;
+  }
+  T uv[SIT][NT], pv[SIT][NT];     // staged values of the next plane
+  T fv[OIT][NT], fn[OIT][NT];     // right-hand side of the output plane / the next one
+  T A[3][OIT][NT + 1], B[3][OIT][NT];
+#pragma unroll
+  for (int q = 0; q < 3; ++q)
+#pragma unroll
+    for (int i = 0; i < OIT; ++i) {
+#pragma unroll
+      for (int c = 0; c <= NT; ++c) A[q][i][c] = T(0);
+#pragma unroll
+      for (int c = 0; c < NT; ++c) B[q][i][c] = T(0);
+    }
+  auto load_plane = [&](int p) {
+    const bool pin = p >= 0 && p < n;
+    const long long po = (long long)p * nn;
+#pragma unroll
+    for (int i = 0; i < SIT; ++i) {
+      const int e = threadIdx.x + BS * i;
+      const long long so = s0 + e;
+      const bool in = pin && e < plane && so >= 0 && so < nn;
+#pragma unroll
+      for (int k = 0; k < NT; ++k) {
+        uv[i][k] = in ? un[k * nx + po + so] : T(0);
+        pv[i][k] = (in && couple) ? up[k * nx + po + so] : T(0);
+      }
+    }
+  };
+  auto load_rhs = [&](int p) {
+    const long long po = (long long)p * nn + o0;
+#pragma unroll
+    for (int i = 0; i < OIT; ++i) {
+      const int e = threadIdx.x + BS * i;
+#pragma unroll
+      for (int k = 0; k < NT; ++k) fn[i][k] = e < nout ? Fn[k * nx + po + e] : T(0);
+    }
+  };
+#pragma unroll
+  for (int i = 0; i < OIT; ++i)
+#pragma unroll
+    for (int k = 0; k < NT; ++k) fn[i][k] = T(0);
+  load_plane(z0 - 1);
+  double ss = 0.0;
+  for (int p = z0 - 1; p <= z1; ++p) {
+    __syncthreads();   // the previous plane's stencils are done with the LDS
+#pragma unroll
+    for (int i = 0; i < SIT; ++i) {
+      const int e = threadIdx.x + BS * i;
+      if (e < plane) {
+        T w = T(0);
+#pragma unroll
+        for (int k = 0; k < NT; ++k) {
+          U[k * plane + e] = uv[i][k];
+          w += a.cb[k] * pv[i][k];
+        }
+        U[NT * plane + e] = w;
+      }
+    }
+    // the right-hand side of this iteration's output plane p - 1 was loaded
+    // one iteration ago; load the one of plane p (output next iteration)
+#pragma unroll
+    for (int i = 0; i < OIT; ++i)
+#pragma unroll
+      for (int k = 0; k < NT; ++k) fv[i][k] = fn[i][k];
+    if (p < z1) load_plane(p + 1);
+    if (p >= z0 && p < z1) load_rhs(p);
+    __syncthreads();
+    // planar stencils of plane p; the window slides by one plane
+#pragma unroll
+    for (int i = 0; i < OIT; ++i) {
+#pragma unroll
+      for (int c = 0; c <= NT; ++c) {
+        A[0][i][c] = A[1][i][c];
+        A[1][i][c] = A[2][i][c];
+      }
+#pragma unroll
+      for (int c = 0; c < NT; ++c) {
+        B[0][i][c] = B[1][i][c];
+        B[1][i][c] = B[2][i][c];
+      }
+      const int e = threadIdx.x + BS * i;
+      if (e < nout) {
+        const int x = ox[i];
+        const bool hl = x > 0, hr = x < n - 1;
+#pragma unroll
+        for (int c = 0; c <= NT; ++c) {
+          T m = T(0), kk = T(0);
+#pragma unroll
+          for (int dr = 0; dr < 3; ++dr) {
+            const T* row = U + c * plane + (oy[i] + dr) * n + x;
+            const T l = hl ? row[-1] : T(0);
+            const T m0 = row[0];
+            const T rt = hr ? row[1] : T(0);
+            const T sm = a.wm[0] * l + a.wm[1] * m0 + a.wm[2] * rt;
+            m += a.wm[dr] * sm;
+            if (c < NT) {
+              const T sk = a.wk[0] * l + a.wk[1] * m0 + a.wk[2] * rt;
+              kk += a.wk[dr] * sm + a.wm[dr] * sk;
+            }
+          }
+          A[2][i][c] = m;
+          if (c < NT) B[2][i][c] = kk;
+          // one component's nine LDS reads at a time: keeps the register
+          // count (and with it the occupancy) of the FP64 kernel in check
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+    }
+    const int o = p - 1;   // output plane: needs planes o - 1, o, o + 1 = p
+    if (o >= z0) {
+      const long long po = (long long)o * nn + o0;
+#pragma unroll
+      for (int i = 0; i < OIT; ++i) {
+        const int e = threadIdx.x + BS * i;
+        if (e < nout) {
+          T mu[NT + 1], ku[NT];
+#pragma unroll
+          for (int c = 0; c <= NT; ++c)
+            mu[c] = a.wm[0] * A[0][i][c] + a.wm[1] * A[1][i][c] + a.wm[2] * A[2][i][c];
+#pragma unroll
+          for (int c = 0; c < NT; ++c)
+            ku[c] = a.wk[0] * A[0][i][c] + a.wk[1] * A[1][i][c] + a.wk[2] * A[2][i][c] +
+                    a.wm[0] * B[0][i][c] + a.wm[1] * B[1][i][c] + a.wm[2] * B[2][i][c];
+#pragma unroll
+          for (int l = 0; l < NT; ++l) {
+            T acc = fv[i][l] + a.ca[l] * mu[NT];
+#pragma unroll
+            for (int k = 0; k < NT; ++k) acc -= a.K[l * NT + k] * mu[k] + a.M[l * NT + k] * ku[k];
+            rn[l * nx + po + e] = (Tout)acc;
+            ss += (double)acc * (double)acc;
+          }
+        }
       }
     }
   }
@@ -464,10 +665,42 @@ int residual_tile_rows(int nt, int n) {
   return fit >= 1 ? fit : 0;
 }
 
-unsigned residual_blocks_per_slab(int dim, int n, long long nx, int nt) {
+// 3-D residual tiles: TY rows of y per workgroup (TY n <= 512 output
+// positions for N_t <= 2, 256 above) on 256 threads, two positions per thread
+// when TY n > 256 (STMG_RES3D_OIT=1: 512 threads with one each instead; on
+// 63^3 x 1024 slabs 3.4 ms against 3.0 ms), z-planes in chunks of ZC so that
+// a level has about 4096 workgroups or more (chunks of at least 8 planes).
+struct Res3dShape {
+  int ty, zc, nyt, nzt, bs, oit, sit;
+};
+Res3dShape residual3d_shape(int nt, int n, long long slabs) {
+  static const int oit_env = [] {
+    const char* e = std::getenv("STMG_RES3D_OIT");
+    return e ? std::atoi(e) : 2;
+  }();
+  Res3dShape sh{};
+  const int cap = nt <= 2 ? 512 : 256;
+  sh.ty = cap / n < 1 ? 1 : (cap / n > n ? n : cap / n);
+  sh.nyt = (n + sh.ty - 1) / sh.ty;
+  long long want = (4096 + (long long)sh.nyt * slabs - 1) / ((long long)sh.nyt * slabs);
+  const int maxc = (n + 7) / 8;
+  const int nzc = (int)(want < 1 ? 1 : (want > maxc ? maxc : want));
+  sh.zc = (n + nzc - 1) / nzc;
+  sh.nzt = (n + sh.zc - 1) / sh.zc;
+  sh.bs = (sh.ty * n > 256 && oit_env == 1) ? 512 : 256;
+  sh.oit = (sh.ty * n + sh.bs - 1) / sh.bs;
+  sh.sit = ((sh.ty + 2) * n + sh.bs - 1) / sh.bs;
+  return sh;
+}
+
+unsigned residual_blocks_per_slab(int dim, int n, long long nx, int nt, long long slabs) {
   if (dim == 2) {
     const int ty = residual_tile_rows(nt, n);
     return ty > 0 ? (unsigned)((n + ty - 1) / ty) : 0u;
+  }
+  if (dim == 3) {
+    const Res3dShape sh = residual3d_shape(nt, n, slabs);
+    return (unsigned)(sh.nyt * sh.nzt);
   }
   return (unsigned)((nx + 255) / 256);
 }
@@ -475,8 +708,26 @@ unsigned residual_blocks_per_slab(int dim, int n, long long nx, int nt) {
 template <typename Tin, typename Tout>
 hipError_t launch_residual(int dim, int nt, const Tin* u, const Tin* F, Tout* r,
                            const ResidArgs<Tin>& a, double* partial, hipStream_t s) {
-  const unsigned gx = residual_blocks_per_slab(dim, a.n, a.nx, nt);
-  const dim3 grid = slab_grid(gx, (long long)a.batch * a.N);
+  const long long slabs = (long long)a.batch * a.N;
+  const unsigned gx = residual_blocks_per_slab(dim, a.n, a.nx, nt, slabs);
+  const dim3 grid = slab_grid(gx, slabs);
+  if (dim == 3) {
+    const Res3dShape sh = residual3d_shape(nt, a.n, slabs);
+    const size_t lds = (size_t)(nt + 1) * (sh.ty + 2) * a.n * sizeof(Tin);
+#define RES3_CASE(NT, BS, OIT, SIT)                                                                    \
+  if (nt == NT && sh.bs == BS && sh.oit == OIT && sh.sit == SIT) {                                     \
+    hipLaunchKernelGGL((k_residual_tile3d<Tin, Tout, NT, BS, OIT, SIT>), grid, dim3(BS), lds, s, u, F, r, \
+                       a, partial, sh.ty, sh.zc);                                                     \
+    return hipGetLastError();                                                                          \
+  }
+#define RES3_NT(NT) RES3_CASE(NT, 256, 1, 1) RES3_CASE(NT, 256, 1, 2) RES3_CASE(NT, 256, 1, 3) \
+                    RES3_CASE(NT, 512, 1, 2) RES3_CASE(NT, 256, 2, 2) RES3_CASE(NT, 256, 2, 3) \
+                    RES3_CASE(NT, 256, 2, 4)
+    RES3_NT(1) RES3_NT(2) RES3_NT(3) RES3_NT(4)
+#undef RES3_NT
+#undef RES3_CASE
+    return hipErrorInvalidValue;
+  }
   if (dim == 2) {
     const int ty = residual_tile_rows(nt, a.n);
     if (ty == 0) return hipErrorInvalidValue;
@@ -502,7 +753,6 @@ hipError_t launch_residual(int dim, int nt, const Tin* u, const Tin* F, Tout* r,
     return hipGetLastError();                                                          \
   }
   RES_CASE(1, 1) RES_CASE(1, 2) RES_CASE(1, 3) RES_CASE(1, 4)
-  RES_CASE(3, 1) RES_CASE(3, 2) RES_CASE(3, 3) RES_CASE(3, 4)
 #undef RES_CASE
   return hipErrorInvalidValue;
 }
