@@ -198,6 +198,21 @@ int st_mg_rhs_adjoint(st_mg_t h, const void* lam, void* grad_f, void* grad_u0, v
  * doubles) receives ||r_b||_2^2 per right-hand side. */
 int st_mg_residual(st_mg_t h, int level, int prec, int transpose, const void* u, const void* F,
                    void* r, double* norms2, void* stream);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * residual and norms as st_mg_residual, with its per-workgroup partial sums
+ * and per-RHS sums kept in a static device array of the library instead of
+ * the workspace.  Needs no bound workspace and calls no allocating routine
+ * (no profiling events are recorded for it).  Limits: at most 2^20 partial
+ * sums (level-0 residual workgroups per slab x N x batch; e.g. 8 x 1024 for
+ * 63^3 x 1024 slabs) and batch <= 256, else ST_EINVAL before any device work.
+ * The array (8 MiB + 2 KiB per GPU) lives until the process ends and is
+ * shared by every handle on that GPU: calls that overlap on one GPU (other
+ * streams or host threads) race on it; calls on one stream are ordered.  Every
+ * partial sum is written before it is read, so nothing is cleared between
+ * calls.  norms2 (nullable, host) as in st_mg_residual, level 0 only. */
+int st_mg_residual_noalloc(st_mg_t h, int level, int prec, int transpose, const void* u, const void* F,
+                           void* r, double* norms2, void* stream);
 /* x = D^{-1} r, D = diag{A}: exact slab solves by fast diagonalisation. */
 int st_mg_block_solve(st_mg_t h, int level, int prec, int transpose, const void* r, void* x,
                       void* stream);

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -225,13 +226,49 @@ struct st_mg {
   // per-launch event pairs while profiling is on
   bool prof = false;
   std::vector<hipEvent_t> ev_pool;
+  // this device's copy of the static scratch array (st_mg_residual_noalloc),
+  // or nullptr with the reason in scratch_err
+  double* scratch = nullptr;
+  std::string scratch_err;
   size_t ev_used = 0;
   struct ProfRec { int kind, level; size_t e0, e1; };
   std::vector<ProfRec> prof_recs;
   std::string err;
 };
 
+// Static scratch of st_mg_residual_noalloc: per-workgroup partial sums of
+// r^2 (NOALLOC_PARTIALS doubles), then one sum per right-hand side
+// (NOALLOC_BATCH doubles); 8 MiB + 2 KiB.  Every GPU the library runs on
+// holds its own copy until the process ends.  Host code never names the
+// array: it uses the address hipGetSymbolAddress returns for the current
+// device (scratch_address below).
+constexpr long long NOALLOC_PARTIALS = 1LL << 20;
+constexpr int NOALLOC_BATCH = 256;
+static __device__ __align__(256) double scratch[NOALLOC_PARTIALS + NOALLOC_BATCH];
+
 namespace {
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// The current device's address of `scratch`, looked up once per device.
+hipError_t scratch_address(double** out) {
+  *out = nullptr;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = (double*)ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
 
 int fail(st_mg_t h, int code, const char* fmt, ...) {
   if (h) {
@@ -710,10 +747,14 @@ MeshRhsArgs<T> mesh_rhs_args(const st_mg* h) {
 }
 
 // ------------------------------------------------------------------ operators
+// partial / norm_out: where the per-workgroup partial sums of r^2 and the
+// per-RHS sums go when norms is set (nullptr: the workspace's buffers).
 template <typename Tin, typename Tout>
 int op_residual(st_mg* h, int l, bool transpose, const Tin* u, const Tin* F, Tout* r, bool norms,
-                hipStream_t s) {
+                hipStream_t s, double* partial = nullptr, double* norm_out = nullptr) {
   const Level& L = h->lv[l];
+  if (partial == nullptr) partial = h->partial;
+  if (norm_out == nullptr) norm_out = h->norm_dev;
   if (h->mesh) {
     const ResidArgs<Tin> ra = resid_args<Tin>(h, L, transpose);
     MeshResidArgs<Tin> a{};
@@ -730,20 +771,20 @@ int op_residual(st_mg* h, int l, bool transpose, const Tin* u, const Tin* F, Tou
     a.batch = h->p.batch;
     a.dir = ra.dir;
     ProfScope ps(h, ST_PROF_RESIDUAL, l, s);
-    HIPCHK(h, (launch_mesh_residual<Tin, Tout>(h->nt, u, F, r, a, norms ? h->partial : nullptr, s)));
+    HIPCHK(h, (launch_mesh_residual<Tin, Tout>(h->nt, u, F, r, a, norms ? partial : nullptr, s)));
   } else if (high_order(h)) {
     ProfScope ps(h, ST_PROF_RESIDUAL, l, s);
     HIPCHK(h, (launch_residual_gen<Tin, Tout>(h->p.dim, u, F, r, gen_args<Tin>(h, L, transpose),
-                                              norms ? h->partial : nullptr, s)));
+                                              norms ? partial : nullptr, s)));
   } else {
     const ResidArgs<Tin> a = resid_args<Tin>(h, L, transpose);
     ProfScope ps(h, ST_PROF_RESIDUAL, l, s);
-    HIPCHK(h, (launch_residual<Tin, Tout>(h->p.dim, h->nt, u, F, r, a, norms ? h->partial : nullptr, s)));
+    HIPCHK(h, (launch_residual<Tin, Tout>(h->p.dim, h->nt, u, F, r, a, norms ? partial : nullptr, s)));
   }
   if (norms) {
     ProfScope ps(h, ST_PROF_OTHER, l, s);
     const long long per = (long long)resid_blocks(h, L) * L.N;
-    HIPCHK(h, launch_norm_final(h->partial, per, h->p.batch, h->norm_dev, s));
+    HIPCHK(h, launch_norm_final(partial, per, h->p.batch, norm_out, s));
   }
   return ST_OK;
 }
@@ -1556,9 +1597,9 @@ size_t layout(st_mg* h, char* base) {
   return off;
 }
 
-int check_level(st_mg* h, int level, int prec, bool need_next) {
+// Level index and arithmetic of a level operator (no workspace needed).
+int check_level_args(st_mg* h, int level, int prec, bool need_next) {
   if (!h) return ST_EINVAL;
-  CHK(check_ready(h));
   if (level < 0 || level >= (int)h->lv.size() || (need_next && level + 1 >= (int)h->lv.size()))
     return fail(h, ST_EINVAL, "level %d out of range (levels: %zu)", level, h->lv.size());
   if (prec != ST_FP64 && prec != ST_FP32) return fail(h, ST_EINVAL, "prec must be ST_FP64 or ST_FP32");
@@ -1567,6 +1608,12 @@ int check_level(st_mg* h, int level, int prec, bool need_next) {
   if (prec == ST_FP32 && h->p.precision == ST_FP64)
     return fail(h, ST_EINVAL, "FP32 level operators need a handle set up with ST_FP32 or ST_MIXED(_BF16)");
   return ST_OK;
+}
+
+int check_level(st_mg* h, int level, int prec, bool need_next) {
+  if (!h) return ST_EINVAL;
+  CHK(check_ready(h));
+  return check_level_args(h, level, prec, need_next);
 }
 
 // ------------------------------------------------------------------ autotune
@@ -2088,6 +2135,10 @@ int setup_impl(const st_mg_params* p, st_mg_t* out, const st_mesh* mesh, int ref
     }
   }
   rc = setup_coarse_tail(h);
+  if (rc == ST_OK) {
+    const hipError_t e = scratch_address(&h->scratch);
+    if (e != hipSuccess) h->scratch_err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+  }
   *out = h;
   return rc;
 }
@@ -2310,6 +2361,45 @@ int st_mg_residual(st_mg_t h, int level, int prec, int transpose, const void* u,
                                    (float*)r, nrm, s)));
   if (nrm) {
     HIPCHK(h, hipMemcpyAsync(norms2, h->norm_dev, sizeof(double) * h->p.batch, hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+  }
+  return ST_OK;
+}
+
+int st_mg_residual_noalloc(st_mg_t h, int level, int prec, int transpose, const void* u, const void* F,
+                           void* r, double* norms2, void* stream) {
+  CHK(check_level_args(h, level, prec, false));
+  if (!u || !F || !r) return fail(h, ST_EINVAL, "null vector");
+  if (norms2 != nullptr && level != 0) return fail(h, ST_EINVAL, "norms only on level 0");
+  const bool nrm = norms2 != nullptr;
+  hipStream_t s = (hipStream_t)stream;
+  double* partial = nullptr;
+  double* sums = nullptr;
+  if (nrm) {
+    if (h->scratch == nullptr) return fail(h, ST_EHIP, "static scratch unavailable: %s", h->scratch_err.c_str());
+    const Level& L = h->lv[0];
+    const long long per = (long long)resid_blocks(h, L) * L.N;
+    if (h->p.batch > NOALLOC_BATCH || per * h->p.batch > NOALLOC_PARTIALS)
+      return fail(h, ST_EINVAL,
+                  "static scratch too small: %lld partial sums for %d right-hand sides (limits %lld and %d)",
+                  per * h->p.batch, h->p.batch, NOALLOC_PARTIALS, NOALLOC_BATCH);
+    partial = h->scratch;
+    sums = h->scratch + NOALLOC_PARTIALS;
+  }
+  // no profiling events here: creating them could allocate
+  const bool prof = h->prof;
+  h->prof = false;
+  int rc;
+  if (prec == ST_FP64)
+    rc = op_residual<double, double>(h, level, transpose != 0, (const double*)u, (const double*)F, (double*)r, nrm,
+                                     s, partial, sums);
+  else
+    rc = op_residual<float, float>(h, level, transpose != 0, (const float*)u, (const float*)F, (float*)r, nrm, s,
+                                   partial, sums);
+  h->prof = prof;
+  CHK(rc);
+  if (nrm) {
+    HIPCHK(h, hipMemcpyAsync(norms2, sums, sizeof(double) * h->p.batch, hipMemcpyDeviceToHost, s));
     HIPCHK(h, hipStreamSynchronize(s));
   }
   return ST_OK;

@@ -64,6 +64,7 @@ SIGNATURES = {
     "st_mg_rhs": (_i, [_vp, _vp, _vp, _vp, _vp]),
     "st_mg_rhs_adjoint": (_i, [_vp, _vp, _vp, _vp, _vp]),
     "st_mg_residual": (_i, [_vp, _i, _i, _i, _vp, _vp, _vp, _dp, _vp]),
+    "st_mg_residual_noalloc": (_i, [_vp, _i, _i, _i, _vp, _vp, _vp, _dp, _vp]),
     "st_mg_block_solve": (_i, [_vp, _i, _i, _i, _vp, _vp, _vp]),
     "st_mg_spatial_cycle": (_i, [_vp, _i, _i, _i, _vp, _vp, _vp]),
     "st_mg_smooth": (_i, [_vp, _i, _i, _i, _vp, _vp, _vp]),
@@ -298,6 +299,20 @@ class Solver:
         nrm = (ctypes.c_double * self.batch)() if norms else None
         self._check(lib().st_mg_residual(self._h, level, p, int(transpose), _ptr(u), _ptr(F), _ptr(r),
                                          nrm, _stream(self.device)))
+        return (r, [x ** 0.5 for x in nrm]) if norms else r
+
+    def residual_noalloc(self, u, F, level=0, prec=None, transpose=False, out=None, norms=False):
+        """As `residual`, through st_mg_residual_noalloc (norm partial sums in the
+        library's static device array; no workspace needed)."""
+        p = self._prec(prec)
+        dt = self._pdtype(p)
+        nd = self.level_dof(level)
+        u = self._vec(u, nd, dt, "u")
+        F = self._vec(F, nd, dt, "F")
+        r = out if out is not None else torch.empty(nd, dtype=dt, device=self.device)
+        nrm = (ctypes.c_double * self.batch)() if norms else None
+        self._check(lib().st_mg_residual_noalloc(self._h, level, p, int(transpose), _ptr(u), _ptr(F), _ptr(r),
+                                                 nrm, _stream(self.device)))
         return (r, [x ** 0.5 for x in nrm]) if norms else r
 
     def block_solve(self, r, level=0, prec=None, transpose=False, out=None):
