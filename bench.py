@@ -1,19 +1,23 @@
 """Benchmark: space-time multigrid V-cycles on one MI355X.
 
-Workload (default): 2-D heat equation on the unit square, Q1 with 127 x 127
-interior nodes, N = 256 DG(p_t=1) slabs on (0,1) (mu = tau/h^2 = 64),
-f = sum of 8 seeded Gaussian bumps, u0 = sin(pi x) sin(pi y); FP64.
+Headline workload: 3-D heat equation on the unit cube, Q1 with 63^3 interior
+nodes, N = 1024 DG(p_t=1) slabs on (0,1) (mu = tau/h^2 = 4, 512,096,256
+space-time DoF), f ~ U[-1,1] per node and slab (seed 3), u0 = 0; FP64.
 A step is one V-cycle of the whole hot path (residual, damped block-Jacobi
 smoothing by fast diagonalisation, restriction, prolongation, coarsest solve)
 plus the fine residual norm used by the stopping test.  Inputs are resident
 in HBM before the timed region starts.
 
 Prints one JSON line.  Besides DoF*V-cycles/s it reports the time to a 1e-10
-relative residual for the FP64 solve and for the mixed-precision solve (FP32
-inner V-cycle inside FP64 iterative refinement), the roofline position of the
-dominant kernel (per-launch durations from HIP events recorded by the library
-around each launch during a profiled pass of the same steps), and the CPU
-oracle timed on a bounded sample of the same workload family.
+relative residual for the FP64 solve and for the two mixed-precision solves
+(FP32 inner V-cycle inside FP64 iterative refinement, with FP32 or BF16
+matrix-core transforms) with their errors against the FP64 solution, the
+roofline position of the dominant fine-level kernel (algorithmic bytes per
+launch over the average launch duration, from HIP events the library records
+around each launch on its stream during a profiled pass of the same steps),
+the CPU oracle timed on a bounded sample of the same workload family, and
+secondary lines: the 2-D 127^2 x 256 workload, the paper's inexact smoother
+there, and the parallel example's P1 tetrahedral mesh.
 """
 import argparse
 import json
@@ -29,12 +33,18 @@ FP64_MFMA_PEAK_TFS = 78.6    # MI355X dense FP64 matrix
 FP32_MFMA_PEAK_TFS = 157.3   # MI355X dense FP32 matrix
 
 
+def progress(msg):
+    """One line per finished stage on stderr (the JSON result goes to stdout)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", type=int, default=2, help="workload index (1..5)")
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", type=int, default=3, help="headline workload index (1..5)")
+    ap.add_argument("--no-secondary", action="store_true", help="skip the 2-D 127^2 x 256 secondary line")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="launch kernels eagerly instead of replaying a hipGraph")
     ap.add_argument("--only-timed", action="store_true", help="timed V-cycles only (for profiler runs)")
@@ -169,21 +179,23 @@ def measure_p1(stmg, torch, dev, args):
 
 
 def cpu_baseline(budget_s=20.0):
-    """Oracle V-cycles on a reduced member of the same family (same mu, p_t)."""
+    """Oracle V-cycles on a reduced member of the headline family (3-D, same
+    mu = 4 and p_t = 1, seeded f ~ U[-1,1], u0 = 0)."""
     import numpy as np
 
     from oracle import multigrid, spacetime
     from paper_1411_0519_amd import workloads
 
-    d, n, N, pt = 2, 63, 64, 1      # mu = (1/64) * 64^2 = 64, like the 127^2 x 256 workload
+    d, n, N, pt = 3, 15, 64, 1      # mu = (1/64) * 16^2 = 4, like the 63^3 x 1024 workload
     t0 = time.perf_counter()
     H = multigrid.Hierarchy(d, n, N, pt)
-    f, u0 = workloads.make(d, n, N, batch=1, seed=2, f="bumps", u0="sine1")
+    f, u0 = workloads.make(d, n, N, batch=1, seed=3, f="uniform", u0="zero")
     F = spacetime.rhs(H.fine, f, u0)
-    setup = time.perf_counter() - t0
     k = len(H.levels) - 1
     u = np.zeros_like(F)
     H.vcycle(k, u, F)                 # factorisations happen on first use
+    setup = time.perf_counter() - t0
+    u = np.zeros_like(F)
     cycles = 0
     t0 = time.perf_counter()
     while True:
@@ -195,9 +207,9 @@ def cpu_baseline(budget_s=20.0):
             break
     rate = H.fine.dof * cycles / el
     return {"value": rate, "unit": "DoF*V-cycles/s", "cores": 1, "kind": "oracle",
-            "sample": f"2-D n={n} N={N} p_t={pt} (mu=64, {H.fine.dof} DoF), {cycles} V-cycles + residual "
-                      f"norm each, {el:.1f} s; setup {setup:.1f} s excluded; scipy CSR SpMV and SuperLU "
-                      f"solves run on one thread",
+            "sample": f"3-D n={n} N={N} p_t={pt} (mu=4 like the headline, schedule {H.schedule}, {H.fine.dof} DoF), "
+                      f"{cycles} V-cycles + residual norm each, {el:.1f} s; hierarchy, assembly and LU "
+                      f"factorisations ({setup:.1f} s) excluded; scipy CSR SpMV and SuperLU solves run on one thread",
             "host_cpus_available": len(os.sched_getaffinity(0))}
 
 
@@ -214,11 +226,12 @@ def tuned_levels(S, tuning):
             for k, t in enumerate(tuning[:-1])]
 
 
-def measured_traffic(workload_name, kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    record (FETCH_SIZE / WRITE_SIZE runs, scaled by a device copy of known
-    size), or None when there is no record or the kernel's source changed
-    since it was taken."""
+def measured_traffic(workload_name, kind):
+    """HBM bytes per fine-level launch of the kernel of `kind` from the
+    committed rocprofv3 counter record of the workload (FETCH_SIZE /
+    WRITE_SIZE runs, scaled by a device copy of known size), or None when
+    there is no record for that kind or the kernel's source changed since it
+    was taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"traffic_{workload_name}.json")
     if not os.path.exists(path):
@@ -226,7 +239,7 @@ def measured_traffic(workload_name, kernel):
     with open(path) as fh:
         rec = json.load(fh)
     src = os.path.join(ROOT, rec["source"])
-    if rec.get("kernel") != kernel or not os.path.exists(src):
+    if rec.get("kind") != kind or not os.path.exists(src):
         return None
     with open(src, "rb") as fh:
         if hashlib.sha256(fh.read()).hexdigest() != rec["source_sha256"]:
@@ -261,16 +274,171 @@ def spatial_cycle_bytes(levels, d, nt, b, nu1x=2, nu2x=2, elem=8):
     return out
 
 
+# Algorithmic HBM bytes per value of each fine-level kernel kind (element size
+# e): the residual reads u and F and writes r (the neighbour slab's values come
+# from cache); a transform pass reads and writes one vector; the last inverse
+# pass of a smoothing step also reads the old iterate (u += omega x).
+KIND_BYTES = {"residual": 3, "resid_x": 3, "pass_fwd": 2, "pass_fwd_y": 2, "fused": 2, "pass_inv_y": 2,
+              "pass_inv": 3}
+KIND_NAMES = {"residual": "residual r = F - L u", "resid_x": "residual fused with the forward x pass",
+              "pass_fwd": "forward sine pass along x", "pass_fwd_y": "forward sine pass along y",
+              "fused": "forward pass + per-mode time solve + inverse pass along the slowest axis",
+              "pass_inv_y": "inverse sine pass along y", "pass_inv": "inverse sine pass along x + update u += omega x"}
+TRANSFORM_KINDS = ("pass_fwd", "pass_fwd_y", "fused", "pass_inv_y", "pass_inv")
+
+
+def executed_flops_per_value(kind, n, twice):
+    """Matrix-core flops the folded kernels execute per value: a twice-folded
+    pass runs four (h/2) x (h/2) products per line of n values (h = (n+1)/2),
+    a once-folded one two h x h products; the fused kind runs a forward and an
+    inverse pass.  The dense sine transform would need 2 n."""
+    per_pass = 2.0 * ((n + 1) / 2) ** 2 / n if twice else 2.0 * 2 * ((n + 1) / 2) ** 2 / n
+    return per_pass * (2 if kind == "fused" else 1)
+
+
+def measure_workload(stmg, torch, idx, args, dev, steps, mixed=True):
+    """Throughput, time to 1e-10 (FP64 and the two mixed solves) and the
+    per-kind fine-level kernel table of one workload."""
+    from paper_1411_0519_amd import workloads
+    w = workloads.WORKLOADS[idx]
+    d, n, N, pt, b = w["dim"], w["n"], w["N"], w["pt"], w["batch"]
+    _, f, u0 = workloads.workload(idx)
+    out = {}
+    S = stmg.Solver(d, n, N, pt=pt, batch=b, device=dev)
+    F = S.rhs(torch.from_numpy(f.ravel()).to(dev), torch.from_numpy(u0.ravel()).to(dev))
+    del f, u0
+    dof = S.level_dof(0)
+    u = torch.zeros(dof, dtype=torch.float64, device=dev)
+    tuning = None if args.no_autotune else S.autotune()
+    if not args.no_graph:
+        S.set_graph(True)
+    S.solve(F, u=u, rtol=0.0, maxit=max(args.warmup, 1), raise_on_noconv=False)   # warmup (records the graph)
+    torch.cuda.synchronize()
+    u.zero_()
+    t0 = time.perf_counter()
+    _, its, _ = S.solve(F, u=u, rtol=0.0, maxit=steps, raise_on_noconv=False)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    assert its == steps
+    progress(f"{w['name']}: {steps} timed V-cycles, {1e3 * el / steps:.3f} ms each")
+    out.update(value=dof * steps / el, ms_per_step=1e3 * el / steps, dof=dof, schedule=S.schedule, levels=S.nlev,
+               autotuned_levels=tuned_levels(S, tuning), name=w["name"],
+               workload=f"{w['name']}: {d}-D Q1 {n}^{d} interior, N={N} slabs, DG p_t={pt}, batch {b}, FP64, "
+                        f"omega=1/2, nu1=nu2=2, schedule {S.schedule}")
+    if args.only_timed:
+        S.close()
+        return out
+    # time to a 1e-10 relative residual, FP64 (setup excluded)
+    u.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    u64, its64, hist64 = S.solve(F, u=u, rtol=1e-10, maxit=100)
+    torch.cuda.synchronize()
+    t64 = time.perf_counter() - t0
+    ttt = {"fp64_s": t64, "fp64_cycles": its64, "fp64_final_relres": hist64[-1][0]}
+    progress(f"{w['name']}: FP64 solve to 1e-10 in {its64} cycles, {t64:.3f} s")
+    # profiled pass (eager, HIP events around every launch on the launch stream)
+    S.set_graph(False)
+    u2 = torch.zeros_like(u)
+    S.solve(F, u=u2, rtol=0.0, maxit=2, raise_on_noconv=False)
+    S.profile_start()
+    S.solve(F, u=u2, rtol=0.0, maxit=steps, raise_on_noconv=False)
+    torch.cuda.synchronize()
+    kinds = list(stmg.PROF_KINDS)
+    prof = {}
+    for k in kinds:
+        tot, cnt = S.profile_read(k, level=-1)
+        tot0, cnt0 = S.profile_read(k, level=0)
+        prof[k] = {"ms_total": tot, "launches": cnt, "fine_ms_total": tot0, "fine_launches": cnt0}
+    S.profile_stop()
+    del u2
+    out["kernel_breakdown_ms_per_step"] = {k: v["ms_total"] / steps for k, v in prof.items() if v["launches"]}
+    out["profiled_ms_per_step"] = sum(v["ms_total"] for v in prof.values()) / steps
+    L0 = S.levels[0]
+    nvals = b * L0["N"] * S.nt * L0["n"] ** d
+    impl0 = 0 if tuning is None else tuning[0][1]
+    twice = impl0 in (0, 3, 5) and L0["n"] in (63, 127)
+    table = {}
+    for k, nb in KIND_BYTES.items():
+        v = prof.get(k)
+        if not v or not v["fine_launches"]:
+            continue
+        avg = v["fine_ms_total"] / v["fine_launches"]
+        by = nb * 8 * nvals
+        row = {"kernel": KIND_NAMES[k], "avg_launch_ms": avg, "launches": v["fine_launches"],
+               "ms_per_step": v["fine_ms_total"] / steps, "bytes_per_launch": by,
+               "hbm_gbs": by / (avg * 1e-3) / 1e9}
+        row["hbm_frac"] = row["hbm_gbs"] / HBM_PEAK_GBS
+        if k in TRANSFORM_KINDS:
+            ex = executed_flops_per_value(k, L0["n"], twice) * nvals
+            dense = 2.0 * L0["n"] * nvals * (2 if k == "fused" else 1)
+            row["executed_mfma_tflops"] = ex / (avg * 1e-3) / 1e12
+            row["executed_mfma_frac"] = row["executed_mfma_tflops"] / FP64_MFMA_PEAK_TFS
+            row["dense_equivalent_tflops"] = dense / (avg * 1e-3) / 1e12
+        table[k] = row
+    out["fine_level_kernels"] = table
+    out["fine_level_values"] = nvals
+    out["twice_folded"] = twice
+    if not args.no_graph:
+        S.set_graph(True)
+    if mixed:
+        for prec, key in (("mixed", "mixed"), ("mixed_bf16", "mixed_bf16")):
+            M = stmg.Solver(d, n, N, pt=pt, batch=b, device=dev, precision=prec)
+            tm_tuning = None if args.no_autotune else M.autotune()
+            if not args.no_graph:
+                M.set_graph(True)
+            um = torch.zeros_like(u)
+            M.solve(F, u=um, rtol=0.0, maxit=2, raise_on_noconv=False)   # warm + record graph
+            um.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            um, itsm, histm = M.solve(F, u=um, rtol=1e-10, maxit=100)
+            torch.cuda.synchronize()
+            tm = time.perf_counter() - t0
+            err = (torch.linalg.vector_norm(um - u64) / torch.linalg.vector_norm(u64)).item()
+            ttt.update({f"{key}_s": tm, f"{key}_cycles": itsm, f"speedup_{key}_vs_fp64": t64 / tm,
+                        f"{key}_rel_error_vs_fp64": err, f"{key}_final_relres": histm[-1][0]})
+            progress(f"{w['name']}: {prec} solve to 1e-10 in {itsm} cycles, {tm:.3f} s")
+            if key == "mixed":
+                ttt["mixed_inner_levels"] = tuned_levels(S, tm_tuning)
+            M.close()
+            del um
+    out["time_to_1e-10"] = ttt
+    out["_solver"], out["_F"], out["_u64"] = S, F, u64
+    return out
+
+
+def roofline_of(m):
+    """Roofline object of the fine-level kernel kind with the most time per step."""
+    table = m["fine_level_kernels"]
+    dom = max(table, key=lambda k: table[k]["ms_per_step"])
+    row = table[dom]
+    roof = {"kernel": row["kernel"] + ", fine level", "kind": dom, "bound": "hbm", "achieved": row["hbm_gbs"],
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": row["hbm_frac"], "traffic": None,
+            "avg_launch_ms": row["avg_launch_ms"], "launches": row["launches"],
+            "bytes_per_launch": row["bytes_per_launch"],
+            "bytes_basis": f"{KIND_BYTES[dom]} x 8 B per value x {m['fine_level_values']} values"}
+    if "executed_mfma_tflops" in row:
+        roof["mfma_executed"] = {"achieved": row["executed_mfma_tflops"], "peak": FP64_MFMA_PEAK_TFS,
+                                 "unit": "TFLOP/s", "frac": row["executed_mfma_frac"]}
+        roof["dense_equivalent_tflops"] = row["dense_equivalent_tflops"]
+    rec = measured_traffic(m["name"], dom)
+    if rec is not None:
+        roof["traffic"] = rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+        roof["traffic_read_write_bytes"] = [rec["fetch_bytes_per_launch"], rec["write_bytes_per_launch"]]
+        roof["traffic_kernel"] = rec["kernel"]
+    return roof
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "the solver runs on one GPU (one process, one device); multi-GPU runs are not supported, use --gpus 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
-    import numpy as np
     import torch
 
-    from paper_1411_0519_amd import stmg, workloads
+    from paper_1411_0519_amd import stmg
 
     dev = "cuda:0"
     if args.copy_probe:
@@ -286,191 +454,70 @@ def main():
         with torch.cuda.stream(torch.cuda.Stream(device=dev)):
             print(json.dumps({"p1_mesh": measure_p1(stmg, torch, dev, args)}))
         return
-    w = workloads.WORKLOADS[args.workload]
-    d, n, N, pt, b = w["dim"], w["n"], w["N"], w["pt"], w["batch"]
-    _, f, u0 = workloads.workload(args.workload)
     stream = torch.cuda.Stream(device=dev)
-    result = {}
     with torch.cuda.stream(stream):
-        S = stmg.Solver(d, n, N, pt=pt, batch=b, device=dev)
-        fg = torch.from_numpy(f.ravel()).to(dev)
-        ug0 = torch.from_numpy(u0.ravel()).to(dev)
-        F = S.rhs(fg, ug0)
-        dof = S.level_dof(0)
-        u = torch.zeros(dof, dtype=torch.float64, device=dev)
-        tuning = None if args.no_autotune else S.autotune()
-        if not args.no_graph:
-            S.set_graph(True)
-        # warmup (also records the graph)
-        S.solve(F, u=u, rtol=0.0, maxit=max(args.warmup, 1), raise_on_noconv=False)
-        torch.cuda.synchronize()
-        u.zero_()
-        t0 = time.perf_counter()
-        _, its, _ = S.solve(F, u=u, rtol=0.0, maxit=args.steps, raise_on_noconv=False)
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t0
-        assert its == args.steps
-        ms = 1e3 * el / args.steps
-        value = dof * args.steps / el
+        head = measure_workload(stmg, torch, args.workload, args, dev, args.steps)
         if args.only_timed:
-            print(json.dumps({"metric": "space-time DoF*V-cycles/s", "value": value, "ms_per_step": ms}))
+            print(json.dumps({"metric": "space-time DoF*V-cycles/s", "value": head["value"],
+                              "ms_per_step": head["ms_per_step"], "workload": head["workload"]}))
             return
-
-        # time to a 1e-10 relative residual, FP64 (setup excluded)
-        u.zero_()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        u64, its64, hist64 = S.solve(F, u=u, rtol=1e-10, maxit=100)
-        torch.cuda.synchronize()
-        t64 = time.perf_counter() - t0
-
-        # profiled pass (eager, HIP events around every launch)
-        S.set_graph(False)
-        u2 = torch.zeros_like(u)
-        S.solve(F, u=u2, rtol=0.0, maxit=2, raise_on_noconv=False)
-        S.profile_start()
-        S.solve(F, u=u2, rtol=0.0, maxit=args.steps, raise_on_noconv=False)
-        torch.cuda.synchronize()
-        kinds = ["residual", "resid_x", "pass_fwd", "pass_inv", "fused", "small", "restrict", "prolong", "other"]
-        prof = {}
-        for k in kinds:
-            tot, cnt = S.profile_read(k, level=-1)
-            tot0, cnt0 = S.profile_read(k, level=0)
-            prof[k] = {"ms_total": tot, "launches": cnt, "fine_ms_total": tot0, "fine_launches": cnt0}
-        S.profile_stop()
-        if not args.no_graph:
-            S.set_graph(True)
-
-        # mixed precision: FP32 inner V-cycle, FP64 refinement
-        M = stmg.Solver(d, n, N, pt=pt, batch=b, device=dev, precision="mixed")
-        tuning_mixed = None if args.no_autotune else M.autotune()
-        if not args.no_graph:
-            M.set_graph(True)
-        um = torch.zeros_like(u)
-        M.solve(F, u=um, rtol=0.0, maxit=2, raise_on_noconv=False)   # warm + record graph
-        um.zero_()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        um, itsm, histm = M.solve(F, u=um, rtol=1e-10, maxit=100)
-        torch.cuda.synchronize()
-        tm = time.perf_counter() - t0
-        err_mixed = (torch.linalg.vector_norm(um - u64) / torch.linalg.vector_norm(u64)).item()
-        M.close()
-
-        # mixed precision with the inner cycle's transforms on the bf16 matrix cores
-        B = stmg.Solver(d, n, N, pt=pt, batch=b, device=dev, precision="mixed_bf16")
-        if not args.no_autotune:
-            B.autotune()
-        if not args.no_graph:
-            B.set_graph(True)
-        ub = torch.zeros_like(u)
-        B.solve(F, u=ub, rtol=0.0, maxit=2, raise_on_noconv=False)
-        ub.zero_()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ub, itsb, histb = B.solve(F, u=ub, rtol=1e-10, maxit=100)
-        torch.cuda.synchronize()
-        tb = time.perf_counter() - t0
-        err_bf16 = (torch.linalg.vector_norm(ub - u64) / torch.linalg.vector_norm(u64)).item()
-        B.close()
-
+        S, F, u64 = head.pop("_solver"), head.pop("_F"), head.pop("_u64")
+        S.close()
+        del S, F, u64
+        torch.cuda.empty_cache()
+        secondary = None
         inexact = None
-        if not args.no_inexact:
-            inexact = measure_inexact(stmg, torch, d, n, N, pt, b, F, u64, dev, args)
+        if not args.no_secondary and args.workload != 2:
+            sec = measure_workload(stmg, torch, 2, args, dev, max(args.steps, 20))
+            S2, F2, u2 = sec.pop("_solver"), sec.pop("_F"), sec.pop("_u64")
+            sec["roofline"] = roofline_of(sec)
+            if not args.no_inexact:
+                from paper_1411_0519_amd import workloads
+                w2 = workloads.WORKLOADS[2]
+                inexact = measure_inexact(stmg, torch, 2, w2["n"], w2["N"], w2["pt"], 1, F2, u2, dev, args)
+            S2.close()
+            del S2, F2, u2
+            secondary = sec
         p1_mesh = None
         if not args.no_mesh:
             p1_mesh = measure_p1(stmg, torch, dev, args)
+            progress("P1 mesh workload done")
 
-    # roofline of the dominant transform kernel on the fine level.  Algorithmic
-    # work is the dense sine transform's: a length-n dot product (2n flop) per
-    # value per transform; the folded kernels execute about half of that on the
-    # matrix cores.  The fused kernel does a forward and an inverse transform.
-    L0 = S.levels[0]
-    nvals = b * L0["N"] * S.nt * L0["n"] ** d
-    cand = {k: v for k, v in prof.items() if k in ("pass_fwd", "pass_inv", "fused") and v["fine_launches"] > 0}
-    dom = max(cand, key=lambda k: cand[k]["fine_ms_total"])
-    avg_ms = cand[dom]["fine_ms_total"] / cand[dom]["fine_launches"]
-    transforms = 2 if dom == "fused" else 1
-    flops = transforms * 2.0 * L0["n"] * nvals
-    hbm_bytes = (24 if dom == "pass_inv" else 16) * nvals
-    achieved = flops / (avg_ms * 1e-3) / 1e12
-    impl0 = 0 if tuning is None else tuning[0][1]
-    # the default FP64 family at n = 63, 127 is twice folded (5: the same with the residual fused in)
-    twice = impl0 in (0, 3, 5) and L0["n"] in (63, 127)
-    if twice:
-        names = {"pass_fwd": "forward x pass (k_pass_reg2<double,2,false,true,false>, twice folded)",
-                 "pass_inv": "inverse x pass + update (k_pass_reg2<double,2,true,true,false>, twice folded)",
-                 "fused": "fused y pass: forward + time solve + inverse (k_fused_pair2<double,2,2,false>, twice folded, one wave per time component)"}
-        kernel_ids = {"pass_fwd": "k_pass_reg2<double, 2, false, true, false>",
-                      "pass_inv": "k_pass_reg2<double, 2, true, true, false>", "fused": "k_fused_pair2<double, 2, 2, false>"}
-        executed = flops * (L0["n"] + 1) / (4.0 * L0["n"])     # four (h/2)^2 products per column
-    else:
-        names = {"pass_fwd": "forward x pass (k_pass_reg<double,4,false>)", "pass_inv": "inverse x pass + update (k_pass_reg<double,4,true>)",
-                 "fused": "fused y pass: forward + time solve + inverse (k_fused_pair<double,4,2>: one wave per time component)"}
-        kernel_ids = {"pass_fwd": "k_pass_reg<double, 4, false, 2, true>", "pass_inv": "k_pass_reg<double, 4, true, 2, true>",
-                      "fused": "k_fused_pair<double, 4, 2>"}
-        executed = flops * (L0["n"] + 1) / (2.0 * L0["n"])     # two h^2 products per column
-    rec = measured_traffic(w["name"], kernel_ids[dom])
-    traffic = None if rec is None else rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
-    roof = {"kernel": names[dom] + ", fine level", "bound": "mfma", "achieved": achieved,
-            "peak": FP64_MFMA_PEAK_TFS, "unit": "TFLOP/s", "frac": achieved / FP64_MFMA_PEAK_TFS, "traffic": traffic,
-            "traffic_read_write_bytes": None if rec is None else [rec["fetch_bytes_per_launch"],
-                                                                  rec["write_bytes_per_launch"]],
-            "avg_launch_ms": avg_ms, "launches": cand[dom]["fine_launches"], "flops_per_launch": flops,
-            "executed_mfma_flops_per_launch": executed,
-            "hbm_bytes_per_launch": hbm_bytes, "hbm_gbs": hbm_bytes / (avg_ms * 1e-3) / 1e9}
-    r0 = prof["residual"]
-    res_avg = r0["fine_ms_total"] / max(r0["fine_launches"], 1)
-    res_bytes = 3 * 8 * nvals                           # read u, F; write r
-    res_gbs = res_bytes / (res_avg * 1e-3) / 1e9
-    rx0 = prof["resid_x"]                               # read u, F; write the x-transformed residual
-    rx_avg = rx0["fine_ms_total"] / rx0["fine_launches"] if rx0["fine_launches"] > 0 else None
-    total_prof = sum(v["ms_total"] for v in prof.values())
+    roof = roofline_of(head)
     out = {
         "metric": "space-time DoF*V-cycles/s (+ time-to-1e-10, mixed vs FP64)",
-        "value": value,
+        "value": head["value"],
         "unit": "DoF*V-cycles/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"{w['name']}: {d}-D Q1 {n}^{d} interior, N={N} slabs, DG p_t={pt}, "
-                               f"batch {b}, FP64, omega=1/2, nu1=nu2=2, schedule {S.schedule}",
-                   "dof": dof, "levels": S.nlev, "graph": not args.no_graph,
-                   "autotuned_levels": tuned_levels(S, tuning)},
-        "time_to_1e-10": {"fp64_s": t64, "fp64_cycles": its64, "mixed_s": tm, "mixed_cycles": itsm,
-                          "mixed_inner_levels": tuned_levels(S, tuning_mixed),
-                          "speedup_mixed_vs_fp64": t64 / tm,
-                          "mixed_rel_error_vs_fp64": err_mixed,
-                          "fp64_final_relres": hist64[-1][0], "mixed_final_relres": histm[-1][0],
-                          "mixed_bf16_s": tb, "mixed_bf16_cycles": itsb, "speedup_mixed_bf16_vs_fp64": t64 / tb,
-                          "mixed_bf16_rel_error_vs_fp64": err_bf16, "mixed_bf16_final_relres": histb[-1][0]},
+        "config": {"workload": head["workload"], "dof": head["dof"], "levels": head["levels"],
+                   "graph": not args.no_graph, "autotuned_levels": head["autotuned_levels"]},
+        "time_to_1e-10": head["time_to_1e-10"],
         "roofline": roof,
-        "residual_kernel": {"kernel": "k_residual_tile2d (fine level: residual norms and restriction)",
-                            "bound": "hbm", "achieved": res_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                            "frac": res_gbs / HBM_PEAK_GBS, "avg_launch_ms": res_avg,
-                            "launches": r0["fine_launches"], "bytes_per_launch": res_bytes},
-        "residual_xfwd_kernel": None if rx_avg is None else {
-            "kernel": "k_resid_xfwd (fine level: residual fused with the forward x pass, smoothing steps)",
-            "bound": "hbm", "achieved": res_bytes / (rx_avg * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": res_bytes / (rx_avg * 1e-3) / 1e9 / HBM_PEAK_GBS, "avg_launch_ms": rx_avg,
-            "launches": prof["resid_x"]["fine_launches"], "bytes_per_launch": res_bytes},
-        "kernel_breakdown_ms_per_step": {k: v["ms_total"] / args.steps for k, v in prof.items()},
-        "profiled_ms_per_step": total_prof / args.steps,
+        "fine_level_kernels": head["fine_level_kernels"],
+        "kernel_breakdown_ms_per_step": head["kernel_breakdown_ms_per_step"],
+        "profiled_ms_per_step": head["profiled_ms_per_step"],
     }
+    if secondary is not None:
+        for k in ("autotuned_levels", "dof", "levels", "schedule", "name"):
+            secondary.pop(k, None)
+        out["secondary_2d_127"] = secondary
     if inexact is not None:
-        out["inexact_smoother"] = inexact
+        out["inexact_smoother_2d_127"] = inexact
     if p1_mesh is not None:
         out["p1_mesh"] = p1_mesh
     if not args.no_cpu_baseline:
+        progress("CPU oracle sample")
         cb = cpu_baseline()
         out["cpu_baseline"] = cb
-        out["gpu_over_cpu"] = value / cb["value"]
+        out["gpu_over_cpu"] = head["value"] / cb["value"]
     print(json.dumps(out))
 
 

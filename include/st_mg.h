@@ -286,15 +286,17 @@ int st_mg_level_tuning(st_mg_t h, int level, int* small, int* impl, float* ms);
  * (level -1 = all levels). */
 enum {
   ST_PROF_RESIDUAL = 0,   /* r = F - L u                                          */
-  ST_PROF_PASS_FWD = 1,   /* forward sine-transform pass along x (and y in 3-D)   */
-  ST_PROF_PASS_INV = 2,   /* inverse pass (the last one applies the update)       */
+  ST_PROF_PASS_FWD = 1,   /* forward sine-transform pass along x                  */
+  ST_PROF_PASS_INV = 2,   /* inverse pass along x (applies the update)            */
   ST_PROF_FUSED = 3,      /* forward + per-mode time solve + inverse, slowest axis */
   ST_PROF_SMALL = 4,      /* whole smoothing step of a small level, one kernel     */
   ST_PROF_RESTRICT = 5, ST_PROF_PROLONG = 6, ST_PROF_OTHER = 7,
   ST_PROF_JACOBI = 8,     /* spatial cycle: block-Jacobi steps and defects        */
   ST_PROF_XFER_X = 9,     /* spatial cycle: restriction / prolongation in space   */
   ST_PROF_RESID_X = 10,   /* residual fused with the forward x pass               */
-  ST_PROF_KINDS = 11
+  ST_PROF_PASS_FWD_Y = 11, /* forward pass along another axis before the last    */
+  ST_PROF_PASS_INV_Y = 12, /* inverse pass along such an axis                     */
+  ST_PROF_KINDS = 13
 };
 int st_mg_profile_start(st_mg_t h);
 int st_mg_profile_stop(st_mg_t h);

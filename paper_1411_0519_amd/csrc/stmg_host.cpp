@@ -825,7 +825,9 @@ int op_block_solve(st_mg* h, int l, bool transpose, const T* src, T* dst, int mo
     long long rest = 1;
     for (int i = axis + 1; i < d; ++i) rest *= nn;
     const long long ncols = slabs * nt * rest * inner;
-    ProfScope ps(h, inv ? ST_PROF_PASS_INV : ST_PROF_PASS_FWD, l, s);
+    const int kind = axis == 0 ? (inv ? ST_PROF_PASS_INV : ST_PROF_PASS_FWD)
+                               : (inv ? ST_PROF_PASS_INV_Y : ST_PROF_PASS_FWD_Y);
+    ProfScope ps(h, kind, l, s);
     if (bf16_level<T>(h, L) && L.S2_16) {
       HIPCHK(h, launch_pass_reg2<float>(n, inv, (const float*)in, (float*)out, (const float*)L.S2_16, inner, ncols,
                                         (float)om, md, s, true));

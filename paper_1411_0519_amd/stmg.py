@@ -82,7 +82,7 @@ SIGNATURES = {
 }
 
 PROF_KINDS = {"residual": 0, "pass_fwd": 1, "pass_inv": 2, "fused": 3, "small": 4, "restrict": 5,
-              "prolong": 6, "other": 7, "jacobi": 8, "xfer_x": 9, "resid_x": 10}
+              "prolong": 6, "other": 7, "jacobi": 8, "xfer_x": 9, "resid_x": 10, "pass_fwd_y": 11, "pass_inv_y": 12}
 
 
 def lib():
