@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", type=int, default=3, help="headline workload index (1..5)")
     ap.add_argument("--no-secondary", action="store_true", help="skip the 2-D 127^2 x 256 secondary line")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched 255^2 x 512 x 64-RHS FP32 line")
+    ap.add_argument("--only-batched", action="store_true", help="only the batched line (for profiler runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="launch kernels eagerly instead of replaying a hipGraph")
     ap.add_argument("--only-timed", action="store_true", help="timed V-cycles only (for profiler runs)")
@@ -296,6 +298,117 @@ def executed_flops_per_value(kind, n, twice):
     return per_pass * (2 if kind == "fused" else 1)
 
 
+def kernel_table(prof, steps, nvals, n, elem, twice, mfma_peak):
+    """Per-kind fine-level rows: average launch, algorithmic HBM bytes and rate,
+    and for the transform kinds the executed matrix-core rate (and, apart, the
+    dense-equivalent rate)."""
+    table = {}
+    for k, nb in KIND_BYTES.items():
+        v = prof.get(k)
+        if not v or not v["fine_launches"]:
+            continue
+        avg = v["fine_ms_total"] / v["fine_launches"]
+        by = nb * elem * nvals
+        row = {"kernel": KIND_NAMES[k], "avg_launch_ms": avg, "launches": v["fine_launches"],
+               "ms_per_step": v["fine_ms_total"] / steps, "bytes_per_launch": by,
+               "hbm_gbs": by / (avg * 1e-3) / 1e9}
+        row["hbm_frac"] = row["hbm_gbs"] / HBM_PEAK_GBS
+        if k in TRANSFORM_KINDS:
+            ex = executed_flops_per_value(k, n, twice) * nvals
+            dense = 2.0 * n * nvals * (2 if k == "fused" else 1)
+            row["executed_mfma_tflops"] = ex / (avg * 1e-3) / 1e12
+            row["executed_mfma_frac"] = row["executed_mfma_tflops"] / mfma_peak
+            row["dense_equivalent_tflops"] = dense / (avg * 1e-3) / 1e12
+        table[k] = row
+    return table
+
+
+def profile_kinds(stmg, S, run):
+    """run() under the library's per-launch event profiling; per-kind totals (all
+    levels) and fine-level totals."""
+    S.profile_start()
+    run()
+    import torch
+    torch.cuda.synchronize()
+    prof = {}
+    for k in stmg.PROF_KINDS:
+        tot, cnt = S.profile_read(k, level=-1)
+        tot0, cnt0 = S.profile_read(k, level=0)
+        prof[k] = {"ms_total": tot, "launches": cnt, "fine_ms_total": tot0, "fine_launches": cnt0}
+    S.profile_stop()
+    return prof
+
+
+def measure_batched(stmg, torch, args, dev):
+    """The batched workload: 2-D Q1 255^2 x 512 slabs, p_t = 2, 64 right-hand
+    sides (f ~ U[-1,1], u0 = 16-mode sine series each) through one V-cycle in
+    FP32 with hipGraph replay; kernel families and launch shapes per level from
+    the autotuner.  Throughput, cycles and time to a 1e-4 relative residual
+    for every right-hand side (FP32 residuals of this operator stall near
+    1e-5), the tuned shapes and the fine-level kernel table with 4-byte
+    values."""
+    import numpy as np
+
+    from paper_1411_0519_amd import workloads
+    w = workloads.WORKLOADS[4]
+    d, n, N, pt, b = w["dim"], w["n"], w["N"], w["pt"], w["batch"]
+    nx = n ** d
+    S = stmg.Solver(d, n, N, pt=pt, batch=b, device=dev, precision="fp32")
+    fdev = torch.empty(b * N * nx, dtype=torch.float32, device=dev)
+    it, u0_fn = workloads.make_streamed(**w)
+    for i, fb in enumerate(it):
+        fdev[i * N * nx:(i + 1) * N * nx].copy_(torch.from_numpy(fb.astype(np.float32).ravel()))
+    u0 = torch.from_numpy(u0_fn().astype(np.float32).ravel()).to(dev)
+    F = S.rhs(fdev, u0)
+    del fdev, u0
+    progress(f"{w['name']}: data ready")
+    tuning = None if args.no_autotune else S.autotune()
+    progress(f"{w['name']}: autotuned")
+    shapes = [dict(level=k, **S.level_shape(k)) for k in range(S.nlev - 1)]
+    dof = S.level_dof(0)
+    steps = max(3, args.steps // 4)
+    u = torch.zeros_like(F)
+    if not args.no_graph:
+        S.set_graph(True)
+    S.solve(F, u=u, rtol=0.0, maxit=1, raise_on_noconv=False)
+    torch.cuda.synchronize()
+    u.zero_()
+    t0 = time.perf_counter()
+    S.solve(F, u=u, rtol=0.0, maxit=steps, raise_on_noconv=False)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    progress(f"{w['name']}: {steps} timed V-cycles, {1e3 * el / steps:.1f} ms each")
+    u.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, its, hist = S.solve(F, u=u, rtol=1e-4, maxit=30, raise_on_noconv=False)
+    torch.cuda.synchronize()
+    tsol = time.perf_counter() - t0
+    S.set_graph(False)
+    u.zero_()
+    prof = profile_kinds(stmg, S, lambda: S.solve(F, u=u, rtol=0.0, maxit=2, raise_on_noconv=False))
+    L0 = S.levels[0]
+    impl0 = 0 if tuning is None else tuning[0][1]
+    twice = impl0 in (0, 3, 5) and L0["n"] in (63, 127, 255)
+    nvals = b * L0["N"] * S.nt * L0["n"] ** d
+    table = kernel_table(prof, 2, nvals, L0["n"], 4, twice, FP32_MFMA_PEAK_TFS)
+    dom = max(table, key=lambda k: table[k]["ms_per_step"])
+    row = table[dom]
+    out = {"workload": f"{w['name']}: {d}-D Q1 {n}^{d} interior, N={N} slabs, DG p_t={pt}, batch {b} right-hand "
+                       f"sides in one V-cycle, FP32, hipGraph replay, omega=1/2, nu1=nu2=2, schedule {S.schedule}",
+           "dof": dof, "value": dof * steps / el, "unit": "DoF*V-cycles/s", "ms_per_step": 1e3 * el / steps,
+           "steps": steps, "time_to_1e-4_s": tsol, "cycles_to_1e-4": its,
+           "final_relres_max_over_rhs": max(hist[-1]), "autotuned_levels": tuned_levels(S, tuning),
+           "autotuned_shapes": shapes,
+           "roofline": {"kernel": row["kernel"] + ", fine level", "kind": dom, "bound": "hbm",
+                        "achieved": row["hbm_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": row["hbm_frac"],
+                        "avg_launch_ms": row["avg_launch_ms"], "bytes_per_launch": row["bytes_per_launch"]},
+           "fine_level_kernels": table,
+           "kernel_breakdown_ms_per_step": {k: v["ms_total"] / 2 for k, v in prof.items() if v["launches"]}}
+    S.close()
+    return out
+
+
 def measure_workload(stmg, torch, idx, args, dev, steps, mixed=True):
     """Throughput, time to 1e-10 (FP64 and the two mixed solves) and the
     per-kind fine-level kernel table of one workload."""
@@ -341,16 +454,7 @@ def measure_workload(stmg, torch, idx, args, dev, steps, mixed=True):
     S.set_graph(False)
     u2 = torch.zeros_like(u)
     S.solve(F, u=u2, rtol=0.0, maxit=2, raise_on_noconv=False)
-    S.profile_start()
-    S.solve(F, u=u2, rtol=0.0, maxit=steps, raise_on_noconv=False)
-    torch.cuda.synchronize()
-    kinds = list(stmg.PROF_KINDS)
-    prof = {}
-    for k in kinds:
-        tot, cnt = S.profile_read(k, level=-1)
-        tot0, cnt0 = S.profile_read(k, level=0)
-        prof[k] = {"ms_total": tot, "launches": cnt, "fine_ms_total": tot0, "fine_launches": cnt0}
-    S.profile_stop()
+    prof = profile_kinds(stmg, S, lambda: S.solve(F, u=u2, rtol=0.0, maxit=steps, raise_on_noconv=False))
     del u2
     out["kernel_breakdown_ms_per_step"] = {k: v["ms_total"] / steps for k, v in prof.items() if v["launches"]}
     out["profiled_ms_per_step"] = sum(v["ms_total"] for v in prof.values()) / steps
@@ -358,24 +462,7 @@ def measure_workload(stmg, torch, idx, args, dev, steps, mixed=True):
     nvals = b * L0["N"] * S.nt * L0["n"] ** d
     impl0 = 0 if tuning is None else tuning[0][1]
     twice = impl0 in (0, 3, 5) and L0["n"] in (63, 127)
-    table = {}
-    for k, nb in KIND_BYTES.items():
-        v = prof.get(k)
-        if not v or not v["fine_launches"]:
-            continue
-        avg = v["fine_ms_total"] / v["fine_launches"]
-        by = nb * 8 * nvals
-        row = {"kernel": KIND_NAMES[k], "avg_launch_ms": avg, "launches": v["fine_launches"],
-               "ms_per_step": v["fine_ms_total"] / steps, "bytes_per_launch": by,
-               "hbm_gbs": by / (avg * 1e-3) / 1e9}
-        row["hbm_frac"] = row["hbm_gbs"] / HBM_PEAK_GBS
-        if k in TRANSFORM_KINDS:
-            ex = executed_flops_per_value(k, L0["n"], twice) * nvals
-            dense = 2.0 * L0["n"] * nvals * (2 if k == "fused" else 1)
-            row["executed_mfma_tflops"] = ex / (avg * 1e-3) / 1e12
-            row["executed_mfma_frac"] = row["executed_mfma_tflops"] / FP64_MFMA_PEAK_TFS
-            row["dense_equivalent_tflops"] = dense / (avg * 1e-3) / 1e12
-        table[k] = row
+    table = kernel_table(prof, steps, nvals, L0["n"], 8, twice, FP64_MFMA_PEAK_TFS)
     out["fine_level_kernels"] = table
     out["fine_level_values"] = nvals
     out["twice_folded"] = twice
@@ -455,6 +542,10 @@ def main():
             print(json.dumps({"p1_mesh": measure_p1(stmg, torch, dev, args)}))
         return
     stream = torch.cuda.Stream(device=dev)
+    if args.only_batched:
+        with torch.cuda.stream(stream):
+            print(json.dumps({"batched": measure_batched(stmg, torch, args, dev)}))
+        return
     with torch.cuda.stream(stream):
         head = measure_workload(stmg, torch, args.workload, args, dev, args.steps)
         if args.only_timed:
@@ -478,6 +569,10 @@ def main():
             S2.close()
             del S2, F2, u2
             secondary = sec
+        batched = None
+        if not args.no_batched:
+            batched = measure_batched(stmg, torch, args, dev)
+            torch.cuda.empty_cache()
         p1_mesh = None
         if not args.no_mesh:
             p1_mesh = measure_p1(stmg, torch, dev, args)
@@ -511,6 +606,8 @@ def main():
         out["secondary_2d_127"] = secondary
     if inexact is not None:
         out["inexact_smoother_2d_127"] = inexact
+    if batched is not None:
+        out["batched_2d_255_b64_fp32"] = batched
     if p1_mesh is not None:
         out["p1_mesh"] = p1_mesh
     if not args.no_cpu_baseline:

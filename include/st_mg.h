@@ -279,6 +279,19 @@ int st_mg_autotune(st_mg_t h, void* u_scratch, void* F_scratch, void* stream);
  * 4 slab-resident, 5 twice folded with the residual fused into the forward x pass), tuned step ms. */
 int st_mg_level_tuning(st_mg_t h, int level, int* small, int* impl, float* ms);
 
+/* Launch shape of the twice-folded sine passes on one level (the autotuner
+ * picks it per level, i.e. per n, precision, batch and slab count, after the
+ * kernel family): waves per workgroup of the line passes (1, 2 or 4); a cap
+ * on their grid in workgroups per compute unit (0 = one 16-line group per
+ * wave; with a cap the workgroups are persistent and each wave loops over a
+ * contiguous range of groups); column groups of 16 per workgroup of the
+ * fused pass along the slowest axis (a power of two <= 4 / N_t; 0 = the
+ * largest); its grid cap (as above).  Results do not depend on the shape
+ * (every line is transformed by the same arithmetic).  set: ST_EINVAL for
+ * values outside these ranges; drops a recorded graph. */
+int st_mg_level_shape(st_mg_t h, int level, int* wpg, int* pass_per_cu, int* fused_cg, int* fused_per_cu);
+int st_mg_set_level_shape(st_mg_t h, int level, int wpg, int pass_per_cu, int fused_cg, int fused_per_cu);
+
 /* Per-kernel timing with HIP events recorded around every launch on the
  * launch stream (eager mode only; ST_ESTATE in graph mode).  start clears
  * previous records; read synchronises on the last event and returns the

@@ -122,6 +122,7 @@ struct Level {
   int small = -1;         // small-level smoother on (1) / off (0) for this level (-1: handle default)
   int rx = -1;            // residual fused with the forward x pass (1) / separate (0) (-1: handle default)
   float tuned_ms = 0.f;   // autotuned smoothing-step time
+  PassShape shape{};      // launch shape of the twice-folded passes (autotuned)
   void* u = nullptr;      // workspace vectors (inner precision), coarse levels only
   void* u2 = nullptr;     // second iterate buffer for the small-level smoother
   void* F = nullptr;
@@ -214,6 +215,7 @@ struct st_mg {
   long long partial_per_batch = 0;
   double* norm_dev = nullptr;
   int graph = 0;
+  int cus = 0;            // compute units of the device (caps of persistent grids)
   int impl = TRANSFORM_AUTO;
   bool small = true;      // one-kernel smoothing steps on levels whose slabs fit in LDS
   bool rx = false;        // residual fused with the forward x pass where it applies (autotuned per level)
@@ -789,6 +791,13 @@ int op_residual(st_mg* h, int l, bool transpose, const Tin* u, const Tin* F, Tou
   return ST_OK;
 }
 
+// The level's launch shape of the twice-folded passes with the device's CU count.
+PassShape level_shape(const st_mg* h, const Level& L) {
+  PassShape sh = L.shape;
+  sh.cus = h->cus;
+  return sh;
+}
+
 // Inner-cycle levels of ST_MIXED_BF16 run their transforms on the bf16 matrix cores.
 template <typename T>
 bool bf16_level(const st_mg* h, const Level& L) {
@@ -830,7 +839,7 @@ int op_block_solve(st_mg* h, int l, bool transpose, const T* src, T* dst, int mo
     ProfScope ps(h, kind, l, s);
     if (bf16_level<T>(h, L) && L.S2_16) {
       HIPCHK(h, launch_pass_reg2<float>(n, inv, (const float*)in, (float*)out, (const float*)L.S2_16, inner, ncols,
-                                        (float)om, md, s, true));
+                                        (float)om, md, s, true, level_shape(h, L)));
       return ST_OK;
     }
     if (bf16_level<T>(h, L)) {
@@ -840,7 +849,7 @@ int op_block_solve(st_mg* h, int l, bool transpose, const T* src, T* dst, int mo
     int impl = L.impl >= 0 ? L.impl : h->impl;
     if (impl == TRANSFORM_SLAB) impl = TRANSFORM_AUTO;   // levels the slab kernel does not take
     if ((impl == TRANSFORM_REG2 || impl == TRANSFORM_AUTO) && S2of<T>(L)) {
-      HIPCHK(h, launch_pass_reg2<T>(n, inv, in, out, S2of<T>(L), inner, ncols, om, md, s));
+      HIPCHK(h, launch_pass_reg2<T>(n, inv, in, out, S2of<T>(L), inner, ncols, om, md, s, false, level_shape(h, L)));
       return ST_OK;
     }
     HIPCHK(h, launch_dst_pass<T>(impl, L.hb, axis == 0, inv, in, out, Sof<T>(L), n, inner, ncols, om, md, s));
@@ -864,7 +873,7 @@ int op_block_solve(st_mg* h, int l, bool transpose, const T* src, T* dst, int mo
     if (bf16_level<T>(h, L) && L.S2_16) {
       HIPCHK(h, launch_fused_pair2<float>(n, nt, (const float*)in, (float*)out, (const float*)L.S2_16,
                                           (const float*)Gof<T>(L), inner, slabs, transpose ? 1 : 0, (float)om, md, s,
-                                          true, (const ModeEig<float>*)mep));
+                                          true, (const ModeEig<float>*)mep, level_shape(h, L)));
       return ST_OK;
     }
     if (bf16_level<T>(h, L)) {
@@ -876,7 +885,7 @@ int op_block_solve(st_mg* h, int l, bool transpose, const T* src, T* dst, int mo
     if (impl == TRANSFORM_SLAB) impl = TRANSFORM_AUTO;
     if ((impl == TRANSFORM_REG2 || impl == TRANSFORM_AUTO) && S2of<T>(L)) {
       HIPCHK(h, launch_fused_pair2<T>(n, nt, in, out, S2of<T>(L), Gof<T>(L), inner, slabs, transpose ? 1 : 0, om, md,
-                                      s, false, mep));
+                                      s, false, mep, level_shape(h, L)));
       return ST_OK;
     }
     HIPCHK(h, launch_dst_fused<T>(impl, L.hb, nt, in, out, Sof<T>(L), Gof<T>(L), n, inner, slabs,
@@ -1628,6 +1637,7 @@ int tune_level(st_mg* h, int l, T* u, T* F, T* r, T* alt, hipStream_t s) {
   const long long len = L.dof(h->nt, h->p.batch);
   HIPCHK(h, launch_fill<T>(u, len, s));
   HIPCHK(h, launch_fill<T>(F, len, s));
+  L.shape = PassShape{};
   struct Cand { int small, impl, rx; };
   std::vector<Cand> cands;
   const bool can_small = !high_order(h) && smooth_small_lds(h->p.dim, L.n, L.nx, h->nt, sizeof(T)) > 0;
@@ -1650,12 +1660,10 @@ int tune_level(st_mg* h, int l, T* u, T* F, T* r, T* alt, hipStream_t s) {
   Cand pick = cands.front();
   const bool prof = h->prof;
   h->prof = false;
-  for (const Cand& c : cands) {
-    L.small = c.small;
-    L.impl = c.impl;
-    L.rx = c.rx;
+  // best of five smoothing steps of the level's current choice (ms; 1e30 on failure)
+  auto time_step = [&]() -> float {
     auto step = [&]() -> int {
-      if (c.small) return op_smooth_small<T>(h, l, false, u, alt, F, false, s);
+      if (L.small == 1) return op_smooth_small<T>(h, l, false, u, alt, F, false, s);
       return smooth_step<T>(h, l, false, u, F, r, (T*)h->tmp, s);
     };
     int rc = step();
@@ -1676,17 +1684,64 @@ int tune_level(st_mg* h, int l, T* u, T* F, T* r, T* alt, hipStream_t s) {
       (void)hipEventElapsedTime(&t, e0, e1);
       ms = std::min(ms, t);
     }
-    if (rc == ST_OK && ms < best) {
+    return rc == ST_OK ? ms : 1e30f;
+  };
+  for (const Cand& c : cands) {
+    L.small = c.small;
+    L.impl = c.impl;
+    L.rx = c.rx;
+    const float ms = time_step();
+    if (ms < best) {
       best = ms;
       pick = c;
     }
   }
-  h->prof = prof;
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   L.small = pick.small;
   L.impl = pick.impl;
   L.rx = pick.rx;
+  // launch shape of the twice-folded passes the pick runs: waves per workgroup
+  // of the line passes, persistent grids (workgroups per compute unit) and
+  // column groups per workgroup of the fused pass, one knob at a time
+  const int impl_pick = pick.impl >= 0 ? pick.impl : h->impl;
+  const bool uses_reg2 = !pick.small && !high_order(h) && !slab_level<T>(h, L) &&
+                         ((bf16_level<T>(h, L) && L.S2_16) ||
+                          ((impl_pick == TRANSFORM_AUTO || impl_pick == TRANSFORM_REG2) && S2of<T>(L)));
+  if (uses_reg2) {
+    PassShape bsh = L.shape;
+    auto try_shape = [&](const PassShape& c) {
+      L.shape = c;
+      const float ms = time_step();
+      if (ms < best) {
+        best = ms;
+        bsh = c;
+      }
+    };
+    for (int wpg : {2, 1}) {
+      PassShape c = bsh;
+      c.wpg = wpg;
+      try_shape(c);
+    }
+    for (int pc : {2, 4, 8}) {
+      PassShape c = bsh;
+      c.pass_per_cu = pc;
+      try_shape(c);
+    }
+    const int cgmax = h->nt >= 3 ? 1 : 4 / h->nt;
+    for (int cg = 1; cg < cgmax; cg *= 2) {
+      PassShape c = bsh;
+      c.fused_cg = cg;
+      try_shape(c);
+    }
+    for (int pc : {2, 4, 8}) {
+      PassShape c = bsh;
+      c.fused_per_cu = pc;
+      try_shape(c);
+    }
+    L.shape = bsh;
+  }
+  h->prof = prof;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   L.tuned_ms = best;
   return ST_OK;
 }
@@ -2138,6 +2193,12 @@ int setup_impl(const st_mg_params* p, st_mg_t* out, const st_mesh* mesh, int ref
   }
   rc = setup_coarse_tail(h);
   if (rc == ST_OK) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&h->cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      h->cus = 0;
+  }
+  if (rc == ST_OK) {
     const hipError_t e = scratch_address(&h->scratch);
     if (e != hipSuccess) h->scratch_err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
   }
@@ -2540,6 +2601,34 @@ int st_mg_level_tuning(st_mg_t h, int level, int* small, int* impl, float* ms) {
   if (small) *small = L.small >= 0 ? L.small : (h->small ? 1 : 0);
   if (impl) *impl = L.rx == 1 ? 5 : (L.impl >= 0 ? L.impl : h->impl);   // 5: twice folded, residual fused in
   if (ms) *ms = L.tuned_ms;
+  return ST_OK;
+}
+
+int st_mg_level_shape(st_mg_t h, int level, int* wpg, int* pass_per_cu, int* fused_cg, int* fused_per_cu) {
+  if (!h || level < 0 || level >= (int)h->lv.size()) return ST_EINVAL;
+  const PassShape& sh = h->lv[level].shape;
+  if (wpg) *wpg = sh.wpg;
+  if (pass_per_cu) *pass_per_cu = sh.pass_per_cu;
+  if (fused_cg) *fused_cg = sh.fused_cg != 0 ? sh.fused_cg : (h->nt >= 3 ? 1 : 4 / h->nt);
+  if (fused_per_cu) *fused_per_cu = sh.fused_per_cu;
+  return ST_OK;
+}
+
+int st_mg_set_level_shape(st_mg_t h, int level, int wpg, int pass_per_cu, int fused_cg, int fused_per_cu) {
+  if (!h || level < 0 || level >= (int)h->lv.size()) return ST_EINVAL;
+  const int cgmax = h->nt >= 3 ? 1 : 4 / h->nt;
+  if (!(wpg == 1 || wpg == 2 || wpg == 4) || pass_per_cu < 0 || fused_per_cu < 0 || fused_cg < 0 ||
+      fused_cg > cgmax || (fused_cg & (fused_cg - 1)) != 0)
+    return fail(h, ST_EINVAL, "shape: wpg in {1,2,4}, fused_cg a power of two <= %d (0 = default), caps >= 0", cgmax);
+  PassShape& sh = h->lv[level].shape;
+  sh.wpg = wpg;
+  sh.pass_per_cu = pass_per_cu;
+  sh.fused_cg = fused_cg;
+  sh.fused_per_cu = fused_per_cu;
+  if (h->gc.exec) {   // a recorded graph holds the old launch shapes
+    (void)hipGraphExecDestroy(h->gc.exec);
+    h->gc.exec = nullptr;
+  }
   return ST_OK;
 }
 

@@ -433,9 +433,23 @@ struct ModeEig {
 // (v_mfma_f32_16x16x16_bf16 operands, rows permuted the same way).
 bool twice_folded_ok(int n, int elem_bytes);
 inline int twice_fold_row(int elem_bytes, int i) { return elem_bytes == 8 ? i : (i >> 2) + 4 * (i & 3); }
+// Launch shape of the twice-folded pass kernels, chosen per level by the
+// autotuner: waves per workgroup of the line passes (1, 2, 4), workgroups per
+// compute unit when the grid is capped (persistent workgroups looping over
+// contiguous ranges of tiles; 0 = one tile per wave / workgroup), column
+// groups of 16 per workgroup of the fused pass (0 = 4 / N_t for N_t <= 2),
+// and the compute-unit count the caps refer to.
+struct PassShape {
+  int wpg = 4;
+  int pass_per_cu = 0;
+  int fused_cg = 0;
+  int fused_per_cu = 0;
+  int cus = 0;
+};
 template <typename T>
 hipError_t launch_pass_reg2(int n, bool inverse, const T* in, T* out, const T* Sfrag2, long long inner,
-                            long long ncols, T omega, int mode, hipStream_t s, bool bf16 = false);
+                            long long ncols, T omega, int mode, hipStream_t s, bool bf16 = false,
+                            const PassShape& sh = PassShape{});
 // 2-D slab-resident block solve with the twice-folded passes (one workgroup
 // per slab, slab in LDS; FP64 n = 63, FP32 n = 63, 127; N_t <= 2): LDS bytes,
 // 0 when the level does not qualify.
@@ -453,6 +467,6 @@ hipError_t launch_resid_xfwd(int n, const T* u, const T* F, T* xhat, const Resid
 template <typename T>
 hipError_t launch_fused_pair2(int n, int nt, const T* in, T* out, const T* Sfrag2, const T* G, long long inner,
                               long long outer, int transpose, T omega, int mode, hipStream_t s, bool bf16 = false,
-                              const ModeEig<T>* me = nullptr);
+                              const ModeEig<T>* me = nullptr, const PassShape& sh = PassShape{});
 
 }  // namespace stmg

@@ -297,16 +297,15 @@ __device__ inline void mode_pq(const ModeEig<T>& me, int n, long long inner, lon
   }
 }
 
+// One pass along an axis: a wave transforms the group of 16 lines gi.
 template <typename T, int HB2, bool INV, bool UNIT, bool BF>
-__global__ __launch_bounds__(256) void k_pass_reg2(const T* __restrict__ in, T* __restrict__ out,
-                                                   const T* __restrict__ Sfrag, int n, long long inner_rt,
-                                                   long long ncols, T omega, int mode) {
+__device__ __forceinline__ void pass2_group(const T* __restrict__ in, T* __restrict__ out,
+                                            const T* __restrict__ Sf, int n, long long inner, long long ncols,
+                                            T omega, int mode, long long gi) {
   typedef typename Mfma<T>::acc_t acc_t;
-  const long long inner = UNIT ? 1 : inner_rt;
   const int lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
-  const long long wv = xcd_linear(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
   const int h = (n + 1) >> 1;
-  const long long lin = wv * 16 + r;
+  const long long lin = gi * 16 + r;
   const bool valid = lin < ncols;
   const long long o = valid ? lin / inner : 0;
   const long long pos = valid ? lin - o * inner : 0;
@@ -334,7 +333,7 @@ __global__ __launch_bounds__(256) void k_pass_reg2(const T* __restrict__ in, T* 
   if (INV && mode == MODE_ADD_SCALED) load_old<T, HB2>(out + base, valid, inner, n, g, old);
   else zero_old<T, HB2>(old);
   acc_t acc[4][HB2];
-  mma4<T, HB2, INV ? 1 : 0, BF>(Sfrag, lane, [&](int m, int ib) { return op[m][ib]; }, acc);
+  mma4<T, HB2, INV ? 1 : 0, BF>(Sf, lane, [&](int m, int ib) { return op[m][ib]; }, acc);
   if (!INV) {
     if (valid) {
 #pragma unroll
@@ -354,32 +353,165 @@ __global__ __launch_bounds__(256) void k_pass_reg2(const T* __restrict__ in, T* 
   }
 }
 
+// Orders one wave's LDS writes before its later reads by other lanes.
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Unit-stride pass (along x) through LDS: the 16 lines of group gi are one
+// contiguous run of 16 n values, loaded with consecutive lanes on consecutive
+// values (eight loads in flight per lane), transformed from the wave's LDS
+// buffer, written back there and stored the same way; the update reads the
+// old iterate at the store.  Same arithmetic as the strided path.  buf: 16 n
+// values of this wave.
+template <typename T, int HB2, bool INV, bool BF>
+__device__ __forceinline__ void pass2_group_staged(const T* __restrict__ in, T* __restrict__ out,
+                                                   const T* __restrict__ Sf, int n, long long ncols, T omega,
+                                                   int mode, long long gi, T* buf) {
+  typedef typename Mfma<T>::acc_t acc_t;
+  const int lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
+  const int h = (n + 1) >> 1;
+  const long long first = gi * 16;
+  if (first >= ncols) return;
+  const int lines = ncols - first < 16 ? (int)(ncols - first) : 16;
+  const int cnt = lines * n;
+  const long long off = first * (long long)n;
+#pragma unroll 1
+  for (int e0 = 0; e0 < cnt; e0 += 64 * 8) {
+    T v[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int e = e0 + 64 * i + lane;
+      v[i] = e < cnt ? in[off + e] : T(0);
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int e = e0 + 64 * i + lane;
+      if (e < cnt) buf[e] = v[i];
+    }
+  }
+  wave_lds_sync();
+  const bool valid = r < lines;
+  T* lp = buf + (valid ? r : 0) * n;
+  T op[4][4 * HB2];
+  if (!INV) {
+    load_twice_folded<T, HB2, int>(lp, valid, 1, n, g, op);
+  } else {
+#pragma unroll
+    for (int ib = 0; ib < 4 * HB2; ++ib) {
+      const int s = cidx(ib, g);
+      const bool middle = s == h / 2 - 1;
+      T yo = 0, yom = 0, ye = 0, yem = 0;
+      if (valid) {
+        yo = lp[s];
+        yom = lp[h - 1 - s];
+        ye = lp[h + s];
+        if (!middle) yem = lp[h + h - 2 - s];
+      }
+      inverse_operands<T>(yo, yom, ye, yem, middle, op[0][ib], op[1][ib], op[2][ib], op[3][ib]);
+    }
+  }
+  acc_t acc[4][HB2];
+  mma4<T, HB2, INV ? 1 : 0, BF>(Sf, lane, [&](int m, int ib) { return op[m][ib]; }, acc);
+  wave_lds_sync();
+  if (!INV) {
+    if (valid) {
+#pragma unroll
+      for (int kb = 0; kb < HB2; ++kb)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int s = orow(kb, g, j);
+          const T P = acc[0][kb][j], Q = acc[1][kb][j], Pe = acc[2][kb][j], Qe = acc[3][kb][j];
+          lp[s] = P + Q;
+          lp[h - 1 - s] = P - Q;
+          lp[h + s] = Pe + Qe;
+          if (s != h / 2 - 1) lp[h + h - 2 - s] = Pe - Qe;
+        }
+    }
+  } else {
+    T none[HB2][4][4];
+    zero_old<T, HB2>(none);
+    store_twice_unfolded<T, HB2, false, int>(lp, valid, 1, n, g, acc, MODE_STORE, T(1), none);
+  }
+  wave_lds_sync();
+#pragma unroll 1
+  for (int e0 = 0; e0 < cnt; e0 += 64 * 8) {
+    T o[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int e = e0 + 64 * i + lane;
+      o[i] = (e < cnt && mode == MODE_ADD_SCALED) ? out[off + e] : T(0);
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int e = e0 + 64 * i + lane;
+      if (e < cnt) out[off + e] = epi<T>(mode, o[i], buf[e], omega);
+    }
+  }
+}
+
+// A pass along an axis, a wave per group of 16 lines, workgroups of
+// blockDim.x / 64 waves.  PERSIST: the grid is smaller than the group count
+// (persistent workgroups); each wave takes a contiguous range of groups and
+// the waves of one XCD cover neighbouring ranges.
+template <typename T, int HB2, bool INV, bool UNIT, bool BF, bool PERSIST>
+__global__ __launch_bounds__(256) void k_pass_reg2(const T* __restrict__ in, T* __restrict__ out,
+                                                   const T* __restrict__ Sfrag, int n, long long inner_rt,
+                                                   long long ncols, T omega, int mode) {
+  const long long inner = UNIT ? 1 : inner_rt;
+  const int wpb = blockDim.x >> 6;
+  const long long wv = xcd_linear(blockIdx.x, gridDim.x) * wpb + (threadIdx.x >> 6);
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  T* buf = reinterpret_cast<T*>(lds_raw) + (threadIdx.x >> 6) * 16 * n;   // unit stride: 16 n values per wave
+  if constexpr (!PERSIST) {
+    if constexpr (UNIT) pass2_group_staged<T, HB2, INV, BF>(in, out, Sfrag, n, ncols, omega, mode, wv, buf);
+    else pass2_group<T, HB2, INV, UNIT, BF>(in, out, Sfrag, n, inner, ncols, omega, mode, wv);
+  } else {
+    const long long nwaves = (long long)gridDim.x * wpb;
+    const long long ngroups = (ncols + 15) >> 4;
+    const long long per = (ngroups + nwaves - 1) / nwaves;
+    const long long gbeg = wv * per;
+    const long long gend = gbeg + per < ngroups ? gbeg + per : ngroups;
+#pragma unroll 1
+    for (long long gi = gbeg; gi < gend; ++gi) {
+      // an opaque copy of the table pointer: its loads stay inside the loop
+      const T* Sf = Sfrag;
+      asm volatile("" : "+s"(Sf));
+      if constexpr (UNIT) pass2_group_staged<T, HB2, INV, BF>(in, out, Sf, n, ncols, omega, mode, gi, buf);
+      else pass2_group<T, HB2, INV, UNIT, BF>(in, out, Sf, n, inner, ncols, omega, mode, gi);
+    }
+  }
+}
+
 // Slowest axis: forward transform, per-mode N_t x N_t solve, inverse transform,
 // one wave per time component (as the once-folded k_fused_pair), the
-// components exchanged through LDS for the solve.
-template <typename T, int HB2, int NT, bool BF>
-__global__ __launch_bounds__(256) void k_fused_pair2(const T* in, T* out, const T* __restrict__ Sfrag,
-                                                     const T* __restrict__ G, int n, long long inner,
-                                                     long long outer, int transpose, T omega, int mode,
-                                                     ModeEig<T> me) {
+// components exchanged through LDS for the solve.  A workgroup of NT * CG
+// waves takes CG groups of 16 columns per tile; with a grid smaller than the
+// tile count (persistent workgroups) each workgroup takes a contiguous range
+// of tiles.
+template <typename T, int HB2, int NT, int CG, bool BF>
+__device__ __forceinline__ void fused2_tile(const T* in, T* out, const T* __restrict__ Sf, const T* __restrict__ G,
+                                            int n, long long inner, long long ncol, int transpose, T omega,
+                                            int mode, const ModeEig<T>& me, T (&xch)[4 * HB2][CG * NT * 64 * 4],
+                                            long long t) {
   typedef typename Mfma<T>::acc_t acc_t;
-  constexpr int CG = NT >= 3 ? 1 : 4 / NT;
-  __shared__ T xch[4 * HB2][CG * NT * 64 * 4];
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
   const int cg = wave / NT, l = wave - (wave / NT) * NT;
-  const long long lin = (xcd_linear(blockIdx.x, gridDim.x) * CG + cg) * 16 + r;
-  const bool valid = lin < outer * inner;
+  const long long cstride = (long long)n * inner;
+  const int h = (n + 1) >> 1;
+  const long long lin = (t * CG + cg) * 16 + r;
+  const bool valid = lin < ncol;
   const long long o = valid ? lin / inner : 0;
   const long long pos = valid ? lin - o * inner : 0;
-  const long long cstride = (long long)n * inner;
   const long long base = o * NT * cstride + (long long)l * cstride + pos;
-  const int h = (n + 1) >> 1;
   acc_t acc[4][HB2];
   {
     T op[4][4 * HB2];
     load_twice_folded<T, HB2>(in + base, valid, inner, n, g, op);
-    mma4<T, HB2, 0, BF>(Sfrag, lane, [&](int m, int ib) { return op[m][ib]; }, acc);
+    mma4<T, HB2, 0, BF>(Sf, lane, [&](int m, int ib) { return op[m][ib]; }, acc);
   }
   // spectral values (o, om, e, em) of every row to LDS, one barrier
 #pragma unroll
@@ -436,10 +568,35 @@ __global__ __launch_bounds__(256) void k_fused_pair2(const T* in, T* out, const 
       inverse_operands<T>(y[0], y[1], y[2], y[3], middle, op[0][ib], op[1][ib], op[2][ib], op[3][ib]);
     }
   acc_t out_acc[4][HB2];
-  mma4<T, HB2, 1, BF>(Sfrag, lane, [&](int m, int ib) { return op[m][ib]; }, out_acc);
+  mma4<T, HB2, 1, BF>(Sf, lane, [&](int m, int ib) { return op[m][ib]; }, out_acc);
   T none[HB2][4][4];
   zero_old<T, HB2>(none);
   store_twice_unfolded<T, HB2, false>(out + base, valid, inner, n, g, out_acc, mode, omega, none);
+}
+
+template <typename T, int HB2, int NT, int CG, bool BF, bool PERSIST>
+__global__ __launch_bounds__(256) void k_fused_pair2(const T* in, T* out, const T* __restrict__ Sfrag,
+                                                     const T* __restrict__ G, int n, long long inner,
+                                                     long long outer, int transpose, T omega, int mode,
+                                                     ModeEig<T> me) {
+  __shared__ T xch[4 * HB2][CG * NT * 64 * 4];
+  const long long ncol = outer * inner;
+  if constexpr (!PERSIST) {
+    fused2_tile<T, HB2, NT, CG, BF>(in, out, Sfrag, G, n, inner, ncol, transpose, omega, mode, me, xch,
+                                    xcd_linear(blockIdx.x, gridDim.x));
+  } else {
+    const long long tiles = (ncol + 16 * CG - 1) / (16 * CG);
+    const long long per = (tiles + gridDim.x - 1) / gridDim.x;
+    const long long tbeg = xcd_linear(blockIdx.x, gridDim.x) * per;
+    const long long tend = tbeg + per < tiles ? tbeg + per : tiles;
+#pragma unroll 1
+    for (long long t = tbeg; t < tend; ++t) {
+      const T* Sf = Sfrag;
+      asm volatile("" : "+s"(Sf));
+      fused2_tile<T, HB2, NT, CG, BF>(in, out, Sf, G, n, inner, ncol, transpose, omega, mode, me, xch, t);
+      __syncthreads();   // the next tile rewrites the exchange buffer
+    }
+  }
 }
 
 // 2-D slab-resident block solve: one workgroup of 512 threads per slab holds
@@ -807,18 +964,38 @@ bool twice_folded_ok(int n, int elem_bytes) {
   return elem_bytes == 4 && n == 255;    // FP64 at h/2 = 64 would not fit in registers
 }
 
+// Launch shape of the twice-folded passes: waves per workgroup of the x (and y)
+// passes (1, 2 or 4; 0 = 4), a cap on their grid in workgroups per compute
+// unit (0 = one wave per group of 16 lines), column groups per workgroup of
+// the fused pass (0 = 4 / N_t for N_t <= 2, else 1) and its grid cap.
+static unsigned capped_grid(long long need, int per_cu, int cus) {
+  if (per_cu <= 0 || cus <= 0) return (unsigned)need;
+  const long long cap = (long long)per_cu * cus;
+  return (unsigned)(need < cap ? need : cap);
+}
+
 template <typename T>
 hipError_t launch_pass_reg2(int n, bool inverse, const T* in, T* out, const T* Sfrag2, long long inner,
-                            long long ncols, T omega, int mode, hipStream_t s, bool bf16) {
-  const unsigned grid = (unsigned)((ncols + 63) / 64);
-#define P2B(HB2, U, B)                                                                                         \
-  if (inverse)                                                                                                 \
-    hipLaunchKernelGGL((k_pass_reg2<T, HB2, true, U, B>), dim3(grid), dim3(256), 0, s, in, out, Sfrag2, n, inner, \
-                       ncols, omega, mode);                                                                    \
-  else                                                                                                         \
-    hipLaunchKernelGGL((k_pass_reg2<T, HB2, false, U, B>), dim3(grid), dim3(256), 0, s, in, out, Sfrag2, n,       \
-                       inner, ncols, omega, mode);                                                             \
-  return hipGetLastError();
+                            long long ncols, T omega, int mode, hipStream_t s, bool bf16, const PassShape& sh) {
+  const int wpg = sh.wpg == 1 || sh.wpg == 2 ? sh.wpg : 4;
+  const long long need = (ncols + 16 * wpg - 1) / (16 * wpg);
+  const unsigned grid = capped_grid(need, sh.pass_per_cu, sh.cus);
+  const bool persist = (long long)grid < need;
+  const dim3 block(64 * wpg);
+#define P2P(HB2, U, B, P)                                                                                      \
+  {                                                                                                            \
+    const size_t lds = U ? (size_t)wpg * 16 * n * sizeof(T) : 0;                                               \
+    if (inverse)                                                                                               \
+      hipLaunchKernelGGL((k_pass_reg2<T, HB2, true, U, B, P>), dim3(grid), block, lds, s, in, out, Sfrag2, n,   \
+                         inner, ncols, omega, mode);                                                           \
+    else                                                                                                       \
+      hipLaunchKernelGGL((k_pass_reg2<T, HB2, false, U, B, P>), dim3(grid), block, lds, s, in, out, Sfrag2, n,  \
+                         inner, ncols, omega, mode);                                                           \
+    return hipGetLastError();                                                                                  \
+  }
+#define P2B(HB2, U, B)            \
+  if (persist) { P2P(HB2, U, B, true) } \
+  P2P(HB2, U, B, false)
 #define P2(HB2, U)                      \
   if constexpr (sizeof(T) == 4) {       \
     if (bf16) { P2B(HB2, U, true) }     \
@@ -841,36 +1018,48 @@ hipError_t launch_pass_reg2(int n, bool inverse, const T* in, T* out, const T* S
   }
 #undef P2
 #undef P2B
+#undef P2P
   return hipErrorInvalidValue;
 }
 
 template <typename T>
 hipError_t launch_fused_pair2(int n, int nt, const T* in, T* out, const T* Sfrag2, const T* G, long long inner,
                               long long outer, int transpose, T omega, int mode, hipStream_t s, bool bf16,
-                              const ModeEig<T>* me) {
+                              const ModeEig<T>* me, const PassShape& sh) {
   ModeEig<T> mev{};
   if (me != nullptr && nt <= 2) mev = *me;
-  const int cg = nt >= 3 ? 1 : 4 / nt;
-  const unsigned grid = (unsigned)((outer * inner + 16 * cg - 1) / (16 * cg));
+  const int cgmax = nt >= 3 ? 1 : 4 / nt;
+  const int cg = (sh.fused_cg >= 1 && sh.fused_cg <= cgmax && (sh.fused_cg & (sh.fused_cg - 1)) == 0)
+                     ? sh.fused_cg : cgmax;
+  const long long need = (outer * inner + 16 * cg - 1) / (16 * cg);
+  const unsigned grid = capped_grid(need, sh.fused_per_cu, sh.cus);
+  const bool persist = (long long)grid < need;
   const dim3 block(64 * nt * cg);
-#define F2B(HB2, NT, B)                                                                                          \
-  if (nt == NT) {                                                                                                \
-    hipLaunchKernelGGL((k_fused_pair2<T, HB2, NT, B>), dim3(grid), block, 0, s, in, out, Sfrag2, G, n, inner,      \
-                       outer, transpose, omega, mode, mev);                                                      \
+#define F2B(HB2, NT, CG, B)                                                                                      \
+  if (nt == NT && cg == CG) {                                                                                    \
+    if (persist)                                                                                                 \
+      hipLaunchKernelGGL((k_fused_pair2<T, HB2, NT, CG, B, true>), dim3(grid), block, 0, s, in, out, Sfrag2, G,  \
+                         n, inner, outer, transpose, omega, mode, mev);                                          \
+    else                                                                                                         \
+      hipLaunchKernelGGL((k_fused_pair2<T, HB2, NT, CG, B, false>), dim3(grid), block, 0, s, in, out, Sfrag2, G, \
+                         n, inner, outer, transpose, omega, mode, mev);                                          \
     return hipGetLastError();                                                                                    \
   }
-#define F2(HB2, NT)                                  \
+#define F2C(HB2, B) F2B(HB2, 1, 1, B) F2B(HB2, 1, 2, B) F2B(HB2, 1, 4, B) F2B(HB2, 2, 1, B) F2B(HB2, 2, 2, B) \
+                    F2B(HB2, 3, 1, B) F2B(HB2, 4, 1, B)
+#define F2(HB2)                                      \
   if constexpr (sizeof(T) == 4) {                    \
-    if (bf16) { F2B(HB2, NT, true) }                 \
+    if (bf16) { F2C(HB2, true) }                     \
   }                                                  \
-  F2B(HB2, NT, false)
+  F2C(HB2, false)
   if (!twice_folded_ok(n, (int)sizeof(T)) || (bf16 && sizeof(T) != 4)) return hipErrorInvalidValue;
   if constexpr (sizeof(T) == 4) {
-    if (n == 255) { F2(4, 1) F2(4, 2) F2(4, 3) F2(4, 4) }
+    if (n == 255) { F2(4) }
   }
-  if (n == 127) { F2(2, 1) F2(2, 2) F2(2, 3) F2(2, 4) }
-  if (n == 63) { F2(1, 1) F2(1, 2) F2(1, 3) F2(1, 4) }
+  if (n == 127) { F2(2) }
+  if (n == 63) { F2(1) }
 #undef F2
+#undef F2C
 #undef F2B
   return hipErrorInvalidValue;
 }
@@ -934,13 +1123,14 @@ template hipError_t launch_resid_xfwd<double>(int, const double*, const double*,
 template hipError_t launch_resid_xfwd<float>(int, const float*, const float*, float*, const ResidArgs<float>&,
                                              const float*, double*, hipStream_t);
 template hipError_t launch_pass_reg2<double>(int, bool, const double*, double*, const double*, long long, long long,
-                                             double, int, hipStream_t, bool);
+                                             double, int, hipStream_t, bool, const PassShape&);
 template hipError_t launch_pass_reg2<float>(int, bool, const float*, float*, const float*, long long, long long,
-                                            float, int, hipStream_t, bool);
+                                            float, int, hipStream_t, bool, const PassShape&);
 template hipError_t launch_fused_pair2<double>(int, int, const double*, double*, const double*, const double*,
                                                long long, long long, int, double, int, hipStream_t, bool,
-                                               const ModeEig<double>*);
+                                               const ModeEig<double>*, const PassShape&);
 template hipError_t launch_fused_pair2<float>(int, int, const float*, float*, const float*, const float*, long long,
-                                              long long, int, float, int, hipStream_t, bool, const ModeEig<float>*);
+                                              long long, int, float, int, hipStream_t, bool, const ModeEig<float>*,
+                                              const PassShape&);
 
 }  // namespace stmg

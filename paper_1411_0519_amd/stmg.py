@@ -76,6 +76,8 @@ SIGNATURES = {
     "st_mg_set_graph": (_i, [_vp, _i]),
     "st_mg_autotune": (_i, [_vp, _vp, _vp, _vp]),
     "st_mg_level_tuning": (_i, [_vp, _i, _ip, _ip, ctypes.POINTER(ctypes.c_float)]),
+    "st_mg_level_shape": (_i, [_vp, _i, _ip, _ip, _ip, _ip]),
+    "st_mg_set_level_shape": (_i, [_vp, _i, _i, _i, _i, _i]),
     "st_mg_profile_start": (_i, [_vp]),
     "st_mg_profile_stop": (_i, [_vp]),
     "st_mg_profile_read": (_i, [_vp, _i, _i, _dp, _ip]),
@@ -429,6 +431,15 @@ class Solver:
         return out
 
     # --------------------------------------------------------------- profiling
+    def level_shape(self, level):
+        """Launch shape of the twice-folded passes on a level: dict(wpg, pass_per_cu, fused_cg, fused_per_cu)."""
+        v = [ctypes.c_int() for _ in range(4)]
+        self._check(lib().st_mg_level_shape(self._h, level, *[ctypes.byref(x) for x in v]))
+        return dict(zip(("wpg", "pass_per_cu", "fused_cg", "fused_per_cu"), (x.value for x in v)))
+
+    def set_level_shape(self, level, wpg=4, pass_per_cu=0, fused_cg=0, fused_per_cu=0):
+        self._check(lib().st_mg_set_level_shape(self._h, level, wpg, pass_per_cu, fused_cg, fused_per_cu))
+
     def profile_start(self):
         self._check(lib().st_mg_profile_start(self._h))
 

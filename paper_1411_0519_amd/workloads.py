@@ -113,6 +113,34 @@ def make(dim, n, N, batch=1, seed=0, f="uniform", u0="sine1", dtype=np.float64, 
     return fa.astype(dtype, copy=False), ua.astype(dtype, copy=False)
 
 
+def make_streamed(dim, n, N, batch=1, seed=0, f="uniform", u0="series16", **_):
+    """The nodal data of `make` for f = "uniform", one right-hand side at a
+    time (for batches too large to hold as one float64 array): returns an
+    iterator over the batch's f[b] of shape (N, n^dim) and a function that,
+    called after the iterator is exhausted, returns u0 of shape (batch,
+    n^dim).  The values equal make()'s: the generator draws the same stream in
+    the same order."""
+    if f != "uniform":
+        raise ValueError(f)
+    rng = np.random.default_rng(seed)
+    nx = n ** dim
+
+    def f_iter():
+        for _ in range(batch):
+            yield rng.uniform(-1.0, 1.0, size=(N, nx))
+
+    def u0_fn():
+        if u0 == "series16":
+            return np.stack([sine_series(dim, n, rng) for _ in range(batch)])
+        if u0 == "sine1":
+            return np.broadcast_to(sine1(dim, n), (batch, nx)).copy()
+        if u0 == "zero":
+            return np.zeros((batch, nx))
+        raise ValueError(u0)
+
+    return f_iter(), u0_fn
+
+
 def workload(idx, **overrides):
     """Parameters and nodal data of workload idx; overrides shrink it (n, N, batch)."""
     w = dict(WORKLOADS[idx])

@@ -29,3 +29,13 @@ def test_reduced_workload_overrides():
     w, f, u0 = workloads.workload(4, n=7, N=4, batch=3)
     assert f.shape == (3, 4, 49) and u0.shape == (3, 49)
     assert not np.allclose(u0[0], u0[1])
+
+
+def test_streamed_batch_equals_make():
+    w = dict(workloads.WORKLOADS[4])
+    w.update(n=15, N=8, batch=5)
+    _, f, u0 = workloads.workload(4, n=15, N=8, batch=5)
+    it, u0_fn = workloads.make_streamed(**w)
+    fs = np.stack(list(it))
+    assert np.array_equal(fs, f)
+    assert np.array_equal(u0_fn(), u0)
