@@ -216,7 +216,7 @@ def cpu_baseline(budget_s=20.0):
 
 
 TRANSFORM_NAMES = ["default", "lds", "register", "register_twice_folded", "slab_resident",
-                   "twice_folded_residual_fused"]
+                   "twice_folded_residual_fused", "x_mode_slab_resident"]
 
 
 def tuned_levels(S, tuning):

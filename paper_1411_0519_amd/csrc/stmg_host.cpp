@@ -808,8 +808,20 @@ bool bf16_level(const st_mg* h, const Level& L) {
 // and is its chosen family.
 template <typename T>
 bool slab_capable(const st_mg* h, const Level& L) {
-  return !high_order(h) && !bf16_level<T>(h, L) && S2of<T>(L) != nullptr &&
-         slab_solve2_lds(h->p.dim, L.n, h->nt, (int)sizeof(T)) > 0;
+  return h->p.dim == 2 && !high_order(h) && !bf16_level<T>(h, L) && S2of<T>(L) != nullptr &&
+         slab_solve2_lds(2, L.n, h->nt, (int)sizeof(T)) > 0;
+}
+// 3-D levels whose (slab, x-mode) planes fit the slab-resident kernel: forward
+// x pass into the x-mode-major layout, one workgroup per plane, inverse x pass.
+template <typename T>
+bool xslab_capable(const st_mg* h, const Level& L) {
+  return h->p.dim == 3 && !high_order(h) && !bf16_level<T>(h, L) && S2of<T>(L) != nullptr &&
+         slab_solve2_lds(3, L.n, h->nt, (int)sizeof(T)) > 0;
+}
+template <typename T>
+bool xslab_level(const st_mg* h, const Level& L) {
+  const int impl = L.impl >= 0 ? L.impl : h->impl;
+  return impl == TRANSFORM_XSLAB && xslab_capable<T>(h, L);
 }
 template <typename T>
 bool slab_level(const st_mg* h, const Level& L) {
@@ -847,7 +859,7 @@ int op_block_solve(st_mg* h, int l, bool transpose, const T* src, T* dst, int mo
       return ST_OK;
     }
     int impl = L.impl >= 0 ? L.impl : h->impl;
-    if (impl == TRANSFORM_SLAB) impl = TRANSFORM_AUTO;   // levels the slab kernel does not take
+    if (impl == TRANSFORM_SLAB || impl == TRANSFORM_XSLAB) impl = TRANSFORM_AUTO;   // levels the slab kernel does not take
     if ((impl == TRANSFORM_REG2 || impl == TRANSFORM_AUTO) && S2of<T>(L)) {
       HIPCHK(h, launch_pass_reg2<T>(n, inv, in, out, S2of<T>(L), inner, ncols, om, md, s, false, level_shape(h, L)));
       return ST_OK;
@@ -855,10 +867,10 @@ int op_block_solve(st_mg* h, int l, bool transpose, const T* src, T* dst, int mo
     HIPCHK(h, launch_dst_pass<T>(impl, L.hb, axis == 0, inv, in, out, Sof<T>(L), n, inner, ncols, om, md, s));
     return ST_OK;
   };
-  // per-mode blocks from the eigenvalues for the twice-folded fused pass (N_t <= 2)
+  // per-mode blocks from the eigenvalues for the twice-folded fused pass
   ModeEig<T> me{};
   const ModeEig<T>* mep = nullptr;
-  if (nt <= 2) {
+  if (nt <= NT_MAX) {
     me.eig = Eigof<T>(L);
     for (int i = 0; i < nt * nt; ++i) {
       me.K[i] = (T)h->Kt[i];
@@ -882,7 +894,7 @@ int op_block_solve(st_mg* h, int l, bool transpose, const T* src, T* dst, int mo
       return ST_OK;
     }
     int impl = L.impl >= 0 ? L.impl : h->impl;
-    if (impl == TRANSFORM_SLAB) impl = TRANSFORM_AUTO;
+    if (impl == TRANSFORM_SLAB || impl == TRANSFORM_XSLAB) impl = TRANSFORM_AUTO;
     if ((impl == TRANSFORM_REG2 || impl == TRANSFORM_AUTO) && S2of<T>(L)) {
       HIPCHK(h, launch_fused_pair2<T>(n, nt, in, out, S2of<T>(L), Gof<T>(L), inner, slabs, transpose ? 1 : 0, om, md,
                                       s, false, mep, level_shape(h, L)));
@@ -892,6 +904,25 @@ int op_block_solve(st_mg* h, int l, bool transpose, const T* src, T* dst, int mo
                                   transpose ? 1 : 0, om, md, s));
     return ST_OK;
   };
+  if (xslab_level<T>(h, L)) {
+    // x pass into [slab][kx][l][z][y], a (z, y) block solve per (slab, kx) in LDS, inverse x pass (+ update)
+    const long long lps = (long long)nt * nn * nn;
+    const long long ncols = slabs * lps;
+    {
+      ProfScope ps(h, ST_PROF_PASS_FWD, l, s);
+      HIPCHK(h, launch_pass_reg2<T>(n, false, src, A, S2of<T>(L), 1, ncols, T(1), MODE_STORE, s, false,
+                                    level_shape(h, L), lps));
+    }
+    {
+      ProfScope ps(h, ST_PROF_FUSED, l, s);
+      HIPCHK(h, launch_slab_solve2<T>(n, nt, A, A, S2of<T>(L), Gof<T>(L), slabs, transpose ? 1 : 0, T(1), MODE_STORE,
+                                      s, &me));
+    }
+    ProfScope ps(h, ST_PROF_PASS_INV, l, s);
+    HIPCHK(h, launch_pass_reg2<T>(n, true, A, dst, S2of<T>(L), 1, ncols, omega, mode, s, false, level_shape(h, L),
+                                  lps));
+    return ST_OK;
+  }
   if (slab_level<T>(h, L)) {
     ProfScope ps(h, ST_PROF_FUSED, l, s);
     HIPCHK(h, launch_slab_solve2<T>(n, nt, src, dst, S2of<T>(L), Gof<T>(L), slabs, transpose ? 1 : 0, omega, mode,
@@ -1651,6 +1682,7 @@ int tune_level(st_mg* h, int l, T* u, T* F, T* r, T* alt, hipStream_t s) {
     cands.push_back({0, TRANSFORM_REG, 0});
   }
   if (slab_capable<T>(h, L)) cands.push_back({0, TRANSFORM_SLAB, 0});
+  if (xslab_capable<T>(h, L)) cands.push_back({0, TRANSFORM_XSLAB, 0});
   if (!high_order(h) && !bf16_level<T>(h, L) && S2of<T>(L) && resid_xfwd_ok(h->p.dim, L.n, h->nt, (int)sizeof(T)))
     cands.push_back({0, TRANSFORM_AUTO, 1});
   hipEvent_t e0, e1;
@@ -1705,7 +1737,8 @@ int tune_level(st_mg* h, int l, T* u, T* F, T* r, T* alt, hipStream_t s) {
   const int impl_pick = pick.impl >= 0 ? pick.impl : h->impl;
   const bool uses_reg2 = !pick.small && !high_order(h) && !slab_level<T>(h, L) &&
                          ((bf16_level<T>(h, L) && L.S2_16) ||
-                          ((impl_pick == TRANSFORM_AUTO || impl_pick == TRANSFORM_REG2) && S2of<T>(L)));
+                          ((impl_pick == TRANSFORM_AUTO || impl_pick == TRANSFORM_REG2 ||
+                            impl_pick == TRANSFORM_XSLAB) && S2of<T>(L)));
   if (uses_reg2) {
     PassShape bsh = L.shape;
     auto try_shape = [&](const PassShape& c) {
@@ -2104,7 +2137,7 @@ int setup_impl(const st_mg_params* p, st_mg_t* out, const st_mesh* mesh, int ref
   if (const char* rx = std::getenv("STMG_RX")) h->rx = std::atoi(rx) != 0;
   if (const char* ti = std::getenv("STMG_TRANSFORM")) {
     const int v = std::atoi(ti);
-    h->impl = (v >= TRANSFORM_AUTO && v <= TRANSFORM_SLAB) ? v : TRANSFORM_AUTO;
+    h->impl = ((v >= TRANSFORM_AUTO && v <= TRANSFORM_SLAB) || v == TRANSFORM_XSLAB) ? v : TRANSFORM_AUTO;
   }
   time_basis(h);
   {

@@ -69,7 +69,8 @@ unsigned residual_blocks_per_slab(int dim, int n, long long nx, int nt, long lon
 int transform_half_blocks(int n);
 // Transform implementation: automatic choice, LDS-staged kernels only, or the
 // FP64 register-resident kernels wherever their state fits.
-enum { TRANSFORM_AUTO = 0, TRANSFORM_LDS = 1, TRANSFORM_REG = 2, TRANSFORM_REG2 = 3, TRANSFORM_SLAB = 4 };
+enum { TRANSFORM_AUTO = 0, TRANSFORM_LDS = 1, TRANSFORM_REG = 2, TRANSFORM_REG2 = 3, TRANSFORM_SLAB = 4,
+       TRANSFORM_XSLAB = 6 };
 template <typename T>
 hipError_t launch_dst_pass(int impl, int hb, bool xaxis, bool inverse, const T* in, T* out, const T* Sfrag,
                            int n, long long inner, long long ncols, T omega, int mode,
@@ -419,15 +420,15 @@ namespace stmg {
 // (row 4 g + j in element j of lane group g) where the f64 one interleaves
 // (g + 4 j), so the FP32 table stores output row twice_fold_row(i) at operand
 // row i and both types share one register order.
-// Per-mode time blocks from the 1-D eigenvalues (N_t <= 2): eig holds m_s then
+// Per-mode time blocks from the 1-D eigenvalues (N_t <= 4): eig holds m_s then
 // kappa_s of one axis in spectral order (2n values), K = K_tau, M = M_tau;
 // the block of mode (s_1, .., s_d) is (mu K + nu M)^{-1} with mu = prod m and
 // nu = sum_a kappa_a prod_{b != a} m_b.  eig == nullptr: read the table G.
 template <typename T>
 struct ModeEig {
   const T* eig;
-  T K[4];
-  T M[4];
+  T K[NT_MAX * NT_MAX];
+  T M[NT_MAX * NT_MAX];
 };
 // With bf16 (FP32 data only) Sfrag2 is the bf16 table of packed quadruples
 // (v_mfma_f32_16x16x16_bf16 operands, rows permuted the same way).
@@ -449,14 +450,16 @@ struct PassShape {
 template <typename T>
 hipError_t launch_pass_reg2(int n, bool inverse, const T* in, T* out, const T* Sfrag2, long long inner,
                             long long ncols, T omega, int mode, hipStream_t s, bool bf16 = false,
-                            const PassShape& sh = PassShape{});
-// 2-D slab-resident block solve with the twice-folded passes (one workgroup
-// per slab, slab in LDS; FP64 n = 63, FP32 n = 63, 127; N_t <= 2): LDS bytes,
-// 0 when the level does not qualify.
+                            const PassShape& sh = PassShape{}, long long lps = 0);
+// Slab-resident block solve with the twice-folded passes (one workgroup per
+// 2-D slab, slab in LDS; FP64 n = 63, FP32 n = 63, 127; N_t <= 2): LDS bytes,
+// 0 when the level does not qualify.  With me3 (dim 3) the blocks are the
+// (slab, x-mode) planes of the x-mode-major layout [slab][kx][l][z][y] after
+// the forward x pass, their per-mode blocks formed from the eigenvalues.
 size_t slab_solve2_lds(int dim, int n, int nt, int elem_bytes);
 template <typename T>
 hipError_t launch_slab_solve2(int n, int nt, const T* src, T* dst, const T* Sfrag2, const T* G, long long slabs,
-                              int transpose, T omega, int mode, hipStream_t s);
+                              int transpose, T omega, int mode, hipStream_t s, const ModeEig<T>* me3 = nullptr);
 // 2-D residual fused with the forward twice-folded x pass (N_t = 2, n = 63,
 // 127): xhat = (S_x (x) I) (F - L u) in the layout of r; with `partial` the
 // per-tile sums of r^2 in the residual kernel's layout.

@@ -244,30 +244,37 @@ __device__ inline void inverse_operands(T o, T om, T e, T em, bool middle, T& u,
   ve = middle ? T(0) : e - em;
 }
 
-// Row l of the per-mode time block G (of G^T with transpose) for N_t <= 2 from
-// the eigenvalues: mode s along the pass axis, (P, Q) = (prod m, sum kappa prod
-// m) over the other axes of the lane's position.
+// Row l of the per-mode time block G (of G^T with transpose) from the
+// eigenvalues: mode s along the pass axis, (P, Q) = (prod m, sum kappa prod m)
+// over the other axes of the lane's position; G = D^{-1} with
+// D = mu K_tau + nu M_tau, mu = P m_s, nu = Q m_s + P kappa_s.  N_t = 1, 2 in
+// closed form; N_t = 3, 4 by elimination without pivoting on D^T g = e_l
+// (D g = e_l for a row of G^T): D's symmetric part is positive definite
+// (mu, nu > 0), so every pivot is positive.
+template <typename T>
+__device__ inline T recip(T d) {
+  if constexpr (sizeof(T) == 8) {
+    // hardware reciprocal refined by two Newton steps r <- r + r (1 - d r): about one ulp, far
+    // cheaper than the IEEE division sequence
+    double r = __builtin_amdgcn_rcp(d);
+    r = __builtin_fma(r, __builtin_fma(-d, r, 1.0), r);
+    r = __builtin_fma(r, __builtin_fma(-d, r, 1.0), r);
+    return r;
+  } else {
+    return T(1) / d;
+  }
+}
+
 template <typename T, int NT>
 __device__ inline void mode_row(const ModeEig<T>& me, int n, T P, T Q, int s, int l, int transpose, T (&g)[NT]) {
   const T ms = me.eig[s], ks = me.eig[n + s];
   const T mu = P * ms, nu = Q * ms + P * ks;
   if constexpr (NT == 1) {
     g[0] = T(1) / (mu * me.K[0] + nu * me.M[0]);
-  } else {
+  } else if constexpr (NT == 2) {
     const T d00 = mu * me.K[0] + nu * me.M[0], d01 = mu * me.K[1] + nu * me.M[1];
     const T d10 = mu * me.K[2] + nu * me.M[2], d11 = mu * me.K[3] + nu * me.M[3];
-    const T det = d00 * d11 - d01 * d10;
-    T inv;
-    if constexpr (sizeof(T) == 8) {
-      // hardware reciprocal refined by two Newton steps r <- r + r (1 - det r): about one ulp, far
-      // cheaper than the IEEE division sequence (det > 0: the block is positive definite)
-      double r = __builtin_amdgcn_rcp(det);
-      r = __builtin_fma(r, __builtin_fma(-det, r, 1.0), r);
-      r = __builtin_fma(r, __builtin_fma(-det, r, 1.0), r);
-      inv = r;
-    } else {
-      inv = T(1) / det;
-    }
+    const T inv = recip<T>(d00 * d11 - d01 * d10);   // det > 0: the block is positive definite
     // G = inv [[d11, -d01], [-d10, d00]]
     const T g00 = d11 * inv, g01 = -d01 * inv, g10 = -d10 * inv, g11 = d00 * inv;
     if (l == 0) {
@@ -276,6 +283,35 @@ __device__ inline void mode_row(const ModeEig<T>& me, int n, T P, T Q, int s, in
     } else {
       g[0] = transpose ? g01 : g10;
       g[1] = g11;
+    }
+  } else {
+    T A[NT][NT], b[NT], piv[NT];
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+#pragma unroll
+      for (int j = 0; j < NT; ++j) {
+        const int ij = transpose ? i * NT + j : j * NT + i;
+        A[i][j] = mu * me.K[ij] + nu * me.M[ij];
+      }
+      b[i] = i == l ? T(1) : T(0);
+    }
+#pragma unroll
+    for (int k = 0; k < NT; ++k) {
+      piv[k] = recip<T>(A[k][k]);
+#pragma unroll
+      for (int i = k + 1; i < NT; ++i) {
+        const T f = A[i][k] * piv[k];
+#pragma unroll
+        for (int j = k + 1; j < NT; ++j) A[i][j] -= f * A[k][j];
+        b[i] -= f * b[k];
+      }
+    }
+#pragma unroll
+    for (int k = NT - 1; k >= 0; --k) {
+      T x = b[k];
+#pragma unroll
+      for (int j = k + 1; j < NT; ++j) x -= A[k][j] * g[j];
+      g[k] = x * piv[k];
     }
   }
 }
@@ -360,16 +396,31 @@ __device__ inline void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Offset in the x-mode-major layout [slab][s][line in slab] of spectral
+// value s of the group's line r, given the slab and in-slab index of the
+// group's first line and lps lines per slab.
+__device__ inline long long xmode_offset(long long slab0, long long ll0, int r, int s, int n, long long lps) {
+  long long ll = ll0 + r, sl = slab0;
+  if (ll >= lps) {
+    ll -= lps;
+    ++sl;
+  }
+  return (sl * n + s) * lps + ll;
+}
+
 // Unit-stride pass (along x) through LDS: the 16 lines of group gi are one
 // contiguous run of 16 n values, loaded with consecutive lanes on consecutive
 // values (eight loads in flight per lane), transformed from the wave's LDS
 // buffer, written back there and stored the same way; the update reads the
 // old iterate at the store.  Same arithmetic as the strided path.  buf: 16 n
-// values of this wave.
+// values of this wave.  lps > 0: the spectral side (output of the forward
+// pass, input of the inverse) is in the x-mode-major layout
+// [slab][s][line in slab] with lps lines per slab, moved with the 16 lines
+// of one s on 16 consecutive lanes.
 template <typename T, int HB2, bool INV, bool BF>
 __device__ __forceinline__ void pass2_group_staged(const T* __restrict__ in, T* __restrict__ out,
                                                    const T* __restrict__ Sf, int n, long long ncols, T omega,
-                                                   int mode, long long gi, T* buf) {
+                                                   int mode, long long gi, T* buf, long long lps) {
   typedef typename Mfma<T>::acc_t acc_t;
   const int lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
   const int h = (n + 1) >> 1;
@@ -378,18 +429,42 @@ __device__ __forceinline__ void pass2_group_staged(const T* __restrict__ in, T* 
   const int lines = ncols - first < 16 ? (int)(ncols - first) : 16;
   const int cnt = lines * n;
   const long long off = first * (long long)n;
+  long long slab0 = 0, ll0 = 0;
+  if (lps > 0) {
+    slab0 = first / lps;
+    ll0 = first - slab0 * lps;
+  }
+  if (INV && lps > 0) {
 #pragma unroll 1
-  for (int e0 = 0; e0 < cnt; e0 += 64 * 8) {
-    T v[8];
+    for (int e0 = 0; e0 < cnt; e0 += 64 * 8) {
+      T v[8];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int e = e0 + 64 * i + lane;
-      v[i] = e < cnt ? in[off + e] : T(0);
+      for (int i = 0; i < 8; ++i) {
+        const int e = e0 + 64 * i + lane;
+        const int s = e / lines, rr = e - s * lines;
+        v[i] = e < cnt ? in[xmode_offset(slab0, ll0, rr, s, n, lps)] : T(0);
+      }
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int e = e0 + 64 * i + lane;
+        const int s = e / lines, rr = e - s * lines;
+        if (e < cnt) buf[rr * n + s] = v[i];
+      }
     }
+  } else {
+#pragma unroll 1
+    for (int e0 = 0; e0 < cnt; e0 += 64 * 8) {
+      T v[8];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int e = e0 + 64 * i + lane;
-      if (e < cnt) buf[e] = v[i];
+      for (int i = 0; i < 8; ++i) {
+        const int e = e0 + 64 * i + lane;
+        v[i] = e < cnt ? in[off + e] : T(0);
+      }
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int e = e0 + 64 * i + lane;
+        if (e < cnt) buf[e] = v[i];
+      }
     }
   }
   wave_lds_sync();
@@ -436,6 +511,18 @@ __device__ __forceinline__ void pass2_group_staged(const T* __restrict__ in, T* 
     store_twice_unfolded<T, HB2, false, int>(lp, valid, 1, n, g, acc, MODE_STORE, T(1), none);
   }
   wave_lds_sync();
+  if (!INV && lps > 0) {
+#pragma unroll 1
+    for (int e0 = 0; e0 < cnt; e0 += 64 * 8) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int e = e0 + 64 * i + lane;
+        const int s = e / lines, rr = e - s * lines;
+        if (e < cnt) out[xmode_offset(slab0, ll0, rr, s, n, lps)] = buf[rr * n + s];
+      }
+    }
+    return;
+  }
 #pragma unroll 1
   for (int e0 = 0; e0 < cnt; e0 += 64 * 8) {
     T o[8];
@@ -459,14 +546,14 @@ __device__ __forceinline__ void pass2_group_staged(const T* __restrict__ in, T* 
 template <typename T, int HB2, bool INV, bool UNIT, bool BF, bool PERSIST>
 __global__ __launch_bounds__(256) void k_pass_reg2(const T* __restrict__ in, T* __restrict__ out,
                                                    const T* __restrict__ Sfrag, int n, long long inner_rt,
-                                                   long long ncols, T omega, int mode) {
+                                                   long long ncols, T omega, int mode, long long lps) {
   const long long inner = UNIT ? 1 : inner_rt;
   const int wpb = blockDim.x >> 6;
   const long long wv = xcd_linear(blockIdx.x, gridDim.x) * wpb + (threadIdx.x >> 6);
   extern __shared__ __align__(16) unsigned char lds_raw[];
   T* buf = reinterpret_cast<T*>(lds_raw) + (threadIdx.x >> 6) * 16 * n;   // unit stride: 16 n values per wave
   if constexpr (!PERSIST) {
-    if constexpr (UNIT) pass2_group_staged<T, HB2, INV, BF>(in, out, Sfrag, n, ncols, omega, mode, wv, buf);
+    if constexpr (UNIT) pass2_group_staged<T, HB2, INV, BF>(in, out, Sfrag, n, ncols, omega, mode, wv, buf, lps);
     else pass2_group<T, HB2, INV, UNIT, BF>(in, out, Sfrag, n, inner, ncols, omega, mode, wv);
   } else {
     const long long nwaves = (long long)gridDim.x * wpb;
@@ -479,7 +566,7 @@ __global__ __launch_bounds__(256) void k_pass_reg2(const T* __restrict__ in, T* 
       // an opaque copy of the table pointer: its loads stay inside the loop
       const T* Sf = Sfrag;
       asm volatile("" : "+s"(Sf));
-      if constexpr (UNIT) pass2_group_staged<T, HB2, INV, BF>(in, out, Sf, n, ncols, omega, mode, gi, buf);
+      if constexpr (UNIT) pass2_group_staged<T, HB2, INV, BF>(in, out, Sf, n, ncols, omega, mode, gi, buf, lps);
       else pass2_group<T, HB2, INV, UNIT, BF>(in, out, Sf, n, inner, ncols, omega, mode, gi);
     }
   }
@@ -527,7 +614,7 @@ __device__ __forceinline__ void fused2_tile(const T* in, T* out, const T* __rest
     }
   __syncthreads();
   T P0 = T(0), Q0 = T(0);
-  if (NT <= 2 && me.eig != nullptr && valid) mode_pq<T>(me, n, inner, pos, P0, Q0);
+  if (me.eig != nullptr && valid) mode_pq<T>(me, n, inner, pos, P0, Q0);
   // per-mode solve of this wave's component, then the inverse operands
   T op[4][4 * HB2];
 #pragma unroll
@@ -543,14 +630,12 @@ __device__ __forceinline__ void fused2_tile(const T* in, T* out, const T* __rest
         T a = T(0);
         if (valid) {
           bool done = false;
-          if constexpr (NT <= 2) {
-            if (me.eig != nullptr) {
-              T gr[NT];
-              mode_row<T, NT>(me, n, P0, Q0, mode_idx[q], l, transpose, gr);
+          if (me.eig != nullptr) {
+            T gr[NT];
+            mode_row<T, NT>(me, n, P0, Q0, mode_idx[q], l, transpose, gr);
 #pragma unroll
-              for (int m = 0; m < NT; ++m) a += gr[m] * xch[q * HB2 + kb][((cg * NT + m) * 64 + lane) * 4 + j];
-              done = true;
-            }
+            for (int m = 0; m < NT; ++m) a += gr[m] * xch[q * HB2 + kb][((cg * NT + m) * 64 + lane) * 4 + j];
+            done = true;
           }
           if (!done) {
             const T* gm = G + (pos + inner * (long long)mode_idx[q]) * (NT * NT);
@@ -607,15 +692,28 @@ __global__ __launch_bounds__(256) void k_fused_pair2(const T* in, T* out, const 
 // passes.  The slab is read once and written once:
 // dst = epi(mode, dst, D^{-1} src).  src and dst may alias (a workgroup reads
 // its whole slab before it writes).  Dynamic LDS: N_t n^2 elements.
-template <typename T, int HB2, int NT>
+//
+// X3: the same solve on the 2-D blocks of a 3-D level after the forward x
+// pass, in the x-mode-major layout [slab][kx][l][z][y] (kx = spectral x index):
+// block b = (slab, kx) is one N_t x n x n problem in (z, y) whose per-mode
+// blocks also carry kx's eigenvalues (formed from the 1-D eigenvalues in
+// `me`; the 2-D form reads the table G).  `slabs` counts blocks.
+template <typename T, int HB2, int NT, bool X3>
 __global__ __launch_bounds__(512) void k_slab_solve2(const T* src, T* dst, const T* __restrict__ Sfrag,
                                                      const T* __restrict__ G, int n, long long slabs, int transpose,
-                                                     T omega, int mode) {
+                                                     T omega, int mode, ModeEig<T> me) {
   typedef typename Mfma<T>::acc_t acc_t;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   T* R = reinterpret_cast<T*>(lds_raw);
-  const long long slab = slab_index();
+  const long long slab = X3 ? xcd_linear(slab_index(), (long long)gridDim.y * gridDim.z) : slab_index();
   if (slab >= slabs) return;
+  // x-mode of a 3-D block: its (m, kappa)
+  T mxk = T(0), kxk = T(0);
+  if constexpr (X3) {
+    const int kx = (int)(slab % n);
+    mxk = me.eig[kx];
+    kxk = me.eig[n + kx];
+  }
   const int nn = n * n;
   const int total = NT * nn;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
@@ -677,6 +775,9 @@ __global__ __launch_bounds__(512) void k_slab_solve2(const T* src, T* dst, const
     const int col = gi * 16 + r;
     const bool valid = col < n;
     const int cc = valid ? col : 0;
+    // (P, Q) of the modes of this column: x-mode and y-mode (3-D blocks)
+    const T P3 = X3 ? mxk * me.eig[cc] : T(0);
+    const T Q3 = X3 ? kxk * me.eig[cc] + mxk * me.eig[n + cc] : T(0);
     acc_t acc[NT][4][HB2];
 #pragma unroll
     for (int l = 0; l < NT; ++l) {
@@ -709,9 +810,16 @@ __global__ __launch_bounds__(512) void k_slab_solve2(const T* src, T* dst, const
           for (int q = 0; q < 4; ++q) {
             T a = T(0);
             if (valid) {
-              const T* gm = G + (cc + n * mode_idx[q]) * (NT * NT);
+              if constexpr (X3) {
+                T gr[NT];
+                mode_row<T, NT>(me, n, P3, Q3, mode_idx[q], l, transpose, gr);
 #pragma unroll
-              for (int m = 0; m < NT; ++m) a += (transpose ? gm[m * NT + l] : gm[l * NT + m]) * v[m][q];
+                for (int m = 0; m < NT; ++m) a += gr[m] * v[m][q];
+              } else {
+                const T* gm = G + (cc + n * mode_idx[q]) * (NT * NT);
+#pragma unroll
+                for (int m = 0; m < NT; ++m) a += (transpose ? gm[m * NT + l] : gm[l * NT + m]) * v[m][q];
+              }
             }
             y[q] = a;
           }
@@ -976,7 +1084,9 @@ static unsigned capped_grid(long long need, int per_cu, int cus) {
 
 template <typename T>
 hipError_t launch_pass_reg2(int n, bool inverse, const T* in, T* out, const T* Sfrag2, long long inner,
-                            long long ncols, T omega, int mode, hipStream_t s, bool bf16, const PassShape& sh) {
+                            long long ncols, T omega, int mode, hipStream_t s, bool bf16, const PassShape& sh,
+                            long long lps) {
+  if (lps > 0 && inner != 1) return hipErrorInvalidValue;   // the x-mode-major side exists for x passes only
   const int wpg = sh.wpg == 1 || sh.wpg == 2 ? sh.wpg : 4;
   const long long need = (ncols + 16 * wpg - 1) / (16 * wpg);
   const unsigned grid = capped_grid(need, sh.pass_per_cu, sh.cus);
@@ -987,10 +1097,10 @@ hipError_t launch_pass_reg2(int n, bool inverse, const T* in, T* out, const T* S
     const size_t lds = U ? (size_t)wpg * 16 * n * sizeof(T) : 0;                                               \
     if (inverse)                                                                                               \
       hipLaunchKernelGGL((k_pass_reg2<T, HB2, true, U, B, P>), dim3(grid), block, lds, s, in, out, Sfrag2, n,   \
-                         inner, ncols, omega, mode);                                                           \
+                         inner, ncols, omega, mode, lps);                                                      \
     else                                                                                                       \
       hipLaunchKernelGGL((k_pass_reg2<T, HB2, false, U, B, P>), dim3(grid), block, lds, s, in, out, Sfrag2, n,  \
-                         inner, ncols, omega, mode);                                                           \
+                         inner, ncols, omega, mode, lps);                                                      \
     return hipGetLastError();                                                                                  \
   }
 #define P2B(HB2, U, B)            \
@@ -1027,7 +1137,7 @@ hipError_t launch_fused_pair2(int n, int nt, const T* in, T* out, const T* Sfrag
                               long long outer, int transpose, T omega, int mode, hipStream_t s, bool bf16,
                               const ModeEig<T>* me, const PassShape& sh) {
   ModeEig<T> mev{};
-  if (me != nullptr && nt <= 2) mev = *me;
+  if (me != nullptr && nt <= NT_MAX) mev = *me;
   const int cgmax = nt >= 3 ? 1 : 4 / nt;
   const int cg = (sh.fused_cg >= 1 && sh.fused_cg <= cgmax && (sh.fused_cg & (sh.fused_cg - 1)) == 0)
                      ? sh.fused_cg : cgmax;
@@ -1065,38 +1175,48 @@ hipError_t launch_fused_pair2(int n, int nt, const T* in, T* out, const T* Sfrag
 }
 
 size_t slab_solve2_lds(int dim, int n, int nt, int elem_bytes) {
-  if (dim != 2 || nt < 1 || nt > 2 || !twice_folded_ok(n, elem_bytes) || n > 127) return 0;
+  if (dim < 2 || dim > 3 || nt < 1 || nt > 2 || !twice_folded_ok(n, elem_bytes) || n > 127) return 0;
   const size_t bytes = (size_t)nt * n * n * elem_bytes;
   return bytes <= 160 * 1024 ? bytes : 0;
 }
 
 template <typename T>
 hipError_t launch_slab_solve2(int n, int nt, const T* src, T* dst, const T* Sfrag2, const T* G, long long slabs,
-                              int transpose, T omega, int mode, hipStream_t s) {
-  const size_t lds = slab_solve2_lds(2, n, nt, (int)sizeof(T));
+                              int transpose, T omega, int mode, hipStream_t s, const ModeEig<T>* me3) {
+  const bool x3 = me3 != nullptr;
+  const size_t lds = slab_solve2_lds(x3 ? 3 : 2, n, nt, (int)sizeof(T));
   if (lds == 0) return hipErrorInvalidValue;
-  const dim3 grid = slab_grid(1, slabs);
-#define SL2(HB2, NT)                                                                                         \
-  if (nt == NT) {                                                                                            \
-    const void* fn = reinterpret_cast<const void*>(&k_slab_solve2<T, HB2, NT>);                              \
-    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);            \
-    if (e != hipSuccess) return e;                                                                           \
-    hipLaunchKernelGGL((k_slab_solve2<T, HB2, NT>), grid, dim3(512), lds, s, src, dst, Sfrag2, G, n, slabs,    \
-                       transpose, omega, mode);                                                              \
-    return hipGetLastError();                                                                                \
+  ModeEig<T> mev{};
+  if (x3) mev = *me3;
+  const long long blocks = x3 ? slabs * n : slabs;
+  const dim3 grid = slab_grid(1, blocks);
+#define SL2X(HB2, NT, X)                                                                                       \
+  {                                                                                                            \
+    const void* fn = reinterpret_cast<const void*>(&k_slab_solve2<T, HB2, NT, X>);                             \
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);              \
+    if (e != hipSuccess) return e;                                                                             \
+    hipLaunchKernelGGL((k_slab_solve2<T, HB2, NT, X>), grid, dim3(512), lds, s, src, dst, Sfrag2, G, n, blocks,  \
+                       transpose, omega, mode, mev);                                                           \
+    return hipGetLastError();                                                                                  \
+  }
+#define SL2(HB2, NT)                        \
+  if (nt == NT) {                           \
+    if (x3) SL2X(HB2, NT, true)             \
+    SL2X(HB2, NT, false)                    \
   }
   if (n == 63) { SL2(1, 1) SL2(1, 2) }
   if constexpr (sizeof(T) == 4) {
     if (n == 127) { SL2(2, 1) SL2(2, 2) }
   }
 #undef SL2
+#undef SL2X
   return hipErrorInvalidValue;
 }
 
 template hipError_t launch_slab_solve2<double>(int, int, const double*, double*, const double*, const double*,
-                                               long long, int, double, int, hipStream_t);
+                                               long long, int, double, int, hipStream_t, const ModeEig<double>*);
 template hipError_t launch_slab_solve2<float>(int, int, const float*, float*, const float*, const float*, long long,
-                                              int, float, int, hipStream_t);
+                                              int, float, int, hipStream_t, const ModeEig<float>*);
 bool resid_xfwd_ok(int dim, int n, int nt, int elem_bytes) {
   return dim == 2 && nt == 2 && (n == 63 || n == 127) && twice_folded_ok(n, elem_bytes);
 }
@@ -1123,9 +1243,9 @@ template hipError_t launch_resid_xfwd<double>(int, const double*, const double*,
 template hipError_t launch_resid_xfwd<float>(int, const float*, const float*, float*, const ResidArgs<float>&,
                                              const float*, double*, hipStream_t);
 template hipError_t launch_pass_reg2<double>(int, bool, const double*, double*, const double*, long long, long long,
-                                             double, int, hipStream_t, bool, const PassShape&);
+                                             double, int, hipStream_t, bool, const PassShape&, long long);
 template hipError_t launch_pass_reg2<float>(int, bool, const float*, float*, const float*, long long, long long,
-                                            float, int, hipStream_t, bool, const PassShape&);
+                                            float, int, hipStream_t, bool, const PassShape&, long long);
 template hipError_t launch_fused_pair2<double>(int, int, const double*, double*, const double*, const double*,
                                                long long, long long, int, double, int, hipStream_t, bool,
                                                const ModeEig<double>*, const PassShape&);

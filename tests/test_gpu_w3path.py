@@ -77,7 +77,7 @@ def test_residual3d_parity(case, transpose):
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("transpose", [False, True])
-@pytest.mark.parametrize("impl", ["0", "1", "2", "3"], ids=["auto", "lds", "reg", "reg2"])
+@pytest.mark.parametrize("impl", ["0", "1", "2", "3", "6"], ids=["auto", "lds", "reg", "reg2", "xslab"])
 def test_block_solve_3d_n63_backward_error(precision, transpose, impl, monkeypatch):
     """x = D^{-1} r on 63^3 slabs: ||A x - r||_inf <= 8 d n u ||A||_inf ||x||_inf with the
     oracle's assembled slab matrix A (2d length-n transform passes and one N_t x N_t solve
@@ -133,3 +133,33 @@ def test_w3_family_iterate_parity(case):
     d, n, N, pt, T, sched, cycles = case
     print(f"W3 family iterates {case}", flush=True)
     iterate_parity(d, n, N, pt, T, 31, sched, cycles)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("transpose", [False, True])
+def test_xslab_smoothing_matches_twice_folded(precision, transpose, monkeypatch):
+    """The x-mode-major family (x pass, one (z, y) block solve per (slab, kx) in
+    LDS, inverse x pass) against the separate twice-folded passes: smoothing
+    step u += omega D^{-1}(F - L u) on 63^3 x 4 slabs, forward and adjoint."""
+    d, n, N, pt = 3, 63, 4, 1
+    print(f"xslab smoothing {precision} transpose={transpose}", flush=True)
+    monkeypatch.setenv("STMG_TRANSFORM", "6")
+    X = stmg.Solver(d, n, N, pt=pt, device=DEV, precision=precision)
+    monkeypatch.setenv("STMG_TRANSFORM", "3")
+    R = stmg.Solver(d, n, N, pt=pt, device=DEV, precision=precision)
+    monkeypatch.delenv("STMG_TRANSFORM")
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    g = torch.Generator(device=DEV).manual_seed(5)
+    u = torch.rand(X.level_dof(0), dtype=dt, device=DEV, generator=g) * 2 - 1
+    F = torch.rand(X.level_dof(0), dtype=dt, device=DEV, generator=g) * 2 - 1
+    ux, ur = u.clone(), u.clone()
+    X.smooth(ux, F, transpose=transpose)
+    R.smooth(ur, F, transpose=transpose)
+    xr = X.block_solve(F, transpose=transpose)
+    rr = R.block_solve(F, transpose=transpose)
+    torch.cuda.synchronize()
+    tol = 1e-13 if precision == "fp64" else 2e-5
+    assert ((ux - ur).abs().max() / ur.abs().max()).item() < tol
+    assert ((xr - rr).abs().max() / rr.abs().max()).item() < tol
+    X.close()
+    R.close()
