@@ -29,6 +29,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 
 #include "stmg_device.h"
 #include "stmg_internal.h"
@@ -684,7 +685,7 @@ __global__ __launch_bounds__(256) void k_fused_pair2(const T* in, T* out, const 
   }
 }
 
-// 2-D slab-resident block solve: one workgroup of 512 threads per slab holds
+// 2-D slab-resident block solve: one workgroup of WG threads (512) per slab holds
 // the slab's N_t x n x n values in LDS and runs the forward x pass, the fused
 // y pass with the per-mode solve, and the inverse x pass there, each wave
 // taking groups of 16 lines (x passes) or 16 columns with all N_t components
@@ -698,8 +699,8 @@ __global__ __launch_bounds__(256) void k_fused_pair2(const T* in, T* out, const 
 // block b = (slab, kx) is one N_t x n x n problem in (z, y) whose per-mode
 // blocks also carry kx's eigenvalues (formed from the 1-D eigenvalues in
 // `me`; the 2-D form reads the table G).  `slabs` counts blocks.
-template <typename T, int HB2, int NT, bool X3>
-__global__ __launch_bounds__(512) void k_slab_solve2(const T* src, T* dst, const T* __restrict__ Sfrag,
+template <typename T, int HB2, int NT, bool X3, int WG = 512>
+__global__ __launch_bounds__(WG) void k_slab_solve2(const T* src, T* dst, const T* __restrict__ Sfrag,
                                                      const T* __restrict__ G, int n, long long slabs, int transpose,
                                                      T omega, int mode, ModeEig<T> me) {
   typedef typename Mfma<T>::acc_t acc_t;
@@ -716,22 +717,23 @@ __global__ __launch_bounds__(512) void k_slab_solve2(const T* src, T* dst, const
   }
   const int nn = n * n;
   const int total = NT * nn;
+  constexpr int NW = WG / 64;   // waves per workgroup
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
   const int h = (n + 1) >> 1;
   const T* sp = src + slab * (long long)total;
   T* dp = dst + slab * (long long)total;
   // ---- slab to LDS, eight loads in flight per thread
 #pragma unroll 1
-  for (int e0 = threadIdx.x; e0 < total; e0 += 512 * 8) {
+  for (int e0 = threadIdx.x; e0 < total; e0 += WG * 8) {
     T v[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-      const int e = e0 + 512 * i;
+      const int e = e0 + WG * i;
       v[i] = e < total ? sp[e] : T(0);
     }
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-      const int e = e0 + 512 * i;
+      const int e = e0 + WG * i;
       if (e < total) R[e] = v[i];
     }
   }
@@ -739,7 +741,7 @@ __global__ __launch_bounds__(512) void k_slab_solve2(const T* src, T* dst, const
   // ---- forward x pass: line = component * n + y, in place in spectral order
   const int xgroups = (NT * n + 15) >> 4;
 #pragma unroll 1
-  for (int gi = wave; gi < xgroups; gi += 8) {
+  for (int gi = wave; gi < xgroups; gi += NW) {
     // an opaque copy of the table pointer: its loads are not hoisted out of the loop and kept live
     const T* Sf = Sfrag;
     asm volatile("" : "+s"(Sf));
@@ -765,11 +767,85 @@ __global__ __launch_bounds__(512) void k_slab_solve2(const T* src, T* dst, const
     }
   }
   __syncthreads();
+  const int ygroups = (n + 15) >> 4;
+  if constexpr (X3) {
+    // ---- y pass, one wave per (column group, component): forward pass of
+    // the component with the spectral column written back in place; barrier;
+    // every wave reads all components of its columns' modes and forms its
+    // component's solved values; barrier; inverse pass and store.  Uses all
+    // eight waves where the all-components-per-wave form below leaves waves
+    // idle (n = 63: four column groups).
+    const int tasks = ygroups * NT;
+    const int iters = (tasks + NW - 1) / NW;
+#pragma unroll 1
+    for (int it = 0; it < iters; ++it) {
+      const T* Sf = Sfrag;
+      asm volatile("" : "+s"(Sf));
+      const int t = it * NW + wave;
+      const bool active = t < tasks;
+      const int gi = active ? t / NT : 0, l = active ? t - (t / NT) * NT : 0;
+      const int col = gi * 16 + r;
+      const bool valid = active && col < n;
+      const int cc = valid ? col : 0;
+      T* cp = R + l * nn + cc;
+      {
+        T op[4][4 * HB2];
+        load_twice_folded<T, HB2, int>(cp, valid, n, n, g, op);
+        acc_t acc[4][HB2];
+        mma4<T, HB2, 0>(Sf, lane, [&](int m, int ib) { return op[m][ib]; }, acc);
+        if (valid) {
+#pragma unroll
+          for (int kb = 0; kb < HB2; ++kb)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              const int s = orow(kb, g, j);
+              const T P = acc[0][kb][j], Q = acc[1][kb][j], Pe = acc[2][kb][j], Qe = acc[3][kb][j];
+              cp[s * n] = P + Q;
+              cp[(h - 1 - s) * n] = P - Q;
+              cp[(h + s) * n] = Pe + Qe;
+              if (s != h / 2 - 1) cp[(h + h - 2 - s) * n] = Pe - Qe;
+            }
+        }
+      }
+      __syncthreads();
+      const T P3 = mxk * me.eig[cc];
+      const T Q3 = kxk * me.eig[cc] + mxk * me.eig[n + cc];
+      T op[4][4 * HB2];
+#pragma unroll
+      for (int kb = 0; kb < HB2; ++kb)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int s = orow(kb, g, j);
+          const bool middle = s == h / 2 - 1;
+          const int mode_idx[4] = {s, h - 1 - s, h + s, h + (middle ? s : h - 2 - s)};
+          T y[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            T a = T(0);
+            if (valid) {
+              T gr[NT];
+              mode_row<T, NT>(me, n, P3, Q3, mode_idx[q], l, transpose, gr);
+#pragma unroll
+              for (int m = 0; m < NT; ++m) a += gr[m] * R[m * nn + mode_idx[q] * n + cc];
+            }
+            y[q] = a;
+          }
+          const int ib = 4 * kb + j;
+          inverse_operands<T>(y[0], y[1], y[2], y[3], middle, op[0][ib], op[1][ib], op[2][ib], op[3][ib]);
+        }
+      __syncthreads();   // every component's modes are read before any column is overwritten
+      acc_t out_acc[4][HB2];
+      mma4<T, HB2, 1>(Sf, lane, [&](int m, int ib) { return op[m][ib]; }, out_acc);
+      T none[HB2][4][4];
+      zero_old<T, HB2>(none);
+      store_twice_unfolded<T, HB2, false, int>(cp, valid, n, n, g, out_acc, MODE_STORE, T(1), none);
+    }
+  }
   // ---- y pass: column c (spectral x index) of every component, forward,
   // per-mode N_t x N_t solve, inverse, in place
-  const int ygroups = (n + 15) >> 4;
+  if constexpr (!X3) {
 #pragma unroll 1
-  for (int gi = wave; gi < ygroups; gi += 8) {
+  for (int gi = wave; gi < ygroups; gi += NW) {
     const T* Sf = Sfrag;
     asm volatile("" : "+s"(Sf));
     const int col = gi * 16 + r;
@@ -843,10 +919,11 @@ __global__ __launch_bounds__(512) void k_slab_solve2(const T* src, T* dst, const
       __builtin_amdgcn_sched_barrier(0);
     }
   }
+  }
   __syncthreads();
   // ---- inverse x pass, in place in physical order
 #pragma unroll 1
-  for (int gi = wave; gi < xgroups; gi += 8) {
+  for (int gi = wave; gi < xgroups; gi += NW) {
     const T* Sf = Sfrag;
     asm volatile("" : "+s"(Sf));
     const int line = gi * 16 + r;
@@ -875,16 +952,16 @@ __global__ __launch_bounds__(512) void k_slab_solve2(const T* src, T* dst, const
   __syncthreads();
   // ---- result to dst
 #pragma unroll 1
-  for (int e0 = threadIdx.x; e0 < total; e0 += 512 * 8) {
+  for (int e0 = threadIdx.x; e0 < total; e0 += WG * 8) {
     T old[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-      const int e = e0 + 512 * i;
+      const int e = e0 + WG * i;
       old[i] = (e < total && mode == MODE_ADD_SCALED) ? dp[e] : T(0);
     }
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-      const int e = e0 + 512 * i;
+      const int e = e0 + WG * i;
       if (e < total) dp[e] = epi<T>(mode, old[i], R[e], omega);
     }
   }
@@ -1190,19 +1267,26 @@ hipError_t launch_slab_solve2(int n, int nt, const T* src, T* dst, const T* Sfra
   if (x3) mev = *me3;
   const long long blocks = x3 ? slabs * n : slabs;
   const dim3 grid = slab_grid(1, blocks);
-#define SL2X(HB2, NT, X)                                                                                       \
+  // 3-D planes: 256 threads (two workgroups per CU, limited by LDS, overlap one's memory phases with the other's
+  // matrix phases; 4.37 ms against 4.52 ms with 512 on 63^3 x 1024); STMG_XSLAB_WG=512 selects the wider form
+  static const int wg_env = [] {
+    const char* e = std::getenv("STMG_XSLAB_WG");
+    return e ? std::atoi(e) : 256;
+  }();
+#define SL2X(HB2, NT, X, W)                                                                                    \
   {                                                                                                            \
-    const void* fn = reinterpret_cast<const void*>(&k_slab_solve2<T, HB2, NT, X>);                             \
+    const void* fn = reinterpret_cast<const void*>(&k_slab_solve2<T, HB2, NT, X, W>);                          \
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);              \
     if (e != hipSuccess) return e;                                                                             \
-    hipLaunchKernelGGL((k_slab_solve2<T, HB2, NT, X>), grid, dim3(512), lds, s, src, dst, Sfrag2, G, n, blocks,  \
-                       transpose, omega, mode, mev);                                                           \
+    hipLaunchKernelGGL((k_slab_solve2<T, HB2, NT, X, W>), grid, dim3(W), lds, s, src, dst, Sfrag2, G, n,         \
+                       blocks, transpose, omega, mode, mev);                                                   \
     return hipGetLastError();                                                                                  \
   }
-#define SL2(HB2, NT)                        \
-  if (nt == NT) {                           \
-    if (x3) SL2X(HB2, NT, true)             \
-    SL2X(HB2, NT, false)                    \
+#define SL2(HB2, NT)                                    \
+  if (nt == NT) {                                       \
+    if (x3 && wg_env == 512) SL2X(HB2, NT, true, 512)   \
+    if (x3) SL2X(HB2, NT, true, 256)                    \
+    SL2X(HB2, NT, false, 512)                           \
   }
   if (n == 63) { SL2(1, 1) SL2(1, 2) }
   if constexpr (sizeof(T) == 4) {

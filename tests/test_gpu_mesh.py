@@ -199,7 +199,7 @@ def test_mesh_iterates_match_oracle(case, gamma):
         S.solve(Fg, u=ug, rtol=0.0, maxit=1, raise_on_noconv=False)
         err = rel_err(o(ug, kind, R, N, pt + 1, b), its[k])
         print(f"  iterate {k}: rel err {err:.2e}", flush=True)
-        assert err < 1e-11, k
+        assert err < 1e-12, k
 
 
 def test_mesh_adjoint_iterates():
@@ -213,7 +213,7 @@ def test_mesh_adjoint_iterates():
         S.adjoint(g(gv, kind, R, N, pt + 1), lam=lam, rtol=0.0, maxit=1, gradients=False, raise_on_noconv=False)
         err = rel_err(o(lam, kind, R, N, pt + 1, 1), its[k])
         print(f"  adjoint iterate {k}: rel err {err:.2e}", flush=True)
-        assert err < 1e-11, k
+        assert err < 1e-12, k
 
 
 def test_mesh_rhs_and_adjoint_map():
