@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--no-secondary", action="store_true", help="skip the 2-D 127^2 x 256 secondary line")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched 255^2 x 512 x 64-RHS FP32 line")
     ap.add_argument("--only-batched", action="store_true", help="only the batched line (for profiler runs)")
+    ap.add_argument("--cpu-full-w2", action="store_true",
+                    help="also time the CPU oracle on the whole 127^2 x 256 workload (about 2 minutes, 12 GB of host memory)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="launch kernels eagerly instead of replaying a hipGraph")
     ap.add_argument("--only-timed", action="store_true", help="timed V-cycles only (for profiler runs)")
@@ -212,6 +214,41 @@ def cpu_baseline(budget_s=20.0):
             "sample": f"3-D n={n} N={N} p_t={pt} (mu=4 like the headline, schedule {H.schedule}, {H.fine.dof} DoF), "
                       f"{cycles} V-cycles + residual norm each, {el:.1f} s; hierarchy, assembly and LU "
                       f"factorisations ({setup:.1f} s) excluded; scipy CSR SpMV and SuperLU solves run on one thread",
+            "host_cpus_available": len(os.sched_getaffinity(0))}
+
+
+def cpu_full_w2(budget_s=30.0):
+    """The oracle on the whole 127^2 x 256 workload (8.26 M DoF, about 294 M
+    nonzeros of the assembled space-time matrix): hierarchy, assembly and LU
+    factorisations timed apart, then V-cycles with the residual norm each for
+    about budget_s seconds (at least two)."""
+    import numpy as np
+
+    from oracle import multigrid, spacetime
+    from paper_1411_0519_amd import workloads
+
+    d, n, N, pt = 2, 127, 256, 1
+    t0 = time.perf_counter()
+    H = multigrid.Hierarchy(d, n, N, pt)
+    f, u0 = workloads.make(d, n, N, batch=1, seed=2, f="bumps", u0="sine1")
+    F = spacetime.rhs(H.fine, f, u0)
+    k = len(H.levels) - 1
+    H.vcycle(k, np.zeros_like(F), F)           # factorisations happen on first use
+    setup = time.perf_counter() - t0
+    u = np.zeros_like(F)
+    cycles = 0
+    t0 = time.perf_counter()
+    while True:
+        u = H.vcycle(k, u, F)
+        _ = np.linalg.norm(H.residual(k, u, F))
+        cycles += 1
+        el = time.perf_counter() - t0
+        if (el > budget_s and cycles >= 2) or cycles >= 20:
+            break
+    return {"value": H.fine.dof * cycles / el, "unit": "DoF*V-cycles/s", "cores": 1, "kind": "oracle",
+            "sample": f"the whole 2-D n={n} N={N} p_t={pt} workload ({H.fine.dof} DoF, {H.fine.L.nnz} nonzeros), "
+                      f"{cycles} V-cycles + residual norm each, {el:.1f} s; hierarchy, assembly and LU "
+                      f"factorisations {setup:.1f} s excluded; one thread",
             "host_cpus_available": len(os.sched_getaffinity(0))}
 
 
@@ -610,6 +647,14 @@ def main():
         out["batched_2d_255_b64_fp32"] = batched
     if p1_mesh is not None:
         out["p1_mesh"] = p1_mesh
+    if args.cpu_full_w2:
+        progress("CPU oracle on the whole 127^2 x 256 workload")
+        cf = cpu_full_w2()
+        if "secondary_2d_127" in out:
+            out["secondary_2d_127"]["cpu_baseline_full_size"] = cf
+            out["secondary_2d_127"]["gpu_over_cpu_full_size"] = out["secondary_2d_127"]["value"] / cf["value"]
+        else:
+            out["cpu_baseline_full_2d_127"] = cf
     if not args.no_cpu_baseline:
         progress("CPU oracle sample")
         cb = cpu_baseline()

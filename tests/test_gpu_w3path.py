@@ -5,7 +5,9 @@ block solve against the oracle's slab matrix A (backward error, FP64 and
 FP32, forward and transposed), and FP64 V-cycle iterates against the oracle
 on reduced members of the same family: the same mu = 4 (15^3 x 64, 7^3 x 16)
 and a 15^3 x 256 instance at mu = 1 whose schedule has the semi-then-full
-step of the full-size hierarchy (ffffsfssss)."""
+step of the full-size hierarchy (ffffsfssss); the x-mode-major 3-D family
+against the separate passes; and the batched workload's family (2-D, p_t = 2,
+mu = 128, 64 right-hand sides) at reduced N."""
 import functools
 
 import numpy as np
@@ -163,3 +165,27 @@ def test_xslab_smoothing_matches_twice_folded(precision, transpose, monkeypatch)
     assert ((xr - rr).abs().max() / rr.abs().max()).item() < tol
     X.close()
     R.close()
+
+
+def test_batched_family_iterate_parity():
+    """The batched workload's family (2-D, p_t = 2, mu = 128, 64 right-hand
+    sides with the workload's data recipe) at 63^2 x 8 slabs on T = 1/4: FP64
+    V-cycle iterates of every right-hand side against the oracle's."""
+    from paper_1411_0519_amd import workloads
+    d, n, N, pt, b, T = 2, 63, 8, 2, 64, 0.25
+    print("batched family iterates", flush=True)
+    S = stmg.Solver(d, n, N, pt=pt, T=T, batch=b, device=DEV)
+    S.autotune()
+    H = multigrid.Hierarchy(d, n, N, pt, T=T)
+    assert S.schedule == H.schedule == "fff" and abs(H.fine.mu - 128.0) < 1e-12
+    f, u0 = workloads.make(d, n, N, batch=b, seed=4, f="uniform", u0="series16")
+    F = spacetime.rhs(H.fine, f, u0)
+    _, _, its = H.solve(F, rtol=0.0, maxit=3, keep_iterates=True)
+    Fg = to_gpu(F)
+    u = torch.zeros_like(Fg)
+    for k in range(1, 4):
+        S.vcycle(u, Fg)
+        torch.cuda.synchronize()
+        err = rel_err(to_oracle(u, b), its[k])
+        assert err < 1e-12, (k, err)
+    S.close()
