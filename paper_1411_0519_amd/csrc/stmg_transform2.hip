@@ -722,17 +722,19 @@ __global__ __launch_bounds__(WG) void k_slab_solve2(const T* src, T* dst, const 
   const int h = (n + 1) >> 1;
   const T* sp = src + slab * (long long)total;
   T* dp = dst + slab * (long long)total;
-  // ---- slab to LDS, eight loads in flight per thread
+  // ---- slab to LDS: LF loads in flight per thread (the whole 63^2 x 2 plane of a 3-D block at once: nothing
+  // else is live yet, so the registers are free)
+  constexpr int LF = X3 ? 32 : 8;
 #pragma unroll 1
-  for (int e0 = threadIdx.x; e0 < total; e0 += WG * 8) {
-    T v[8];
+  for (int e0 = threadIdx.x; e0 < total; e0 += WG * LF) {
+    T v[LF];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
+    for (int i = 0; i < LF; ++i) {
       const int e = e0 + WG * i;
       v[i] = e < total ? sp[e] : T(0);
     }
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
+    for (int i = 0; i < LF; ++i) {
       const int e = e0 + WG * i;
       if (e < total) R[e] = v[i];
     }
