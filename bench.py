@@ -316,10 +316,13 @@ def spatial_cycle_bytes(levels, d, nt, b, nu1x=2, nu2x=2, elem=8):
 # Algorithmic HBM bytes per value of each fine-level kernel kind (element size
 # e): the residual reads u and F and writes r (the neighbour slab's values come
 # from cache); a transform pass reads and writes one vector; the last inverse
-# pass of a smoothing step also reads the old iterate (u += omega x).
+# pass of a smoothing step also reads the old iterate (u += omega x); the
+# residual + restriction reads u and F and writes the coarse vector, 2^-(d+1)
+# values per fine value (added in kernel_bytes).
 KIND_BYTES = {"residual": 3, "resid_x": 3, "pass_fwd": 2, "pass_fwd_y": 2, "fused": 2, "pass_inv_y": 2,
-              "pass_inv": 3}
+              "pass_inv": 3, "resid_restrict": 2}
 KIND_NAMES = {"residual": "residual r = F - L u", "resid_x": "residual fused with the forward x pass",
+              "resid_restrict": "residual + full restriction F_c = P^T (F - L u)",
               "pass_fwd": "forward sine pass along x", "pass_fwd_y": "forward sine pass along y",
               "fused": "forward pass + per-mode time solve + inverse pass along the slowest axis",
               "pass_inv_y": "inverse sine pass along y", "pass_inv": "inverse sine pass along x + update u += omega x"}
@@ -335,17 +338,22 @@ def executed_flops_per_value(kind, n, twice):
     return per_pass * (2 if kind == "fused" else 1)
 
 
-def kernel_table(prof, steps, nvals, n, elem, twice, mfma_peak):
+def kernel_bytes(kind, d):
+    """Algorithmic bytes per fine value and element byte of a kernel kind."""
+    return KIND_BYTES[kind] + (0.5 ** (d + 1) if kind == "resid_restrict" else 0.0)
+
+
+def kernel_table(prof, steps, nvals, n, elem, twice, mfma_peak, d):
     """Per-kind fine-level rows: average launch, algorithmic HBM bytes and rate,
     and for the transform kinds the executed matrix-core rate (and, apart, the
     dense-equivalent rate)."""
     table = {}
-    for k, nb in KIND_BYTES.items():
+    for k in KIND_BYTES:
         v = prof.get(k)
         if not v or not v["fine_launches"]:
             continue
         avg = v["fine_ms_total"] / v["fine_launches"]
-        by = nb * elem * nvals
+        by = kernel_bytes(k, d) * elem * nvals
         row = {"kernel": KIND_NAMES[k], "avg_launch_ms": avg, "launches": v["fine_launches"],
                "ms_per_step": v["fine_ms_total"] / steps, "bytes_per_launch": by,
                "hbm_gbs": by / (avg * 1e-3) / 1e9}
@@ -428,7 +436,7 @@ def measure_batched(stmg, torch, args, dev):
     impl0 = 0 if tuning is None else tuning[0][1]
     twice = impl0 in (0, 3, 5) and L0["n"] in (63, 127, 255)
     nvals = b * L0["N"] * S.nt * L0["n"] ** d
-    table = kernel_table(prof, 2, nvals, L0["n"], 4, twice, FP32_MFMA_PEAK_TFS)
+    table = kernel_table(prof, 2, nvals, L0["n"], 4, twice, FP32_MFMA_PEAK_TFS, d)
     dom = max(table, key=lambda k: table[k]["ms_per_step"])
     row = table[dom]
     out = {"workload": f"{w['name']}: {d}-D Q1 {n}^{d} interior, N={N} slabs, DG p_t={pt}, batch {b} right-hand "
@@ -499,9 +507,10 @@ def measure_workload(stmg, torch, idx, args, dev, steps, mixed=True):
     nvals = b * L0["N"] * S.nt * L0["n"] ** d
     impl0 = 0 if tuning is None else tuning[0][1]
     twice = impl0 in (0, 3, 5) and L0["n"] in (63, 127)
-    table = kernel_table(prof, steps, nvals, L0["n"], 8, twice, FP64_MFMA_PEAK_TFS)
+    table = kernel_table(prof, steps, nvals, L0["n"], 8, twice, FP64_MFMA_PEAK_TFS, d)
     out["fine_level_kernels"] = table
     out["fine_level_values"] = nvals
+    out["dim"] = d
     out["twice_folded"] = twice
     if not args.no_graph:
         S.set_graph(True)
@@ -541,7 +550,7 @@ def roofline_of(m):
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": row["hbm_frac"], "traffic": None,
             "avg_launch_ms": row["avg_launch_ms"], "launches": row["launches"],
             "bytes_per_launch": row["bytes_per_launch"],
-            "bytes_basis": f"{KIND_BYTES[dom]} x 8 B per value x {m['fine_level_values']} values"}
+            "bytes_basis": f"{kernel_bytes(dom, m['dim']):g} x 8 B per value x {m['fine_level_values']} values"}
     if "executed_mfma_tflops" in row:
         roof["mfma_executed"] = {"achieved": row["executed_mfma_tflops"], "peak": FP64_MFMA_PEAK_TFS,
                                  "unit": "TFLOP/s", "frac": row["executed_mfma_frac"]}

@@ -233,6 +233,17 @@ int st_mg_smooth(st_mg_t h, int level, int prec, int transpose, void* u, const v
                  void* stream);
 /* F_c = R r_f = P^T r_f from level to level+1. */
 int st_mg_restrict(st_mg_t h, int level, int prec, const void* r_fine, void* F_coarse, void* stream);
+/* F_c = P^T (F - L u) from level to level+1 (eq. chap4_generalLinearSystem
+ * followed by eq. chap4_restrictionTime and, on fully coarsened levels, eq.
+ * chap4_spaceRestrictionProlongation): the pre-restriction defect of the
+ * cycle.  On fully coarsened levels of dimension 2 or 3 with p_t <= 3 (n =
+ * 2 n_c + 1) the residual kernel restricts its own output, so the fine defect
+ * is never stored (its per-slab restricted parts use the level's workspace
+ * defect buffer); elsewhere the residual goes through that buffer and is
+ * restricted in a second pass.  u, F on the level, F_coarse on level+1, same
+ * layout as every level vector. */
+int st_mg_residual_restrict(st_mg_t h, int level, int prec, int transpose, const void* u, const void* F,
+                            void* F_coarse, void* stream);
 /* u_f += P e_c from level+1 to level. */
 int st_mg_prolong_add(st_mg_t h, int level, int prec, const void* e_coarse, void* u_fine,
                       void* stream);
@@ -309,7 +320,8 @@ enum {
   ST_PROF_RESID_X = 10,   /* residual fused with the forward x pass               */
   ST_PROF_PASS_FWD_Y = 11, /* forward pass along another axis before the last    */
   ST_PROF_PASS_INV_Y = 12, /* inverse pass along such an axis                     */
-  ST_PROF_KINDS = 13
+  ST_PROF_RESID_RESTRICT = 13, /* residual and full restriction in one pass       */
+  ST_PROF_KINDS = 14
 };
 int st_mg_profile_start(st_mg_t h);
 int st_mg_profile_stop(st_mg_t h);

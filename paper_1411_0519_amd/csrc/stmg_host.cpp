@@ -121,6 +121,7 @@ struct Level {
   int impl = -1;          // transform family chosen for this level (-1: handle default)
   int small = -1;         // small-level smoother on (1) / off (0) for this level (-1: handle default)
   int rx = -1;            // residual fused with the forward x pass (1) / separate (0) (-1: handle default)
+  int rr = -1;            // pre-restriction defect restricted by the residual kernel (1) / two passes (0)
   float tuned_ms = 0.f;   // autotuned smoothing-step time
   PassShape shape{};      // launch shape of the twice-folded passes (autotuned)
   void* u = nullptr;      // workspace vectors (inner precision), coarse levels only
@@ -219,6 +220,7 @@ struct st_mg {
   int impl = TRANSFORM_AUTO;
   bool small = true;      // one-kernel smoothing steps on levels whose slabs fit in LDS
   bool rx = false;        // residual fused with the forward x pass where it applies (autotuned per level)
+  bool rr = true;         // residual and full restriction in one pass where it applies
   // coarse end of every cycle in one workgroup from level `tail` down (-1: off);
   // argument blocks in device memory for the forward and the adjoint cycle
   int tail = -1;
@@ -1006,6 +1008,32 @@ int op_restrict(st_mg* h, int l, const T* rf, T* Fc, hipStream_t s) {
   return ST_OK;
 }
 
+// F_c = P^T (F - L u) from level l to l + 1: on fully coarsened 2-D/3-D levels
+// the residual kernel restricts its own output (per-slab parts in r, n_c^d /
+// n^d of its size, then the pair sums), else the residual into r followed by
+// the restriction.
+template <typename T>
+bool rr_level(const st_mg* h, int l) {
+  if (h->mesh || high_order(h) || l + 1 >= (int)h->lv.size() || h->lv[l].kind != 'f') return false;
+  if (!(h->lv[l].rr >= 0 ? h->lv[l].rr != 0 : h->rr)) return false;
+  ResRestrictShape sh;
+  return resid_restrict_shape(h->p.dim, h->nt, h->lv[l].n, h->lv[l + 1].n, (long long)h->p.batch * h->lv[l].N,
+                              (int)sizeof(T), sh);
+}
+
+template <typename T>
+int op_resid_restrict(st_mg* h, int l, bool transpose, const T* u, const T* F, T* r, T* Fc, hipStream_t s) {
+  if (rr_level<T>(h, l)) {
+    const ResidArgs<T> a = resid_args<T>(h, h->lv[l], transpose);
+    const TransferArgs<T> t = transfer_args<T>(h, l);
+    ProfScope ps(h, ST_PROF_RESID_RESTRICT, l, s);
+    HIPCHK(h, launch_resid_restrict<T>(h->p.dim, h->nt, u, F, Fc, r, a, t, s));
+    return ST_OK;
+  }
+  CHK((op_residual<T, T>(h, l, transpose, u, F, r, false, s)));
+  return op_restrict<T>(h, l, r, Fc, s);
+}
+
 template <typename T>
 int op_prolong(st_mg* h, int l, const T* ec, T* uf, hipStream_t s) {
   ProfScope ps(h, ST_PROF_PROLONG, l, s);
@@ -1404,8 +1432,7 @@ int vcycle_small(st_mg* h, int l, bool transpose, T* u, const T* F, bool u_zero,
     CHK(op_restrict<T>(h, l, F, Fc, s));
     HIPCHK(h, launch_fill<T>(u, len, s));
   } else {
-    CHK((op_residual<T, T>(h, l, transpose, u, F, r, false, s)));
-    CHK(op_restrict<T>(h, l, r, Fc, s));
+    CHK(op_resid_restrict<T>(h, l, transpose, u, F, r, Fc, s));
   }
   for (int g = 0; g < h->p.gamma; ++g) CHK(vcycle<T>(h, l + 1, transpose, uc, Fc, g == 0, false, s));
   CHK(op_prolong<T>(h, l, uc, u, s));
@@ -1451,9 +1478,10 @@ int vcycle(st_mg* h, int l, bool transpose, T* u, const T* F, bool u_zero, bool 
   T* Fc = (T*)C.F;
   if (h->p.nu1 == 0 && u_zero) {
     CHK(op_restrict<T>(h, l, F, Fc, s));
-  } else {
-    if (!(h->p.nu1 == 0 && r_ready)) CHK((op_residual<T, T>(h, l, transpose, u, F, r, false, s)));
+  } else if (h->p.nu1 == 0 && r_ready) {
     CHK(op_restrict<T>(h, l, r, Fc, s));
+  } else {
+    CHK(op_resid_restrict<T>(h, l, transpose, u, F, r, Fc, s));
   }
   for (int g = 0; g < h->p.gamma; ++g) CHK(vcycle<T>(h, l + 1, transpose, uc, Fc, g == 0, false, s));
   if (h->p.nu1 == 0 && u_zero) {
@@ -1771,6 +1799,31 @@ int tune_level(st_mg* h, int l, T* u, T* F, T* r, T* alt, hipStream_t s) {
       try_shape(c);
     }
     L.shape = bsh;
+  }
+  // the cycle's pre-restriction defect: residual kernel with the restricting
+  // epilogue, or the residual stored and restricted in a second pass
+  L.rr = -1;
+  T* Fc = l + 1 < (int)h->lv.size() ? (T*)h->lv[l + 1].F : nullptr;
+  if (h->rr && Fc != nullptr && rr_level<T>(h, l)) {
+    float t2[2] = {1e30f, 1e30f};
+    for (int v = 0; v < 2; ++v) {
+      L.rr = v;
+      int rc = op_resid_restrict<T>(h, l, false, u, F, r, Fc, s);
+      for (int rep = 0; rep < 5 && rc == ST_OK; ++rep) {
+        if (launch_spin(200.0, s) != hipSuccess) {
+          rc = ST_EHIP;
+          break;
+        }
+        (void)hipEventRecord(e0, s);
+        rc = op_resid_restrict<T>(h, l, false, u, F, r, Fc, s);
+        (void)hipEventRecord(e1, s);
+        (void)hipEventSynchronize(e1);
+        float t = 0.f;
+        (void)hipEventElapsedTime(&t, e0, e1);
+        if (rc == ST_OK) t2[v] = std::min(t2[v], t);
+      }
+    }
+    L.rr = t2[1] <= t2[0] ? 1 : 0;
   }
   h->prof = prof;
   (void)hipEventDestroy(e0);
@@ -2135,6 +2188,8 @@ int setup_impl(const st_mg_params* p, st_mg_t* out, const st_mesh* mesh, int ref
   // tuning knob: STMG_SMALL=0 turns the one-kernel small-level smoother off
   if (const char* sm = std::getenv("STMG_SMALL")) h->small = std::atoi(sm) != 0;
   if (const char* rx = std::getenv("STMG_RX")) h->rx = std::atoi(rx) != 0;
+  // tuning knob: STMG_RR=0 stores the fine defect and restricts it in a second pass
+  if (const char* rr = std::getenv("STMG_RR")) h->rr = std::atoi(rr) != 0;
   if (const char* ti = std::getenv("STMG_TRANSFORM")) {
     const int v = std::atoi(ti);
     h->impl = ((v >= TRANSFORM_AUTO && v <= TRANSFORM_SLAB) || v == TRANSFORM_XSLAB) ? v : TRANSFORM_AUTO;
@@ -2556,6 +2611,18 @@ int st_mg_restrict(st_mg_t h, int level, int prec, const void* r_fine, void* F_c
   hipStream_t s = (hipStream_t)stream;
   if (prec == ST_FP64) return op_restrict<double>(h, level, (const double*)r_fine, (double*)F_coarse, s);
   return op_restrict<float>(h, level, (const float*)r_fine, (float*)F_coarse, s);
+}
+
+int st_mg_residual_restrict(st_mg_t h, int level, int prec, int transpose, const void* u, const void* F,
+                            void* F_coarse, void* stream) {
+  CHK(check_level(h, level, prec, true));
+  if (!u || !F || !F_coarse) return fail(h, ST_EINVAL, "null vector");
+  hipStream_t s = (hipStream_t)stream;
+  if (prec == ST_FP64)
+    return op_resid_restrict<double>(h, level, transpose != 0, (const double*)u, (const double*)F,
+                                     level_r<double>(h, level), (double*)F_coarse, s);
+  return op_resid_restrict<float>(h, level, transpose != 0, (const float*)u, (const float*)F,
+                                  level_r<float>(h, level), (float*)F_coarse, s);
 }
 
 int st_mg_prolong_add(st_mg_t h, int level, int prec, const void* e_coarse, void* u_fine, void* stream) {

@@ -91,6 +91,18 @@ hipError_t launch_restrict(int dim, int nt, bool full, const T* rf, T* Fc, const
 template <typename T>
 hipError_t launch_prolong(int dim, int nt, bool full, const T* ec, T* uf, const TransferArgs<T>& a,
                           hipStream_t s);
+// Pre-restriction defect of a fully coarsened level (n = 2 n_c + 1) of
+// dimension 2 or 3, N_t <= 4, without storing it: F_c = P^T (F - L u) through
+// per-slab restricted parts in Hs (N slabs x N_t x n_c^d values), then their
+// pair sums.  resid_restrict_shape is false where it does not apply.
+struct ResRestrictShape {
+  int tyc, zcc, nyt, nzt, bs, oit, sit;
+  size_t lds;
+};
+bool resid_restrict_shape(int dim, int nt, int n, int nc, long long slabs, int tbytes, ResRestrictShape& sh);
+template <typename T>
+hipError_t launch_resid_restrict(int dim, int nt, const T* u, const T* F, T* Fc, T* Hs, const ResidArgs<T>& a,
+                                 const TransferArgs<T>& t, hipStream_t s);
 template <typename T>
 hipError_t launch_rhs(int dim, int nt, const T* f, const T* u0, T* F, const RhsArgs<T>& a,
                       hipStream_t s);

@@ -549,6 +549,246 @@ __global__ __launch_bounds__(256) void k_prolong(const T* __restrict__ ec, T* __
   }
 }
 
+// ------------------------------------------------ residual + full restriction
+// The pre-restriction defect of a fully coarsened level without storing it:
+// F_c[m] = R1 W r[2m] + R2 W r[2m+1] (eq. chap4_generalLinearSystem for r =
+// F - L u, eq. chap4_restrictionTime for R1, R2, W the full weighting (1/2, 1,
+// 1/2) per axis of eq. chap4_spaceRestrictionProlongation).  k_resid_weigh
+// computes, per fine slab s = 2m + j, h_s = R_{j+1} W r[s] on coarse nodes;
+// k_pair_sum adds the two slabs of each pair.  A workgroup takes fine slab s,
+// coarse rows cy0 .. cy1 - 1 of y (3-D; the whole x line in 2-D) and coarse
+// planes cz0 .. cz1 - 1 of the slowest axis (z in 3-D, y in 2-D), and marches
+// the fine planes 2 cz0 .. 2 cz1 (n = 2 n_c + 1: coarse node c sits on fine node
+// 2c + 1, so a coarse plane takes fine planes 2c .. 2c + 2 and neighbouring
+// tiles share one fine row or plane, which both compute).  The stencils use
+// the planar split of the 3-D residual (per staged plane A_c = mass and
+// B_c = stiffness parts within the plane, x only in 2-D), kept as the open
+// sums of the two output planes the last staged plane contributes to; each
+// fine output plane's R_{j+1}^T-combined defect goes through LDS for the
+// in-plane weighting, which runs after the next barrier beside the next
+// plane's staging; sums over fine planes stay in registers.  Thread t owns
+// fine positions t + BS i (i < OIT; R rows of n), coarse position t and staged
+// positions t + BS i (i < SIT; R + 2 rows in 3-D).
+template <typename T, int D, int NT, int BS, int OIT, int SIT>
+__global__ __launch_bounds__(BS) void k_resid_weigh(const T* __restrict__ u, const T* __restrict__ F,
+                                                    T* __restrict__ Hs, ResidArgs<T> a, TransferArgs<T> t,
+                                                    int TYC, int ZCC) {
+  constexpr int H = D == 3 ? 1 : 0;        // halo rows of y in a staged plane
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  T* U = reinterpret_cast<T*>(lds_raw);
+  const long long lg = xcd_linear(blockIdx.x + (long long)gridDim.x * slab_index(),
+                                  (long long)gridDim.x * gridDim.y * gridDim.z);
+  const long long slab = lg / gridDim.x;   // fine slab (batch-major)
+  const int tile = (int)(lg - slab * gridDim.x);
+  if (slab >= (long long)a.batch * a.N) return;
+  const int n = a.n, nc = t.nc;
+  const long long nx = a.nx, nxc = t.nxc;
+  const int nyt = D == 3 ? (nc + TYC - 1) / TYC : 1;
+  const int cy0 = D == 3 ? (tile % nyt) * TYC : 0;
+  const int cy1 = D == 3 ? (cy0 + TYC < nc ? cy0 + TYC : nc) : 1;
+  const int cz0 = (tile / nyt) * ZCC;
+  const int cz1 = cz0 + ZCC < nc ? cz0 + ZCC : nc;
+  const int R = D == 3 ? 2 * (cy1 - cy0) + 1 : 1;   // fine rows computed
+  const int plane = (R + 2 * H) * n;               // staged elements per component
+  const int nout = R * n;
+  const int ncout = (cy1 - cy0) * nc;
+  const long long pn = D == 3 ? (long long)n * n : n;
+  const long long pnc = D == 3 ? (long long)nc * nc : nc;
+  const long long s0 = (long long)(2 * cy0 - H) * n;   // first staged offset within a fine plane
+  const long long o0 = (long long)(2 * cy0) * n;       // first output offset
+  const int sn = (int)(slab % a.N);
+  const bool couple = (sn + a.dir >= 0) && (sn + a.dir < a.N);
+  const long long slabsz = (long long)NT * nx;
+  const T* un = u + slab * slabsz;
+  const T* up = u + (slab + a.dir) * slabsz;
+  const T* Fn = F + slab * slabsz;
+  const T* RT = (sn & 1) ? t.R2T : t.R1T;
+  T* out = Hs + slab * NT * nxc + (long long)cy0 * nc;
+  T* G = U + (NT + 1) * plane;             // [NT][nout]
+
+  const float inv_n = 1.0f / (float)n;
+  int oy[OIT], ox[OIT];
+#pragma unroll
+  for (int i = 0; i < OIT; ++i) {
+    const int e = threadIdx.x + BS * i;
+    oy[i] = D == 3 ? div_small(e, n, inv_n) : 0;
+    ox[i] = e - oy[i] * n;
+  }
+  const bool cact = threadIdx.x < ncout;
+  const int cyl = D == 3 ? div_small(threadIdx.x, nc, 1.0f / (float)nc) : 0;
+  const int cx = threadIdx.x - cyl * nc;
+
+  T uv[SIT][NT], pv[SIT][NT];        // staged loads of the next plane: own slab, upwind neighbour
+  T fv[OIT][NT], fn[OIT][NT];        // right-hand side of the output plane / the next one
+  // mass (NT + 1) and stiffness (NT) sums of the two output planes still open
+  T P0[OIT][2 * NT + 1], P1[OIT][2 * NT + 1], acc[NT];
+#pragma unroll
+  for (int i = 0; i < OIT; ++i) {
+#pragma unroll
+    for (int c = 0; c <= 2 * NT; ++c) P0[i][c] = P1[i][c] = T(0);
+#pragma unroll
+    for (int k = 0; k < NT; ++k) fn[i][k] = T(0);
+  }
+#pragma unroll
+  for (int k = 0; k < NT; ++k) acc[k] = T(0);
+  auto load_plane = [&](int p) {
+    const bool pin = p >= 0 && p < n;
+    const long long po = (long long)p * pn;
+#pragma unroll
+    for (int i = 0; i < SIT; ++i) {
+      const int e2 = threadIdx.x + BS * i;
+      const long long so = s0 + e2;
+      const bool in = pin && e2 < plane && so >= 0 && so < pn;
+#pragma unroll
+      for (int k = 0; k < NT; ++k) {
+        uv[i][k] = in ? un[k * nx + po + so] : T(0);
+        pv[i][k] = (in && couple) ? up[k * nx + po + so] : T(0);
+      }
+    }
+  };
+  auto load_rhs = [&](int p) {
+    const long long po = (long long)p * pn + o0;
+#pragma unroll
+    for (int i = 0; i < OIT; ++i) {
+      const int e = threadIdx.x + BS * i;
+#pragma unroll
+      for (int k = 0; k < NT; ++k) fn[i][k] = e < nout ? Fn[k * nx + po + e] : T(0);
+    }
+  };
+  // in-plane full weighting of fine plane o and its share of the coarse planes
+  auto weigh = [&](int o) {
+    if (!cact) return;
+#pragma unroll
+    for (int l = 0; l < NT; ++l) {
+      T gc = T(0);
+#pragma unroll
+      for (int dr = 0; dr < 2 * H + 1; ++dr) {
+        const T* row = G + l * nout + (2 * cyl + dr) * n + 2 * cx;
+        const T v = T(0.5) * row[0] + row[1] + T(0.5) * row[2];
+        gc += (D == 3 && dr != 1) ? T(0.5) * v : v;
+      }
+      if (o & 1) {
+        acc[l] += gc;                       // fine plane 2c + 1: weight 1 on coarse plane c
+      } else {
+        if (o > 2 * cz0) {                  // fine plane 2c: last part of coarse plane c - 1
+          acc[l] += T(0.5) * gc;
+          out[l * nxc + (long long)(o / 2 - 1) * pnc + (long long)cyl * nc + cx] = acc[l];
+        }
+        acc[l] = T(0.5) * gc;               // first part of coarse plane c
+      }
+    }
+  };
+  const int f0 = 2 * cz0, f1 = 2 * cz1;   // fine output planes f0 .. f1
+  load_plane(f0 - 1);
+  for (int p = f0 - 1; p <= f1 + 1; ++p) {
+    __syncthreads();   // the previous plane's stencils and contributions are done
+    if (p - 2 >= f0) weigh(p - 2);
+#pragma unroll
+    for (int i = 0; i < SIT; ++i) {
+      const int e2 = threadIdx.x + BS * i;
+      if (e2 < plane) {
+        T w = T(0);
+#pragma unroll
+        for (int k = 0; k < NT; ++k) {
+          U[k * plane + e2] = uv[i][k];
+          w += a.cb[k] * pv[i][k];
+        }
+        U[NT * plane + e2] = w;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < OIT; ++i)
+#pragma unroll
+      for (int k = 0; k < NT; ++k) fv[i][k] = fn[i][k];
+    if (p <= f1) load_plane(p + 1);
+    if (p >= f0 && p <= f1) load_rhs(p);
+    __syncthreads();
+    const int o = p - 1;   // fine output plane: complete once plane p = o + 1 is in
+#pragma unroll
+    for (int i = 0; i < OIT; ++i) {
+      const int e = threadIdx.x + BS * i;
+      if (e >= nout) continue;
+      const int x = ox[i];
+      const bool hl = x > 0, hr = x < n - 1;
+      T Ap[NT + 1], Bp[NT];
+#pragma unroll
+      for (int c = 0; c <= NT; ++c) {
+        T mm = T(0), kk = T(0);
+#pragma unroll
+        for (int dr = 0; dr < 2 * H + 1; ++dr) {
+          const T* row = U + c * plane + (oy[i] + dr) * n + x;
+          const T l = hl ? row[-1] : T(0);
+          const T m0 = row[0];
+          const T rt = hr ? row[1] : T(0);
+          const T sm = a.wm[0] * l + a.wm[1] * m0 + a.wm[2] * rt;
+          if (D == 3) {
+            mm += a.wm[dr] * sm;
+            if (c < NT) kk += a.wk[dr] * sm + a.wm[dr] * (a.wk[0] * l + a.wk[1] * m0 + a.wk[2] * rt);
+          } else {
+            mm = sm;
+            if (c < NT) kk = a.wk[0] * l + a.wk[1] * m0 + a.wk[2] * rt;
+          }
+        }
+        Ap[c] = mm;
+        if (c < NT) Bp[c] = kk;
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      // plane p closes output plane o (weights [2]), adds to plane p (weights
+      // [1]) and opens plane p + 1 (weights [0]); P1 holds plane o, P0 plane p
+#pragma unroll
+      for (int c = 0; c <= NT; ++c) {
+        P1[i][c] += a.wm[2] * Ap[c];
+        P0[i][c] += a.wm[1] * Ap[c];
+      }
+#pragma unroll
+      for (int c = 0; c < NT; ++c) {
+        P1[i][NT + 1 + c] += a.wk[2] * Ap[c] + a.wm[2] * Bp[c];
+        P0[i][NT + 1 + c] += a.wk[1] * Ap[c] + a.wm[1] * Bp[c];
+      }
+      if (o >= f0) {
+        T r[NT];
+#pragma unroll
+        for (int l = 0; l < NT; ++l) {
+          T s = fv[i][l] + a.ca[l] * P1[i][NT];
+#pragma unroll
+          for (int k = 0; k < NT; ++k) s -= a.K[l * NT + k] * P1[i][k] + a.M[l * NT + k] * P1[i][NT + 1 + k];
+          r[l] = s;
+        }
+#pragma unroll
+        for (int l = 0; l < NT; ++l) {
+          T g = T(0);
+#pragma unroll
+          for (int k = 0; k < NT; ++k) g += RT[k * NT + l] * r[k];
+          G[l * nout + e] = g;
+        }
+      }
+#pragma unroll
+      for (int c = 0; c <= NT; ++c) {
+        P1[i][c] = P0[i][c];
+        P0[i][c] = a.wm[0] * Ap[c];
+      }
+#pragma unroll
+      for (int c = 0; c < NT; ++c) {
+        P1[i][NT + 1 + c] = P0[i][NT + 1 + c];
+        P0[i][NT + 1 + c] = a.wk[0] * Ap[c] + a.wm[0] * Bp[c];
+      }
+    }
+  }
+  __syncthreads();
+  weigh(f1);
+}
+
+// F_c[m] = h[2m] + h[2m + 1] per coarse slab (len = values of the coarse vector).
+template <typename T>
+__global__ __launch_bounds__(256) void k_pair_sum(const T* __restrict__ Hs, T* __restrict__ Fc, long long per,
+                                                  long long len) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= len) return;
+  const long long cs = i / per, rem = i - cs * per;
+  const T* h = Hs + 2 * cs * per + rem;
+  Fc[i] = h[0] + h[per];
+}
+
 // --------------------------------------------------------------- load vector
 template <typename T, int D, int NT>
 __global__ __launch_bounds__(256) void k_rhs(const T* __restrict__ f, const T* __restrict__ u0,
@@ -757,6 +997,75 @@ hipError_t launch_residual(int dim, int nt, const Tin* u, const Tin* F, Tout* r,
   return hipErrorInvalidValue;
 }
 
+// Shape of the residual with the restricting epilogue: 3-D workgroups of 256
+// threads own TYC coarse rows (R = 2 TYC + 1 fine rows of n, R n <= 512, two
+// positions a thread), 2-D workgroups one x line (n <= 512; 128, 256 or 512
+// threads); chunks of ZCC coarse planes so that a level has about 8192
+// workgroups (at least 4 planes a chunk).
+bool resid_restrict_shape(int dim, int nt, int n, int nc, long long slabs, int tbytes, ResRestrictShape& sh) {
+  if ((dim != 2 && dim != 3) || nt < 1 || nt > 4 || nc < 1 || n != 2 * nc + 1) return false;
+  sh = ResRestrictShape{};
+  int R;
+  if (dim == 3) {
+    sh.bs = 256;
+    sh.tyc = (2 * sh.bs / n - 1) / 2;
+    if (sh.tyc < 1) return false;
+    if (sh.tyc > nc) sh.tyc = nc;
+    R = 2 * sh.tyc + 1;
+    sh.nyt = (nc + sh.tyc - 1) / sh.tyc;
+  } else {
+    if (n > 512) return false;
+    sh.bs = n <= 128 ? 128 : (n <= 256 ? 256 : 512);
+    sh.tyc = 1;
+    R = 1;
+    sh.nyt = 1;
+  }
+  const int plane = (R + (dim == 3 ? 2 : 0)) * n;
+  sh.oit = (R * n + sh.bs - 1) / sh.bs;
+  sh.sit = (plane + sh.bs - 1) / sh.bs;
+  if (sh.oit > 2 || sh.sit > 3) return false;
+  const long long per = (long long)sh.nyt * slabs;
+  const long long want = (8192 + per - 1) / per;
+  long long zc = (nc + want - 1) / want;
+  const int zmin = nc < 4 ? nc : 4;
+  if (zc < zmin) zc = zmin;
+  sh.zcc = (int)zc;
+  sh.nzt = (nc + sh.zcc - 1) / sh.zcc;
+  sh.lds = ((size_t)(nt + 1) * plane + (size_t)nt * R * n) * (size_t)tbytes;
+  return sh.lds <= 65536;
+}
+
+template <typename T>
+hipError_t launch_resid_restrict(int dim, int nt, const T* u, const T* F, T* Fc, T* Hs, const ResidArgs<T>& a,
+                                 const TransferArgs<T>& t, hipStream_t s) {
+  const long long slabs = (long long)a.batch * a.N;
+  ResRestrictShape sh;
+  if (!resid_restrict_shape(dim, nt, a.n, t.nc, slabs, (int)sizeof(T), sh) || t.nf != a.n || a.N != 2 * t.Nc ||
+      a.batch != t.batch)
+    return hipErrorInvalidValue;
+  const dim3 grid = slab_grid((unsigned)(sh.nyt * sh.nzt), slabs);
+  bool done = false;
+#define RR_CASE(D, NT, BS, OIT, SIT)                                                                       \
+  if (!done && dim == D && nt == NT && sh.bs == BS && sh.oit == OIT && sh.sit == SIT) {                    \
+    hipLaunchKernelGGL((k_resid_weigh<T, D, NT, BS, OIT, SIT>), grid, dim3(BS), sh.lds, s, u, F, Hs, a, t, \
+                       sh.tyc, sh.zcc);                                                                     \
+    done = true;                                                                                           \
+  }
+#define RR_NT(NT) RR_CASE(3, NT, 256, 2, 1) RR_CASE(3, NT, 256, 2, 2) RR_CASE(3, NT, 256, 2, 3) \
+                  RR_CASE(3, NT, 256, 1, 1) RR_CASE(3, NT, 256, 1, 2) \
+                  RR_CASE(2, NT, 128, 1, 1) RR_CASE(2, NT, 256, 1, 1) RR_CASE(2, NT, 512, 1, 1)
+  RR_NT(1) RR_NT(2) RR_NT(3) RR_NT(4)
+#undef RR_NT
+#undef RR_CASE
+  if (!done) return hipErrorInvalidValue;
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const long long per = (long long)nt * t.nxc;
+  const long long len = per * t.Nc * t.batch;
+  hipLaunchKernelGGL((k_pair_sum<T>), dim3(blocks_for(len)), dim3(256), 0, s, Hs, Fc, per, len);
+  return hipGetLastError();
+}
+
 #define TRANSFER_DISPATCH(KERNEL, TOTAL, ...)                                            \
   const unsigned grid = blocks_for(TOTAL);                                               \
   if (full) {                                                                            \
@@ -880,6 +1189,8 @@ template hipError_t launch_residual<float, float>(int, int, const float*, const 
                                          hipStream_t);                                              \
   template hipError_t launch_prolong<T>(int, int, bool, const T*, T*, const TransferArgs<T>&,       \
                                         hipStream_t);                                               \
+  template hipError_t launch_resid_restrict<T>(int, int, const T*, const T*, T*, T*, const ResidArgs<T>&, \
+                                               const TransferArgs<T>&, hipStream_t);                       \
   template hipError_t launch_rhs<T>(int, int, const T*, const T*, T*, const RhsArgs<T>&, hipStream_t); \
   template hipError_t launch_rhs_adjoint<T>(int, int, const T*, T*, T*, const RhsArgs<T>&,          \
                                             hipStream_t);                                           \

@@ -69,6 +69,7 @@ SIGNATURES = {
     "st_mg_spatial_cycle": (_i, [_vp, _i, _i, _i, _vp, _vp, _vp]),
     "st_mg_smooth": (_i, [_vp, _i, _i, _i, _vp, _vp, _vp]),
     "st_mg_restrict": (_i, [_vp, _i, _i, _vp, _vp, _vp]),
+    "st_mg_residual_restrict": (_i, [_vp, _i, _i, _i, _vp, _vp, _vp, _vp]),
     "st_mg_prolong_add": (_i, [_vp, _i, _i, _vp, _vp, _vp]),
     "st_mg_vcycle": (_i, [_vp, _vp, _vp, _dp, _vp]),
     "st_mg_solve": (_i, [_vp, _vp, _vp, _d, _i, _ip, _dp, _vp]),
@@ -84,7 +85,8 @@ SIGNATURES = {
 }
 
 PROF_KINDS = {"residual": 0, "pass_fwd": 1, "pass_inv": 2, "fused": 3, "small": 4, "restrict": 5,
-              "prolong": 6, "other": 7, "jacobi": 8, "xfer_x": 9, "resid_x": 10, "pass_fwd_y": 11, "pass_inv_y": 12}
+              "prolong": 6, "other": 7, "jacobi": 8, "xfer_x": 9, "resid_x": 10, "pass_fwd_y": 11, "pass_inv_y": 12,
+              "resid_restrict": 13}
 
 
 def lib():
@@ -353,6 +355,18 @@ class Solver:
         r = self._vec(r, self.level_dof(level), dt, "r")
         Fc = out if out is not None else torch.empty(self.level_dof(level + 1), dtype=dt, device=self.device)
         self._check(lib().st_mg_restrict(self._h, level, p, _ptr(r), _ptr(Fc), _stream(self.device)))
+        return Fc
+
+    def residual_restrict(self, u, F, level=0, prec=None, transpose=False, out=None):
+        """F_c = P^T (F - L u) on level + 1 (the cycle's pre-restriction defect)."""
+        p = self._prec(prec)
+        dt = self._pdtype(p)
+        nd = self.level_dof(level)
+        u = self._vec(u, nd, dt, "u")
+        F = self._vec(F, nd, dt, "F")
+        Fc = out if out is not None else torch.empty(self.level_dof(level + 1), dtype=dt, device=self.device)
+        self._check(lib().st_mg_residual_restrict(self._h, level, p, int(transpose), _ptr(u), _ptr(F), _ptr(Fc),
+                                                  _stream(self.device)))
         return Fc
 
     def prolong_add(self, e, u, level=0, prec=None):
