@@ -267,8 +267,9 @@ __device__ inline T recip(T d) {
 }
 
 template <typename T, int NT>
-__device__ inline void mode_row(const ModeEig<T>& me, int n, T P, T Q, int s, int l, int transpose, T (&g)[NT]) {
-  const T ms = me.eig[s], ks = me.eig[n + s];
+__device__ inline void mode_row(const ModeEig<T>& me, const T* eig, int n, T P, T Q, int s, int l, int transpose,
+                                T (&g)[NT]) {
+  const T ms = eig[s], ks = eig[n + s];
   const T mu = P * ms, nu = Q * ms + P * ks;
   if constexpr (NT == 1) {
     g[0] = T(1) / (mu * me.K[0] + nu * me.M[0]);
@@ -314,6 +315,27 @@ __device__ inline void mode_row(const ModeEig<T>& me, int n, T P, T Q, int s, in
       for (int j = k + 1; j < NT; ++j) x -= A[k][j] * g[j];
       g[k] = x * piv[k];
     }
+  }
+}
+
+// The whole block of mode s for N_t <= 2 (the rows mode_row gives one at a
+// time): G[l][m] = (D^{-1})[l][m], or (D^{-T})[l][m] when transposed.
+template <typename T, int NT>
+__device__ inline void mode_block(const ModeEig<T>& me, const T* eig, int n, T P, T Q, int s, int transpose,
+                                  T (&G)[NT][NT]) {
+  static_assert(NT <= 2, "closed form for N_t <= 2");
+  const T ms = eig[s], ks = eig[n + s];
+  const T mu = P * ms, nu = Q * ms + P * ks;
+  if constexpr (NT == 1) {
+    G[0][0] = T(1) / (mu * me.K[0] + nu * me.M[0]);
+  } else {
+    const T d00 = mu * me.K[0] + nu * me.M[0], d01 = mu * me.K[1] + nu * me.M[1];
+    const T d10 = mu * me.K[2] + nu * me.M[2], d11 = mu * me.K[3] + nu * me.M[3];
+    const T inv = recip<T>(d00 * d11 - d01 * d10);
+    G[0][0] = d11 * inv;
+    G[1][1] = d00 * inv;
+    G[0][1] = (transpose ? -d10 : -d01) * inv;
+    G[1][0] = (transpose ? -d01 : -d10) * inv;
   }
 }
 
@@ -582,8 +604,8 @@ __global__ __launch_bounds__(256) void k_pass_reg2(const T* __restrict__ in, T* 
 template <typename T, int HB2, int NT, int CG, bool BF>
 __device__ __forceinline__ void fused2_tile(const T* in, T* out, const T* __restrict__ Sf, const T* __restrict__ G,
                                             int n, long long inner, long long ncol, int transpose, T omega,
-                                            int mode, const ModeEig<T>& me, T (&xch)[4 * HB2][CG * NT * 64 * 4],
-                                            long long t) {
+                                            int mode, const ModeEig<T>& me, const T* eig,
+                                            T (&xch)[4 * HB2][CG * NT * 64 * 4], long long t) {
   typedef typename Mfma<T>::acc_t acc_t;
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
@@ -633,7 +655,7 @@ __device__ __forceinline__ void fused2_tile(const T* in, T* out, const T* __rest
           bool done = false;
           if (me.eig != nullptr) {
             T gr[NT];
-            mode_row<T, NT>(me, n, P0, Q0, mode_idx[q], l, transpose, gr);
+            mode_row<T, NT>(me, eig, n, P0, Q0, mode_idx[q], l, transpose, gr);
 #pragma unroll
             for (int m = 0; m < NT; ++m) a += gr[m] * xch[q * HB2 + kb][((cg * NT + m) * 64 + lane) * 4 + j];
             done = true;
@@ -666,9 +688,14 @@ __global__ __launch_bounds__(256) void k_fused_pair2(const T* in, T* out, const 
                                                      long long outer, int transpose, T omega, int mode,
                                                      ModeEig<T> me) {
   __shared__ T xch[4 * HB2][CG * NT * 64 * 4];
+  // the 1-D eigenvalues of the per-mode blocks, read by every mode: staged in
+  // LDS before the first barrier (n < 2h = 64 HB2)
+  __shared__ T eig[128 * HB2];
+  if (me.eig != nullptr)
+    for (int i = threadIdx.x; i < 2 * n; i += blockDim.x) eig[i] = me.eig[i];
   const long long ncol = outer * inner;
   if constexpr (!PERSIST) {
-    fused2_tile<T, HB2, NT, CG, BF>(in, out, Sfrag, G, n, inner, ncol, transpose, omega, mode, me, xch,
+    fused2_tile<T, HB2, NT, CG, BF>(in, out, Sfrag, G, n, inner, ncol, transpose, omega, mode, me, eig, xch,
                                     xcd_linear(blockIdx.x, gridDim.x));
   } else {
     const long long tiles = (ncol + 16 * CG - 1) / (16 * CG);
@@ -679,7 +706,7 @@ __global__ __launch_bounds__(256) void k_fused_pair2(const T* in, T* out, const 
     for (long long t = tbeg; t < tend; ++t) {
       const T* Sf = Sfrag;
       asm volatile("" : "+s"(Sf));
-      fused2_tile<T, HB2, NT, CG, BF>(in, out, Sf, G, n, inner, ncol, transpose, omega, mode, me, xch, t);
+      fused2_tile<T, HB2, NT, CG, BF>(in, out, Sf, G, n, inner, ncol, transpose, omega, mode, me, eig, xch, t);
       __syncthreads();   // the next tile rewrites the exchange buffer
     }
   }
@@ -708,6 +735,10 @@ __global__ __launch_bounds__(WG) void k_slab_solve2(const T* src, T* dst, const 
   T* R = reinterpret_cast<T*>(lds_raw);
   const long long slab = X3 ? xcd_linear(slab_index(), (long long)gridDim.y * gridDim.z) : slab_index();
   if (slab >= slabs) return;
+  // X3: the 1-D eigenvalues (2n) after the plane, read by every mode of the z pass
+  T* E = R + NT * n * n;
+  if constexpr (X3)
+    for (int i = threadIdx.x; i < 2 * n; i += WG) E[i] = me.eig[i];
   // x-mode of a 3-D block: its (m, kappa)
   T mxk = T(0), kxk = T(0);
   if constexpr (X3) {
@@ -771,13 +802,13 @@ __global__ __launch_bounds__(WG) void k_slab_solve2(const T* src, T* dst, const 
   __syncthreads();
   const int ygroups = (n + 15) >> 4;
   if constexpr (X3) {
-    // ---- y pass, one wave per (column group, component): forward pass of
+    // ---- y pass, one wave per (column group, component), where there are
+    // fewer column groups than waves (n = 63 on eight waves): forward pass of
     // the component with the spectral column written back in place; barrier;
     // every wave reads all components of its columns' modes and forms its
-    // component's solved values; barrier; inverse pass and store.  Uses all
-    // eight waves where the all-components-per-wave form below leaves waves
-    // idle (n = 63: four column groups).
-    const int tasks = ygroups * NT;
+    // component's solved values; barrier; inverse pass and store.  The
+    // all-components-per-wave form below would leave waves idle there.
+    const int tasks = ygroups < NW ? ygroups * NT : 0;
     const int iters = (tasks + NW - 1) / NW;
 #pragma unroll 1
     for (int it = 0; it < iters; ++it) {
@@ -810,8 +841,8 @@ __global__ __launch_bounds__(WG) void k_slab_solve2(const T* src, T* dst, const 
         }
       }
       __syncthreads();
-      const T P3 = mxk * me.eig[cc];
-      const T Q3 = kxk * me.eig[cc] + mxk * me.eig[n + cc];
+      const T P3 = mxk * E[cc];
+      const T Q3 = kxk * E[cc] + mxk * E[n + cc];
       T op[4][4 * HB2];
 #pragma unroll
       for (int kb = 0; kb < HB2; ++kb)
@@ -826,7 +857,7 @@ __global__ __launch_bounds__(WG) void k_slab_solve2(const T* src, T* dst, const 
             T a = T(0);
             if (valid) {
               T gr[NT];
-              mode_row<T, NT>(me, n, P3, Q3, mode_idx[q], l, transpose, gr);
+              mode_row<T, NT>(me, E, n, P3, Q3, mode_idx[q], l, transpose, gr);
 #pragma unroll
               for (int m = 0; m < NT; ++m) a += gr[m] * R[m * nn + mode_idx[q] * n + cc];
             }
@@ -844,8 +875,9 @@ __global__ __launch_bounds__(WG) void k_slab_solve2(const T* src, T* dst, const 
     }
   }
   // ---- y pass: column c (spectral x index) of every component, forward,
-  // per-mode N_t x N_t solve, inverse, in place
-  if constexpr (!X3) {
+  // per-mode N_t x N_t solve, inverse, in place (3-D blocks: where there are
+  // at least as many column groups as waves, n = 63 on four waves)
+  if (!X3 || ygroups >= NW) {
 #pragma unroll 1
   for (int gi = wave; gi < ygroups; gi += NW) {
     const T* Sf = Sfrag;
@@ -854,8 +886,8 @@ __global__ __launch_bounds__(WG) void k_slab_solve2(const T* src, T* dst, const 
     const bool valid = col < n;
     const int cc = valid ? col : 0;
     // (P, Q) of the modes of this column: x-mode and y-mode (3-D blocks)
-    const T P3 = X3 ? mxk * me.eig[cc] : T(0);
-    const T Q3 = X3 ? kxk * me.eig[cc] + mxk * me.eig[n + cc] : T(0);
+    const T P3 = X3 ? mxk * E[cc] : T(0);
+    const T Q3 = X3 ? kxk * E[cc] + mxk * E[n + cc] : T(0);
     acc_t acc[NT][4][HB2];
 #pragma unroll
     for (int l = 0; l < NT; ++l) {
@@ -881,28 +913,32 @@ __global__ __launch_bounds__(WG) void k_slab_solve2(const T* src, T* dst, const 
           v[l][2] = Pe + Qe;
           v[l][3] = Pe - Qe;
         }
+        T y[NT][4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+#pragma unroll
+          for (int l = 0; l < NT; ++l) y[l][q] = T(0);
+          if (valid) {
+            if constexpr (X3) {
+              T gb[NT][NT];   // one block per mode for every component
+              mode_block<T, NT>(me, E, n, P3, Q3, mode_idx[q], transpose, gb);
+#pragma unroll
+              for (int l = 0; l < NT; ++l)
+#pragma unroll
+                for (int m = 0; m < NT; ++m) y[l][q] += gb[l][m] * v[m][q];
+            } else {
+              const T* gm = G + (cc + n * mode_idx[q]) * (NT * NT);
+#pragma unroll
+              for (int l = 0; l < NT; ++l)
+#pragma unroll
+                for (int m = 0; m < NT; ++m) y[l][q] += (transpose ? gm[m * NT + l] : gm[l * NT + m]) * v[m][q];
+            }
+          }
+        }
 #pragma unroll
         for (int l = 0; l < NT; ++l) {
-          T y[4];
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            T a = T(0);
-            if (valid) {
-              if constexpr (X3) {
-                T gr[NT];
-                mode_row<T, NT>(me, n, P3, Q3, mode_idx[q], l, transpose, gr);
-#pragma unroll
-                for (int m = 0; m < NT; ++m) a += gr[m] * v[m][q];
-              } else {
-                const T* gm = G + (cc + n * mode_idx[q]) * (NT * NT);
-#pragma unroll
-                for (int m = 0; m < NT; ++m) a += (transpose ? gm[m * NT + l] : gm[l * NT + m]) * v[m][q];
-              }
-            }
-            y[q] = a;
-          }
           T u0, u1, u2, u3;
-          inverse_operands<T>(y[0], y[1], y[2], y[3], middle, u0, u1, u2, u3);
+          inverse_operands<T>(y[l][0], y[l][1], y[l][2], y[l][3], middle, u0, u1, u2, u3);
           acc[l][0][kb][j] = u0;   // the operand of chunk 4 kb + j, kept in place
           acc[l][1][kb][j] = u1;
           acc[l][2][kb][j] = u2;
@@ -1255,7 +1291,7 @@ hipError_t launch_fused_pair2(int n, int nt, const T* in, T* out, const T* Sfrag
 
 size_t slab_solve2_lds(int dim, int n, int nt, int elem_bytes) {
   if (dim < 2 || dim > 3 || nt < 1 || nt > 2 || !twice_folded_ok(n, elem_bytes) || n > 127) return 0;
-  const size_t bytes = (size_t)nt * n * n * elem_bytes;
+  const size_t bytes = ((size_t)nt * n * n + (dim == 3 ? 2 * n : 0)) * elem_bytes;
   return bytes <= 160 * 1024 ? bytes : 0;
 }
 
