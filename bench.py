@@ -253,7 +253,7 @@ def cpu_full_w2(budget_s=30.0):
 
 
 TRANSFORM_NAMES = ["default", "lds", "register", "register_twice_folded", "slab_resident",
-                   "twice_folded_residual_fused", "x_mode_slab_resident"]
+                   "twice_folded_residual_fused", "x_mode_slab_resident", "x_mode_slab_resident_residual_fused"]
 
 
 def tuned_levels(S, tuning):
@@ -326,16 +326,26 @@ KIND_NAMES = {"residual": "residual r = F - L u", "resid_x": "residual fused wit
               "pass_fwd": "forward sine pass along x", "pass_fwd_y": "forward sine pass along y",
               "fused": "forward pass + per-mode time solve + inverse pass along the slowest axis",
               "pass_inv_y": "inverse sine pass along y", "pass_inv": "inverse sine pass along x + update u += omega x"}
-TRANSFORM_KINDS = ("pass_fwd", "pass_fwd_y", "fused", "pass_inv_y", "pass_inv")
+TRANSFORM_KINDS = ("pass_fwd", "pass_fwd_y", "fused", "pass_inv_y", "pass_inv", "resid_x")
 
 
-def executed_flops_per_value(kind, n, twice):
+def kind_passes(kind, xslab):
+    """Transform passes per value of a kernel kind: the fused kind runs a
+    forward and an inverse pass along the slowest axis, or, for the
+    x-mode-major slab solve of a 3-D level, forward and inverse passes along y
+    and z; the residual fused with the x pass runs one."""
+    if kind == "fused":
+        return 4 if xslab else 2
+    return 1
+
+
+def executed_flops_per_value(kind, n, twice, xslab=False):
     """Matrix-core flops the folded kernels execute per value: a twice-folded
     pass runs four (h/2) x (h/2) products per line of n values (h = (n+1)/2),
-    a once-folded one two h x h products; the fused kind runs a forward and an
-    inverse pass.  The dense sine transform would need 2 n."""
+    a once-folded one two h x h products.  The dense sine transform would need
+    2 n per pass."""
     per_pass = 2.0 * ((n + 1) / 2) ** 2 / n if twice else 2.0 * 2 * ((n + 1) / 2) ** 2 / n
-    return per_pass * (2 if kind == "fused" else 1)
+    return per_pass * kind_passes(kind, xslab)
 
 
 def kernel_bytes(kind, d):
@@ -343,7 +353,7 @@ def kernel_bytes(kind, d):
     return KIND_BYTES[kind] + (0.5 ** (d + 1) if kind == "resid_restrict" else 0.0)
 
 
-def kernel_table(prof, steps, nvals, n, elem, twice, mfma_peak, d):
+def kernel_table(prof, steps, nvals, n, elem, twice, mfma_peak, d, xslab=False):
     """Per-kind fine-level rows: average launch, algorithmic HBM bytes and rate,
     and for the transform kinds the executed matrix-core rate (and, apart, the
     dense-equivalent rate)."""
@@ -359,8 +369,8 @@ def kernel_table(prof, steps, nvals, n, elem, twice, mfma_peak, d):
                "hbm_gbs": by / (avg * 1e-3) / 1e9}
         row["hbm_frac"] = row["hbm_gbs"] / HBM_PEAK_GBS
         if k in TRANSFORM_KINDS:
-            ex = executed_flops_per_value(k, n, twice) * nvals
-            dense = 2.0 * n * nvals * (2 if k == "fused" else 1)
+            ex = executed_flops_per_value(k, n, twice, xslab) * nvals
+            dense = 2.0 * n * nvals * kind_passes(k, xslab)
             row["executed_mfma_tflops"] = ex / (avg * 1e-3) / 1e12
             row["executed_mfma_frac"] = row["executed_mfma_tflops"] / mfma_peak
             row["dense_equivalent_tflops"] = dense / (avg * 1e-3) / 1e12
@@ -434,7 +444,7 @@ def measure_batched(stmg, torch, args, dev):
     prof = profile_kinds(stmg, S, lambda: S.solve(F, u=u, rtol=0.0, maxit=2, raise_on_noconv=False))
     L0 = S.levels[0]
     impl0 = 0 if tuning is None else tuning[0][1]
-    twice = impl0 in (0, 3, 5) and L0["n"] in (63, 127, 255)
+    twice = impl0 in (0, 3, 5, 6, 7) and L0["n"] in (63, 127, 255)
     nvals = b * L0["N"] * S.nt * L0["n"] ** d
     table = kernel_table(prof, 2, nvals, L0["n"], 4, twice, FP32_MFMA_PEAK_TFS, d)
     dom = max(table, key=lambda k: table[k]["ms_per_step"])
@@ -506,8 +516,9 @@ def measure_workload(stmg, torch, idx, args, dev, steps, mixed=True):
     L0 = S.levels[0]
     nvals = b * L0["N"] * S.nt * L0["n"] ** d
     impl0 = 0 if tuning is None else tuning[0][1]
-    twice = impl0 in (0, 3, 5) and L0["n"] in (63, 127)
-    table = kernel_table(prof, steps, nvals, L0["n"], 8, twice, FP64_MFMA_PEAK_TFS, d)
+    twice = impl0 in (0, 3, 5, 6, 7) and L0["n"] in (63, 127)
+    xslab = impl0 in (6, 7)
+    table = kernel_table(prof, steps, nvals, L0["n"], 8, twice, FP64_MFMA_PEAK_TFS, d, xslab)
     out["fine_level_kernels"] = table
     out["fine_level_values"] = nvals
     out["dim"] = d

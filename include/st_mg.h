@@ -287,7 +287,8 @@ int st_mg_set_graph(st_mg_t h, int enable);
  * bound workspace; synchronises the stream. */
 int st_mg_autotune(st_mg_t h, void* u_scratch, void* F_scratch, void* stream);
 /* Choice for one level: small (1/0), transform family (0 default, 1 LDS, 2 register once folded, 3 twice folded,
- * 4 slab-resident, 5 twice folded with the residual fused into the forward x pass), tuned step ms. */
+ * 4 slab-resident, 5 twice folded with the residual fused into the forward x pass, 6 x-mode-major slab-resident
+ * (3-D), 7 the same with the residual fused into its forward x pass), tuned step ms. */
 int st_mg_level_tuning(st_mg_t h, int level, int* small, int* impl, float* ms);
 
 /* Launch shape of the twice-folded sine passes on one level (the autotuner

@@ -908,9 +908,10 @@ int op_block_solve(st_mg* h, int l, bool transpose, const T* src, T* dst, int mo
   };
   if (xslab_level<T>(h, L)) {
     // x pass into [slab][kx][l][z][y], a (z, y) block solve per (slab, kx) in LDS, inverse x pass (+ update)
+    // (x_done: src already holds the x-transformed values in that layout, in A)
     const long long lps = (long long)nt * nn * nn;
     const long long ncols = slabs * lps;
-    {
+    if (!x_done) {
       ProfScope ps(h, ST_PROF_PASS_FWD, l, s);
       HIPCHK(h, launch_pass_reg2<T>(n, false, src, A, S2of<T>(L), 1, ncols, T(1), MODE_STORE, s, false,
                                     level_shape(h, L), lps));
@@ -1391,10 +1392,28 @@ bool norm_xhat(const st_mg* h) {
   return !is_mixed(h) && h->p.nu1 >= 1 && rx_level<T>(h, 0);
 }
 
+// 3-D x-mode-major levels: the residual kernel applies the forward x pass and
+// writes the slab solve's layout (autotuned per level like the 2-D fusion).
+template <typename T>
+bool rx3_level(const st_mg* h, int l) {
+  const Level& L = h->lv[l];
+  if (h->mesh || inexact_level(h, l) || !xslab_level<T>(h, L)) return false;
+  const bool on = L.rx >= 0 ? L.rx != 0 : h->rx;
+  return on && resid_xfwd3_ok(L.n, h->nt, (int)sizeof(T));
+}
+
 // One damped block-Jacobi step u += omega D^{-1}(F - L u) on level l (r and A are scratch).
 template <typename T>
 int smooth_step(st_mg* h, int l, bool transpose, T* u, const T* F, T* r, T* A, hipStream_t s) {
   const T om = (T)h->p.omega;
+  if (rx3_level<T>(h, l)) {
+    const Level& L = h->lv[l];
+    {
+      ProfScope ps(h, ST_PROF_RESID_X, l, s);
+      HIPCHK(h, launch_resid_xfwd3<T>(L.n, h->nt, u, F, A, resid_args<T>(h, L, transpose), S2of<T>(L), nullptr, s));
+    }
+    return op_block_solve<T>(h, l, transpose, A, u, MODE_ADD_SCALED, om, A, r, s, true);
+  }
   if (rx_level<T>(h, l)) {
     const Level& L = h->lv[l];
     const ResidArgs<T> a = resid_args<T>(h, L, transpose);
@@ -1710,7 +1729,10 @@ int tune_level(st_mg* h, int l, T* u, T* F, T* r, T* alt, hipStream_t s) {
     cands.push_back({0, TRANSFORM_REG, 0});
   }
   if (slab_capable<T>(h, L)) cands.push_back({0, TRANSFORM_SLAB, 0});
-  if (xslab_capable<T>(h, L)) cands.push_back({0, TRANSFORM_XSLAB, 0});
+  if (xslab_capable<T>(h, L)) {
+    cands.push_back({0, TRANSFORM_XSLAB, 0});
+    if (resid_xfwd3_ok(L.n, h->nt, (int)sizeof(T))) cands.push_back({0, TRANSFORM_XSLAB, 1});
+  }
   if (!high_order(h) && !bf16_level<T>(h, L) && S2of<T>(L) && resid_xfwd_ok(h->p.dim, L.n, h->nt, (int)sizeof(T)))
     cands.push_back({0, TRANSFORM_AUTO, 1});
   hipEvent_t e0, e1;
@@ -2699,7 +2721,11 @@ int st_mg_level_tuning(st_mg_t h, int level, int* small, int* impl, float* ms) {
   if (!h || level < 0 || level >= (int)h->lv.size()) return ST_EINVAL;
   const Level& L = h->lv[level];
   if (small) *small = L.small >= 0 ? L.small : (h->small ? 1 : 0);
-  if (impl) *impl = L.rx == 1 ? 5 : (L.impl >= 0 ? L.impl : h->impl);   // 5: twice folded, residual fused in
+  if (impl) {
+    const int f = L.impl >= 0 ? L.impl : h->impl;
+    // 5: twice folded, residual fused in; 7: x-mode-major slab solve, residual fused in
+    *impl = L.rx == 1 ? (f == TRANSFORM_XSLAB ? 7 : 5) : f;
+  }
   if (ms) *ms = L.tuned_ms;
   return ST_OK;
 }

@@ -476,6 +476,13 @@ hipError_t launch_slab_solve2(int n, int nt, const T* src, T* dst, const T* Sfra
 // 127): xhat = (S_x (x) I) (F - L u) in the layout of r; with `partial` the
 // per-tile sums of r^2 in the residual kernel's layout.
 bool resid_xfwd_ok(int dim, int n, int nt, int elem_bytes);
+// 3-D residual fused with the forward x pass into the x-mode-major layout of
+// the slab-resident solves (n = 63, 127; N_t <= 2); partial as in the residual
+// (per-workgroup sums of r^2, its own tile count).
+bool resid_xfwd3_ok(int n, int nt, int elem_bytes);
+template <typename T>
+hipError_t launch_resid_xfwd3(int n, int nt, const T* u, const T* F, T* xhat, const ResidArgs<T>& a,
+                              const T* Sfrag2, double* partial, hipStream_t s);
 template <typename T>
 hipError_t launch_resid_xfwd(int n, const T* u, const T* F, T* xhat, const ResidArgs<T>& a, const T* Sfrag2,
                              double* partial, hipStream_t s);

@@ -1180,6 +1180,260 @@ __global__ __launch_bounds__(256) void k_resid_xfwd(const T* __restrict__ u, con
   }
 }
 
+// 3-D residual fused with the forward x pass into the x-mode-major layout
+// [slab][kx][l][z][y] of the slab-resident solves: the z-marching residual
+// (TY rows of y per workgroup, zero halo rows and planes at the Dirichlet
+// boundary, planar stencil sums kept as the open sums of the two output
+// planes the last staged plane contributes to) leaves each output plane's
+// N_t TY lines of r (N_t TY <= 16, one twice-folded group) in one of four LDS
+// slots instead of HBM.  After every fourth plane (and at the end of the
+// chunk) wave w runs the twice-folded forward transform on slot w's lines,
+// right after the next staging barrier, and stores the spectral values to
+// xhat (TY consecutive y per (kx, l, z)).  With `partial` the workgroup's sum
+// of r^2 is written as the residual kernel does.  Dynamic LDS:
+// ((N_t + 1)(TY + 2) n + 4 * 16 n) elements.  Two workgroups per CU: the
+// register budget is capped at 256 (the accumulators then stay out of the
+// matrix registers; n = 63, FP64: 241, no spills).
+template <typename T, int HB2, int NT, int OIT, int SIT>
+__global__ __launch_bounds__(256, 2) void k_resid_xfwd3(const T* __restrict__ u, const T* __restrict__ F,
+                                                     T* __restrict__ xhat, ResidArgs<T> a,
+                                                     const T* __restrict__ Sfrag, double* __restrict__ partial,
+                                                     int TY, int ZC) {
+  constexpr int BS = 256, PB = 4;
+  typedef typename Mfma<T>::acc_t acc_t;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  T* U = reinterpret_cast<T*>(lds_raw);
+  const long long lg = xcd_linear(blockIdx.x + (long long)gridDim.x * slab_index(),
+                                  (long long)gridDim.x * gridDim.y * gridDim.z);
+  const long long slab = lg / gridDim.x;
+  const int tile = (int)(lg - slab * gridDim.x);
+  if (slab >= (long long)a.batch * a.N) return;
+  const int n = a.n;
+  const long long nx = a.nx;
+  const long long nn = (long long)n * n;
+  const int h = (n + 1) >> 1;
+  const int nyt = (n + TY - 1) / TY;
+  const int yt = tile % nyt;
+  const int z0 = (tile / nyt) * ZC;
+  const int z1 = z0 + ZC < n ? z0 + ZC : n;
+  const int y0 = yt * TY;
+  const int rows = (y0 + TY < n ? y0 + TY : n) - y0;
+  const int plane = (TY + 2) * n;
+  const int nout = rows * n;
+  const int sn = (int)(slab % a.N);
+  const bool couple = (sn + a.dir >= 0) && (sn + a.dir < a.N);
+  const long long slabsz = (long long)NT * nx;
+  const T* un = u + slab * slabsz;
+  const T* up = u + (slab + a.dir) * slabsz;
+  const T* Fn = F + slab * slabsz;
+  const long long s0 = (long long)(y0 - 1) * n;
+  const long long o0 = (long long)y0 * n;
+  T* Rb = U + (NT + 1) * plane;   // slots [PB][16 lines][n], line l * TY + row
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
+
+  const float inv_n = 1.0f / (float)n;
+  int oy[OIT], ox[OIT];
+#pragma unroll
+  for (int i = 0; i < OIT; ++i) {
+    const int e = threadIdx.x + BS * i;
+    oy[i] = div_small(e, n, inv_n);
+    ox[i] = e - oy[i] * n;
+  }
+  T uv[SIT][NT], pv[SIT][NT];
+  T fv[OIT][NT], fn[OIT][NT];
+  T P0[OIT][2 * NT + 1], P1[OIT][2 * NT + 1];
+#pragma unroll
+  for (int i = 0; i < OIT; ++i) {
+#pragma unroll
+    for (int c = 0; c <= 2 * NT; ++c) P0[i][c] = P1[i][c] = T(0);
+#pragma unroll
+    for (int k = 0; k < NT; ++k) fn[i][k] = T(0);
+  }
+  auto load_plane = [&](int p) {
+    const bool pin = p >= 0 && p < n;
+    const long long po = (long long)p * nn;
+#pragma unroll
+    for (int i = 0; i < SIT; ++i) {
+      const int e = threadIdx.x + BS * i;
+      const long long so = s0 + e;
+      const bool in = pin && e < plane && so >= 0 && so < nn;
+#pragma unroll
+      for (int k = 0; k < NT; ++k) {
+        uv[i][k] = in ? un[k * nx + po + so] : T(0);
+        pv[i][k] = (in && couple) ? up[k * nx + po + so] : T(0);
+      }
+    }
+  };
+  auto load_rhs = [&](int p) {
+    const long long po = (long long)p * nn + o0;
+#pragma unroll
+    for (int i = 0; i < OIT; ++i) {
+      const int e = threadIdx.x + BS * i;
+#pragma unroll
+      for (int k = 0; k < NT; ++k) fn[i][k] = e < nout ? Fn[k * nx + po + e] : T(0);
+    }
+  };
+  // forward x transform of the nb planes ob .. ob + nb - 1 in the slots: wave w takes plane ob + w
+  const long long lps = (long long)NT * nn;
+  auto xform = [&](int ob, int nb) {
+    if (wave >= nb) return;
+    const T* Sf = Sfrag;
+    asm volatile("" : "+s"(Sf));
+    const int zb = ob + wave;
+    const int l = r / TY, yl = r - (r / TY) * TY;
+    const bool valid = l < NT && yl < rows;
+    const T* lp = Rb + ((long long)wave * 16 + (valid ? r : 0)) * n;
+    // the four folded products one at a time, each operand formed from LDS
+    // (the operands of one product live at a time)
+    acc_t acc[4][HB2];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      T op[4 * HB2];
+#pragma unroll
+      for (int ib = 0; ib < 4 * HB2; ++ib) {
+        const int pp = cidx(ib, g);
+        const int i = 2 * pp + (m & 1);
+        const bool pair = (m & 1) == 0 || i < h - 1;   // the odd row h - 1 has no mirror
+        T v = T(0);
+        if (valid && (pair || m == 1)) {
+          const T x = lp[i];
+          const T y = pair ? lp[n - 1 - i] : T(0);
+          v = m < 2 ? x + y : x - y;
+        }
+        op[ib] = v;
+      }
+      mma1<T, HB2, 0>(Sf, lane, m, [&](int ib) { return op[ib]; }, acc[m]);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if (valid) {
+      T* xo = xhat + slab * n * lps + ((long long)l * n + zb) * n + y0 + yl;
+#pragma unroll
+      for (int kb = 0; kb < HB2; ++kb)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int s = orow(kb, g, j);
+          const T P = acc[0][kb][j], Q = acc[1][kb][j], Pe = acc[2][kb][j], Qe = acc[3][kb][j];
+          xo[(long long)s * lps] = P + Q;
+          xo[(long long)(h - 1 - s) * lps] = P - Q;
+          xo[(long long)(h + s) * lps] = Pe + Qe;
+          if (s != h / 2 - 1) xo[(long long)(h + h - 2 - s) * lps] = Pe - Qe;
+        }
+    }
+  };
+  double ss = 0.0;
+  int pend_ob = -1, pend_nb = 0;   // a batch of planes in the slots waiting for its transform
+  load_plane(z0 - 1);
+  for (int p = z0 - 1; p <= z1; ++p) {
+    __syncthreads();   // the previous plane's stencils and slot writes are done
+#pragma unroll
+    for (int i = 0; i < SIT; ++i) {
+      const int e = threadIdx.x + BS * i;
+      if (e < plane) {
+        T w = T(0);
+#pragma unroll
+        for (int k = 0; k < NT; ++k) {
+          U[k * plane + e] = uv[i][k];
+          w += a.cb[k] * pv[i][k];
+        }
+        U[NT * plane + e] = w;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < OIT; ++i)
+#pragma unroll
+      for (int k = 0; k < NT; ++k) fv[i][k] = fn[i][k];
+    if (pend_nb > 0) {
+      // the transform runs between the staging and the next plane's loads, so
+      // that its operands and accumulators never share registers with those loads
+      __builtin_amdgcn_sched_barrier(0);
+      xform(pend_ob, pend_nb);
+      __builtin_amdgcn_sched_barrier(0);
+      pend_nb = 0;
+    }
+    if (p < z1) load_plane(p + 1);
+    if (p >= z0 && p < z1) load_rhs(p);
+    __syncthreads();
+    const int o = p - 1;   // output plane: complete once plane p = o + 1 is in
+    const int slot = (o - z0) & (PB - 1);
+#pragma unroll
+    for (int i = 0; i < OIT; ++i) {
+      const int e = threadIdx.x + BS * i;
+      if (e >= nout) continue;
+      const int x = ox[i];
+      const bool hl = x > 0, hr = x < n - 1;
+      T Ap[NT + 1], Bp[NT];
+#pragma unroll
+      for (int c = 0; c <= NT; ++c) {
+        T mm = T(0), kk = T(0);
+#pragma unroll
+        for (int dr = 0; dr < 3; ++dr) {
+          const T* row = U + c * plane + (oy[i] + dr) * n + x;
+          const T lft = hl ? row[-1] : T(0);
+          const T m0 = row[0];
+          const T rt = hr ? row[1] : T(0);
+          const T sm = a.wm[0] * lft + a.wm[1] * m0 + a.wm[2] * rt;
+          mm += a.wm[dr] * sm;
+          if (c < NT) kk += a.wk[dr] * sm + a.wm[dr] * (a.wk[0] * lft + a.wk[1] * m0 + a.wk[2] * rt);
+        }
+        Ap[c] = mm;
+        if (c < NT) Bp[c] = kk;
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      // plane p closes output plane o (weights [2]), adds to plane p (weights
+      // [1]) and opens plane p + 1 (weights [0]); P1 holds plane o, P0 plane p
+#pragma unroll
+      for (int c = 0; c <= NT; ++c) {
+        P1[i][c] += a.wm[2] * Ap[c];
+        P0[i][c] += a.wm[1] * Ap[c];
+      }
+#pragma unroll
+      for (int c = 0; c < NT; ++c) {
+        P1[i][NT + 1 + c] += a.wk[2] * Ap[c] + a.wm[2] * Bp[c];
+        P0[i][NT + 1 + c] += a.wk[1] * Ap[c] + a.wm[1] * Bp[c];
+      }
+      if (o >= z0) {
+        T* sp = Rb + (long long)slot * 16 * n + oy[i] * n + x;
+#pragma unroll
+        for (int l = 0; l < NT; ++l) {
+          T s = fv[i][l] + a.ca[l] * P1[i][NT];
+#pragma unroll
+          for (int k = 0; k < NT; ++k) s -= a.K[l * NT + k] * P1[i][k] + a.M[l * NT + k] * P1[i][NT + 1 + k];
+          sp[l * TY * n] = s;
+          ss += (double)s * (double)s;
+        }
+      }
+#pragma unroll
+      for (int c = 0; c <= NT; ++c) {
+        P1[i][c] = P0[i][c];
+        P0[i][c] = a.wm[0] * Ap[c];
+      }
+#pragma unroll
+      for (int c = 0; c < NT; ++c) {
+        P1[i][NT + 1 + c] = P0[i][NT + 1 + c];
+        P0[i][NT + 1 + c] = a.wk[0] * Ap[c] + a.wm[0] * Bp[c];
+      }
+    }
+    if (o >= z0 && (slot == PB - 1 || o == z1 - 1)) {
+      pend_ob = o - slot;
+      pend_nb = slot + 1;
+    }
+  }
+  __syncthreads();
+  if (pend_nb > 0) xform(pend_ob, pend_nb);
+  if (partial != nullptr) {
+    __shared__ double red[BS / 64];
+    for (int off = 32; off > 0; off >>= 1) ss += __shfl_down(ss, off, 64);
+    if (lane == 0) red[wave] = ss;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+#pragma unroll
+      for (int w = 0; w < BS / 64; ++w) t += red[w];
+      partial[slab * gridDim.x + tile] = t;
+    }
+  }
+}
+
 }  // namespace
 
 bool twice_folded_ok(int n, int elem_bytes) {
@@ -1360,6 +1614,57 @@ hipError_t launch_resid_xfwd(int n, const T* u, const T* F, T* xhat, const Resid
   return hipGetLastError();
 }
 
+// 3-D form: TY rows of y per workgroup with N_t TY <= 16 lines a plane and
+// TY n <= 512 positions (two a thread), z chunks of at least 8 planes so that
+// a level has about 4096 workgroups.
+bool resid_xfwd3_ok(int n, int nt, int elem_bytes) {
+  return (n == 63 || n == 127) && nt >= 1 && nt <= 2 && twice_folded_ok(n, elem_bytes);
+}
+
+struct Rx3Shape {
+  int ty, zc, nyt, nzt, oit, sit;
+  size_t lds;
+};
+static Rx3Shape rx3_shape(int n, int nt, long long slabs, int elem_bytes) {
+  Rx3Shape sh{};
+  sh.ty = std::min(16 / nt, 512 / n);
+  sh.nyt = (n + sh.ty - 1) / sh.ty;
+  const long long want = (4096 + (long long)sh.nyt * slabs - 1) / ((long long)sh.nyt * slabs);
+  const int maxc = (n + 7) / 8;
+  const int nzc = (int)(want < 1 ? 1 : (want > maxc ? maxc : want));
+  sh.zc = (n + nzc - 1) / nzc;
+  sh.nzt = (n + sh.zc - 1) / sh.zc;
+  sh.oit = (sh.ty * n + 255) / 256;
+  sh.sit = ((sh.ty + 2) * n + 255) / 256;
+  sh.lds = ((size_t)(nt + 1) * (sh.ty + 2) * n + (size_t)4 * 16 * n) * elem_bytes;
+  return sh;
+}
+
+template <typename T>
+hipError_t launch_resid_xfwd3(int n, int nt, const T* u, const T* F, T* xhat, const ResidArgs<T>& a,
+                              const T* Sfrag2, double* partial, hipStream_t s) {
+  if (!resid_xfwd3_ok(n, nt, (int)sizeof(T)) || a.n != n) return hipErrorInvalidValue;
+  const long long slabs = (long long)a.batch * a.N;
+  const Rx3Shape sh = rx3_shape(n, nt, slabs, (int)sizeof(T));
+  const dim3 grid = slab_grid((unsigned)(sh.nyt * sh.nzt), slabs);
+#define RX3(HB2, NT, OIT, SIT)                                                                                  \
+  if (n == 32 * HB2 * 2 - 1 && nt == NT && sh.oit == OIT && sh.sit == SIT) {                                    \
+    const void* fn = reinterpret_cast<const void*>(&k_resid_xfwd3<T, HB2, NT, OIT, SIT>);                      \
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds);         \
+    if (e != hipSuccess) return e;                                                                             \
+    hipLaunchKernelGGL((k_resid_xfwd3<T, HB2, NT, OIT, SIT>), grid, dim3(256), sh.lds, s, u, F, xhat, a, Sfrag2, \
+                       partial, sh.ty, sh.zc);                                                                  \
+    return hipGetLastError();                                                                                  \
+  }
+  RX3(1, 1, 2, 3) RX3(1, 2, 2, 3) RX3(2, 1, 2, 3) RX3(2, 2, 2, 3)
+#undef RX3
+  return hipErrorInvalidValue;
+}
+
+template hipError_t launch_resid_xfwd3<double>(int, int, const double*, const double*, double*,
+                                               const ResidArgs<double>&, const double*, double*, hipStream_t);
+template hipError_t launch_resid_xfwd3<float>(int, int, const float*, const float*, float*, const ResidArgs<float>&,
+                                              const float*, double*, hipStream_t);
 template hipError_t launch_resid_xfwd<double>(int, const double*, const double*, double*, const ResidArgs<double>&,
                                               const double*, double*, hipStream_t);
 template hipError_t launch_resid_xfwd<float>(int, const float*, const float*, float*, const ResidArgs<float>&,

@@ -139,17 +139,24 @@ def test_w3_family_iterate_parity(case):
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("transpose", [False, True])
-def test_xslab_smoothing_matches_twice_folded(precision, transpose, monkeypatch):
+@pytest.mark.parametrize("rx", ["0", "1"], ids=["resid", "resid_xfwd"])
+@pytest.mark.parametrize("pt", [1, 0])
+def test_xslab_smoothing_matches_twice_folded(precision, transpose, rx, pt, monkeypatch):
     """The x-mode-major family (x pass, one (z, y) block solve per (slab, kx) in
-    LDS, inverse x pass) against the separate twice-folded passes: smoothing
-    step u += omega D^{-1}(F - L u) on 63^3 x 4 slabs, forward and adjoint."""
-    d, n, N, pt = 3, 63, 4, 1
-    print(f"xslab smoothing {precision} transpose={transpose}", flush=True)
+    LDS, inverse x pass; with STMG_RX=1 the residual kernel applies the x pass
+    and writes that layout itself) against the separate twice-folded passes:
+    smoothing step u += omega D^{-1}(F - L u) on 63^3 x 4 slabs, forward and
+    adjoint, N_t = 2 and 1."""
+    d, n, N = 3, 63, 4
+    print(f"xslab smoothing {precision} transpose={transpose} rx={rx} pt={pt}", flush=True)
     monkeypatch.setenv("STMG_TRANSFORM", "6")
+    monkeypatch.setenv("STMG_RX", rx)
     X = stmg.Solver(d, n, N, pt=pt, device=DEV, precision=precision)
     monkeypatch.setenv("STMG_TRANSFORM", "3")
+    monkeypatch.setenv("STMG_RX", "0")
     R = stmg.Solver(d, n, N, pt=pt, device=DEV, precision=precision)
     monkeypatch.delenv("STMG_TRANSFORM")
+    monkeypatch.delenv("STMG_RX")
     dt = torch.float64 if precision == "fp64" else torch.float32
     g = torch.Generator(device=DEV).manual_seed(5)
     u = torch.rand(X.level_dof(0), dtype=dt, device=DEV, generator=g) * 2 - 1
@@ -189,3 +196,35 @@ def test_batched_family_iterate_parity():
         err = rel_err(to_oracle(u, b), its[k])
         assert err < 1e-12, (k, err)
     S.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_xslab_resid_xfwd_vcycles_match_twice_folded(precision, monkeypatch):
+    """Three V-cycles with the residual kernel writing the x-mode-major layout
+    (STMG_TRANSFORM=6, STMG_RX=1) against the twice-folded passes on 63^3 x 8
+    slabs (a fully coarsened fine level, the headline's smoothing steps)."""
+    d, n, N, pt = 3, 63, 8, 1
+    print(f"xslab + residual/x-pass V-cycles {precision}", flush=True)
+    monkeypatch.setenv("STMG_TRANSFORM", "6")
+    monkeypatch.setenv("STMG_RX", "1")
+    X = stmg.Solver(d, n, N, pt=pt, device=DEV, precision=precision)
+    monkeypatch.setenv("STMG_TRANSFORM", "3")
+    monkeypatch.setenv("STMG_RX", "0")
+    R = stmg.Solver(d, n, N, pt=pt, device=DEV, precision=precision)
+    monkeypatch.delenv("STMG_TRANSFORM")
+    monkeypatch.delenv("STMG_RX")
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    g = torch.Generator(device=DEV).manual_seed(12)
+    F = torch.rand(X.level_dof(0), dtype=dt, device=DEV, generator=g) * 2 - 1
+    ux, ur = torch.zeros_like(F), torch.zeros_like(F)
+    X.profile_start()
+    for _ in range(3):
+        X.vcycle(ux, F)
+        R.vcycle(ur, F)
+    torch.cuda.synchronize()
+    assert X.profile_read("resid_x", level=0)[1] > 0
+    X.profile_stop()
+    tol = 1e-12 if precision == "fp64" else 1e-4
+    assert ((ux - ur).abs().max() / ur.abs().max()).item() < tol
+    X.close()
+    R.close()
