@@ -198,6 +198,80 @@ __global__ __launch_bounds__(MB) void k_mesh_residual_lds(const Tin* __restrict_
   }
 }
 
+// Runs of consecutive slabs: a workgroup takes one node tile of up to SR
+// slabs of one right-hand side in the order of the time coupling (increasing
+// for the forward operator, decreasing for the adjoint).  Staging a slab's
+// halo also forms the coupling combination w = sum_k cb_k u_k that the next
+// slab of the run needs (two alternating buffers), so only the first slab of
+// a run reads its neighbour from memory (u is read 1 + 1/SR times).  Partial
+// sums of r^2 per (slab, tile) as in the one-slab kernels.  Dynamic LDS:
+// (N_t + 2) hmax elements.
+template <typename Tin, typename Tout, int NT>
+__global__ __launch_bounds__(MB) void k_mesh_residual_run(const Tin* __restrict__ u, const Tin* __restrict__ F,
+                                                          Tout* __restrict__ r, MeshResidArgs<Tin> a,
+                                                          double* __restrict__ partial, int SR) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  const int hmax = a.op.hmax;
+  Tin* lx = reinterpret_cast<Tin*>(lds_raw);
+  Tin* lwb = lx + NT * hmax;   // [2][hmax]: coupling combinations, alternating
+  const long long nx = a.op.nx;
+  const long long tiles = (nx + MB - 1) / MB;
+  const long long runs = (a.N + SR - 1) / SR;   // runs per right-hand side
+  long long run, tile;
+  slab_tile(tiles, run, tile);
+  const long long bi = run / runs;
+  const int sa = (int)(run - bi * runs) * SR;
+  const int sb = sa + SR < a.N ? sa + SR : a.N;
+  const long long i = tile * MB + threadIdx.x;
+  const int h0 = a.op.hoff[tile], hn = a.op.hoff[tile + 1] - h0;
+  for (int q = 0; q < sb - sa; ++q) {
+    const int sn = a.dir < 0 ? sa + q : sb - 1 - q;
+    const long long slab = bi * a.N + sn;
+    const bool couple = sn + a.dir >= 0 && sn + a.dir < a.N;
+    const Tin* xs = u + slab * NT * nx;
+    const Tin* xn = u + (slab + a.dir) * NT * nx;
+    Tin* lw = lwb + (q & 1) * hmax;          // this slab's coupling (formed one slab earlier)
+    Tin* lw_next = lwb + (1 - (q & 1)) * hmax;
+    for (int j = threadIdx.x; j < hn; j += MB) {
+      const long long c = a.op.hcol[h0 + j];
+      Tin w = Tin(0);
+#pragma unroll
+      for (int k = 0; k < NT; ++k) {
+        const Tin v = xs[k * nx + c];
+        lx[k * hmax + j] = v;
+        w += a.cb[k] * v;
+      }
+      lw_next[j] = w;
+      if (q == 0 && couple) {
+        Tin wn = Tin(0);
+#pragma unroll
+        for (int k = 0; k < NT; ++k) wn += a.cb[k] * xn[k * nx + c];
+        lw[j] = wn;
+      }
+    }
+    __syncthreads();
+    double ss = 0.0;
+    if (i < nx) {
+      const long long off = slab * NT * nx;
+      Tin mu[NT], ku[NT], mw;
+      row_mk_lds<Tin, NT>(a.op, lx, couple ? lw : nullptr, i, mu, ku, mw);
+#pragma unroll
+      for (int l = 0; l < NT; ++l) {
+        Tin acc = F[off + l * nx + i] + a.ca[l] * mw;
+#pragma unroll
+        for (int k = 0; k < NT; ++k) acc -= a.K[l * NT + k] * mu[k] + a.M[l * NT + k] * ku[k];
+        r[off + l * nx + i] = (Tout)acc;
+        ss += (double)acc * (double)acc;
+      }
+    }
+    if (partial != nullptr) {
+      const double t = block_sum(ss);
+      if (threadIdx.x == 0) partial[slab * tiles + tile] = t;
+    }
+    __syncthreads();   // every row is done with lx and lw before the next slab is staged
+  }
+}
+
 // Solve D y = r for the node block D = m K + k M (N_t x N_t) by elimination
 // without pivoting: the symmetric part of D is positive definite (that of K is
 // semidefinite for the DG basis, M and the diagonals are positive), so every
@@ -604,6 +678,19 @@ hipError_t launch_mesh_residual(int nt, const Tin* u, const Tin* F, Tout* r, con
   const long long blocks = (long long)blocks_for(a.op.nx) * a.batch * a.N;
   if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
   const dim3 grid((unsigned)blocks);
+  // runs of SR slabs per workgroup (fewer where the grid would drop below 2048 workgroups)
+  const long long tiles = blocks_for(a.op.nx);
+  int SR = 8;
+  while (SR > 1 && tiles * a.batch * ((a.N + SR - 1) / SR) < 2048) SR /= 2;
+  const size_t lds_run = (size_t)(nt + 2) * a.op.hmax * sizeof(Tin);
+  if (SR > 1 && lds_run <= 65536) {
+    const dim3 rgrid((unsigned)(tiles * a.batch * ((a.N + SR - 1) / SR)));
+#define L_(NT) hipLaunchKernelGGL((k_mesh_residual_run<Tin, Tout, NT>), rgrid, dim3(MB), lds_run, s, u, F, r, a, \
+                                  partial, SR)
+    NT_SWITCH(L_)
+#undef L_
+    return hipGetLastError();
+  }
   const size_t lds = (size_t)(nt + 1) * a.op.hmax * sizeof(Tin);
   if (lds <= 65536) {
 #define L_(NT) hipLaunchKernelGGL((k_mesh_residual_lds<Tin, Tout, NT>), grid, dim3(MB), lds, s, u, F, r, a, partial)
