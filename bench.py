@@ -235,6 +235,7 @@ def cpu_full_w2(budget_s=30.0):
     k = len(H.levels) - 1
     H.vcycle(k, np.zeros_like(F), F)           # factorisations happen on first use
     setup = time.perf_counter() - t0
+    progress(f"CPU oracle, whole 127^2 x 256 workload: set up in {setup:.1f} s")
     u = np.zeros_like(F)
     cycles = 0
     t0 = time.perf_counter()
@@ -243,6 +244,7 @@ def cpu_full_w2(budget_s=30.0):
         _ = np.linalg.norm(H.residual(k, u, F))
         cycles += 1
         el = time.perf_counter() - t0
+        progress(f"CPU oracle, whole 127^2 x 256 workload: {cycles} V-cycles in {el:.1f} s")
         if (el > budget_s and cycles >= 2) or cycles >= 20:
             break
     return {"value": H.fine.dof * cycles / el, "unit": "DoF*V-cycles/s", "cores": 1, "kind": "oracle",
@@ -269,21 +271,25 @@ def measured_traffic(workload_name, kind):
     """HBM bytes per fine-level launch of the kernel of `kind` from the
     committed rocprofv3 counter record of the workload (FETCH_SIZE /
     WRITE_SIZE runs, scaled by a device copy of known size), or None when
-    there is no record for that kind or the kernel's source changed since it
-    was taken."""
+    the record has no entry for that kind or the kernel's source file changed
+    since it was taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"traffic_{workload_name}.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh)
-    src = os.path.join(ROOT, rec["source"])
-    if rec.get("kind") != kind or not os.path.exists(src):
-        return None
-    with open(src, "rb") as fh:
-        if hashlib.sha256(fh.read()).hexdigest() != rec["source_sha256"]:
+    for ent in rec.get("kernels", []):
+        if ent.get("kind") != kind:
+            continue
+        src = os.path.join(ROOT, ent["source"])
+        if not os.path.exists(src):
             return None
-    return rec
+        with open(src, "rb") as fh:
+            if hashlib.sha256(fh.read()).hexdigest() != ent["source_sha256"]:
+                return None
+        return ent
+    return None
 
 
 def spatial_cycle_bytes(levels, d, nt, b, nu1x=2, nu2x=2, elem=8):
@@ -519,6 +525,10 @@ def measure_workload(stmg, torch, idx, args, dev, steps, mixed=True):
     twice = impl0 in (0, 3, 5, 6, 7) and L0["n"] in (63, 127)
     xslab = impl0 in (6, 7)
     table = kernel_table(prof, steps, nvals, L0["n"], 8, twice, FP64_MFMA_PEAK_TFS, d, xslab)
+    for k, row in table.items():   # HBM bytes by counters where the committed record covers the kernel
+        rec = measured_traffic(w["name"], k)
+        if rec is not None:
+            row["counter_read_write_bytes"] = [rec["fetch_bytes_per_launch"], rec["write_bytes_per_launch"]]
     out["fine_level_kernels"] = table
     out["fine_level_values"] = nvals
     out["dim"] = d
