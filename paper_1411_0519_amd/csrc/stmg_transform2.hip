@@ -568,8 +568,10 @@ __device__ __forceinline__ void pass2_group_staged(const T* __restrict__ in, T* 
 // the waves of one XCD cover neighbouring ranges.
 template <typename T, int HB2, bool INV, bool UNIT, bool BF, bool PERSIST>
 __global__ __launch_bounds__(256) void k_pass_reg2(const T* __restrict__ in, T* __restrict__ out,
-                                                   const T* __restrict__ Sfrag, int n, long long inner_rt,
+                                                   const T* __restrict__ Sfrag, int n_arg, long long inner_rt,
                                                    long long ncols, T omega, int mode, long long lps) {
+  constexpr int n = 64 * HB2 - 1;   // fixed by the twice folding (the host checks n_arg)
+  (void)n_arg;
   const long long inner = UNIT ? 1 : inner_rt;
   const int wpb = blockDim.x >> 6;
   const long long wv = xcd_linear(blockIdx.x, gridDim.x) * wpb + (threadIdx.x >> 6);
@@ -684,9 +686,11 @@ __device__ __forceinline__ void fused2_tile(const T* in, T* out, const T* __rest
 
 template <typename T, int HB2, int NT, int CG, bool BF, bool PERSIST>
 __global__ __launch_bounds__(256) void k_fused_pair2(const T* in, T* out, const T* __restrict__ Sfrag,
-                                                     const T* __restrict__ G, int n, long long inner,
+                                                     const T* __restrict__ G, int n_arg, long long inner,
                                                      long long outer, int transpose, T omega, int mode,
                                                      ModeEig<T> me) {
+  constexpr int n = 64 * HB2 - 1;   // fixed by the twice folding (the host checks n_arg)
+  (void)n_arg;
   __shared__ T xch[4 * HB2][CG * NT * 64 * 4];
   // the 1-D eigenvalues of the per-mode blocks, read by every mode: staged in
   // LDS before the first barrier (n < 2h = 64 HB2)
@@ -728,9 +732,13 @@ __global__ __launch_bounds__(256) void k_fused_pair2(const T* in, T* out, const 
 // `me`; the 2-D form reads the table G).  `slabs` counts blocks.
 template <typename T, int HB2, int NT, bool X3, int WG = 512>
 __global__ __launch_bounds__(WG) void k_slab_solve2(const T* src, T* dst, const T* __restrict__ Sfrag,
-                                                     const T* __restrict__ G, int n, long long slabs, int transpose,
-                                                     T omega, int mode, ModeEig<T> me) {
+                                                     const T* __restrict__ G, int n_arg, long long slabs,
+                                                     int transpose, T omega, int mode, ModeEig<T> me) {
   typedef typename Mfma<T>::acc_t acc_t;
+  // the twice-folded transform fixes n = 64 HB2 - 1 (the host checks n_arg): with n a
+  // compile-time constant every LDS address of the passes is a base plus an immediate offset
+  constexpr int n = 64 * HB2 - 1;
+  (void)n_arg;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   T* R = reinterpret_cast<T*>(lds_raw);
   const long long slab = X3 ? xcd_linear(slab_index(), (long long)gridDim.y * gridDim.z) : slab_index();
@@ -1198,8 +1206,12 @@ template <typename T, int HB2, int NT, int OIT, int SIT>
 __global__ __launch_bounds__(256, 2) void k_resid_xfwd3(const T* __restrict__ u, const T* __restrict__ F,
                                                      T* __restrict__ xhat, ResidArgs<T> a,
                                                      const T* __restrict__ Sfrag, double* __restrict__ partial,
-                                                     int TY, int ZC) {
+                                                     int TY_arg, int ZC) {
   constexpr int BS = 256, PB = 4;
+  // n = 64 HB2 - 1 and TY = min(16 / N_t, 512 / n) are fixed by the template (the host checks them)
+  constexpr int n = 64 * HB2 - 1;
+  constexpr int TY = 16 / NT < 512 / n ? 16 / NT : 512 / n;
+  (void)TY_arg;
   typedef typename Mfma<T>::acc_t acc_t;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   T* U = reinterpret_cast<T*>(lds_raw);
@@ -1208,17 +1220,16 @@ __global__ __launch_bounds__(256, 2) void k_resid_xfwd3(const T* __restrict__ u,
   const long long slab = lg / gridDim.x;
   const int tile = (int)(lg - slab * gridDim.x);
   if (slab >= (long long)a.batch * a.N) return;
-  const int n = a.n;
   const long long nx = a.nx;
-  const long long nn = (long long)n * n;
-  const int h = (n + 1) >> 1;
-  const int nyt = (n + TY - 1) / TY;
+  constexpr long long nn = (long long)n * n;
+  constexpr int h = (n + 1) >> 1;
+  constexpr int nyt = (n + TY - 1) / TY;
   const int yt = tile % nyt;
   const int z0 = (tile / nyt) * ZC;
   const int z1 = z0 + ZC < n ? z0 + ZC : n;
   const int y0 = yt * TY;
   const int rows = (y0 + TY < n ? y0 + TY : n) - y0;
-  const int plane = (TY + 2) * n;
+  constexpr int plane = (TY + 2) * n;
   const int nout = rows * n;
   const int sn = (int)(slab % a.N);
   const bool couple = (sn + a.dir >= 0) && (sn + a.dir < a.N);
@@ -1231,12 +1242,11 @@ __global__ __launch_bounds__(256, 2) void k_resid_xfwd3(const T* __restrict__ u,
   T* Rb = U + (NT + 1) * plane;   // slots [PB][16 lines][n], line l * TY + row
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
 
-  const float inv_n = 1.0f / (float)n;
   int oy[OIT], ox[OIT];
 #pragma unroll
   for (int i = 0; i < OIT; ++i) {
     const int e = threadIdx.x + BS * i;
-    oy[i] = div_small(e, n, inv_n);
+    oy[i] = e / n;
     ox[i] = e - oy[i] * n;
   }
   T uv[SIT][NT], pv[SIT][NT];
