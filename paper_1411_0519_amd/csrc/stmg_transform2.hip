@@ -1193,24 +1193,26 @@ __global__ __launch_bounds__(256) void k_resid_xfwd(const T* __restrict__ u, con
 // (TY rows of y per workgroup, zero halo rows and planes at the Dirichlet
 // boundary, planar stencil sums kept as the open sums of the two output
 // planes the last staged plane contributes to) leaves each output plane's
-// N_t TY lines of r (N_t TY <= 16, one twice-folded group) in one of four LDS
-// slots instead of HBM.  After every fourth plane (and at the end of the
-// chunk) wave w runs the twice-folded forward transform on slot w's lines,
+// N_t TY lines of r (GP groups of 16 for the twice-folded transform) in one
+// of PB LDS slots instead of HBM.  After every PB-th plane (and at the end of
+// the chunk) each wave runs the forward transform on one group of the slots,
 // right after the next staging barrier, and stores the spectral values to
 // xhat (TY consecutive y per (kx, l, z)).  With `partial` the workgroup's sum
 // of r^2 is written as the residual kernel does.  Dynamic LDS:
-// ((N_t + 1)(TY + 2) n + 4 * 16 n) elements.  Two workgroups per CU: the
-// register budget is capped at 256 (the accumulators then stay out of the
-// matrix registers; n = 63, FP64: 241, no spills).
-template <typename T, int HB2, int NT, int OIT, int SIT>
-__global__ __launch_bounds__(256, 2) void k_resid_xfwd3(const T* __restrict__ u, const T* __restrict__ F,
-                                                     T* __restrict__ xhat, ResidArgs<T> a,
-                                                     const T* __restrict__ Sfrag, double* __restrict__ partial,
-                                                     int TY_arg, int ZC) {
-  constexpr int BS = 256, PB = 4;
-  // n = 64 HB2 - 1 and TY = min(16 / N_t, 512 / n) are fixed by the template (the host checks them)
+// ((N_t + 1)(TY + 2) n + (BS / 64) 16 n) elements.  The register budget is
+// capped at 256 (two 256-thread or one 512-thread workgroup per CU; the
+// accumulators then stay out of the matrix registers).
+template <typename T, int HB2, int NT, int OIT, int SIT, int BS>
+__global__ __launch_bounds__(BS, 512 / BS) void k_resid_xfwd3(const T* __restrict__ u, const T* __restrict__ F,
+                                                            T* __restrict__ xhat, ResidArgs<T> a,
+                                                            const T* __restrict__ Sfrag, double* __restrict__ partial,
+                                                            int TY_arg, int ZC) {
+  // n = 64 HB2 - 1 and TY = min(16 / N_t, 512 / n) x BS / 256 are fixed by the template (the host
+  // checks them); a plane's N_t TY lines are GP groups of 16, and PB planes fill the BS / 64 waves
   constexpr int n = 64 * HB2 - 1;
-  constexpr int TY = 16 / NT < 512 / n ? 16 / NT : 512 / n;
+  constexpr int TY = (16 / NT < 512 / n ? 16 / NT : 512 / n) * (BS / 256);
+  constexpr int GP = (NT * TY + 15) / 16;
+  constexpr int PB = BS / 64 / GP;
   (void)TY_arg;
   typedef typename Mfma<T>::acc_t acc_t;
   extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -1239,7 +1241,7 @@ __global__ __launch_bounds__(256, 2) void k_resid_xfwd3(const T* __restrict__ u,
   const T* Fn = F + slab * slabsz;
   const long long s0 = (long long)(y0 - 1) * n;
   const long long o0 = (long long)y0 * n;
-  T* Rb = U + (NT + 1) * plane;   // slots [PB][16 lines][n], line l * TY + row
+  T* Rb = U + (NT + 1) * plane;   // slots [PB][GP 16 lines][n], line l * TY + row
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
 
   int oy[OIT], ox[OIT];
@@ -1286,13 +1288,15 @@ __global__ __launch_bounds__(256, 2) void k_resid_xfwd3(const T* __restrict__ u,
   // forward x transform of the nb planes ob .. ob + nb - 1 in the slots: wave w takes plane ob + w
   const long long lps = (long long)NT * nn;
   auto xform = [&](int ob, int nb) {
-    if (wave >= nb) return;
+    const int pw = wave / GP, gp = wave - (wave / GP) * GP;   // plane of the batch, group of the plane
+    if (pw >= nb) return;
     const T* Sf = Sfrag;
     asm volatile("" : "+s"(Sf));
-    const int zb = ob + wave;
-    const int l = r / TY, yl = r - (r / TY) * TY;
+    const int zb = ob + pw;
+    const int line = gp * 16 + r;
+    const int l = line / TY, yl = line - (line / TY) * TY;
     const bool valid = l < NT && yl < rows;
-    const T* lp = Rb + ((long long)wave * 16 + (valid ? r : 0)) * n;
+    const T* lp = Rb + ((long long)pw * GP * 16 + (valid ? line : 0)) * n;
     // the four folded products one at a time, each operand formed from LDS
     // (the operands of one product live at a time)
     acc_t acc[4][HB2];
@@ -1364,7 +1368,7 @@ __global__ __launch_bounds__(256, 2) void k_resid_xfwd3(const T* __restrict__ u,
     if (p >= z0 && p < z1) load_rhs(p);
     __syncthreads();
     const int o = p - 1;   // output plane: complete once plane p = o + 1 is in
-    const int slot = (o - z0) & (PB - 1);
+    const int slot = (o - z0) % PB;
 #pragma unroll
     for (int i = 0; i < OIT; ++i) {
       const int e = threadIdx.x + BS * i;
@@ -1402,7 +1406,7 @@ __global__ __launch_bounds__(256, 2) void k_resid_xfwd3(const T* __restrict__ u,
         P0[i][NT + 1 + c] += a.wk[1] * Ap[c] + a.wm[1] * Bp[c];
       }
       if (o >= z0) {
-        T* sp = Rb + (long long)slot * 16 * n + oy[i] * n + x;
+        T* sp = Rb + (long long)slot * GP * 16 * n + oy[i] * n + x;
 #pragma unroll
         for (int l = 0; l < NT; ++l) {
           T s = fv[i][l] + a.ca[l] * P1[i][NT];
@@ -1624,29 +1628,36 @@ hipError_t launch_resid_xfwd(int n, const T* u, const T* F, T* xhat, const Resid
   return hipGetLastError();
 }
 
-// 3-D form: TY rows of y per workgroup with N_t TY <= 16 lines a plane and
-// TY n <= 512 positions (two a thread), z chunks of at least 8 planes so that
-// a level has about 4096 workgroups.
+// 3-D form: TY rows of y per workgroup of BS threads with N_t TY <= 16 BS /
+// 256 lines a plane and TY n <= 2 BS positions (two a thread), z chunks of at
+// least 8 planes so that a level has about 4096 workgroups.
 bool resid_xfwd3_ok(int n, int nt, int elem_bytes) {
   return (n == 63 || n == 127) && nt >= 1 && nt <= 2 && twice_folded_ok(n, elem_bytes);
 }
 
 struct Rx3Shape {
-  int ty, zc, nyt, nzt, oit, sit;
+  int ty, zc, nyt, nzt, oit, sit, bs;
   size_t lds;
 };
 static Rx3Shape rx3_shape(int n, int nt, long long slabs, int elem_bytes) {
+  // n = 63: 512-thread workgroups of 16 rows (runs of 16 y in the output: 4.5 instead of 5.9 GB
+  // written per launch on 63^3 x 1024, 3.94 against 4.19 ms); tuning knob STMG_RX3_BS=256 takes 8 rows
+  static const int bs = [] {
+    const char* e = std::getenv("STMG_RX3_BS");
+    return e && std::atoi(e) == 256 ? 256 : 512;
+  }();
   Rx3Shape sh{};
-  sh.ty = std::min(16 / nt, 512 / n);
+  sh.bs = n == 63 ? bs : 256;
+  sh.ty = std::min(16 / nt, 512 / n) * (sh.bs / 256);
   sh.nyt = (n + sh.ty - 1) / sh.ty;
   const long long want = (4096 + (long long)sh.nyt * slabs - 1) / ((long long)sh.nyt * slabs);
   const int maxc = (n + 7) / 8;
   const int nzc = (int)(want < 1 ? 1 : (want > maxc ? maxc : want));
   sh.zc = (n + nzc - 1) / nzc;
   sh.nzt = (n + sh.zc - 1) / sh.zc;
-  sh.oit = (sh.ty * n + 255) / 256;
-  sh.sit = ((sh.ty + 2) * n + 255) / 256;
-  sh.lds = ((size_t)(nt + 1) * (sh.ty + 2) * n + (size_t)4 * 16 * n) * elem_bytes;
+  sh.oit = (sh.ty * n + sh.bs - 1) / sh.bs;
+  sh.sit = ((sh.ty + 2) * n + sh.bs - 1) / sh.bs;
+  sh.lds = ((size_t)(nt + 1) * (sh.ty + 2) * n + (size_t)(sh.bs / 64) * 16 * n) * elem_bytes;
   return sh;
 }
 
@@ -1657,16 +1668,17 @@ hipError_t launch_resid_xfwd3(int n, int nt, const T* u, const T* F, T* xhat, co
   const long long slabs = (long long)a.batch * a.N;
   const Rx3Shape sh = rx3_shape(n, nt, slabs, (int)sizeof(T));
   const dim3 grid = slab_grid((unsigned)(sh.nyt * sh.nzt), slabs);
-#define RX3(HB2, NT, OIT, SIT)                                                                                  \
-  if (n == 32 * HB2 * 2 - 1 && nt == NT && sh.oit == OIT && sh.sit == SIT) {                                    \
-    const void* fn = reinterpret_cast<const void*>(&k_resid_xfwd3<T, HB2, NT, OIT, SIT>);                      \
+#define RX3(HB2, NT, OIT, SIT, BS)                                                                              \
+  if (n == 32 * HB2 * 2 - 1 && nt == NT && sh.oit == OIT && sh.sit == SIT && sh.bs == BS) {                     \
+    const void* fn = reinterpret_cast<const void*>(&k_resid_xfwd3<T, HB2, NT, OIT, SIT, BS>);                  \
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds);         \
     if (e != hipSuccess) return e;                                                                             \
-    hipLaunchKernelGGL((k_resid_xfwd3<T, HB2, NT, OIT, SIT>), grid, dim3(256), sh.lds, s, u, F, xhat, a, Sfrag2, \
-                       partial, sh.ty, sh.zc);                                                                  \
+    hipLaunchKernelGGL((k_resid_xfwd3<T, HB2, NT, OIT, SIT, BS>), grid, dim3(BS), sh.lds, s, u, F, xhat, a,     \
+                       Sfrag2, partial, sh.ty, sh.zc);                                                          \
     return hipGetLastError();                                                                                  \
   }
-  RX3(1, 1, 2, 3) RX3(1, 2, 2, 3) RX3(2, 1, 2, 3) RX3(2, 2, 2, 3)
+  RX3(1, 1, 2, 3, 256) RX3(1, 2, 2, 3, 256) RX3(2, 1, 2, 3, 256) RX3(2, 2, 2, 3, 256)
+  RX3(1, 1, 2, 3, 512) RX3(1, 2, 2, 3, 512)
 #undef RX3
   return hipErrorInvalidValue;
 }
