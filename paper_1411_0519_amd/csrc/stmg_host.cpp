@@ -1385,13 +1385,6 @@ bool rx_level(const st_mg* h, int l) {
   return on && S2of<T>(L) != nullptr && resid_xfwd_ok(h->p.dim, L.n, h->nt, (int)sizeof(T));
 }
 
-// The fine-level residual norm kernel also applies the forward x pass and leaves the result in the transform
-// buffer, where the first pre-smoothing step of the next cycle takes it (FP64/FP32 handles, nu1 >= 1).
-template <typename T>
-bool norm_xhat(const st_mg* h) {
-  return !is_mixed(h) && h->p.nu1 >= 1 && rx_level<T>(h, 0);
-}
-
 // 3-D x-mode-major levels: the residual kernel applies the forward x pass and
 // writes the slab solve's layout (autotuned per level like the 2-D fusion).
 template <typename T>
@@ -1400,6 +1393,14 @@ bool rx3_level(const st_mg* h, int l) {
   if (h->mesh || inexact_level(h, l) || !xslab_level<T>(h, L)) return false;
   const bool on = L.rx >= 0 ? L.rx != 0 : h->rx;
   return on && resid_xfwd3_ok(L.n, h->nt, (int)sizeof(T));
+}
+
+// The fine-level residual norm kernel also applies the forward x pass and leaves the result in the transform
+// buffer (in the x-mode-major layout on 3-D levels), where the first pre-smoothing step of the next cycle takes it
+// (FP64/FP32 handles, nu1 >= 1).
+template <typename T>
+bool norm_xhat(const st_mg* h) {
+  return !is_mixed(h) && h->p.nu1 >= 1 && (rx_level<T>(h, 0) || rx3_level<T>(h, 0));
 }
 
 // One damped block-Jacobi step u += omega D^{-1}(F - L u) on level l (r and A are scratch).
@@ -1530,13 +1531,20 @@ int fine_residual_norm(st_mg* h, bool transpose, const void* u, const void* F, h
                                       (float*)h->F32, true, s);
   if (norm_xhat<T>(h)) {
     const Level& L = h->lv[0];
+    const bool x3 = rx3_level<T>(h, 0);
     {
       ProfScope ps(h, ST_PROF_RESID_X, 0, s);
-      HIPCHK(h, launch_resid_xfwd<T>(L.n, (const T*)u, (const T*)F, (T*)h->tmp, resid_args<T>(h, L, transpose),
-                                     S2of<T>(L), h->partial, s));
+      if (x3)
+        HIPCHK(h, launch_resid_xfwd3<T>(L.n, h->nt, (const T*)u, (const T*)F, (T*)h->tmp,
+                                        resid_args<T>(h, L, transpose), S2of<T>(L), h->partial, s));
+      else
+        HIPCHK(h, launch_resid_xfwd<T>(L.n, (const T*)u, (const T*)F, (T*)h->tmp, resid_args<T>(h, L, transpose),
+                                       S2of<T>(L), h->partial, s));
     }
     ProfScope ps(h, ST_PROF_OTHER, 0, s);
-    const long long per = (long long)resid_blocks(h, L) * L.N;
+    const long long per =
+        (long long)(x3 ? resid_xfwd3_blocks_per_slab(L.n, h->nt, (long long)h->p.batch * L.N, (int)sizeof(T))
+                       : resid_blocks(h, L)) * L.N;
     HIPCHK(h, launch_norm_final(h->partial, per, h->p.batch, h->norm_dev, s));
     return ST_OK;
   }
@@ -1680,7 +1688,11 @@ size_t layout(st_mg* h, char* base) {
     h->ct64 = (double*)take(cl * 8);
   }
   const Level& L0 = h->lv[0];
-  h->partial_per_batch = std::max<long long>((long long)resid_blocks(h, L0) * L0.N, 1024);
+  h->partial_per_batch = std::max<long long>(
+      (long long)std::max(resid_blocks(h, L0),
+                          h->p.dim == 3 ? resid_xfwd3_blocks_per_slab(L0.n, nt, (long long)b * L0.N, (int)ib) : 0u) *
+          L0.N,
+      1024);
   h->partial = (double*)take(sizeof(double) * h->partial_per_batch * b);
   h->norm_dev = (double*)take(sizeof(double) * b);
   return off;

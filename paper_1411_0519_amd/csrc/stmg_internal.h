@@ -480,6 +480,7 @@ bool resid_xfwd_ok(int dim, int n, int nt, int elem_bytes);
 // the slab-resident solves (n = 63, 127; N_t <= 2); partial as in the residual
 // (per-workgroup sums of r^2, its own tile count).
 bool resid_xfwd3_ok(int n, int nt, int elem_bytes);
+unsigned resid_xfwd3_blocks_per_slab(int n, int nt, long long slabs, int elem_bytes);
 template <typename T>
 hipError_t launch_resid_xfwd3(int n, int nt, const T* u, const T* F, T* xhat, const ResidArgs<T>& a,
                               const T* Sfrag2, double* partial, hipStream_t s);

@@ -1661,6 +1661,12 @@ static Rx3Shape rx3_shape(int n, int nt, long long slabs, int elem_bytes) {
   return sh;
 }
 
+unsigned resid_xfwd3_blocks_per_slab(int n, int nt, long long slabs, int elem_bytes) {
+  if (!resid_xfwd3_ok(n, nt, elem_bytes)) return 0;
+  const Rx3Shape sh = rx3_shape(n, nt, slabs, elem_bytes);
+  return (unsigned)(sh.nyt * sh.nzt);
+}
+
 template <typename T>
 hipError_t launch_resid_xfwd3(int n, int nt, const T* u, const T* F, T* xhat, const ResidArgs<T>& a,
                               const T* Sfrag2, double* partial, hipStream_t s) {
