@@ -743,10 +743,27 @@ __global__ __launch_bounds__(WG) void k_slab_solve2(const T* src, T* dst, const 
   T* R = reinterpret_cast<T*>(lds_raw);
   const long long slab = X3 ? xcd_linear(slab_index(), (long long)gridDim.y * gridDim.z) : slab_index();
   if (slab >= slabs) return;
-  // X3: the 1-D eigenvalues (2n) after the plane, read by every mode of the z pass
+  // X3: the 1-D eigenvalues (2n) after the plane, read by every mode of the z pass,
+  // then the twice-folded fragment tables of both directions (2048 HB2^2 values),
+  // read by every product of the four passes
   T* E = R + NT * n * n;
-  if constexpr (X3)
+  T* Sl = E + 2 * n;
+  constexpr int NFRAG = 2048 * HB2 * HB2;
+  if constexpr (X3) {
     for (int i = threadIdx.x; i < 2 * n; i += WG) E[i] = me.eig[i];
+    for (int i = threadIdx.x; i < NFRAG; i += WG) Sl[i] = Sfrag[i];
+  }
+  // the fragment table of the passes: LDS (X3), else global memory through an
+  // opaque copy of the pointer (its loads are not hoisted out of the loops and kept live)
+  auto frag = [&]() -> const T* {
+    if constexpr (X3) {
+      return Sl;
+    } else {
+      const T* Sf = Sfrag;
+      asm volatile("" : "+s"(Sf));
+      return Sf;
+    }
+  };
   // x-mode of a 3-D block: its (m, kappa)
   T mxk = T(0), kxk = T(0);
   if constexpr (X3) {
@@ -784,8 +801,7 @@ __global__ __launch_bounds__(WG) void k_slab_solve2(const T* src, T* dst, const 
 #pragma unroll 1
   for (int gi = wave; gi < xgroups; gi += NW) {
     // an opaque copy of the table pointer: its loads are not hoisted out of the loop and kept live
-    const T* Sf = Sfrag;
-    asm volatile("" : "+s"(Sf));
+    const T* Sf = frag();
     const int line = gi * 16 + r;
     const bool valid = line < NT * n;
     T* lp = R + (valid ? line : 0) * n;
@@ -820,8 +836,7 @@ __global__ __launch_bounds__(WG) void k_slab_solve2(const T* src, T* dst, const 
     const int iters = (tasks + NW - 1) / NW;
 #pragma unroll 1
     for (int it = 0; it < iters; ++it) {
-      const T* Sf = Sfrag;
-      asm volatile("" : "+s"(Sf));
+      const T* Sf = frag();
       const int t = it * NW + wave;
       const bool active = t < tasks;
       const int gi = active ? t / NT : 0, l = active ? t - (t / NT) * NT : 0;
@@ -888,8 +903,7 @@ __global__ __launch_bounds__(WG) void k_slab_solve2(const T* src, T* dst, const 
   if (!X3 || ygroups >= NW) {
 #pragma unroll 1
   for (int gi = wave; gi < ygroups; gi += NW) {
-    const T* Sf = Sfrag;
-    asm volatile("" : "+s"(Sf));
+    const T* Sf = frag();
     const int col = gi * 16 + r;
     const bool valid = col < n;
     const int cc = valid ? col : 0;
@@ -970,8 +984,7 @@ __global__ __launch_bounds__(WG) void k_slab_solve2(const T* src, T* dst, const 
   // ---- inverse x pass, in place in physical order
 #pragma unroll 1
   for (int gi = wave; gi < xgroups; gi += NW) {
-    const T* Sf = Sfrag;
-    asm volatile("" : "+s"(Sf));
+    const T* Sf = frag();
     const int line = gi * 16 + r;
     const bool valid = line < NT * n;
     T* lp = R + (valid ? line : 0) * n;
@@ -1559,7 +1572,8 @@ hipError_t launch_fused_pair2(int n, int nt, const T* in, T* out, const T* Sfrag
 
 size_t slab_solve2_lds(int dim, int n, int nt, int elem_bytes) {
   if (dim < 2 || dim > 3 || nt < 1 || nt > 2 || !twice_folded_ok(n, elem_bytes) || n > 127) return 0;
-  const size_t bytes = ((size_t)nt * n * n + (dim == 3 ? 2 * n : 0)) * elem_bytes;
+  const int hb2 = (n + 1) / 64;   // twice-folded fragment tables in LDS for the 3-D form
+  const size_t bytes = ((size_t)nt * n * n + (dim == 3 ? 2 * n + 2048 * hb2 * hb2 : 0)) * elem_bytes;
   return bytes <= 160 * 1024 ? bytes : 0;
 }
 
