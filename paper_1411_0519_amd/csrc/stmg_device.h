@@ -115,6 +115,27 @@ __device__ inline void stencil_mk(const T* __restrict__ base, long long nx, int 
   }
 }
 
+// The same for a node index below 2^31 with 32-bit arithmetic.
+template <int D>
+__device__ inline void node_coords32(int j, int n, int& x, int& y, int& z) {
+  const unsigned uj = (unsigned)j, un = (unsigned)n;
+  if (D == 1) {
+    x = j;
+    y = z = 0;
+    return;
+  }
+  const unsigned q = uj / un;
+  x = (int)(uj - q * un);
+  if (D == 2) {
+    y = (int)q;
+    z = 0;
+  } else {
+    const unsigned q2 = q / un;
+    y = (int)(q - q2 * un);
+    z = (int)q2;
+  }
+}
+
 template <int D>
 __device__ inline void node_coords(long long j, int n, int& x, int& y, int& z) {
   x = (int)(j % n);

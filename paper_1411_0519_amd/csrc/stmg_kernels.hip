@@ -479,12 +479,12 @@ __global__ __launch_bounds__(256) void k_restrict(const T* __restrict__ rf, T* _
 template <typename T, int D, int NT, bool FULL>
 __global__ __launch_bounds__(256) void k_prolong(const T* __restrict__ ec, T* __restrict__ uf,
                                                  TransferArgs<T> a) {
-  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  // grid: x over the fine nodes of a slab, (y, z) over the coarse slabs: the
+  // slab decode is per workgroup and the node decode 32-bit
+  const long long cs = slab_index();           // coarse slab (batch-major)
+  const int jf = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (cs >= (long long)a.Nc * a.batch || jf >= a.nxf) return;
   const long long nxc = a.nxc, nxf = a.nxf;
-  const long long total = nxf * a.Nc * a.batch;
-  if (idx >= total) return;
-  const long long jf = idx % nxf;
-  const long long cs = idx / nxf;
   const long long m = cs % a.Nc;
   const long long bi = cs / a.Nc;
   const long long fs0 = bi * (2LL * a.Nc) + 2 * m;
@@ -492,7 +492,7 @@ __global__ __launch_bounds__(256) void k_prolong(const T* __restrict__ ec, T* __
   T e[NT];
   if (FULL) {
     int fx, fy, fz;
-    node_coords<D>(jf, a.nf, fx, fy, fz);
+    node_coords32<D>(jf, a.nf, fx, fy, fz);
     const int nc = a.nc;
     // per dimension: odd fine index 2c+1 -> coarse c (weight 1); even 2c -> c-1, c (1/2 each)
     int cxs[2], cys[2], czs[2];
@@ -1100,7 +1100,16 @@ hipError_t launch_restrict(int dim, int nt, bool full, const T* rf, T* Fc, const
 template <typename T>
 hipError_t launch_prolong(int dim, int nt, bool full, const T* ec, T* uf, const TransferArgs<T>& a,
                           hipStream_t s) {
-  TRANSFER_DISPATCH(k_prolong, a.nxf * a.Nc * a.batch, ec, uf, a)
+  if (a.nxf > 0x7fffffffLL) return hipErrorInvalidValue;
+  const dim3 pgrid = slab_grid(blocks_for(a.nxf), (long long)a.Nc * a.batch);
+#define PR_CASE(D, NT, FULL) \
+  if (dim == D && nt == NT && full == FULL) { hipLaunchKernelGGL((k_prolong<T, D, NT, FULL>), pgrid, dim3(256), 0, s, ec, uf, a); return hipGetLastError(); }
+#define PR_NT(NT) PR_CASE(1, NT, true) PR_CASE(2, NT, true) PR_CASE(3, NT, true) \
+                  PR_CASE(1, NT, false) PR_CASE(2, NT, false) PR_CASE(3, NT, false)
+  PR_NT(1) PR_NT(2) PR_NT(3) PR_NT(4)
+#undef PR_NT
+#undef PR_CASE
+  return hipErrorInvalidValue;
 }
 #undef TRANSFER_DISPATCH
 
