@@ -262,7 +262,10 @@ __device__ inline T recip(T d) {
     r = __builtin_fma(r, __builtin_fma(-d, r, 1.0), r);
     return r;
   } else {
-    return T(1) / d;
+    // hardware reciprocal (1 ulp) refined by one Newton step
+    float r = __builtin_amdgcn_rcpf(d);
+    r = __builtin_fmaf(r, __builtin_fmaf(-d, r, 1.0f), r);
+    return r;
   }
 }
 
